@@ -1,0 +1,185 @@
+/*
+ * nspnp.h -- C ABI of the MI355X (gfx950) solver for the coupled
+ * Navier-Stokes / Poisson-Nernst-Planck equations of sheared electrolyte
+ * between two sliding charged walls (plane Couette flow), after
+ * Ostilla-Monico & Lee, arXiv:1701.02005.
+ *
+ * What is solved (Sec. II, Eqs. (1)-(4)), in units of the half gap h, the
+ * wall speed U, the bulk concentration c0 and the thermal voltage V_T:
+ *   du/dt + div(u u) = -grad p + Re^-1 lap u + sF K (c+ - c-) grad Phi
+ *   div u = 0
+ *   dc+-/dt + div(u c+-) = (Re Sc)^-1 div(grad c+- +- c+- grad Phi)
+ *   lap phi = -(c+ - c-) / (2 lam^2),  Phi = (vhat/2) y + phi,  phi(+-1) = 0
+ * K = beta / (2 Sc Re^2 lam^2), lam = lambda_D / h.  Walls y = -1, +1 move at
+ * u_bot, u_top; no slip, no penetration, zero ion flux through the walls
+ * (Fig. 1 caption), wall potentials -vhat/2, +vhat/2 (Phi_0 = V y / h,
+ * Sec. II).  x (length lx) and z (length lz) are periodic.
+ *
+ * Discretisation (Sec. II, Fig. 1): second-order central differences on a
+ * staggered mesh, tanh-stretched in y; p, c+-, phi at cell centres, velocity
+ * components and ion fluxes on the cell faces.  One call of nspnp_step with
+ * n = 1 advances one Runge-Kutta substep: explicit advection, horizontal
+ * diffusion, Coulomb force and migration; implicit (Crank-Nicolson) wall-
+ * normal diffusion of u, v, w, c+, c- as batched tridiagonal systems; the
+ * pressure projection and the potential solve, each by FFT in x and z plus a
+ * tridiagonal (Thomas) solve in y per Fourier mode (Sec. II).
+ *
+ * Memory and ownership.  All field memory is ONE device buffer owned by the
+ * caller (size from nspnp_workspace_bytes); the library owns only the small
+ * host handle.  Every field is stored as a contiguous array of
+ * nx * nz * (ny - 1) values indexed x + nx * (z + nz * j), x fastest, j the
+ * cell row across the gap.  v is stored at the bottom face of each row (row 0
+ * is the bottom wall and holds 0; the top wall face is implicit).  u sits on
+ * the x-face at x = i*lx/nx, w on the z-face at z = k*lz/nz.  Work is queued
+ * on the caller's HIP stream and is asynchronous unless stated otherwise.
+ *
+ * Errors.  Every int-returning call returns NSPNP_OK (0) or a negative code;
+ * nothing throws or aborts across the ABI.  nspnp_last_error() gives a
+ * message for the calling thread.  A device-side failure (HIP error) is
+ * reported by the call that detects it.
+ */
+#ifndef NSPNP_H
+#define NSPNP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* symbols of this header are the only ones the shared library exports */
+#if defined(__GNUC__) || defined(__clang__)
+#define NSPNP_API __attribute__((visibility("default")))
+#else
+#define NSPNP_API
+#endif
+
+#define NSPNP_OK 0
+#define NSPNP_ERR_INVALID (-1)     /* bad argument or configuration                 */
+#define NSPNP_ERR_SIZE (-2)        /* unsupported size (see nspnp_config)            */
+#define NSPNP_ERR_HIP (-3)         /* a HIP runtime call failed                      */
+#define NSPNP_ERR_NONFINITE (-4)   /* NaN/Inf or negative concentration detected     */
+#define NSPNP_ERR_WORKSPACE (-5)   /* workspace missing, too small or misaligned     */
+
+#define NSPNP_PREC_FP64 0  /* every field and every operation in FP64              */
+#define NSPNP_PREC_MIXED 1 /* FP32 state, stencils and transport; FP64 elliptic
+                              solves, tridiagonal eliminations and reductions */
+
+/* field ids for get/set */
+#define NSPNP_FIELD_U 0
+#define NSPNP_FIELD_V 1
+#define NSPNP_FIELD_W 2
+#define NSPNP_FIELD_CP 3   /* cation concentration c+            */
+#define NSPNP_FIELD_CM 4   /* anion concentration c-             */
+#define NSPNP_FIELD_PHI 5  /* potential perturbation phi         */
+#define NSPNP_FIELD_P 6    /* pressure                           */
+
+/*
+ * Configuration.  Sizes: nx, nz of the form 2^a 3^b, even, 4..1024; ny (the
+ * number of wall-normal NODES, so ny - 1 cell rows) at least 5.  Lengths in
+ * units of h.  stretch is the tanh clustering factor g of the y nodes
+ * y_j = tanh(g xi_j)/tanh(g), xi_j uniform on [-1, 1] (g = 0: uniform).
+ * force_sign sF: -1 is the physical Coulomb force rho E = -rho grad Phi,
+ * +1 the sign printed in Eq. (1).  dt > 0 fixes the full Runge-Kutta step;
+ * dt <= 0 selects the adaptive step min(cfl / max(|u|/dx + |v|/dy + |w|/dz),
+ * 2 lam^2 Re Sc / max(c+ + c-), min(Re, Re Sc) / (4/dx^2 + 4/dz^2)),
+ * recomputed at the first stage of every step.  Initial state (init_state):
+ * linear Couette profile plus seeded uniform noise of amplitude u_noise on
+ * every velocity unknown, concentrations 1 plus seeded noise of amplitude
+ * c_noise with the volume mean removed, one projection, phi from the charge,
+ * p = 0.  The noise is SplitMix64 (Steele, Lea & Flood 2014) output number
+ * (field << 40) + index + 1 for the given seed, mapped to [-1, 1).
+ */
+typedef struct nspnp_config {
+    int32_t nx, ny, nz;
+    int32_t precision; /* NSPNP_PREC_FP64 or NSPNP_PREC_MIXED */
+    double lx, lz, stretch;
+    double re, sc, beta, debye, vhat;
+    double u_top, u_bot, force_sign;
+    double dt, cfl;
+    uint64_t seed;
+    double u_noise, c_noise;
+} nspnp_config;
+
+typedef struct nspnp_state nspnp_state;
+
+/* Bytes of device memory the caller must provide for this configuration
+ * (0 if the configuration is invalid).  The buffer must be 256-byte aligned. */
+NSPNP_API size_t nspnp_workspace_bytes(const nspnp_config *cfg);
+
+/* Build the grid and operator tables, lay the fields out in dev_workspace
+ * and compute the seeded initial state (Sec. II geometry and boundary
+ * conditions).  hip_stream is a hipStream_t (NULL: the null stream).  The
+ * workspace must stay allocated until nspnp_destroy.  Synchronises the
+ * stream before returning.  On success *out receives the handle. */
+NSPNP_API int nspnp_init_state(const nspnp_config *cfg, void *dev_workspace, size_t bytes, void *hip_stream,
+                     nspnp_state **out);
+
+/* Advance n_substeps Runge-Kutta substeps (stage = substep count mod 3, three
+ * substeps make one full step dt).  Asynchronous. */
+NSPNP_API int nspnp_step(nspnp_state *s, int32_t n_substeps);
+
+/* Solve the elliptic problem of the pressure projection (kind 0) or of the
+ * potential (kind 1) on this grid (Sec. II): (Lxx + Lzz + Lyy) out = rhs with
+ * three-point periodic Lxx, Lzz and the finite-volume Lyy across the gap;
+ * kind 0 has zero-flux walls and a zero volume-mean solution (rhs must have
+ * zero volume mean), kind 1 has out = 0 on the walls.  rhs and out are
+ * caller-owned FP64 device arrays of nx*nz*(ny-1) cell values; they may
+ * alias.  Asynchronous. */
+NSPNP_API int nspnp_poisson_solve(nspnp_state *s, int32_t kind, const double *dev_rhs, double *dev_out);
+
+/* Mean wall shear stress in units of rho_w U^2 (Sec. II, tau_w = eta d<u_x>/dy):
+ * the plane-averaged viscous flux through the bottom and top wall faces,
+ * Re^-1 (<u>_0 - u_bot)/(dy_0/2) and Re^-1 (u_top - <u>_last)/(dy_last/2).
+ * Host FP64 outputs.  Synchronises the stream. */
+NSPNP_API int nspnp_wall_shear_stress(nspnp_state *s, double *tau_bottom, double *tau_top);
+
+/* Plane-averaged total wall-normal flux of each ion species (advection +
+ * diffusion + migration) at the ny y-nodes, exactly zero on the two walls
+ * (Fig. 1 caption); and the total ion contents sum(c Omega).  jy_plus and
+ * jy_minus are caller-owned host arrays of ny doubles.  Synchronises. */
+NSPNP_API int nspnp_ion_flux(nspnp_state *s, double *jy_plus, double *jy_minus, double *mass_plus,
+                   double *mass_minus);
+
+/* ---- extras used by drivers and tests -------------------------------- */
+
+/* Copy a field to / from a caller-owned FP64 device array of nx*nz*(ny-1)
+ * values (converted to / from FP32 in the mixed form).  Asynchronous.
+ * Setting u, v, w, c+- does not re-solve phi; call nspnp_refresh_potential. */
+NSPNP_API int nspnp_get_field(nspnp_state *s, int32_t field, double *dev_out);
+NSPNP_API int nspnp_set_field(nspnp_state *s, int32_t field, const double *dev_in);
+
+/* Re-solve phi from the current c+-.  Asynchronous. */
+NSPNP_API int nspnp_refresh_potential(nspnp_state *s);
+
+/* Explicit right-hand sides H (advection, horizontal diffusion, Coulomb force,
+ * migration) of u, v, w, c+, c- for the current state, written to five
+ * caller-owned FP64 device arrays out[0..4].  Asynchronous. */
+NSPNP_API int nspnp_explicit_terms(nspnp_state *s, double *const dev_out[5]);
+
+/* Scalar diagnostics, FP64, synchronising: out[0] kinetic energy
+ * 1/2 sum(|u|^2 Omega), out[1] max |div u| over the cells, out[2] min c+,
+ * out[3] min c-, out[4] max(c+ + c-).  Returns NSPNP_ERR_NONFINITE if any
+ * is not finite. */
+NSPNP_API int nspnp_diagnostics(nspnp_state *s, double out[5]);
+
+/* Simulation clock: time, current full step dt, next stage (0..2), substeps
+ * taken.  get synchronises; set is used to restart from saved fields. */
+NSPNP_API int nspnp_get_clock(nspnp_state *s, double *t, double *dt, int32_t *stage, int64_t *substeps);
+NSPNP_API int nspnp_set_clock(nspnp_state *s, double t, double dt, int32_t stage, int64_t substeps);
+
+/* Wait for all queued work of this state. */
+NSPNP_API int nspnp_sync(nspnp_state *s);
+
+/* Release the host handle (the workspace stays the caller's). */
+NSPNP_API void nspnp_destroy(nspnp_state *s);
+
+/* Message of the last failed call on this thread ("" if none). */
+NSPNP_API const char *nspnp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NSPNP_H */

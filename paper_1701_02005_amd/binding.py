@@ -1,0 +1,239 @@
+"""Thin ctypes binding of ``libnspnp.so`` (the C ABI in include/nspnp.h).
+
+Argument marshalling only: every step of the solver runs in the HIP
+library.  PyTorch provides the device memory (one workspace tensor per
+solver) and the stream.  There is no CPU fallback: constructing a solver
+without the built library or without a GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, fields, asdict
+from pathlib import Path
+from typing import Dict, Tuple
+
+import torch
+
+LIB_PATH = Path(__file__).resolve().parent / "libnspnp.so"
+
+FIELDS = {"u": 0, "v": 1, "w": 2, "cp": 3, "cm": 4, "phi": 5, "p": 6}
+PREC = {"fp64": 0, "mixed": 1}
+
+NSPNP_OK = 0
+ERRORS = {-1: "invalid argument", -2: "unsupported size", -3: "HIP error", -4: "non-finite state",
+          -5: "workspace"}
+
+
+class NsPnpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"nspnp error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class _CConfig(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("lx", ctypes.c_double), ("lz", ctypes.c_double), ("stretch", ctypes.c_double),
+        ("re", ctypes.c_double), ("sc", ctypes.c_double), ("beta", ctypes.c_double),
+        ("debye", ctypes.c_double), ("vhat", ctypes.c_double),
+        ("u_top", ctypes.c_double), ("u_bot", ctypes.c_double), ("force_sign", ctypes.c_double),
+        ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("u_noise", ctypes.c_double), ("c_noise", ctypes.c_double),
+    ]
+
+
+@dataclass
+class Config:
+    """Mirror of ``nspnp_config``; see include/nspnp.h for every field."""
+    nx: int = 32
+    ny: int = 33
+    nz: int = 32
+    precision: str = "fp64"
+    lx: float = 6.283185307179586
+    lz: float = 3.141592653589793
+    stretch: float = 1.5
+    re: float = 400.0
+    sc: float = 1.0
+    beta: float = 0.5
+    debye: float = 0.1
+    vhat: float = 5.0
+    u_top: float = 1.0
+    u_bot: float = -1.0
+    force_sign: float = -1.0
+    dt: float = 1e-3
+    cfl: float = 0.5
+    seed: int = 0
+    u_noise: float = 0.01
+    c_noise: float = 1e-3
+
+    def to_c(self) -> _CConfig:
+        c = _CConfig()
+        for f in fields(self):
+            val = getattr(self, f.name)
+            if f.name == "precision":
+                val = PREC[val]
+            setattr(c, f.name, val)
+        return c
+
+    def oracle_kwargs(self) -> dict:
+        """The same physical configuration as keyword arguments of the oracle."""
+        d = asdict(self)
+        for k in ("precision", "seed", "u_noise", "c_noise"):
+            d.pop(k)
+        return d
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.nz * (self.ny - 1)
+
+    @property
+    def points(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+
+def load_library() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not LIB_PATH.exists():
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(str(LIB_PATH))
+    sig = {
+        "nspnp_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(_CConfig)]),
+        "nspnp_init_state": (_I, [ctypes.POINTER(_CConfig), _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+        "nspnp_step": (_I, [_P, ctypes.c_int32]),
+        "nspnp_poisson_solve": (_I, [_P, ctypes.c_int32, _P, _P]),
+        "nspnp_wall_shear_stress": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+        "nspnp_ion_flux": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                ctypes.POINTER(_D)]),
+        "nspnp_get_field": (_I, [_P, ctypes.c_int32, _P]),
+        "nspnp_set_field": (_I, [_P, ctypes.c_int32, _P]),
+        "nspnp_refresh_potential": (_I, [_P]),
+        "nspnp_explicit_terms": (_I, [_P, ctypes.POINTER(_P)]),
+        "nspnp_diagnostics": (_I, [_P, ctypes.POINTER(_D)]),
+        "nspnp_get_clock": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_int64)]),
+        "nspnp_set_clock": (_I, [_P, _D, _D, ctypes.c_int32, ctypes.c_int64]),
+        "nspnp_sync": (_I, [_P]),
+        "nspnp_destroy": (None, [_P]),
+        "nspnp_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != NSPNP_OK:
+        raise NsPnpError(rc, load_library().nspnp_last_error().decode())
+
+
+def workspace_bytes(cfg: Config) -> int:
+    c = cfg.to_c()
+    return int(load_library().nspnp_workspace_bytes(ctypes.byref(c)))
+
+
+class Solver:
+    """One NS-PNP state on one GPU.  Method names follow the C ABI."""
+
+    def __init__(self, cfg: Config, device: str = "cuda:0", stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("nspnp needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.lib = load_library()
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._c = cfg.to_c()
+        nbytes = self.lib.nspnp_workspace_bytes(ctypes.byref(self._c))
+        if nbytes == 0:
+            raise NsPnpError(-1, self.lib.nspnp_last_error().decode())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.M = cfg.ny - 1
+        self.shape = (self.M, cfg.nz, cfg.nx)
+        h = _P()
+        with torch.cuda.device(self.device):
+            _check(self.lib.nspnp_init_state(ctypes.byref(self._c), ctypes.c_void_p(self.workspace.data_ptr()),
+                                             nbytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            try:
+                self.lib.nspnp_sync(self._h)
+            finally:
+                self.lib.nspnp_destroy(self._h)
+                self._h = None
+
+    def _f64(self, t: torch.Tensor) -> torch.Tensor:
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device or t.numel() != self.M * self.cfg.nz * self.cfg.nx:
+            raise ValueError("expected a contiguous float64 tensor of nx*nz*(ny-1) values on the solver's device")
+        return t
+
+    # ---- the C ABI -------------------------------------------------------
+    def step(self, n_substeps: int = 1):
+        _check(self.lib.nspnp_step(self._h, int(n_substeps)))
+
+    def poisson_solve(self, kind: int, rhs: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._f64(rhs)
+        out = torch.empty_like(rhs) if out is None else self._f64(out)
+        _check(self.lib.nspnp_poisson_solve(self._h, int(kind), ctypes.c_void_p(rhs.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def wall_shear_stress(self) -> Tuple[float, float]:
+        tb, tt = _D(), _D()
+        _check(self.lib.nspnp_wall_shear_stress(self._h, ctypes.byref(tb), ctypes.byref(tt)))
+        return tb.value, tt.value
+
+    def ion_flux(self):
+        n = self.cfg.ny
+        jp, jm = (_D * n)(), (_D * n)()
+        mp, mm = _D(), _D()
+        _check(self.lib.nspnp_ion_flux(self._h, jp, jm, ctypes.byref(mp), ctypes.byref(mm)))
+        return list(jp), list(jm), mp.value, mm.value
+
+    def get_field(self, name: str) -> torch.Tensor:
+        out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        _check(self.lib.nspnp_get_field(self._h, FIELDS[name], ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def set_field(self, name: str, value: torch.Tensor):
+        value = self._f64(value.contiguous())
+        _check(self.lib.nspnp_set_field(self._h, FIELDS[name], ctypes.c_void_p(value.data_ptr())))
+        self.sync()
+
+    def refresh_potential(self):
+        _check(self.lib.nspnp_refresh_potential(self._h))
+
+    def explicit_terms(self) -> Dict[str, torch.Tensor]:
+        outs = [torch.empty(self.shape, dtype=torch.float64, device=self.device) for _ in range(5)]
+        arr = (_P * 5)(*[o.data_ptr() for o in outs])
+        _check(self.lib.nspnp_explicit_terms(self._h, arr))
+        return dict(zip(("u", "v", "w", "cp", "cm"), outs))
+
+    def diagnostics(self) -> Dict[str, float]:
+        out = (_D * 5)()
+        _check(self.lib.nspnp_diagnostics(self._h, out))
+        return dict(zip(("ke", "max_div", "min_cp", "min_cm", "max_csum"), list(out)))
+
+    def clock(self):
+        t, dt, st, ns = _D(), _D(), ctypes.c_int32(), ctypes.c_int64()
+        _check(self.lib.nspnp_get_clock(self._h, ctypes.byref(t), ctypes.byref(dt), ctypes.byref(st),
+                                        ctypes.byref(ns)))
+        return t.value, dt.value, st.value, ns.value
+
+    def set_clock(self, t: float, dt: float, stage: int, substeps: int):
+        _check(self.lib.nspnp_set_clock(self._h, t, dt, int(stage), int(substeps)))
+
+    def sync(self):
+        _check(self.lib.nspnp_sync(self._h))

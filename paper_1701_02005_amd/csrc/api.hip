@@ -1,0 +1,408 @@
+// api.hip -- the C ABI declared in include/nspnp.h: configuration checks,
+// workspace layout, grid and operator tables, initial state, the substep
+// sequence and the host side of the diagnostics.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+
+using namespace nspnp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                                  \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) return fail(NSPNP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Low-storage three-stage Runge-Kutta (Sec. II): gamma, zeta, alpha = gamma + zeta
+constexpr double kGam[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+constexpr double kZet[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+
+bool smooth_size(int n) {
+    if (n < 1) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+FftPlan make_plan(int n) {
+    FftPlan p{};
+    p.n = n;
+    int m = n, s = 0;
+    while (m % 4 == 0) { p.radix[s++] = 4; m /= 4; }
+    while (m % 2 == 0) { p.radix[s++] = 2; m /= 2; }
+    while (m % 3 == 0) { p.radix[s++] = 3; m /= 3; }
+    p.nstages = s;
+    return p;
+}
+
+int check_config(const nspnp_config *c) {
+    if (!c) return fail(NSPNP_ERR_INVALID, "config is NULL");
+    if (c->precision != NSPNP_PREC_FP64 && c->precision != NSPNP_PREC_MIXED)
+        return fail(NSPNP_ERR_INVALID, "precision must be 0 (FP64) or 1 (mixed)");
+    for (int n : {c->nx, c->nz}) {
+        if (n < 4 || n > 1024 || n % 2 != 0 || !smooth_size(n))
+            return fail(NSPNP_ERR_SIZE, "nx and nz must be even, of the form 2^a 3^b, and within 4..1024");
+    }
+    if (c->ny < 5) return fail(NSPNP_ERR_SIZE, "ny (wall-normal nodes) must be at least 5");
+    const double pos[] = {c->lx, c->lz, c->re, c->sc, c->debye};
+    for (double v : pos)
+        if (!(v > 0.0) || !std::isfinite(v)) return fail(NSPNP_ERR_INVALID, "lx, lz, re, sc, debye must be > 0");
+    if (!(c->stretch >= 0.0) || !std::isfinite(c->beta) || !std::isfinite(c->vhat) || !std::isfinite(c->u_top) ||
+        !std::isfinite(c->u_bot) || !std::isfinite(c->force_sign) || !std::isfinite(c->dt))
+        return fail(NSPNP_ERR_INVALID, "non-finite configuration value");
+    if (c->dt <= 0.0 && !(c->cfl > 0.0)) return fail(NSPNP_ERR_INVALID, "adaptive dt needs cfl > 0");
+    return NSPNP_OK;
+}
+
+struct Layout {
+    size_t off_f[7], off_h[5], off_r[5], off_rhs, off_psi, off_spec, off_cpr, off_clock, off_red, off_tab;
+    size_t ntab, nred, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout make_layout(const nspnp_config *c) {
+    Layout L{};
+    const int64_t M = c->ny - 1, nxh = c->nx / 2 + 1;
+    const int64_t n = (int64_t)c->nx * c->nz * M;
+    const size_t ws = c->precision == NSPNP_PREC_FP64 ? 8 : 4;
+    size_t o = 0;
+    for (int q = 0; q < 7; ++q) { L.off_f[q] = o; o = align256(o + n * ws); }
+    for (int q = 0; q < 5; ++q) { L.off_h[q] = o; o = align256(o + n * ws); }
+    for (int q = 0; q < 5; ++q) { L.off_r[q] = o; o = align256(o + n * 8); }
+    L.off_rhs = o; o = align256(o + n * 8);
+    L.off_psi = o; o = align256(o + n * 8);
+    const int64_t nspec = nxh * c->nz * M;
+    L.off_spec = o; o = align256(o + nspec * 16);
+    L.off_cpr = o; o = align256(o + nspec * 8);
+    L.off_clock = o; o = align256(o + 4 * 8);
+    L.nred = std::max<int64_t>(2 * 1024, M * 10);
+    L.off_red = o; o = align256(o + L.nred * 8);
+    L.ntab = 7 * M + 1 + nxh + c->nz + 2 * c->nx + 2 * c->nz;
+    L.off_tab = o; o = align256(o + L.ntab * 8);
+    L.total = o;
+    return L;
+}
+
+// Host tables: tanh-stretched y nodes, finite-volume L_y coefficients,
+// modified wavenumbers of the three-point x/z Laplacians, FFT twiddles.
+void build_tables(nspnp_state *s, double *dev_tab) {
+    const nspnp_config &c = s->cfg;
+    const int M = s->d.M, nx = c.nx, nz = c.nz, nxh = s->d.nxh;
+    std::vector<double> yn(M + 1);
+    for (int j = 0; j <= M; ++j) {
+        const double xi = -1.0 + 2.0 * j / (double)M;
+        yn[j] = (c.stretch > 0.0) ? std::tanh(c.stretch * xi) / std::tanh(c.stretch) : xi;
+    }
+    yn[0] = -1.0;
+    yn[M] = 1.0;
+    std::vector<double> &t = s->host_tables;
+    t.assign(7 * M + 1 + nxh + nz + 2 * nx + 2 * nz, 0.0);
+    double *yc = t.data(), *dn = yc + M, *dc = dn + M, *lyc_lo = dc + M + 1, *lyc_up = lyc_lo + M;
+    double *lyn_lo = lyc_up + M, *lyn_up = lyn_lo + M, *kx2 = lyn_up + M, *kz2 = kx2 + nxh;
+    double *twx = kz2 + nz, *twz = twx + 2 * nx;
+    for (int j = 0; j < M; ++j) {
+        yc[j] = 0.5 * (yn[j] + yn[j + 1]);
+        dn[j] = yn[j + 1] - yn[j];
+    }
+    dc[0] = yc[0] - yn[0];
+    for (int j = 1; j < M; ++j) dc[j] = yc[j] - yc[j - 1];
+    dc[M] = yn[M] - yc[M - 1];
+    for (int j = 0; j < M; ++j) {
+        lyc_lo[j] = 1.0 / (dn[j] * dc[j]);
+        lyc_up[j] = 1.0 / (dn[j] * dc[j + 1]);
+        lyn_lo[j] = (j > 0) ? 1.0 / (dc[j] * dn[j - 1]) : 0.0;
+        lyn_up[j] = (j > 0) ? 1.0 / (dc[j] * dn[j]) : 0.0;
+    }
+    const double dx = s->d.dx, dz = s->d.dz;
+    const double twopi = 6.283185307179586476925286766559;
+    for (int m = 0; m < nxh; ++m) kx2[m] = (2.0 - 2.0 * std::cos(twopi * m / nx)) / (dx * dx);
+    for (int m = 0; m < nz; ++m) kz2[m] = (2.0 - 2.0 * std::cos(twopi * m / nz)) / (dz * dz);
+    for (int m = 0; m < nx; ++m) {
+        twx[2 * m] = std::cos(twopi * m / nx);
+        twx[2 * m + 1] = -std::sin(twopi * m / nx);
+    }
+    for (int m = 0; m < nz; ++m) {
+        twz[2 * m] = std::cos(twopi * m / nz);
+        twz[2 * m + 1] = -std::sin(twopi * m / nz);
+    }
+    s->tb.yc = dev_tab;
+    s->tb.dn = dev_tab + M;
+    s->tb.dc = dev_tab + 2 * M;
+    s->tb.lyc_lo = dev_tab + 3 * M + 1;
+    s->tb.lyc_up = dev_tab + 4 * M + 1;
+    s->tb.lyn_lo = dev_tab + 5 * M + 1;
+    s->tb.lyn_up = dev_tab + 6 * M + 1;
+    s->tb.kx2 = dev_tab + 7 * M + 1;
+    s->tb.kz2 = s->tb.kx2 + nxh;
+    s->tb.twx = (const double2 *)(s->tb.kz2 + nz);
+    s->tb.twz = (const double2 *)((const double *)s->tb.twx + 2 * nx);
+}
+
+int plane_reduce(nspnp_state *s, std::vector<double> &host) {
+    HIP_TRY(launch_plane_sums(s, 0, s->red));
+    host.resize((size_t)s->d.M * 10);
+    HIP_TRY(hipMemcpyAsync(host.data(), s->red, host.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return NSPNP_OK;
+}
+
+int solve_potential(nspnp_state *s) {
+    HIP_TRY(launch_charge(s, s->rhs));
+    double *out = s->fp64 ? (double *)s->f[5] : s->psi;
+    HIP_TRY(launch_poisson(s, 1, s->rhs, out));
+    if (!s->fp64) HIP_TRY(launch_store_phi(s, s->psi));
+    return NSPNP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nspnp_last_error(void) { return g_last_error.c_str(); }
+
+size_t nspnp_workspace_bytes(const nspnp_config *cfg) {
+    if (check_config(cfg) != NSPNP_OK) return 0;
+    return make_layout(cfg).total;
+}
+
+int nspnp_init_state(const nspnp_config *cfg, void *dev_workspace, size_t bytes, void *hip_stream,
+                     nspnp_state **out) {
+    if (!out) return fail(NSPNP_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    const Layout L = make_layout(cfg);
+    if (!dev_workspace || bytes < L.total)
+        return fail(NSPNP_ERR_WORKSPACE, "workspace missing or smaller than nspnp_workspace_bytes()");
+    if (((uintptr_t)dev_workspace & 255) != 0) return fail(NSPNP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    nspnp_state *s = new nspnp_state();
+    s->cfg = *cfg;
+    s->stream = (hipStream_t)hip_stream;
+    s->fp64 = cfg->precision == NSPNP_PREC_FP64;
+    s->wsize = s->fp64 ? 8 : 4;
+    Dims &d = s->d;
+    d.nx = cfg->nx;
+    d.nz = cfg->nz;
+    d.M = cfg->ny - 1;
+    d.nxh = cfg->nx / 2 + 1;
+    d.plane = (int64_t)cfg->nx * cfg->nz;
+    d.n = d.plane * d.M;
+    d.dx = cfg->lx / cfg->nx;
+    d.dz = cfg->lz / cfg->nz;
+    Phys &ph = s->ph;
+    ph.re = cfg->re;
+    ph.ire = 1.0 / cfg->re;
+    ph.kd = 1.0 / (cfg->re * cfg->sc);
+    ph.kf = cfg->force_sign * cfg->beta / (2.0 * cfg->sc * cfg->re * cfg->re * cfg->debye * cfg->debye);
+    ph.e0 = 0.5 * cfg->vhat;
+    ph.ch = -1.0 / (2.0 * cfg->debye * cfg->debye);
+    ph.u_top = cfg->u_top;
+    ph.u_bot = cfg->u_bot;
+    ph.debye = cfg->debye;
+    ph.cfl = cfg->cfl;
+    s->planx = make_plan(cfg->nx);
+    s->planz = make_plan(cfg->nz);
+    char *base = (char *)dev_workspace;
+    for (int q = 0; q < 7; ++q) s->f[q] = base + L.off_f[q];
+    for (int q = 0; q < 5; ++q) s->h[q] = base + L.off_h[q];
+    for (int q = 0; q < 5; ++q) s->r[q] = (double *)(base + L.off_r[q]);
+    s->rhs = (double *)(base + L.off_rhs);
+    s->psi = (double *)(base + L.off_psi);
+    s->spec = (double2 *)(base + L.off_spec);
+    s->cpr = (double *)(base + L.off_cpr);
+    s->clock = (double *)(base + L.off_clock);
+    s->red = (double *)(base + L.off_red);
+    s->nred = L.nred;
+    build_tables(s, (double *)(base + L.off_tab));
+    s->substeps = 0;
+
+    auto bail = [&](int code) {
+        delete s;
+        return code;
+    };
+    hipError_t e = hipMemcpyAsync(base + L.off_tab, s->host_tables.data(), s->host_tables.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) return bail(fail(NSPNP_ERR_HIP, std::string("table upload: ") + hipGetErrorString(e)));
+    const double clock0[4] = {0.0, cfg->dt > 0.0 ? cfg->dt : 0.0, 0.0, 0.0};
+    e = hipMemcpyAsync(s->clock, clock0, sizeof(clock0), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = launch_init_fields(s);
+    if (e != hipSuccess) return bail(fail(NSPNP_ERR_HIP, std::string("init: ") + hipGetErrorString(e)));
+    // remove the volume mean of the concentration noise
+    std::vector<double> ps;
+    if ((rc = plane_reduce(s, ps))) return bail(rc);
+    double sp = 0.0, sm = 0.0, vol = 0.0;
+    for (int j = 0; j < d.M; ++j) {
+        const double dn = s->host_tables[d.M + j];
+        sp += ps[j * 10 + 1] * dn;
+        sm += ps[j * 10 + 2] * dn;
+        vol += dn * (double)d.plane;
+    }
+    e = launch_shift_conc(s, sp / vol, sm / vol);
+    // project the initial velocity (no pressure), then the initial potential
+    if (e == hipSuccess) e = launch_divergence(s, 1.0, Stage{0, 0, 0, 0}, s->rhs);
+    if (e == hipSuccess) e = launch_poisson(s, 0, s->rhs, s->psi);
+    if (e == hipSuccess) e = launch_correct(s, Stage{0, 0, 0, 0}, false, 1.0);
+    if (e != hipSuccess) return bail(fail(NSPNP_ERR_HIP, std::string("initial projection: ") + hipGetErrorString(e)));
+    if ((rc = solve_potential(s))) return bail(rc);
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return bail(fail(NSPNP_ERR_HIP, std::string("init sync: ") + hipGetErrorString(e)));
+    *out = s;
+    return NSPNP_OK;
+}
+
+int nspnp_step(nspnp_state *s, int32_t n_substeps) {
+    if (!s || n_substeps < 0) return fail(NSPNP_ERR_INVALID, "bad state or substep count");
+    const bool adaptive = s->cfg.dt <= 0.0;
+    for (int32_t it = 0; it < n_substeps; ++it) {
+        const int k = (int)(s->substeps % 3);
+        const Stage st{kGam[k], kZet[k], kGam[k] + kZet[k], k};
+        if (k == 0 && adaptive) HIP_TRY(launch_dt(s));
+        HIP_TRY(launch_explicit(s, st, true));
+        HIP_TRY(launch_cn_solve(s, st));
+        HIP_TRY(launch_divergence(s, 0.0, st, s->rhs));
+        HIP_TRY(launch_poisson(s, 0, s->rhs, s->psi));
+        HIP_TRY(launch_correct(s, st, true, 0.0));
+        int rc = solve_potential(s);
+        if (rc) return rc;
+        HIP_TRY(launch_advance_clock(s, st.alp));
+        s->substeps++;
+    }
+    return NSPNP_OK;
+}
+
+int nspnp_poisson_solve(nspnp_state *s, int32_t kind, const double *dev_rhs, double *dev_out) {
+    if (!s || !dev_rhs || !dev_out || (kind != 0 && kind != 1)) return fail(NSPNP_ERR_INVALID, "bad poisson_solve arguments");
+    HIP_TRY(launch_poisson(s, kind, dev_rhs, dev_out));
+    return NSPNP_OK;
+}
+
+int nspnp_wall_shear_stress(nspnp_state *s, double *tau_bottom, double *tau_top) {
+    if (!s || !tau_bottom || !tau_top) return fail(NSPNP_ERR_INVALID, "bad wall_shear_stress arguments");
+    std::vector<double> ps;
+    int rc = plane_reduce(s, ps);
+    if (rc) return rc;
+    const int M = s->d.M;
+    const double pl = (double)s->d.plane;
+    const double *dc = s->host_tables.data() + 2 * M;
+    *tau_bottom = s->ph.ire * (ps[0] / pl - s->cfg.u_bot) / dc[0];
+    *tau_top = s->ph.ire * (s->cfg.u_top - ps[(M - 1) * 10] / pl) / dc[M];
+    if (!std::isfinite(*tau_bottom) || !std::isfinite(*tau_top)) return fail(NSPNP_ERR_NONFINITE, "non-finite wall stress");
+    return NSPNP_OK;
+}
+
+int nspnp_ion_flux(nspnp_state *s, double *jp, double *jm, double *mass_p, double *mass_m) {
+    if (!s || !jp || !jm || !mass_p || !mass_m) return fail(NSPNP_ERR_INVALID, "bad ion_flux arguments");
+    std::vector<double> ps;
+    int rc = plane_reduce(s, ps);
+    if (rc) return rc;
+    const int M = s->d.M;
+    const double pl = (double)s->d.plane;
+    const double *dn = s->host_tables.data() + M;
+    jp[0] = jm[0] = jp[M] = jm[M] = 0.0;
+    for (int j = 1; j < M; ++j) {
+        jp[j] = ps[j * 10 + 3] / pl;
+        jm[j] = ps[j * 10 + 4] / pl;
+    }
+    double a = 0.0, b = 0.0;
+    for (int j = 0; j < M; ++j) {
+        a += ps[j * 10 + 1] * s->d.dx * dn[j] * s->d.dz;
+        b += ps[j * 10 + 2] * s->d.dx * dn[j] * s->d.dz;
+    }
+    *mass_p = a;
+    *mass_m = b;
+    if (!std::isfinite(a) || !std::isfinite(b)) return fail(NSPNP_ERR_NONFINITE, "non-finite ion content");
+    return NSPNP_OK;
+}
+
+int nspnp_get_field(nspnp_state *s, int32_t field, double *dev_out) {
+    if (!s || !dev_out || field < 0 || field > 6) return fail(NSPNP_ERR_INVALID, "bad get_field arguments");
+    HIP_TRY(launch_convert(s, field, nullptr, dev_out, false));
+    return NSPNP_OK;
+}
+
+int nspnp_set_field(nspnp_state *s, int32_t field, const double *dev_in) {
+    if (!s || !dev_in || field < 0 || field > 6) return fail(NSPNP_ERR_INVALID, "bad set_field arguments");
+    HIP_TRY(launch_convert(s, field, dev_in, nullptr, true));
+    return NSPNP_OK;
+}
+
+int nspnp_refresh_potential(nspnp_state *s) {
+    if (!s) return fail(NSPNP_ERR_INVALID, "state is NULL");
+    return solve_potential(s);
+}
+
+int nspnp_explicit_terms(nspnp_state *s, double *const dev_out[5]) {
+    if (!s || !dev_out) return fail(NSPNP_ERR_INVALID, "bad explicit_terms arguments");
+    for (int q = 0; q < 5; ++q)
+        if (!dev_out[q]) return fail(NSPNP_ERR_INVALID, "explicit_terms output is NULL");
+    HIP_TRY(launch_explicit_debug(s, dev_out));
+    return NSPNP_OK;
+}
+
+int nspnp_diagnostics(nspnp_state *s, double out[5]) {
+    if (!s || !out) return fail(NSPNP_ERR_INVALID, "bad diagnostics arguments");
+    std::vector<double> ps;
+    int rc = plane_reduce(s, ps);
+    if (rc) return rc;
+    double ke = 0.0, dv = 0.0, mp = 1e300, mm = 1e300, cs = 0.0;
+    for (int j = 0; j < s->d.M; ++j) {
+        ke += ps[j * 10 + 5];
+        dv = std::fmax(dv, ps[j * 10 + 6]);
+        mp = std::fmin(mp, ps[j * 10 + 7]);
+        mm = std::fmin(mm, ps[j * 10 + 8]);
+        cs = std::fmax(cs, ps[j * 10 + 9]);
+    }
+    out[0] = ke;
+    out[1] = dv;
+    out[2] = mp;
+    out[3] = mm;
+    out[4] = cs;
+    for (int q = 0; q < 5; ++q)
+        if (!std::isfinite(out[q])) return fail(NSPNP_ERR_NONFINITE, "non-finite diagnostics");
+    return NSPNP_OK;
+}
+
+int nspnp_get_clock(nspnp_state *s, double *t, double *dt, int32_t *stage, int64_t *substeps) {
+    if (!s) return fail(NSPNP_ERR_INVALID, "state is NULL");
+    double c[2];
+    HIP_TRY(hipMemcpyAsync(c, s->clock, sizeof(c), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (t) *t = c[0];
+    if (dt) *dt = c[1];
+    if (stage) *stage = (int32_t)(s->substeps % 3);
+    if (substeps) *substeps = s->substeps;
+    return NSPNP_OK;
+}
+
+int nspnp_set_clock(nspnp_state *s, double t, double dt, int32_t stage, int64_t substeps) {
+    if (!s || stage < 0 || stage > 2 || substeps < 0 || substeps % 3 != stage)
+        return fail(NSPNP_ERR_INVALID, "bad set_clock arguments (stage must equal substeps mod 3)");
+    double c[2] = {t, dt};
+    HIP_TRY(hipMemcpyAsync(s->clock, c, sizeof(c), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->substeps = substeps;
+    return NSPNP_OK;
+}
+
+int nspnp_sync(nspnp_state *s) {
+    if (!s) return fail(NSPNP_ERR_INVALID, "state is NULL");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return NSPNP_OK;
+}
+
+void nspnp_destroy(nspnp_state *s) { delete s; }
+
+}  // extern "C"

@@ -1,0 +1,239 @@
+// reduce.hip -- seeded initial state, adaptive time step and the plane
+// reductions behind the diagnostics (wall shear stress and friction of
+// Sec. II, ion fluxes through the y-faces of Fig. 1, ion contents, kinetic
+// energy, divergence).  Every reduction runs in a fixed order (fixed launch
+// shape, fixed LDS tree) so results are bitwise reproducible.
+#include "internal.h"
+
+namespace nspnp {
+namespace {
+
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): output n of the generator
+// seeded with s is mix(s + n * 0x9E3779B97F4A7C15).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t n) {
+    uint64_t z = seed + n * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// uniform on [-1, 1) from stream (field, index)
+__device__ __forceinline__ double noise(uint64_t seed, int field, int64_t idx) {
+    const uint64_t n = ((uint64_t)field << 40) + (uint64_t)idx + 1ull;
+    const double u01 = (double)(splitmix64(seed, n) >> 11) * (1.0 / 9007199254740992.0);
+    return 2.0 * u01 - 1.0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_init(Dims d, Tables tb, double u_top, double u_bot, uint64_t seed,
+                                              double an, double cn, T *u, T *v, T *w, T *cp, T *cm, T *phi, T *p,
+                                              T *h0, T *h1, T *h2, T *h3, T *h4) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= d.n) return;
+    const int j = (int)(q / d.plane);
+    const double ulin = 0.5 * (u_top + u_bot) + 0.5 * (u_top - u_bot) * tb.yc[j];
+    u[q] = (T)(ulin + an * noise(seed, 0, q));
+    v[q] = (T)((j > 0) ? an * noise(seed, 1, q) : 0.0);
+    w[q] = (T)(an * noise(seed, 2, q));
+    cp[q] = (T)(cn * noise(seed, 3, q));
+    cm[q] = (T)(cn * noise(seed, 4, q));
+    phi[q] = (T)0;
+    p[q] = (T)0;
+    h0[q] = h1[q] = h2[q] = h3[q] = h4[q] = (T)0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_shift_conc(Dims d, double mp, double mm, T *cp, T *cm) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= d.n) return;
+    cp[q] = (T)(1.0 + ((double)cp[q] - mp));
+    cm[q] = (T)(1.0 + ((double)cm[q] - mm));
+}
+
+constexpr int kRedThreads = 256;
+constexpr int kDtBlocks = 1024;
+
+// ---- adaptive time step: max of the advective rate and of c+ + c- ----
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) k_dt_partial(Dims d, Tables tb, const T *u, const T *v,
+                                                            const T *w, const T *cp, const T *cm,
+                                                            double *part) {
+    __shared__ double s_r[kRedThreads], s_c[kRedThreads];
+    double rate = 0.0, cmax = 0.0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < d.n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(q % d.nx);
+        const int64_t r = q / d.nx;
+        const int k = (int)(r % d.nz);
+        const int j = (int)(r / d.nz);
+        const int64_t xp = q - i + ((i + 1 == d.nx) ? 0 : i + 1);
+        const int64_t zp = q + (int64_t)(((k + 1 == d.nz) ? 0 : k + 1) - k) * d.nx;
+        const double uc = 0.5 * ((double)u[q] + (double)u[xp]);
+        const double vt = (j + 1 < d.M) ? (double)v[q + d.plane] : 0.0;
+        const double vc = 0.5 * ((double)v[q] + vt);
+        const double wc = 0.5 * ((double)w[q] + (double)w[zp]);
+        const double rr = fabs(uc) / d.dx + fabs(vc) / tb.dn[j] + fabs(wc) / d.dz;
+        rate = fmax(rate, rr);
+        cmax = fmax(cmax, (double)cp[q] + (double)cm[q]);
+    }
+    s_r[threadIdx.x] = rate;
+    s_c[threadIdx.x] = cmax;
+    __syncthreads();
+    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            s_r[threadIdx.x] = fmax(s_r[threadIdx.x], s_r[threadIdx.x + o]);
+            s_c[threadIdx.x] = fmax(s_c[threadIdx.x], s_c[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s_r[0];
+        part[2 * blockIdx.x + 1] = s_c[0];
+    }
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_dt_final(int nparts, const double *part, Phys ph, Dims d,
+                                                          double *clock) {
+    __shared__ double s_r[kRedThreads], s_c[kRedThreads];
+    double rate = 0.0, cmax = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+        rate = fmax(rate, part[2 * b]);
+        cmax = fmax(cmax, part[2 * b + 1]);
+    }
+    s_r[threadIdx.x] = rate;
+    s_c[threadIdx.x] = cmax;
+    __syncthreads();
+    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            s_r[threadIdx.x] = fmax(s_r[threadIdx.x], s_r[threadIdx.x + o]);
+            s_c[threadIdx.x] = fmax(s_c[threadIdx.x], s_c[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double re = ph.re, rs = 1.0 / ph.kd;
+        double dt = 1e30;
+        if (s_r[0] > 0.0) dt = ph.cfl / s_r[0];
+        if (s_c[0] > 0.0) dt = fmin(dt, 2.0 * ph.debye * ph.debye * rs / s_c[0]);
+        const double nu_min = re < rs ? re : rs;
+        dt = fmin(dt, nu_min / (4.0 / (d.dx * d.dx) + 4.0 / (d.dz * d.dz)));
+        clock[1] = dt;
+    }
+}
+
+// ---- per-plane sums for diagnostics ----
+// out[j * kPlaneQ + q]:
+//   0 sum u, 1 sum c+, 2 sum c-, 3 flux+ at node j, 4 flux- at node j,
+//   5 kinetic energy of row j, 6 max |div u|, 7 min c+, 8 min c-, 9 max (c+ + c-)
+constexpr int kPlaneQ = 10;
+
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) k_plane(Dims d, Phys ph, Tables tb, const T *u, const T *v,
+                                                       const T *w, const T *cp, const T *cm, const T *phi,
+                                                       double *out) {
+    __shared__ double s[kPlaneQ][kRedThreads];
+    const int j = blockIdx.x;
+    const int64_t pl = d.plane;
+    const int64_t base = (int64_t)j * pl;
+    double acc[kPlaneQ] = {0, 0, 0, 0, 0, 0, 0, 1e300, 1e300, 0};
+    const double dn = tb.dn[j];
+    const double dcj = tb.dc[j];
+    for (int64_t e = threadIdx.x; e < pl; e += blockDim.x) {
+        const int64_t q = base + e;
+        const int i = (int)(e % d.nx), k = (int)(e / d.nx);
+        const int64_t xp = q - i + ((i + 1 == d.nx) ? 0 : i + 1);
+        const int64_t zp = q + (int64_t)(((k + 1 == d.nz) ? 0 : k + 1) - k) * d.nx;
+        const double uu = (double)u[q], ww = (double)w[q], vv = (double)v[q];
+        const double c1 = (double)cp[q], c2 = (double)cm[q];
+        acc[0] += uu;
+        acc[1] += c1;
+        acc[2] += c2;
+        if (j > 0) {
+            const int64_t qd = q - pl;
+            const double e_y = ph.e0 + ((double)phi[q] - (double)phi[qd]) / dcj;
+            const double f1 = 0.5 * (c1 + (double)cp[qd]);
+            const double f2 = 0.5 * (c2 + (double)cm[qd]);
+            acc[3] += vv * f1 - ph.kd * ((c1 - (double)cp[qd]) / dcj + f1 * e_y);
+            acc[4] += vv * f2 - ph.kd * ((c2 - (double)cm[qd]) / dcj - f2 * e_y);
+            acc[5] += 0.5 * vv * vv * d.dx * dcj * d.dz;
+        }
+        acc[5] += 0.5 * (uu * uu + ww * ww) * d.dx * dn * d.dz;
+        const double vt = (j + 1 < d.M) ? (double)v[q + pl] : 0.0;
+        const double vb = (j > 0) ? vv : 0.0;
+        const double div = ((double)u[xp] - uu) / d.dx + (vt - vb) / dn + ((double)w[zp] - ww) / d.dz;
+        acc[6] = fmax(acc[6], fabs(div));
+        acc[7] = fmin(acc[7], c1);
+        acc[8] = fmin(acc[8], c2);
+        acc[9] = fmax(acc[9], c1 + c2);
+    }
+#pragma unroll
+    for (int qq = 0; qq < kPlaneQ; ++qq) s[qq][threadIdx.x] = acc[qq];
+    __syncthreads();
+    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            for (int qq = 0; qq < 6; ++qq) s[qq][threadIdx.x] += s[qq][threadIdx.x + o];
+            s[6][threadIdx.x] = fmax(s[6][threadIdx.x], s[6][threadIdx.x + o]);
+            s[7][threadIdx.x] = fmin(s[7][threadIdx.x], s[7][threadIdx.x + o]);
+            s[8][threadIdx.x] = fmin(s[8][threadIdx.x], s[8][threadIdx.x + o]);
+            s[9][threadIdx.x] = fmax(s[9][threadIdx.x], s[9][threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < kPlaneQ) out[(int64_t)j * kPlaneQ + threadIdx.x] = s[threadIdx.x][0];
+}
+
+inline dim3 grid1(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
+
+}  // namespace
+
+hipError_t launch_init_fields(nspnp_state *s) {
+    const nspnp_config &c = s->cfg;
+    if (s->fp64) {
+        double **f = (double **)s->f;
+        double **h = (double **)s->h;
+        k_init<double><<<grid1(s->d.n), 256, 0, s->stream>>>(s->d, s->tb, c.u_top, c.u_bot, c.seed, c.u_noise,
+                                                            c.c_noise, f[0], f[1], f[2], f[3], f[4], f[5], f[6],
+                                                            h[0], h[1], h[2], h[3], h[4]);
+    } else {
+        float **f = (float **)s->f;
+        float **h = (float **)s->h;
+        k_init<float><<<grid1(s->d.n), 256, 0, s->stream>>>(s->d, s->tb, c.u_top, c.u_bot, c.seed, c.u_noise,
+                                                           c.c_noise, f[0], f[1], f[2], f[3], f[4], f[5], f[6],
+                                                           h[0], h[1], h[2], h[3], h[4]);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_shift_conc(nspnp_state *s, double mp, double mm) {
+    if (s->fp64)
+        k_shift_conc<double><<<grid1(s->d.n), 256, 0, s->stream>>>(s->d, mp, mm, (double *)s->f[3], (double *)s->f[4]);
+    else
+        k_shift_conc<float><<<grid1(s->d.n), 256, 0, s->stream>>>(s->d, mp, mm, (float *)s->f[3], (float *)s->f[4]);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt(nspnp_state *s) {
+    if (s->fp64)
+        k_dt_partial<double><<<kDtBlocks, kRedThreads, 0, s->stream>>>(
+            s->d, s->tb, (const double *)s->f[0], (const double *)s->f[1], (const double *)s->f[2],
+            (const double *)s->f[3], (const double *)s->f[4], s->red);
+    else
+        k_dt_partial<float><<<kDtBlocks, kRedThreads, 0, s->stream>>>(
+            s->d, s->tb, (const float *)s->f[0], (const float *)s->f[1], (const float *)s->f[2],
+            (const float *)s->f[3], (const float *)s->f[4], s->red);
+    k_dt_final<<<1, kRedThreads, 0, s->stream>>>(kDtBlocks, s->red, s->ph, s->d, s->clock);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_sums(nspnp_state *s, int /*what*/, double *dev_out) {
+    if (s->fp64)
+        k_plane<double><<<s->d.M, kRedThreads, 0, s->stream>>>(
+            s->d, s->ph, s->tb, (const double *)s->f[0], (const double *)s->f[1], (const double *)s->f[2],
+            (const double *)s->f[3], (const double *)s->f[4], (const double *)s->f[5], dev_out);
+    else
+        k_plane<float><<<s->d.M, kRedThreads, 0, s->stream>>>(
+            s->d, s->ph, s->tb, (const float *)s->f[0], (const float *)s->f[1], (const float *)s->f[2],
+            (const float *)s->f[3], (const float *)s->f[4], (const float *)s->f[5], dev_out);
+    return hipGetLastError();
+}
+
+}  // namespace nspnp

@@ -1,0 +1,155 @@
+"""GPU (HIP, gfx950) path against the FP64 CPU oracle on the same seeded
+inputs, through the C ABI.  Parity measure per field: max|gpu - oracle| /
+max|oracle|; the FP64 bar is 1e-10 after the full run."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+from inputs import parity, random_field
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("u", "v", "w", "cp", "cm", "phi", "p")
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1701_02005_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle as mod
+    mod._load()
+    return mod
+
+
+def make_pair(P, O, cfg):
+    note(f"case: nx={cfg.nx} ny={cfg.ny} nz={cfg.nz} prec={cfg.precision} dt={cfg.dt} seed={cfg.seed}")
+    g = P.Solver(cfg)
+    o = O.Oracle(**cfg.oracle_kwargs())
+    o.init(cfg.seed, cfg.u_noise, cfg.c_noise)
+    return g, o
+
+
+def gpu_fields(g):
+    g.sync()
+    return {k: g.get_field(k).cpu().numpy() for k in FIELDS}
+
+
+def worst(g, o):
+    gf = gpu_fields(g)
+    return {k: parity(gf[k], o.field(k)) for k in FIELDS}
+
+
+SMALL = dict(nx=32, ny=33, nz=32)
+RAGGED = dict(nx=48, ny=27, nz=36)       # 2^a 3^b sizes that leave partial tiles everywhere
+TINY = dict(nx=6, ny=7, nz=4)
+
+
+def cfg_of(P, **kw):
+    return dataclasses.replace(P.configs.couette_small(), **kw)
+
+
+@pytest.mark.parametrize("dims", [SMALL, RAGGED, TINY], ids=["small", "ragged", "tiny"])
+def test_initial_state_matches_oracle(P, O, dims):
+    g, o = make_pair(P, O, cfg_of(P, **dims, seed=3))
+    err = worst(g, o)
+    assert max(err.values()) < 1e-12, err
+
+
+@pytest.mark.parametrize("dims", [SMALL, RAGGED], ids=["small", "ragged"])
+def test_explicit_terms_match_oracle(P, O, dims):
+    g, o = make_pair(P, O, cfg_of(P, **dims, seed=4, u_noise=0.2, c_noise=0.05))
+    h = {k: v.cpu().numpy() for k, v in g.explicit_terms().items()}
+    ho = o.explicit_terms()
+    err = {k: parity(h[k], ho[k]) for k in h}
+    assert max(err.values()) < 1e-12, err
+
+
+@pytest.mark.parametrize("dims", [SMALL, RAGGED, TINY], ids=["small", "ragged", "tiny"])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_poisson_solve_matches_oracle(P, O, dims, kind):
+    import torch
+    g, o = make_pair(P, O, cfg_of(P, **dims))
+    rhs = random_field(o.shape, 10 + kind)
+    if kind == 0:
+        vol = o.dn[:, None, None] * np.ones(o.shape)
+        rhs -= np.sum(rhs * vol) / np.sum(vol)
+    t = torch.tensor(rhs, dtype=torch.float64, device="cuda")
+    out = g.poisson_solve(kind, t).cpu().numpy()
+    ref = o.poisson(kind, rhs)
+    assert parity(out, ref) < 1e-12
+
+
+def test_small_case_200_substeps_match_oracle(P, O):
+    """32x33x32, Re 400, lam 0.1, vhat 5, dt 1e-3: 200 RK substeps."""
+    g, o = make_pair(P, O, P.configs.couette_small(seed=0))
+    for chunk in range(4):
+        g.step(50)
+        o.run(50)
+        err = worst(g, o)
+        note(f"after {50 * (chunk + 1)} substeps: {max(err.values()):.3e}")
+        assert max(err.values()) < 1e-10, err
+    tb, tt = g.wall_shear_stress()
+    otb, ott = o.wall_shear()
+    assert abs(tb - otb) < 1e-10 * abs(otb) and abs(tt - ott) < 1e-10 * abs(ott)
+    jp, jm, mp, mm = g.ion_flux()
+    ojp, ojm, omp, omm = o.ion_flux()
+    assert jp[0] == 0.0 and jp[-1] == 0.0 and jm[0] == 0.0 and jm[-1] == 0.0
+    scale = max(np.max(np.abs(ojp)), 1e-30)
+    assert np.max(np.abs(np.array(jp) - ojp)) < 1e-10 * scale
+    assert abs(mp - omp) < 1e-12 * omp and abs(mm - omm) < 1e-12 * omm
+    t, dt, stage, ns = g.clock()
+    assert ns == 200 and stage == 200 % 3
+    assert abs(t - o.t) < 1e-14
+    d = g.diagnostics()
+    assert d["max_div"] < 1e-12
+    assert abs(d["ke"] - o.kinetic_energy()) < 1e-12 * o.kinetic_energy()
+
+
+def test_ragged_adaptive_case_matches_oracle(P, O):
+    """48x27x36 with the adaptive time step: 30 substeps."""
+    cfg = cfg_of(P, **RAGGED, dt=0.0, cfl=0.5, re=800.0, vhat=8.0, debye=0.08, seed=5, u_noise=0.05)
+    g, o = make_pair(P, O, cfg)
+    g.step(30)
+    o.run(30)
+    err = worst(g, o)
+    assert max(err.values()) < 1e-10, err
+    t, dt, _, _ = g.clock()
+    assert abs(dt - o.dt) < 1e-13 * o.dt and abs(t - o.t) < 1e-13
+
+
+def test_printed_force_sign_matches_oracle(P, O):
+    cfg = cfg_of(P, nx=16, ny=17, nz=12, force_sign=1.0, re=100.0, debye=0.2, vhat=6.0, u_noise=0.05, seed=9)
+    g, o = make_pair(P, O, cfg)
+    g.step(21)
+    o.run(21)
+    err = worst(g, o)
+    assert max(err.values()) < 1e-10, err
+
+
+def test_mixed_precision_tracks_oracle(P, O):
+    """FP32 state and stencils, FP64 solves: errors at FP32 rounding level."""
+    g, o = make_pair(P, O, P.configs.couette_small(precision="mixed", seed=0))
+    g.step(60)
+    o.run(60)
+    err = worst(g, o)
+    note(f"mixed errors: {err}")
+    for k in ("u", "cp", "cm"):
+        assert err[k] < 1e-5, err
+    tb, tt = g.wall_shear_stress()
+    otb, ott = o.wall_shear()
+    assert abs(tb - otb) < 1e-4 * otb and abs(tt - ott) < 1e-4 * ott

@@ -169,6 +169,16 @@ NSPNP_API int nspnp_diagnostics(nspnp_state *s, double out[5]);
 NSPNP_API int nspnp_get_clock(nspnp_state *s, double *t, double *dt, int32_t *stage, int64_t *substeps);
 NSPNP_API int nspnp_set_clock(nspnp_state *s, double t, double dt, int32_t stage, int64_t substeps);
 
+/* Kernel timing with HIP events recorded on the solver's stream around every
+ * kernel launch (off by default).  enable(1) clears the totals and starts
+ * recording; read() synchronises, folds the recorded events into per-kernel
+ * totals and reports, for each of *count kernel classes, its name (static
+ * strings), the accumulated milliseconds and the number of launches.  names,
+ * total_ms and launches may be NULL or arrays of at least 16 entries. */
+NSPNP_API int nspnp_profile_enable(nspnp_state *s, int32_t on);
+NSPNP_API int nspnp_profile_read(nspnp_state *s, int32_t *count, const char **names, double *total_ms,
+                                 int64_t *launches);
+
 /* Wait for all queued work of this state. */
 NSPNP_API int nspnp_sync(nspnp_state *s);
 

@@ -122,6 +122,9 @@ def load_library() -> ctypes.CDLL:
                                  ctypes.POINTER(ctypes.c_int64)]),
         "nspnp_set_clock": (_I, [_P, _D, _D, ctypes.c_int32, ctypes.c_int64]),
         "nspnp_sync": (_I, [_P]),
+        "nspnp_profile_enable": (_I, [_P, ctypes.c_int32]),
+        "nspnp_profile_read": (_I, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_char_p),
+                                    ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_int64)]),
         "nspnp_destroy": (None, [_P]),
         "nspnp_last_error": (ctypes.c_char_p, []),
     }
@@ -237,3 +240,15 @@ class Solver:
 
     def sync(self):
         _check(self.lib.nspnp_sync(self._h))
+
+    def profile_enable(self, on: bool = True):
+        _check(self.lib.nspnp_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> Dict[str, Tuple[float, int]]:
+        """{kernel class: (total ms, launches)} since profile_enable."""
+        n = ctypes.c_int32()
+        names = (ctypes.c_char_p * 16)()
+        ms = (_D * 16)()
+        cnt = (ctypes.c_int64 * 16)()
+        _check(self.lib.nspnp_profile_read(self._h, ctypes.byref(n), names, ms, cnt))
+        return {names[k].decode(): (ms[k], cnt[k]) for k in range(n.value)}

@@ -169,9 +169,54 @@ int solve_potential(nspnp_state *s) {
 
 }  // namespace
 
+nspnp_state::~nspnp_state() {
+    for (hipEvent_t e : prof.ev) hipEventDestroy(e);
+}
+
+namespace {
+const char *const kKernelNames[K_NKERNEL] = {
+    "dt", "explicit_rhs", "cn_tridiag", "divergence", "fft_x_r2c", "fft_z_fwd", "thomas_modes",
+    "fft_z_inv", "fft_x_c2r", "correct", "charge", "store_phi", "clock"};
+}
+
 extern "C" {
 
 const char *nspnp_last_error(void) { return g_last_error.c_str(); }
+
+int nspnp_profile_enable(nspnp_state *s, int32_t on) {
+    if (!s) return fail(NSPNP_ERR_INVALID, "state is NULL");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->prof.on = on != 0;
+    s->prof.used = 0;
+    s->prof.ids.clear();
+    for (int k = 0; k < K_NKERNEL; ++k) {
+        s->prof.total_ms[k] = 0.0;
+        s->prof.launches[k] = 0;
+    }
+    return NSPNP_OK;
+}
+
+int nspnp_profile_read(nspnp_state *s, int32_t *count, const char **names, double *total_ms, int64_t *launches) {
+    if (!s || !count) return fail(NSPNP_ERR_INVALID, "bad profile_read arguments");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    Profiler &p = s->prof;
+    const size_t pairs = std::min(p.ids.size(), p.used / 2);
+    for (size_t q = 0; q < pairs; ++q) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p.ev[2 * q], p.ev[2 * q + 1]));
+        p.total_ms[p.ids[q]] += ms;
+        p.launches[p.ids[q]] += 1;
+    }
+    p.used = 0;
+    p.ids.clear();
+    *count = K_NKERNEL;
+    for (int k = 0; k < K_NKERNEL; ++k) {
+        if (names) names[k] = kKernelNames[k];
+        if (total_ms) total_ms[k] = p.total_ms[k];
+        if (launches) launches[k] = p.launches[k];
+    }
+    return NSPNP_OK;
+}
 
 size_t nspnp_workspace_bytes(const nspnp_config *cfg) {
     if (check_config(cfg) != NSPNP_OK) return 0;

@@ -62,6 +62,30 @@ struct Stage {
     int k;              // 0, 1, 2
 };
 
+// Kernel classes timed by the optional event profiler.
+enum KernelId {
+    K_DT = 0, K_EXPLICIT, K_CN, K_DIV, K_FFTX_FWD, K_FFTZ_FWD, K_THOMAS, K_FFTZ_INV, K_FFTX_INV,
+    K_CORRECT, K_CHARGE, K_STORE_PHI, K_CLOCK, K_NKERNEL
+};
+
+// hipEvent pairs around kernel launches on the solver's stream.
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ids;
+    size_t used = 0;
+    double total_ms[K_NKERNEL] = {};
+    int64_t launches[K_NKERNEL] = {};
+    hipEvent_t next() {
+        if (used == ev.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            ev.push_back(e);
+        }
+        return ev[used++];
+    }
+};
+
 }  // namespace nspnp
 
 // Host handle (opaque to users).
@@ -86,9 +110,35 @@ struct nspnp_state {
     int64_t nred;
     int64_t substeps;
     std::vector<double> host_tables;
+    nspnp::Profiler prof;
+    ~nspnp_state();
 };
 
 namespace nspnp {
+
+// Records an event before and after the launches in its scope when the
+// profiler is on.
+class ProfScope {
+  public:
+    ProfScope(nspnp_state *s, int id) : s_(s), id_(id) {
+        if (s_->prof.on) {
+            hipEvent_t e = s_->prof.next();
+            if (e) { hipEventRecord(e, s_->stream); s_->prof.ids.push_back(id_); }
+            else s_ = nullptr;
+        } else {
+            s_ = nullptr;
+        }
+    }
+    ~ProfScope() {
+        if (s_) {
+            hipEvent_t e = s_->prof.next();
+            if (e) hipEventRecord(e, s_->stream);
+        }
+    }
+  private:
+    nspnp_state *s_;
+    int id_;
+};
 
 // launchers (one translation unit each; all queue on s->stream)
 hipError_t launch_explicit(nspnp_state *s, const Stage &st, bool write_r);

@@ -278,15 +278,30 @@ hipError_t launch_poisson(nspnp_state *s, int kind, const double *rhs, double *o
     const int64_t npairs = (nlines + 1) / 2;
     const unsigned gx = (unsigned)((npairs + ppb - 1) / ppb);
     const size_t ldsx = 2 * (size_t)ppb * d.nx * sizeof(double2);
-    k_fft_x_r2c<<<gx, 256, ldsx, s->stream>>>(d, s->planx, s->tb.twx, rhs, s->spec, ppb);
+    {
+        ProfScope prof_(s, K_FFTX_FWD);
+        k_fft_x_r2c<<<gx, 256, ldsx, s->stream>>>(d, s->planx, s->tb.twx, rhs, s->spec, ppb);
+    }
     const int tk = modes_per_tile(d.nz, d.nxh);
     const unsigned gz = (unsigned)(d.M * ((d.nxh + tk - 1) / tk));
     const size_t ldsz = 2 * (size_t)tk * d.nz * sizeof(double2);
-    k_fft_z<<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, tk, 0);
+    {
+        ProfScope prof_(s, K_FFTZ_FWD);
+        k_fft_z<<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, tk, 0);
+    }
     const int64_t nmodes = (int64_t)d.nxh * d.nz;
-    k_thomas_modes<<<(unsigned)((nmodes + 255) / 256), 256, 0, s->stream>>>(d, s->tb, s->spec, s->cpr, kind);
-    k_fft_z<<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, tk, 1);
-    k_fft_x_c2r<<<gx, 256, ldsx, s->stream>>>(d, s->planx, s->tb.twx, s->spec, out, ppb);
+    {
+        ProfScope prof_(s, K_THOMAS);
+        k_thomas_modes<<<(unsigned)((nmodes + 255) / 256), 256, 0, s->stream>>>(d, s->tb, s->spec, s->cpr, kind);
+    }
+    {
+        ProfScope prof_(s, K_FFTZ_INV);
+        k_fft_z<<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, tk, 1);
+    }
+    {
+        ProfScope prof_(s, K_FFTX_INV);
+        k_fft_x_c2r<<<gx, 256, ldsx, s->stream>>>(d, s->planx, s->tb.twx, s->spec, out, ppb);
+    }
     return hipGetLastError();
 }
 

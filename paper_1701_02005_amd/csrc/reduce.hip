@@ -212,6 +212,7 @@ hipError_t launch_shift_conc(nspnp_state *s, double mp, double mm) {
 }
 
 hipError_t launch_dt(nspnp_state *s) {
+    ProfScope prof_(s, K_DT);
     if (s->fp64)
         k_dt_partial<double><<<kDtBlocks, kRedThreads, 0, s->stream>>>(
             s->d, s->tb, (const double *)s->f[0], (const double *)s->f[1], (const double *)s->f[2],

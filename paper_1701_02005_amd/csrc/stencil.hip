@@ -396,6 +396,7 @@ inline dim3 grid1(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) /
 }  // namespace
 
 hipError_t launch_explicit(nspnp_state *s, const Stage &st, bool /*write_r*/) {
+    ProfScope prof_(s, K_EXPLICIT);
     ExplicitArgs a{};
     a.d = s->d;
     a.ph = s->ph;
@@ -426,6 +427,7 @@ hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]) {
 }
 
 hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
+    ProfScope prof_(s, K_CN);
     CnArgs a{};
     a.d = s->d;
     a.ph = s->ph;
@@ -441,6 +443,7 @@ hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
 }
 
 hipError_t launch_divergence(nspnp_state *s, double fixed, const Stage &st, double *out) {
+    ProfScope prof_(s, K_DIV);
     DivArgs a{};
     a.d = s->d;
     a.tb = s->tb;
@@ -455,6 +458,7 @@ hipError_t launch_divergence(nspnp_state *s, double fixed, const Stage &st, doub
 }
 
 hipError_t launch_correct(nspnp_state *s, const Stage &st, bool update_p, double fixed) {
+    ProfScope prof_(s, K_CORRECT);
     CorrArgs a{};
     a.d = s->d;
     a.ph = s->ph;
@@ -471,6 +475,7 @@ hipError_t launch_correct(nspnp_state *s, const Stage &st, bool update_p, double
 }
 
 hipError_t launch_charge(nspnp_state *s, double *out) {
+    ProfScope prof_(s, K_CHARGE);
     if (s->fp64)
         k_charge<double><<<grid1(s->d.n), 256, 0, s->stream>>>(s->d, s->ph.ch, (const double *)s->f[3],
                                                               (const double *)s->f[4], out);
@@ -481,6 +486,7 @@ hipError_t launch_charge(nspnp_state *s, double *out) {
 }
 
 hipError_t launch_store_phi(nspnp_state *s, const double *src) {
+    ProfScope prof_(s, K_STORE_PHI);
     if (s->fp64)
         k_copy_convert<double, double><<<grid1(s->d.n), 256, 0, s->stream>>>(s->d.n, src, (double *)s->f[5]);
     else
@@ -504,6 +510,7 @@ hipError_t launch_convert(nspnp_state *s, int field, const double *in, double *o
 }
 
 hipError_t launch_advance_clock(nspnp_state *s, double alp) {
+    ProfScope prof_(s, K_CLOCK);
     k_advance_clock<double><<<1, 64, 0, s->stream>>>(s->clock, alp);
     return hipGetLastError();
 }

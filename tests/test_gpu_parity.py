@@ -153,3 +153,23 @@ def test_mixed_precision_tracks_oracle(P, O):
     tb, tt = g.wall_shear_stress()
     otb, ott = o.wall_shear()
     assert abs(tb - otb) < 1e-4 * otb and abs(tt - ott) < 1e-4 * ott
+
+
+def test_full_size_turbulent_case_matches_oracle(P, O):
+    """256x193x256, Re 3000, lam 0.05, vhat 10, adaptive dt (the benchmarked
+    case, same launch configuration): initial state and one full RK3 step."""
+    O.set_threads(16)
+    g, o = make_pair(P, O, P.configs.couette_turbulent(seed=0))
+    err0 = worst(g, o)
+    note(f"full size, initial state: {max(err0.values()):.3e}")
+    assert max(err0.values()) < 1e-12, err0
+    g.step(3)
+    o.run(3)
+    err = worst(g, o)
+    note(f"full size, 3 substeps: {max(err.values()):.3e}")
+    assert max(err.values()) < 1e-10, err
+    t, dt, _, _ = g.clock()
+    assert abs(dt - o.dt) < 1e-13 * o.dt
+    tb, tt = g.wall_shear_stress()
+    otb, ott = o.wall_shear()
+    assert abs(tb - otb) < 1e-10 * otb and abs(tt - ott) < 1e-10 * ott

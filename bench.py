@@ -27,42 +27,34 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_bytes(cfg, name: str, launches: int, substeps: int) -> float:
-    """Algorithmic (compulsory) HBM bytes of all launches of one kernel class.
+    """Algorithmic (compulsory) HBM bytes of all launches of one kernel class
+    inside the substep loop.
 
-    w = state word (8 FP64, 4 mixed); scratch and spectral buffers are FP64.
-    Per cell: explicit_rhs reads the 7 state fields, reads H^{k-1} (stages 2
-    and 3), writes H^k (stages 1 and 2) and the 5 Crank-Nicolson right-hand
-    sides; cn_tridiag reads r and the field and writes the field (5 fields);
-    the x transforms read or write one real FP64 value and one half spectrum
-    (nx/2+1 complex per line of nx); z transforms and the mode Thomas solve
-    read and write the half spectrum once; correct reads psi and updates
-    u, v, w, p; divergence reads u, v, w and writes one FP64 value; charge
-    reads c+, c- and writes one FP64 value.
+    w = state word (8 FP64, 4 mixed); spectral and scratch buffers are FP64;
+    s = 16 (nx/2+1)/nx bytes of half spectrum per cell.  Per cell and launch:
+    explicit_rhs reads the 7 state fields, reads H^{k-1} on stages 2 and 3,
+    writes H^k on stages 1 and 2 and the 5 Crank-Nicolson right-hand sides
+    (FP64); cn_tridiag reads r and the field and writes the field, 5 fields.
+    The pressure and potential solves run batched: fft_x_r2c reads u, v, w
+    (divergence) and c+, c- (charge) and writes two half spectra; fft_z_*
+    and thomas_modes read and write both half spectra once; fft_x_c2r reads
+    them and writes psi (FP64) and phi (state); correct reads psi and
+    updates u, v, w, p; dt reads u, v, w, c+, c- once per three substeps.
     """
     w = 8 if cfg.precision == "fp64" else 4
     n = cfg.nx * cfg.nz * (cfg.ny - 1)
-    spec = 16.0 * (cfg.nx // 2 + 1) / cfg.nx  # half-spectrum bytes per cell
-    if name == "explicit_rhs":
-        # stages cycle 1,2,3: H_old read on 2 of 3, H_new written on 2 of 3
-        per = 7 * w + 40 + 5 * w * (2.0 / 3.0) + 5 * w * (2.0 / 3.0)
-    elif name == "cn_tridiag":
-        per = 5 * (8 + 2 * w)
-    elif name == "divergence":
-        per = 3 * w + 8
-    elif name in ("fft_x_r2c", "fft_x_c2r"):
-        per = 8 + spec
-    elif name in ("fft_z_fwd", "fft_z_inv", "thomas_modes"):
-        per = 2 * spec
-    elif name == "correct":
-        per = 8 + 8 * w
-    elif name == "charge":
-        per = 2 * w + 8
-    elif name == "store_phi":
-        per = 8 + w
-    elif name == "dt":
-        per = 5 * w
-    else:
-        per = 0.0
+    sp = 16.0 * (cfg.nx // 2 + 1) / cfg.nx
+    per = {
+        "explicit_rhs": 7 * w + 40 + 5 * w * (2.0 / 3.0) + 5 * w * (2.0 / 3.0),
+        "cn_tridiag": 5 * (8 + 2 * w),
+        "fft_x_r2c": 5 * w + 2 * sp,
+        "fft_z_fwd": 4 * sp,
+        "thomas_modes": 4 * sp,
+        "fft_z_inv": 4 * sp,
+        "fft_x_c2r": 2 * sp + 8 + w,
+        "correct": 8 + 8 * w,
+        "dt": 5 * w,
+    }.get(name, 0.0)
     return per * n * launches
 
 
@@ -90,6 +82,9 @@ def main():
     ap.add_argument("--workload", default="couette_turbulent")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="before timing, run one plain device-to-device copy of this many MiB (a "
+                         "reference kernel of known traffic for hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -103,6 +98,15 @@ def main():
     cfg = P.configs.WORKLOADS[args.workload](precision=args.precision)
     print(f"[bench] workload {args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz} {args.precision}", file=sys.stderr,
           flush=True)
+    if args.copy_calibration_mb > 0:
+        nbytes = args.copy_calibration_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {nbytes} bytes read + {nbytes} bytes written", file=sys.stderr,
+              flush=True)
+        del src, dst
     solver = P.Solver(cfg, device="cuda:0")
     stream = solver.stream
     solver.step(args.warmup)

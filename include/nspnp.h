@@ -179,6 +179,97 @@ NSPNP_API int nspnp_profile_enable(nspnp_state *s, int32_t on);
 NSPNP_API int nspnp_profile_read(nspnp_state *s, int32_t *count, const char **names, double *total_ms,
                                  int64_t *launches);
 
+/* ---- ensembles of independent runs ----------------------------------- */
+
+/*
+ * An ensemble advances n independent runs together, each with its own
+ * configuration (Re, Sc, beta, Debye length, voltage, walls, seed, noise, dt
+ * rule).  Runs with the same grid (nx, ny, nz, lx, lz, stretch, precision,
+ * fixed-or-adaptive dt) share every kernel launch; each run keeps its own
+ * adaptive dt and clock, and gives the same result as a single run of the
+ * same configuration.  The caller owns one device workspace of
+ * nspnp_ensemble_workspace_bytes(); members are numbered as in cfgs.
+ */
+typedef struct nspnp_ensemble nspnp_ensemble;
+
+NSPNP_API size_t nspnp_ensemble_workspace_bytes(const nspnp_config *cfgs, int32_t n);
+/* Initialise every member as nspnp_init_state does.  hip_stream must not be
+ * the legacy null stream if nspnp_ensemble_capture is used.  Synchronises. */
+NSPNP_API int nspnp_ensemble_init(const nspnp_config *cfgs, int32_t n, void *dev_workspace, size_t bytes,
+                                  void *hip_stream, nspnp_ensemble **out);
+/* Advance every member n_substeps substeps (replaying the captured graph for
+ * whole multiples of its length when one exists).  Asynchronous. */
+NSPNP_API int nspnp_ensemble_step(nspnp_ensemble *e, int32_t n_substeps);
+/* Capture substeps_per_replay substeps (a multiple of 3, from the start of a
+ * Runge-Kutta step) of all members into one hipGraph, replayed by step().
+ * Nothing is executed by the capture itself. */
+NSPNP_API int nspnp_ensemble_capture(nspnp_ensemble *e, int32_t substeps_per_replay);
+/* on = 1: clear and start accumulating, after every substep, the plane means
+ * of u, c+ - c- and phi of every cell row, weighted by the substep duration;
+ * on = 0: stop.  Asynchronous. */
+NSPNP_API int nspnp_ensemble_stats(nspnp_ensemble *e, int32_t on);
+/* Time means since statistics were switched on of member's plane-averaged
+ * u, c+ - c-, phi per cell row (host arrays of ny-1 doubles) and the
+ * averaging time.  Synchronises. */
+NSPNP_API int nspnp_ensemble_profiles(nspnp_ensemble *e, int32_t member, double *u, double *rho, double *phi,
+                                      double *time_weight);
+/* Single-run diagnostics of one member (see the single-run calls). */
+NSPNP_API int nspnp_ensemble_get_field(nspnp_ensemble *e, int32_t member, int32_t field, double *dev_out);
+NSPNP_API int nspnp_ensemble_wall_shear_stress(nspnp_ensemble *e, int32_t member, double *tau_bottom,
+                                               double *tau_top);
+NSPNP_API int nspnp_ensemble_ion_flux(nspnp_ensemble *e, int32_t member, double *jy_plus, double *jy_minus,
+                                      double *mass_plus, double *mass_minus);
+NSPNP_API int nspnp_ensemble_clock(nspnp_ensemble *e, int32_t member, double *t, double *dt, int64_t *substeps);
+/* Choose the launch shapes of every size class (threads per block of the
+ * stencil, Crank-Nicolson, mode-Thomas and correction kernels, points per
+ * block of the x and z transforms) by timing trial_substeps substeps (a
+ * multiple of 3) per candidate, coordinate by coordinate.  Results are
+ * read from / appended to the text cache at cache_path (NULL: no cache),
+ * one line per (arch, grid, precision, members) key.  Trials advance the
+ * members (the launch shape does not change any result); on return every
+ * member has advanced by the same number of substeps.  tiles_out (NULL or
+ * 6 ints per class) receives the choice.  Synchronises. */
+NSPNP_API int nspnp_ensemble_autotune(nspnp_ensemble *e, const char *cache_path, int32_t trial_substeps,
+                                      int32_t *tiles_out);
+/* Number of size classes. */
+NSPNP_API int32_t nspnp_ensemble_classes(const nspnp_ensemble *e);
+NSPNP_API void nspnp_ensemble_destroy(nspnp_ensemble *e);
+
+/* ---- warm-start surrogate network ------------------------------------- */
+
+/*
+ * A fully connected network x -> GELU(x W_0 + b_0) -> ... -> x W_L + b_L
+ * (GELU in erf form on every hidden layer) trained by mean-squared error and
+ * Adam (beta1 0.9, beta2 0.999, eps 1e-8) with FP32 master weights.  All
+ * matrix products run on the matrix cores in BF16 with FP32 accumulation;
+ * activations are rounded to BF16 between layers.  n_layers weight layers
+ * map sizes[0] inputs to sizes[n_layers] outputs; max_rows bounds the rows
+ * of one call.  Parameters cross the ABI as FP32 host arrays ordered
+ * W_0 [sizes[0] x sizes[1]] row-major, b_0 [sizes[1]], W_1, b_1, ...; inputs
+ * [rows x sizes[0]] and targets / outputs [rows x sizes[n_layers]] are
+ * caller-owned FP32 device arrays.
+ */
+typedef struct nspnp_mlp nspnp_mlp;
+
+NSPNP_API size_t nspnp_mlp_workspace_bytes(int32_t n_layers, const int32_t *sizes, int32_t max_rows);
+NSPNP_API int nspnp_mlp_init(int32_t n_layers, const int32_t *sizes, int32_t max_rows, const float *host_params,
+                             void *dev_workspace, size_t bytes, void *hip_stream, nspnp_mlp **out);
+NSPNP_API int nspnp_mlp_set_params(nspnp_mlp *h, const float *host_params);
+/* FP32 master parameters and / or the gradients of the last gradients() or
+ * train_step() call, in the parameter order above (either may be NULL). */
+NSPNP_API int nspnp_mlp_get_params(nspnp_mlp *h, float *host_params, float *host_grads);
+/* Network outputs for rows inputs.  Asynchronous. */
+NSPNP_API int nspnp_mlp_forward(nspnp_mlp *h, const float *dev_x, int32_t rows, float *dev_y);
+/* Loss and gradients without updating the parameters; *loss (host, may be
+ * NULL) receives the mean squared error.  Synchronises when loss != NULL. */
+NSPNP_API int nspnp_mlp_gradients(nspnp_mlp *h, const float *dev_x, const float *dev_y, int32_t rows, float *loss);
+/* One full-batch Adam step with learning rate lr; the loss before the step is
+ * written to dev_loss (device FP32, may be NULL).  Asynchronous. */
+NSPNP_API int nspnp_mlp_train_step(nspnp_mlp *h, const float *dev_x, const float *dev_y, int32_t rows, float lr,
+                                   float *dev_loss);
+NSPNP_API int nspnp_mlp_sync(nspnp_mlp *h);
+NSPNP_API void nspnp_mlp_destroy(nspnp_mlp *h);
+
 /* Wait for all queued work of this state. */
 NSPNP_API int nspnp_sync(nspnp_state *s);
 

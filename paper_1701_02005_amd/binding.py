@@ -127,6 +127,33 @@ def load_library() -> ctypes.CDLL:
                                     ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_int64)]),
         "nspnp_destroy": (None, [_P]),
         "nspnp_last_error": (ctypes.c_char_p, []),
+        "nspnp_ensemble_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(_CConfig), ctypes.c_int32]),
+        "nspnp_ensemble_init": (_I, [ctypes.POINTER(_CConfig), ctypes.c_int32, _P, ctypes.c_size_t, _P,
+                                     ctypes.POINTER(_P)]),
+        "nspnp_ensemble_step": (_I, [_P, ctypes.c_int32]),
+        "nspnp_ensemble_capture": (_I, [_P, ctypes.c_int32]),
+        "nspnp_ensemble_stats": (_I, [_P, ctypes.c_int32]),
+        "nspnp_ensemble_profiles": (_I, [_P, ctypes.c_int32, ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                         ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+        "nspnp_ensemble_get_field": (_I, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
+        "nspnp_ensemble_wall_shear_stress": (_I, [_P, ctypes.c_int32, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+        "nspnp_ensemble_ion_flux": (_I, [_P, ctypes.c_int32, ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                         ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+        "nspnp_ensemble_clock": (_I, [_P, ctypes.c_int32, ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                      ctypes.POINTER(ctypes.c_int64)]),
+        "nspnp_ensemble_autotune": (_I, [_P, ctypes.c_char_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+        "nspnp_ensemble_classes": (ctypes.c_int32, [_P]),
+        "nspnp_ensemble_destroy": (None, [_P]),
+        "nspnp_mlp_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
+        "nspnp_mlp_init": (_I, [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_float), _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+        "nspnp_mlp_set_params": (_I, [_P, ctypes.POINTER(ctypes.c_float)]),
+        "nspnp_mlp_get_params": (_I, [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+        "nspnp_mlp_forward": (_I, [_P, _P, ctypes.c_int32, _P]),
+        "nspnp_mlp_gradients": (_I, [_P, _P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]),
+        "nspnp_mlp_train_step": (_I, [_P, _P, _P, ctypes.c_int32, ctypes.c_float, _P]),
+        "nspnp_mlp_sync": (_I, [_P]),
+        "nspnp_mlp_destroy": (None, [_P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -252,3 +279,169 @@ class Solver:
         cnt = (ctypes.c_int64 * 16)()
         _check(self.lib.nspnp_profile_read(self._h, ctypes.byref(n), names, ms, cnt))
         return {names[k].decode(): (ms[k], cnt[k]) for k in range(n.value)}
+
+
+class Ensemble:
+    """Independent runs advanced together (nspnp_ensemble_* calls).
+
+    Work is queued on a dedicated stream of default priority (the legacy
+    null stream cannot be captured into a graph); every call that returns
+    data synchronises that stream."""
+
+    TILE_NAMES = ("expl", "cn", "fftx", "fftz", "thomas", "corr")
+
+    def __init__(self, cfgs, device: str = "cuda:0"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("nspnp needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.lib = load_library()
+        self.cfgs = list(cfgs)
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        arr = (_CConfig * len(self.cfgs))(*[c.to_c() for c in self.cfgs])
+        self._arr = arr
+        nbytes = self.lib.nspnp_ensemble_workspace_bytes(arr, len(self.cfgs))
+        if nbytes == 0:
+            raise NsPnpError(-1, self.lib.nspnp_last_error().decode())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        h = _P()
+        _check(self.lib.nspnp_ensemble_init(arr, len(self.cfgs), ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self.lib.nspnp_ensemble_destroy(self._h)
+            self._h = None
+
+    def __len__(self):
+        return len(self.cfgs)
+
+    def sync(self):
+        self.stream.synchronize()
+
+    def step(self, n_substeps: int):
+        _check(self.lib.nspnp_ensemble_step(self._h, int(n_substeps)))
+
+    def capture(self, substeps_per_replay: int):
+        _check(self.lib.nspnp_ensemble_capture(self._h, int(substeps_per_replay)))
+
+    def stats(self, on: bool):
+        _check(self.lib.nspnp_ensemble_stats(self._h, 1 if on else 0))
+
+    def profiles(self, member: int):
+        m = self.cfgs[member].ny - 1
+        u, r, p = (_D * m)(), (_D * m)(), (_D * m)()
+        wt = _D()
+        _check(self.lib.nspnp_ensemble_profiles(self._h, member, u, r, p, ctypes.byref(wt)))
+        return list(u), list(r), list(p), wt.value
+
+    def get_field(self, member: int, name: str) -> torch.Tensor:
+        c = self.cfgs[member]
+        out = torch.empty((c.ny - 1, c.nz, c.nx), dtype=torch.float64, device=self.device)
+        torch.cuda.synchronize(self.device)
+        _check(self.lib.nspnp_ensemble_get_field(self._h, member, FIELDS[name], ctypes.c_void_p(out.data_ptr())))
+        self.sync()
+        return out
+
+    def wall_shear_stress(self, member: int):
+        tb, tt = _D(), _D()
+        _check(self.lib.nspnp_ensemble_wall_shear_stress(self._h, member, ctypes.byref(tb), ctypes.byref(tt)))
+        return tb.value, tt.value
+
+    def ion_flux(self, member: int):
+        n = self.cfgs[member].ny
+        jp, jm = (_D * n)(), (_D * n)()
+        mp, mm = _D(), _D()
+        _check(self.lib.nspnp_ensemble_ion_flux(self._h, member, jp, jm, ctypes.byref(mp), ctypes.byref(mm)))
+        return list(jp), list(jm), mp.value, mm.value
+
+    def clock(self, member: int):
+        t, dt, ns = _D(), _D(), ctypes.c_int64()
+        _check(self.lib.nspnp_ensemble_clock(self._h, member, ctypes.byref(t), ctypes.byref(dt), ctypes.byref(ns)))
+        return t.value, dt.value, ns.value
+
+    def classes(self) -> int:
+        return int(self.lib.nspnp_ensemble_classes(self._h))
+
+    def autotune(self, cache_path: str | None = None, trial_substeps: int = 6):
+        nc = self.classes()
+        out = (ctypes.c_int32 * (6 * nc))()
+        path = cache_path.encode() if cache_path else None
+        _check(self.lib.nspnp_ensemble_autotune(self._h, path, int(trial_substeps), out))
+        return [dict(zip(self.TILE_NAMES, list(out)[6 * c: 6 * c + 6])) for c in range(nc)]
+
+
+class Mlp:
+    """BF16 matrix-core surrogate network (nspnp_mlp_* calls).  Parameters
+    cross as one flat FP32 array: W_0 [in x out] row-major, b_0, W_1, b_1..."""
+
+    def __init__(self, sizes, max_rows: int, params, device: str = "cuda:0"):
+        import numpy as np
+        if not torch.cuda.is_available():
+            raise RuntimeError("nspnp needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.lib = load_library()
+        self.sizes = [int(x) for x in sizes]
+        self.nl = len(self.sizes) - 1
+        self.max_rows = int(max_rows)
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self._sz = (ctypes.c_int32 * len(self.sizes))(*self.sizes)
+        self.nparams = sum(a * b + b for a, b in zip(self.sizes[:-1], self.sizes[1:]))
+        nbytes = self.lib.nspnp_mlp_workspace_bytes(self.nl, self._sz, self.max_rows)
+        if nbytes == 0:
+            raise NsPnpError(-1, self.lib.nspnp_last_error().decode())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == self.nparams
+        h = _P()
+        _check(self.lib.nspnp_mlp_init(self.nl, self._sz, self.max_rows,
+                                       p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                       ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self._loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self.lib.nspnp_mlp_sync(self._h)
+            self.lib.nspnp_mlp_destroy(self._h)
+            self._h = None
+
+    @staticmethod
+    def _dev(t):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
+            raise ValueError("expected a contiguous float32 CUDA tensor")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(self.lib.nspnp_mlp_set_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def get_params(self):
+        import numpy as np
+        p = np.zeros(self.nparams, dtype=np.float32)
+        g = np.zeros(self.nparams, dtype=np.float32)
+        _check(self.lib.nspnp_mlp_get_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                             g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return p, g
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        out = torch.empty((x.shape[0], self.sizes[-1]), dtype=torch.float32, device=self.device)
+        _check(self.lib.nspnp_mlp_forward(self._h, self._dev(x), int(x.shape[0]), self._dev(out)))
+        return out
+
+    def gradients(self, x: torch.Tensor, y: torch.Tensor) -> float:
+        loss = ctypes.c_float()
+        _check(self.lib.nspnp_mlp_gradients(self._h, self._dev(x), self._dev(y), int(x.shape[0]),
+                                            ctypes.byref(loss)))
+        return loss.value
+
+    def train_step(self, x: torch.Tensor, y: torch.Tensor, lr: float) -> torch.Tensor:
+        _check(self.lib.nspnp_mlp_train_step(self._h, self._dev(x), self._dev(y), int(x.shape[0]), float(lr),
+                                             self._dev(self._loss)))
+        return self._loss
+
+    def sync(self):
+        _check(self.lib.nspnp_mlp_sync(self._h))

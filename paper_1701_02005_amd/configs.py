@@ -38,3 +38,21 @@ WORKLOADS = {
     "couette_turbulent": couette_turbulent,
     "couette_large": couette_large,
 }
+
+
+def ensemble_members(seed: int = 0, n_large: int = 32, n_small: int = 32, precision: str = "mixed"):
+    """Uneven ensemble: n_large runs on 64 x 65 x 64 and n_small on 48 x 49 x 48.
+    Member i draws (Re, vhat, Debye length) from a generator seeded with
+    (seed, i): Re uniform on [500, 3000], vhat uniform on [0, 20], Debye
+    length log-uniform on [0.02, 0.2]; Sc = 1, beta = 0.5, CFL 0.5."""
+    import numpy as np
+    members = []
+    for i in range(n_large + n_small):
+        rng = np.random.default_rng([seed, i])
+        re = float(rng.uniform(500.0, 3000.0))
+        vhat = float(rng.uniform(0.0, 20.0))
+        lam = float(math.exp(rng.uniform(math.log(0.02), math.log(0.2))))
+        n, ny = (64, 65) if i < n_large else (48, 49)
+        members.append(Config(nx=n, ny=ny, nz=n, precision=precision, lx=TWO_PI, lz=math.pi, stretch=1.5, re=re,
+                              sc=1.0, beta=0.5, debye=lam, vhat=vhat, dt=0.0, cfl=0.5, seed=seed * 1000 + i))
+    return members

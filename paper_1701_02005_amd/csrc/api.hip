@@ -56,6 +56,8 @@ int check_config(const nspnp_config *c) {
             return fail(NSPNP_ERR_SIZE, "nx and nz must be even, of the form 2^a 3^b, and within 4..1024");
     }
     if (c->ny < 5) return fail(NSPNP_ERR_SIZE, "ny (wall-normal nodes) must be at least 5");
+    if ((int64_t)c->nx * c->nz * (c->ny - 1) > 2147483647LL)
+        return fail(NSPNP_ERR_SIZE, "nx * nz * (ny - 1) must stay below 2^31 cells (32-bit cell indices)");
     const double pos[] = {c->lx, c->lz, c->re, c->sc, c->debye};
     for (double v : pos)
         if (!(v > 0.0) || !std::isfinite(v)) return fail(NSPNP_ERR_INVALID, "lx, lz, re, sc, debye must be > 0");
@@ -67,7 +69,7 @@ int check_config(const nspnp_config *c) {
 }
 
 struct Layout {
-    size_t off_f[7], off_h[5], off_r[5], off_rhs, off_psi, off_spec, off_cpr, off_clock, off_red, off_tab;
+    size_t off_f[7], off_h[5], off_r[5], off_psi, off_spec, off_cpr, off_clock, off_phys, off_stats, off_red, off_tab;
     size_t ntab, nred, total;
 };
 
@@ -82,22 +84,26 @@ Layout make_layout(const nspnp_config *c) {
     for (int q = 0; q < 7; ++q) { L.off_f[q] = o; o = align256(o + n * ws); }
     for (int q = 0; q < 5; ++q) { L.off_h[q] = o; o = align256(o + n * ws); }
     for (int q = 0; q < 5; ++q) { L.off_r[q] = o; o = align256(o + n * 8); }
-    L.off_rhs = o; o = align256(o + n * 8);
     L.off_psi = o; o = align256(o + n * 8);
     const int64_t nspec = nxh * c->nz * M;
-    L.off_spec = o; o = align256(o + nspec * 16);
-    L.off_cpr = o; o = align256(o + nspec * 8);
+    L.off_spec = o; o = align256(o + 2 * nspec * 16);
+    L.off_cpr = o; o = align256(o + 2 * nspec * 8);
     L.off_clock = o; o = align256(o + 4 * 8);
+    L.off_phys = o; o = align256(o + sizeof(Phys));
+    L.off_stats = o; o = align256(o + (3 * M + 2) * 8);
     L.nred = std::max<int64_t>(2 * 1024, M * 10);
     L.off_red = o; o = align256(o + L.nred * 8);
-    L.ntab = 7 * M + 1 + nxh + c->nz + 2 * c->nx + 2 * c->nz;
+    L.ntab = 11 * M + 2 + nxh + c->nz + 2 * c->nx + 2 * c->nz;
     L.off_tab = o; o = align256(o + L.ntab * 8);
     L.total = o;
     return L;
 }
 
-// Host tables: tanh-stretched y nodes, finite-volume L_y coefficients,
-// modified wavenumbers of the three-point x/z Laplacians, FFT twiddles.
+size_t table_count(int M, int nx, int nz) { return 11 * (size_t)M + 2 + (nx / 2 + 1) + nz + 2 * nx + 2 * nz; }
+
+// Host tables: tanh-stretched y nodes, finite-volume L_y coefficients and
+// reciprocals, modified wavenumbers of the three-point x/z Laplacians, FFT
+// twiddles.  All FP64; the layout is a sequence of named arrays.
 void build_tables(nspnp_state *s, double *dev_tab) {
     const nspnp_config &c = s->cfg;
     const int M = s->d.M, nx = c.nx, nz = c.nz, nxh = s->d.nxh;
@@ -109,10 +115,24 @@ void build_tables(nspnp_state *s, double *dev_tab) {
     yn[0] = -1.0;
     yn[M] = 1.0;
     std::vector<double> &t = s->host_tables;
-    t.assign(7 * M + 1 + nxh + nz + 2 * nx + 2 * nz, 0.0);
-    double *yc = t.data(), *dn = yc + M, *dc = dn + M, *lyc_lo = dc + M + 1, *lyc_up = lyc_lo + M;
-    double *lyn_lo = lyc_up + M, *lyn_up = lyn_lo + M, *kx2 = lyn_up + M, *kz2 = kx2 + nxh;
-    double *twx = kz2 + nz, *twz = twx + 2 * nx;
+    t.assign(table_count(M, nx, nz), 0.0);
+    size_t off = 0;
+    auto take = [&](size_t len, const double **dev) {
+        double *h = t.data() + off;
+        *dev = dev_tab + off;
+        off += len;
+        return h;
+    };
+    double *yc = take(M, &s->tb.yc), *dn = take(M, &s->tb.dn), *dc = take(M + 1, &s->tb.dc);
+    double *lyc_lo = take(M, &s->tb.lyc_lo), *lyc_up = take(M, &s->tb.lyc_up);
+    double *lyn_lo = take(M, &s->tb.lyn_lo), *lyn_up = take(M, &s->tb.lyn_up);
+    double *idn = take(M, &s->tb.idn), *idc = take(M + 1, &s->tb.idc);
+    double *vwl = take(M, &s->tb.vwl), *vwu = take(M, &s->tb.vwu);
+    double *kx2 = take(nxh, &s->tb.kx2), *kz2 = take(nz, &s->tb.kz2);
+    const double *twx_dev, *twz_dev;
+    double *twx = take(2 * nx, &twx_dev), *twz = take(2 * nz, &twz_dev);
+    s->tb.twx = (const double2 *)twx_dev;
+    s->tb.twz = (const double2 *)twz_dev;
     for (int j = 0; j < M; ++j) {
         yc[j] = 0.5 * (yn[j] + yn[j + 1]);
         dn[j] = yn[j + 1] - yn[j];
@@ -125,7 +145,11 @@ void build_tables(nspnp_state *s, double *dev_tab) {
         lyc_up[j] = 1.0 / (dn[j] * dc[j + 1]);
         lyn_lo[j] = (j > 0) ? 1.0 / (dc[j] * dn[j - 1]) : 0.0;
         lyn_up[j] = (j > 0) ? 1.0 / (dc[j] * dn[j]) : 0.0;
+        idn[j] = 1.0 / dn[j];
+        vwl[j] = (j > 0) ? dn[j - 1] / (2.0 * dc[j]) : 0.0;
+        vwu[j] = (j > 0) ? dn[j] / (2.0 * dc[j]) : 0.0;
     }
+    for (int j = 0; j <= M; ++j) idc[j] = 1.0 / dc[j];
     const double dx = s->d.dx, dz = s->d.dz;
     const double twopi = 6.283185307179586476925286766559;
     for (int m = 0; m < nxh; ++m) kx2[m] = (2.0 - 2.0 * std::cos(twopi * m / nx)) / (dx * dx);
@@ -138,18 +162,10 @@ void build_tables(nspnp_state *s, double *dev_tab) {
         twz[2 * m] = std::cos(twopi * m / nz);
         twz[2 * m + 1] = -std::sin(twopi * m / nz);
     }
-    s->tb.yc = dev_tab;
-    s->tb.dn = dev_tab + M;
-    s->tb.dc = dev_tab + 2 * M;
-    s->tb.lyc_lo = dev_tab + 3 * M + 1;
-    s->tb.lyc_up = dev_tab + 4 * M + 1;
-    s->tb.lyn_lo = dev_tab + 5 * M + 1;
-    s->tb.lyn_up = dev_tab + 6 * M + 1;
-    s->tb.kx2 = dev_tab + 7 * M + 1;
-    s->tb.kz2 = s->tb.kx2 + nxh;
-    s->tb.twx = (const double2 *)(s->tb.kz2 + nz);
-    s->tb.twz = (const double2 *)((const double *)s->tb.twx + 2 * nx);
 }
+
+const double *host_dn(const nspnp_state *s) { return s->host_tables.data() + s->d.M; }
+const double *host_dc(const nspnp_state *s) { return s->host_tables.data() + 2 * s->d.M; }
 
 int plane_reduce(nspnp_state *s, std::vector<double> &host) {
     HIP_TRY(launch_plane_sums(s, 0, s->red));
@@ -159,15 +175,191 @@ int plane_reduce(nspnp_state *s, std::vector<double> &host) {
     return NSPNP_OK;
 }
 
+PoissonSrc div_source(nspnp_state *s, double alp, double fixed) {
+    return PoissonSrc{SRC_DIV, s->f[0], s->f[1], s->f[2], fixed, alp};
+}
+
+PoissonSrc charge_source(nspnp_state *s) { return PoissonSrc{SRC_CHARGE, s->f[3], s->f[4], nullptr, 0.0, 0.0}; }
+
+// A batch over the members of this handle (member stride) or over caller
+// arrays for member 0 (stride 0).
+PoissonBatch make_batch(nspnp_state *s, bool members) {
+    PoissonBatch b{};
+    b.ms = members ? s->mstride : 0;
+    b.phys = s->d_phys;
+    return b;
+}
+
+// phi from the current c+- (potential-type solve straight into the state)
 int solve_potential(nspnp_state *s) {
-    HIP_TRY(launch_charge(s, s->rhs));
-    double *out = s->fp64 ? (double *)s->f[5] : s->psi;
-    HIP_TRY(launch_poisson(s, 1, s->rhs, out));
-    if (!s->fp64) HIP_TRY(launch_store_phi(s, s->psi));
+    PoissonBatch b = make_batch(s, true);
+    b.nprob = 1;
+    b.kind[0] = 1;
+    b.src[0] = charge_source(s);
+    b.out[0] = s->f[5];
+    b.out_state[0] = 1;
+    HIP_TRY(launch_poisson_batch(s, b));
     return NSPNP_OK;
 }
 
 }  // namespace
+
+namespace nspnp {
+
+int fail_code(int code, const std::string &msg) { return fail(code, msg); }
+
+int check(const nspnp_config *c) { return check_config(c); }
+
+size_t layout_bytes(const nspnp_config *c) { return make_layout(c).total; }
+
+Phys make_phys(const nspnp_config *cfg) {
+    Phys ph{};
+    ph.re = cfg->re;
+    ph.ire = 1.0 / cfg->re;
+    ph.kd = 1.0 / (cfg->re * cfg->sc);
+    ph.kf = cfg->force_sign * cfg->beta / (2.0 * cfg->sc * cfg->re * cfg->re * cfg->debye * cfg->debye);
+    ph.e0 = 0.5 * cfg->vhat;
+    ph.ch = -1.0 / (2.0 * cfg->debye * cfg->debye);
+    ph.u_top = cfg->u_top;
+    ph.u_bot = cfg->u_bot;
+    ph.debye = cfg->debye;
+    ph.cfl = cfg->cfl;
+    ph.adaptive = cfg->dt > 0.0 ? 0.0 : 1.0;
+    return ph;
+}
+
+// Handle over nmem members of one size class: member m's workspace starts at
+// base + m * layout_bytes(cfg); pointers refer to member 0.
+void setup_handle(nspnp_state *s, const nspnp_config *cfg, char *base, int nmem, hipStream_t stream) {
+    const Layout L = make_layout(cfg);
+    s->cfg = *cfg;
+    s->stream = stream;
+    s->fp64 = cfg->precision == NSPNP_PREC_FP64;
+    s->wsize = s->fp64 ? 8 : 4;
+    Dims &d = s->d;
+    d.nx = cfg->nx;
+    d.nz = cfg->nz;
+    d.M = cfg->ny - 1;
+    d.nxh = cfg->nx / 2 + 1;
+    d.plane = (int64_t)cfg->nx * cfg->nz;
+    d.n = d.plane * d.M;
+    d.dx = cfg->lx / cfg->nx;
+    d.dz = cfg->lz / cfg->nz;
+    s->ph = make_phys(cfg);
+    s->nmem = nmem;
+    s->mstride = nmem > 1 ? L.total : 0;
+    s->planx = make_plan(cfg->nx);
+    s->planz = make_plan(cfg->nz);
+    s->tiles = Tiles{256, 256, 1024, 1024, 64, 256};
+    for (int q = 0; q < 7; ++q) s->f[q] = base + L.off_f[q];
+    for (int q = 0; q < 5; ++q) s->h[q] = base + L.off_h[q];
+    for (int q = 0; q < 5; ++q) s->r[q] = (double *)(base + L.off_r[q]);
+    s->psi = (double *)(base + L.off_psi);
+    s->spec = (double2 *)(base + L.off_spec);
+    s->cpr = (double *)(base + L.off_cpr);
+    s->clock = (double *)(base + L.off_clock);
+    s->d_phys = (Phys *)(base + L.off_phys);
+    s->stats = (double *)(base + L.off_stats);
+    s->red = (double *)(base + L.off_red);
+    s->nred = L.nred;
+    s->tab_base = base + L.off_tab;
+    build_tables(s, (double *)(base + L.off_tab));
+    s->substeps = 0;
+    s->stats_on = false;
+}
+
+int upload_tables(nspnp_state *s) {
+    HIP_TRY(hipMemcpyAsync(s->tab_base, s->host_tables.data(), s->host_tables.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s->stream));
+    return NSPNP_OK;
+}
+
+// A single-member handle for member m of a class handle (same tables).
+nspnp_state *member_view(const nspnp_state *cls, int m, const nspnp_config *cfg) {
+    nspnp_state *v = new nspnp_state(*cls);
+    v->prof = Profiler{};
+    const size_t off = (size_t)m * cls->mstride;
+    auto sh = [off](auto *p) { return (decltype(p))((char *)p + off); };
+    for (int q = 0; q < 7; ++q) v->f[q] = sh(cls->f[q]);
+    for (int q = 0; q < 5; ++q) { v->h[q] = sh(cls->h[q]); v->r[q] = sh(cls->r[q]); }
+    v->psi = sh(cls->psi);
+    v->spec = sh(cls->spec);
+    v->cpr = sh(cls->cpr);
+    v->clock = sh(cls->clock);
+    v->d_phys = sh(cls->d_phys);
+    v->stats = sh(cls->stats);
+    v->red = sh(cls->red);
+    v->nmem = 1;
+    v->mstride = 0;
+    if (cfg) {
+        v->cfg = *cfg;
+        v->ph = make_phys(cfg);
+    }
+    return v;
+}
+
+// Seeded initial state of a single-member handle (Sec. II geometry and
+// boundary conditions; noise recipe in include/nspnp.h).
+int init_member(nspnp_state *s) {
+    const Dims &d = s->d;
+    const double clock0[4] = {0.0, s->cfg.dt > 0.0 ? s->cfg.dt : 0.0, 0.0, 0.0};
+    HIP_TRY(hipMemcpyAsync(s->clock, clock0, sizeof(clock0), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->d_phys, &s->ph, sizeof(Phys), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(launch_init_fields(s));
+    // remove the volume mean of the concentration noise
+    std::vector<double> ps;
+    int rc = plane_reduce(s, ps);  // synchronises: the stack clock0 is consumed
+    if (rc) return rc;
+    double sp = 0.0, sm = 0.0, vol = 0.0;
+    for (int j = 0; j < d.M; ++j) {
+        const double dn = host_dn(s)[j];
+        sp += ps[j * 10 + 1] * dn;
+        sm += ps[j * 10 + 2] * dn;
+        vol += dn * (double)d.plane;
+    }
+    HIP_TRY(launch_shift_conc(s, sp / vol, sm / vol));
+    // project the initial velocity (no pressure), then the initial potential
+    PoissonBatch b = make_batch(s, true);
+    b.nprob = 1;
+    b.kind[0] = 0;
+    b.src[0] = div_source(s, 0.0, 1.0);
+    b.out[0] = s->psi;
+    b.out_state[0] = 0;
+    HIP_TRY(launch_poisson_batch(s, b));
+    HIP_TRY(launch_correct(s, Stage{0, 0, 0, 0}, false, 1.0, false));
+    return solve_potential(s);
+}
+
+// n Runge-Kutta substeps of every member of the handle.
+int step_handle(nspnp_state *s, int n) {
+    const bool adaptive = s->cfg.dt <= 0.0;
+    for (int it = 0; it < n; ++it) {
+        const int k = (int)(s->substeps % 3);
+        const Stage st{kGam[k], kZet[k], kGam[k] + kZet[k], k};
+        if (k == 0 && adaptive) HIP_TRY(launch_dt(s));
+        HIP_TRY(launch_explicit(s, st, true));
+        HIP_TRY(launch_cn_solve(s, st));
+        // pressure projection and potential depend only on the updated
+        // fields, so both elliptic solves share one batched pipeline
+        PoissonBatch b = make_batch(s, true);
+        b.nprob = 2;
+        b.kind[0] = 0;
+        b.src[0] = div_source(s, st.alp, 0.0);
+        b.out[0] = s->psi;
+        b.out_state[0] = 0;
+        b.kind[1] = 1;
+        b.src[1] = charge_source(s);
+        b.out[1] = s->f[5];
+        b.out_state[1] = 1;
+        HIP_TRY(launch_poisson_batch(s, b));
+        HIP_TRY(launch_correct(s, st, true, 0.0, true));
+        if (s->stats_on) HIP_TRY(launch_stats_accum(s, st.alp));
+        s->substeps++;
+    }
+    return NSPNP_OK;
+}
+
+}  // namespace nspnp
 
 nspnp_state::~nspnp_state() {
     for (hipEvent_t e : prof.ev) hipEventDestroy(e);
@@ -175,8 +367,8 @@ nspnp_state::~nspnp_state() {
 
 namespace {
 const char *const kKernelNames[K_NKERNEL] = {
-    "dt", "explicit_rhs", "cn_tridiag", "divergence", "fft_x_r2c", "fft_z_fwd", "thomas_modes",
-    "fft_z_inv", "fft_x_c2r", "correct", "charge", "store_phi", "clock"};
+    "dt", "explicit_rhs", "cn_tridiag", "fft_x_r2c", "fft_z_fwd", "thomas_modes",
+    "fft_z_inv", "fft_x_c2r", "correct"};
 }
 
 extern "C" {
@@ -229,108 +421,39 @@ int nspnp_init_state(const nspnp_config *cfg, void *dev_workspace, size_t bytes,
     *out = nullptr;
     int rc = check_config(cfg);
     if (rc) return rc;
-    const Layout L = make_layout(cfg);
-    if (!dev_workspace || bytes < L.total)
+    const size_t need = layout_bytes(cfg);
+    if (!dev_workspace || bytes < need)
         return fail(NSPNP_ERR_WORKSPACE, "workspace missing or smaller than nspnp_workspace_bytes()");
     if (((uintptr_t)dev_workspace & 255) != 0) return fail(NSPNP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     nspnp_state *s = new nspnp_state();
-    s->cfg = *cfg;
-    s->stream = (hipStream_t)hip_stream;
-    s->fp64 = cfg->precision == NSPNP_PREC_FP64;
-    s->wsize = s->fp64 ? 8 : 4;
-    Dims &d = s->d;
-    d.nx = cfg->nx;
-    d.nz = cfg->nz;
-    d.M = cfg->ny - 1;
-    d.nxh = cfg->nx / 2 + 1;
-    d.plane = (int64_t)cfg->nx * cfg->nz;
-    d.n = d.plane * d.M;
-    d.dx = cfg->lx / cfg->nx;
-    d.dz = cfg->lz / cfg->nz;
-    Phys &ph = s->ph;
-    ph.re = cfg->re;
-    ph.ire = 1.0 / cfg->re;
-    ph.kd = 1.0 / (cfg->re * cfg->sc);
-    ph.kf = cfg->force_sign * cfg->beta / (2.0 * cfg->sc * cfg->re * cfg->re * cfg->debye * cfg->debye);
-    ph.e0 = 0.5 * cfg->vhat;
-    ph.ch = -1.0 / (2.0 * cfg->debye * cfg->debye);
-    ph.u_top = cfg->u_top;
-    ph.u_bot = cfg->u_bot;
-    ph.debye = cfg->debye;
-    ph.cfl = cfg->cfl;
-    s->planx = make_plan(cfg->nx);
-    s->planz = make_plan(cfg->nz);
-    char *base = (char *)dev_workspace;
-    for (int q = 0; q < 7; ++q) s->f[q] = base + L.off_f[q];
-    for (int q = 0; q < 5; ++q) s->h[q] = base + L.off_h[q];
-    for (int q = 0; q < 5; ++q) s->r[q] = (double *)(base + L.off_r[q]);
-    s->rhs = (double *)(base + L.off_rhs);
-    s->psi = (double *)(base + L.off_psi);
-    s->spec = (double2 *)(base + L.off_spec);
-    s->cpr = (double *)(base + L.off_cpr);
-    s->clock = (double *)(base + L.off_clock);
-    s->red = (double *)(base + L.off_red);
-    s->nred = L.nred;
-    build_tables(s, (double *)(base + L.off_tab));
-    s->substeps = 0;
-
-    auto bail = [&](int code) {
+    setup_handle(s, cfg, (char *)dev_workspace, 1, (hipStream_t)hip_stream);
+    if ((rc = upload_tables(s)) || (rc = init_member(s))) {
         delete s;
-        return code;
-    };
-    hipError_t e = hipMemcpyAsync(base + L.off_tab, s->host_tables.data(), s->host_tables.size() * sizeof(double),
-                                  hipMemcpyHostToDevice, s->stream);
-    if (e != hipSuccess) return bail(fail(NSPNP_ERR_HIP, std::string("table upload: ") + hipGetErrorString(e)));
-    const double clock0[4] = {0.0, cfg->dt > 0.0 ? cfg->dt : 0.0, 0.0, 0.0};
-    e = hipMemcpyAsync(s->clock, clock0, sizeof(clock0), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = launch_init_fields(s);
-    if (e != hipSuccess) return bail(fail(NSPNP_ERR_HIP, std::string("init: ") + hipGetErrorString(e)));
-    // remove the volume mean of the concentration noise
-    std::vector<double> ps;
-    if ((rc = plane_reduce(s, ps))) return bail(rc);
-    double sp = 0.0, sm = 0.0, vol = 0.0;
-    for (int j = 0; j < d.M; ++j) {
-        const double dn = s->host_tables[d.M + j];
-        sp += ps[j * 10 + 1] * dn;
-        sm += ps[j * 10 + 2] * dn;
-        vol += dn * (double)d.plane;
+        return rc;
     }
-    e = launch_shift_conc(s, sp / vol, sm / vol);
-    // project the initial velocity (no pressure), then the initial potential
-    if (e == hipSuccess) e = launch_divergence(s, 1.0, Stage{0, 0, 0, 0}, s->rhs);
-    if (e == hipSuccess) e = launch_poisson(s, 0, s->rhs, s->psi);
-    if (e == hipSuccess) e = launch_correct(s, Stage{0, 0, 0, 0}, false, 1.0);
-    if (e != hipSuccess) return bail(fail(NSPNP_ERR_HIP, std::string("initial projection: ") + hipGetErrorString(e)));
-    if ((rc = solve_potential(s))) return bail(rc);
-    e = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess) return bail(fail(NSPNP_ERR_HIP, std::string("init sync: ") + hipGetErrorString(e)));
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        delete s;
+        return fail(NSPNP_ERR_HIP, std::string("init sync: ") + hipGetErrorString(e));
+    }
     *out = s;
     return NSPNP_OK;
 }
 
 int nspnp_step(nspnp_state *s, int32_t n_substeps) {
     if (!s || n_substeps < 0) return fail(NSPNP_ERR_INVALID, "bad state or substep count");
-    const bool adaptive = s->cfg.dt <= 0.0;
-    for (int32_t it = 0; it < n_substeps; ++it) {
-        const int k = (int)(s->substeps % 3);
-        const Stage st{kGam[k], kZet[k], kGam[k] + kZet[k], k};
-        if (k == 0 && adaptive) HIP_TRY(launch_dt(s));
-        HIP_TRY(launch_explicit(s, st, true));
-        HIP_TRY(launch_cn_solve(s, st));
-        HIP_TRY(launch_divergence(s, 0.0, st, s->rhs));
-        HIP_TRY(launch_poisson(s, 0, s->rhs, s->psi));
-        HIP_TRY(launch_correct(s, st, true, 0.0));
-        int rc = solve_potential(s);
-        if (rc) return rc;
-        HIP_TRY(launch_advance_clock(s, st.alp));
-        s->substeps++;
-    }
-    return NSPNP_OK;
+    return step_handle(s, n_substeps);
 }
 
 int nspnp_poisson_solve(nspnp_state *s, int32_t kind, const double *dev_rhs, double *dev_out) {
     if (!s || !dev_rhs || !dev_out || (kind != 0 && kind != 1)) return fail(NSPNP_ERR_INVALID, "bad poisson_solve arguments");
-    HIP_TRY(launch_poisson(s, kind, dev_rhs, dev_out));
+    PoissonBatch b = make_batch(s, false);
+    b.nprob = 1;
+    b.kind[0] = kind;
+    b.src[0] = PoissonSrc{SRC_REAL, dev_rhs, nullptr, nullptr, 0.0, 0.0};
+    b.out[0] = dev_out;
+    b.out_state[0] = 0;
+    HIP_TRY(launch_poisson_batch(s, b));
     return NSPNP_OK;
 }
 
@@ -341,7 +464,7 @@ int nspnp_wall_shear_stress(nspnp_state *s, double *tau_bottom, double *tau_top)
     if (rc) return rc;
     const int M = s->d.M;
     const double pl = (double)s->d.plane;
-    const double *dc = s->host_tables.data() + 2 * M;
+    const double *dc = host_dc(s);
     *tau_bottom = s->ph.ire * (ps[0] / pl - s->cfg.u_bot) / dc[0];
     *tau_top = s->ph.ire * (s->cfg.u_top - ps[(M - 1) * 10] / pl) / dc[M];
     if (!std::isfinite(*tau_bottom) || !std::isfinite(*tau_top)) return fail(NSPNP_ERR_NONFINITE, "non-finite wall stress");
@@ -355,7 +478,7 @@ int nspnp_ion_flux(nspnp_state *s, double *jp, double *jm, double *mass_p, doubl
     if (rc) return rc;
     const int M = s->d.M;
     const double pl = (double)s->d.plane;
-    const double *dn = s->host_tables.data() + M;
+    const double *dn = host_dn(s);
     jp[0] = jm[0] = jp[M] = jm[M] = 0.0;
     for (int j = 1; j < M; ++j) {
         jp[j] = ps[j * 10 + 3] / pl;

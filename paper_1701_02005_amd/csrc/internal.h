@@ -39,13 +39,18 @@ struct Tables {
     const double *lyc_up;   // M   1/(dn_j dc_{j+1})
     const double *lyn_lo;   // M   1/(dc_j dn_{j-1}) (node rows, row 0 unused)
     const double *lyn_up;   // M   1/(dc_j dn_j)
+    const double *idn;      // M   1/dn_j
+    const double *idc;      // M+1 1/dc_j
+    const double *vwl;      // M   dn_{j-1}/(2 dc_j): weight of row j-1 at node j
+    const double *vwu;      // M   dn_j/(2 dc_j): weight of row j at node j
     const double *kx2;      // nxh modified wavenumbers (2 - 2 cos(2 pi m / nx)) / dx^2
     const double *kz2;      // nz
     const double2 *twx;     // nx  exp(-2 pi i m / nx)
     const double2 *twz;     // nz
 };
 
-// Physical constants of the nondimensional equations.
+// Physical constants of the nondimensional equations (one per member run;
+// each member's copy lives in its own workspace).
 struct Phys {
     double re, ire;     // Re, 1/Re
     double kd;          // 1 / (Re Sc)
@@ -54,7 +59,16 @@ struct Phys {
     double ch;          // -1 / (2 lam^2): charge factor of the potential equation
     double u_top, u_bot;
     double debye, cfl;
+    double adaptive;    // 1: dt from the CFL rule at stage 1; 0: fixed dt
 };
+
+// Every member of a batch has the same workspace layout; device pointers in
+// kernel arguments refer to member 0 and member blockIdx.z sits stride bytes
+// further per member.
+template <typename P>
+__device__ __forceinline__ P *member_ptr(P *p, size_t stride) {
+    return (P *)((char *)p + (size_t)blockIdx.z * stride);
+}
 
 // Runge-Kutta coefficients of one substep.
 struct Stage {
@@ -62,10 +76,41 @@ struct Stage {
     int k;              // 0, 1, 2
 };
 
+// Right-hand side of one elliptic solve, produced while the x-lines load.
+enum PoissonSrcType { SRC_REAL = 0, SRC_DIV = 1, SRC_CHARGE = 2 };
+struct PoissonSrc {
+    int type;
+    const void *a, *b, *c;  // REAL: a = FP64 array; DIV: u, v, w; CHARGE: c+, c-
+    double fixed;           // DIV: scale when alp <= 0; CHARGE: -1/(2 lam^2)
+    double alp;             // DIV: scale 1/(alp dt) with dt from the device clock
+};
+// Up to two independent solves sharing one pipeline (pressure and potential).
+struct PoissonBatch {
+    int nprob;
+    int kind[2];        // 0 pressure-type, 1 potential-type
+    PoissonSrc src[2];
+    void *out[2];       // result arrays
+    int out_state[2];   // 1: store in the state type, 0: FP64
+    size_t ms;          // member stride in bytes (0 for caller-owned arrays)
+    const Phys *phys;   // member 0's constants (charge factor)
+};
+
+// Launch shapes chosen by the autotuner.  None of them changes the
+// arithmetic done per cell, column, line or mode, so results are bitwise
+// independent of the choice.
+struct Tiles {
+    int expl;     // threads per block of the explicit kernel (64..256)
+    int cn;       // threads per block (columns) of the Crank-Nicolson solve
+    int fftx;     // complex points per block of the x transforms
+    int fftz;     // complex points per block of the z transforms
+    int thomas;   // threads per block (modes) of the mode Thomas solve
+    int corr;     // threads per block of the projection correction
+};
+
 // Kernel classes timed by the optional event profiler.
 enum KernelId {
-    K_DT = 0, K_EXPLICIT, K_CN, K_DIV, K_FFTX_FWD, K_FFTZ_FWD, K_THOMAS, K_FFTZ_INV, K_FFTX_INV,
-    K_CORRECT, K_CHARGE, K_STORE_PHI, K_CLOCK, K_NKERNEL
+    K_DT = 0, K_EXPLICIT, K_CN, K_FFTX_FWD, K_FFTZ_FWD, K_THOMAS, K_FFTZ_INV, K_FFTX_INV,
+    K_CORRECT, K_NKERNEL
 };
 
 // hipEvent pairs around kernel launches on the solver's stream.
@@ -92,22 +137,28 @@ struct Profiler {
 struct nspnp_state {
     nspnp_config cfg;
     nspnp::Dims d;
-    nspnp::Phys ph;
+    nspnp::Phys ph;       // host copy (member 0)
+    nspnp::Phys *d_phys;  // device copy inside the workspace (member 0)
+    int nmem;             // members batched in this handle (1 for a single run)
+    size_t mstride;       // bytes between members' workspaces
     nspnp::Tables tb;
     nspnp::FftPlan planx, planz;
+    nspnp::Tiles tiles;
     hipStream_t stream;
     bool fp64;
     size_t wsize;        // bytes of one state-type element
     void *f[7];          // u v w c+ c- phi p, state type
     void *h[5];          // H^{k-1} -> H^k, state type
     double *r[5];        // Crank-Nicolson right-hand sides / Thomas scratch
-    double *rhs;         // real Poisson scratch (n)
-    double *psi;         // real Poisson solution (n)
-    double2 *spec;       // half spectrum nxh * nz * M
-    double *cpr;         // spectral Thomas elimination factors (nxh * nz * M)
+    double *psi;         // pressure increment (n, FP64)
+    double2 *spec;       // two half spectra, 2 * nxh * nz * M
+    double *cpr;         // their Thomas elimination factors
     double *clock;       // device [t, dt]
     double *red;         // reduction scratch
     int64_t nred;
+    double *stats;       // time sums of the plane means of u, c+ - c-, phi (3 per row) and the time
+    bool stats_on;
+    char *tab_base;      // device tables (member 0)
     int64_t substeps;
     std::vector<double> host_tables;
     nspnp::Profiler prof;
@@ -144,16 +195,25 @@ class ProfScope {
 hipError_t launch_explicit(nspnp_state *s, const Stage &st, bool write_r);
 hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]);
 hipError_t launch_cn_solve(nspnp_state *s, const Stage &st);
-hipError_t launch_divergence(nspnp_state *s, double scale_by_alpha_dt, const Stage &st, double *out);
-hipError_t launch_correct(nspnp_state *s, const Stage &st, bool update_p, double fixed_scale);
-hipError_t launch_charge(nspnp_state *s, double *out);
-hipError_t launch_store_phi(nspnp_state *s, const double *src);
-hipError_t launch_poisson(nspnp_state *s, int kind, const double *rhs, double *out);
+hipError_t launch_correct(nspnp_state *s, const Stage &st, bool update_p, double fixed_scale, bool advance_clock);
+hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b);
 hipError_t launch_dt(nspnp_state *s);
-hipError_t launch_advance_clock(nspnp_state *s, double alp);
 hipError_t launch_init_fields(nspnp_state *s);
 hipError_t launch_plane_sums(nspnp_state *s, int what, double *dev_out);
 hipError_t launch_shift_conc(nspnp_state *s, double mean_p, double mean_m);
 hipError_t launch_convert(nspnp_state *s, int field, const double *in, double *out, bool to_state);
+hipError_t launch_stats_accum(nspnp_state *s, double alp);
+hipError_t launch_stats_reset(nspnp_state *s);
+
+// handle management shared by the single-run and ensemble entry points
+int fail_code(int code, const std::string &msg);
+int check(const nspnp_config *c);
+size_t layout_bytes(const nspnp_config *c);
+Phys make_phys(const nspnp_config *cfg);
+void setup_handle(nspnp_state *s, const nspnp_config *cfg, char *base, int nmem, hipStream_t stream);
+int upload_tables(nspnp_state *s);
+nspnp_state *member_view(const nspnp_state *cls, int m, const nspnp_config *cfg);
+int init_member(nspnp_state *s);
+int step_handle(nspnp_state *s, int n);
 
 }  // namespace nspnp

@@ -107,22 +107,57 @@ __device__ int lds_fft(double2 *b0, double2 *b1, int N, int nl, const FftPlan &p
 }
 
 // ---- x direction: real lines <-> half spectra, two lines per transform ----
-__global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, FftPlan pl, const double2 *tw, const double *in,
-                                                   double2 *out, int ppb) {
+// The right-hand side of each line is produced while it is loaded: a plain
+// FP64 array, the divergence of the staggered velocity (pressure), or the
+// charge -(c+ - c-)/(2 lam^2) (potential).
+template <typename T>
+__device__ __forceinline__ double line_value(const PoissonSrc &src, const Dims &d, const Tables &tb,
+                                             const double *clock, double ch, int64_t line, int i) {
+    const int64_t q = line * d.nx + i;
+    if (src.type == SRC_REAL) return ((const double *)src.a)[q];
+    if (src.type == SRC_CHARGE) {
+        const T *cp = (const T *)src.a, *cm = (const T *)src.b;
+        return ch * ((double)cp[q] - (double)cm[q]);
+    }
+    // divergence: (u_{i+1} - u_i)/dx + (v_{j+1} - v_j)/dy_j + (w_{k+1} - w_k)/dz
+    const T *u = (const T *)src.a, *v = (const T *)src.b, *w = (const T *)src.c;
+    const int j = (int)(line / d.nz);
+    const int k = (int)(line - (int64_t)j * d.nz);
+    const int64_t xp = q - i + ((i + 1 == d.nx) ? 0 : i + 1);
+    const int64_t zp = q + (int64_t)(((k + 1 == d.nz) ? 0 : k + 1) - k) * d.nx;
+    const double vt = (j + 1 < d.M) ? (double)v[q + d.plane] : 0.0;
+    const double vb = (j > 0) ? (double)v[q] : 0.0;
+    const double div = ((double)u[xp] - (double)u[q]) / d.dx + (vt - vb) * tb.idn[j] +
+                       ((double)w[zp] - (double)w[q]) / d.dz;
+    const double sc = (src.alp > 0.0) ? 1.0 / (src.alp * clock[1]) : src.fixed;
+    return div * sc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl, PoissonBatch b,
+                                                   const double *clock, double2 *spec, int64_t nspec, int ppb) {
     extern __shared__ double2 sm[];
+    const int prob = blockIdx.y;
+    PoissonSrc src = b.src[prob];
+    src.a = member_ptr(src.a, b.ms);
+    src.b = member_ptr(src.b, b.ms);
+    src.c = member_ptr(src.c, b.ms);
+    clock = member_ptr(clock, b.ms);
+    const double ch = member_ptr(b.phys, b.ms)->ch;
+    double2 *out = member_ptr(spec, b.ms) + prob * nspec;
     const int nx = d.nx, nxh = d.nxh;
     const int64_t nlines = (int64_t)d.M * d.nz;
-    double2 *b[2] = {sm, sm + ppb * nx};
+    double2 *bf[2] = {sm, sm + ppb * nx};
     const int64_t pair0 = (int64_t)blockIdx.x * ppb;
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
         const int p = e / nx, i = e - p * nx;
         const int64_t la = 2 * (pair0 + p), lb = la + 1;
-        const double re = (la < nlines) ? in[la * nx + i] : 0.0;
-        const double im = (lb < nlines) ? in[lb * nx + i] : 0.0;
-        b[0][e] = make_double2(re, im);
+        const double re = (la < nlines) ? line_value<T>(src, d, tb, clock, ch, la, i) : 0.0;
+        const double im = (lb < nlines) ? line_value<T>(src, d, tb, clock, ch, lb, i) : 0.0;
+        bf[0][e] = make_double2(re, im);
     }
     __syncthreads();
-    const double2 *z = b[lds_fft(b[0], b[1], nx, ppb, pl, tw, false)];
+    const double2 *z = bf[lds_fft(bf[0], bf[1], nx, ppb, pl, tb.twx, false)];
     for (int e = threadIdx.x; e < ppb * nxh; e += blockDim.x) {
         const int p = e / nxh, kk = e - p * nxh;
         const int64_t la = 2 * (pair0 + p), lb = la + 1;
@@ -136,12 +171,15 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, FftPlan pl, const dou
     }
 }
 
-__global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, FftPlan pl, const double2 *tw, const double2 *in,
-                                                   double *out, int ppb) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl, PoissonBatch b,
+                                                   const double2 *spec, int64_t nspec, int ppb) {
     extern __shared__ double2 sm[];
+    const int prob = blockIdx.y;
+    const double2 *in = member_ptr(spec, b.ms) + prob * nspec;
     const int nx = d.nx, nxh = d.nxh;
     const int64_t nlines = (int64_t)d.M * d.nz;
-    double2 *b[2] = {sm, sm + ppb * nx};
+    double2 *bf[2] = {sm, sm + ppb * nx};
     const int64_t pair0 = (int64_t)blockIdx.x * ppb;
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
         const int p = e / nx, kk = e - p * nx;
@@ -154,37 +192,45 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, FftPlan pl, const dou
             A.y = -A.y;
             B.y = -B.y;
         }
-        // Z = A + i B
-        b[0][e] = make_double2(A.x - B.y, A.y + B.x);
+        bf[0][e] = make_double2(A.x - B.y, A.y + B.x);  // Z = A + i B
     }
     __syncthreads();
-    const double2 *z = b[lds_fft(b[0], b[1], nx, ppb, pl, tw, true)];
+    const double2 *z = bf[lds_fft(bf[0], bf[1], nx, ppb, pl, tb.twx, true)];
+    const bool as_state = b.out_state[prob] != 0;
+    double *o64 = (double *)member_ptr(b.out[prob], b.ms);
+    T *ot = (T *)member_ptr(b.out[prob], b.ms);
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
         const int p = e / nx, i = e - p * nx;
         const int64_t la = 2 * (pair0 + p), lb = la + 1;
         const double2 v = z[e];
-        if (la < nlines) out[la * nx + i] = v.x;
-        if (lb < nlines) out[lb * nx + i] = v.y;
+        if (as_state) {
+            if (la < nlines) ot[la * nx + i] = (T)v.x;
+            if (lb < nlines) ot[lb * nx + i] = (T)v.y;
+        } else {
+            if (la < nlines) o64[la * nx + i] = v.x;
+            if (lb < nlines) o64[lb * nx + i] = v.y;
+        }
     }
 }
 
 // ---- z direction: complex lines of stride nxh, a tile of tk modes per block ----
-__global__ void __launch_bounds__(256) k_fft_z(Dims d, FftPlan pl, const double2 *tw, double2 *data, int tk,
-                                               int inverse) {
+__global__ void __launch_bounds__(256) k_fft_z(Dims d, FftPlan pl, const double2 *tw, double2 *spec, int64_t nspec,
+                                               int tk, int inverse, size_t ms) {
     extern __shared__ double2 sm[];
+    double2 *data = member_ptr(spec, ms) + blockIdx.y * nspec;
     const int nz = d.nz, nxh = d.nxh;
     const int tiles = (nxh + tk - 1) / tk;
     const int j = blockIdx.x / tiles;
     const int kx0 = (blockIdx.x - j * tiles) * tk;
-    double2 *b[2] = {sm, sm + tk * nz};
+    double2 *bf[2] = {sm, sm + tk * nz};
     double2 *base = data + (int64_t)j * nz * nxh;
     for (int e = threadIdx.x; e < tk * nz; e += blockDim.x) {
         const int t = e % tk, k = e / tk;
         const int kx = kx0 + t;
-        b[0][t * nz + k] = (kx < nxh) ? base[(int64_t)k * nxh + kx] : make_double2(0.0, 0.0);
+        bf[0][t * nz + k] = (kx < nxh) ? base[(int64_t)k * nxh + kx] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    const double2 *z = b[lds_fft(b[0], b[1], nz, tk, pl, tw, inverse != 0)];
+    const double2 *z = bf[lds_fft(bf[0], bf[1], nz, tk, pl, tw, inverse != 0)];
     for (int e = threadIdx.x; e < tk * nz; e += blockDim.x) {
         const int t = e % tk, k = e / tk;
         const int kx = kx0 + t;
@@ -195,8 +241,16 @@ __global__ void __launch_bounds__(256) k_fft_z(Dims d, FftPlan pl, const double2
 // ---- y direction: one Thomas solve per (kx, kz) mode ----
 // (lo_j psi_{j-1} + (di_j - kx^2 - kz^2) psi_j + up_j psi_{j+1}) = rhs_j / (nx nz)
 // kind 0: zero-flux walls, mode (0,0) pinned at row 0 then shifted to zero
-// volume mean; kind 1: zero wall value at the half-cell distance.
-__global__ void __launch_bounds__(256) k_thomas_modes(Dims d, Tables tb, double2 *spec, double *cpr, int kind) {
+// volume mean; kind 1: zero wall value at the half-cell distance.  Rows are
+// prefetched kPf ahead so the elimination chain does not wait on memory.
+constexpr int kPf = 4;
+
+__global__ void __launch_bounds__(256) k_thomas_modes(Dims d, Tables tb, PoissonBatch b, double2 *spec_all,
+                                                     double *cpr_all, int64_t nspec) {
+    const int prob = blockIdx.y;
+    const int kind = b.kind[prob];
+    double2 *spec = member_ptr(spec_all, b.ms) + prob * nspec;
+    double *cpr = member_ptr(cpr_all, b.ms) + prob * nspec;
     const int64_t nmodes = (int64_t)d.nxh * d.nz;
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= nmodes) return;
@@ -207,46 +261,73 @@ __global__ void __launch_bounds__(256) k_thomas_modes(Dims d, Tables tb, double2
     const bool pin = (kind == 0 && kx == 0 && kz == 0);
     double cprev = 0.0;
     double2 dprev = make_double2(0.0, 0.0);
-    for (int j = 0; j < M; ++j) {
-        const int64_t o = (int64_t)j * nmodes + m;
-        const double aa = tb.lyc_lo[j], cc = tb.lyc_up[j];
-        double lo = (j > 0) ? aa : 0.0;
-        double up = (j < M - 1) ? cc : 0.0;
-        double di = -(lo + up);
-        if (kind == 1) {
-            if (j == 0) di -= aa;
-            if (j == M - 1) di -= cc;
+    double2 buf[kPf];
+#pragma unroll
+    for (int p = 0; p < kPf; ++p) buf[p] = (p < M) ? spec[p * nmodes + m] : make_double2(0.0, 0.0);
+    for (int jb = 0; jb < M; jb += kPf) {
+#pragma unroll
+        for (int p = 0; p < kPf; ++p) {
+            const int j = jb + p;
+            if (j < M) {
+                double2 rhs = buf[p];
+                if (j + kPf < M) buf[p] = spec[(int64_t)(j + kPf) * nmodes + m];
+                const double aa = tb.lyc_lo[j], cc = tb.lyc_up[j];
+                double lo = (j > 0) ? aa : 0.0;
+                double up = (j < M - 1) ? cc : 0.0;
+                double di = -(lo + up);
+                if (kind == 1) {
+                    if (j == 0) di -= aa;
+                    if (j == M - 1) di -= cc;
+                }
+                double B = di - k2;
+                rhs.x *= scale;
+                rhs.y *= scale;
+                if (pin && j == 0) {
+                    B = 1.0;
+                    up = 0.0;
+                    rhs = make_double2(0.0, 0.0);
+                }
+                const double den = B - lo * cprev;
+                const double cj = up / den;
+                const double2 dj = make_double2((rhs.x - lo * dprev.x) / den, (rhs.y - lo * dprev.y) / den);
+                const int64_t o = (int64_t)j * nmodes + m;
+                spec[o] = dj;
+                cpr[o] = cj;
+                cprev = cj;
+                dprev = dj;
+            }
         }
-        double B = di - k2;
-        double2 rhs = spec[o];
-        rhs.x *= scale;
-        rhs.y *= scale;
-        if (pin && j == 0) {
-            B = 1.0;
-            up = 0.0;
-            rhs = make_double2(0.0, 0.0);
-        }
-        const double den = B - lo * cprev;
-        const double cj = up / den;
-        const double2 dj = make_double2((rhs.x - lo * dprev.x) / den, (rhs.y - lo * dprev.y) / den);
-        spec[o] = dj;
-        cpr[o] = cj;
-        cprev = cj;
-        dprev = dj;
     }
     double2 xn = make_double2(0.0, 0.0);
     double sx = 0.0, sy = 0.0, vol = 0.0;
-    for (int j = M - 1; j >= 0; --j) {
-        const int64_t o = (int64_t)j * nmodes + m;
-        const double cj = cpr[o];
-        const double2 dj = spec[o];
-        const double2 xj = make_double2(dj.x - cj * xn.x, dj.y - cj * xn.y);
-        spec[o] = xj;
-        xn = xj;
-        if (pin) {
-            sx += xj.x * tb.dn[j];
-            sy += xj.y * tb.dn[j];
-            vol += tb.dn[j];
+    double2 bd[kPf];
+    double bc[kPf];
+#pragma unroll
+    for (int p = 0; p < kPf; ++p) {
+        const int j = M - 1 - p;
+        bd[p] = (j >= 0) ? spec[(int64_t)j * nmodes + m] : make_double2(0.0, 0.0);
+        bc[p] = (j >= 0) ? cpr[(int64_t)j * nmodes + m] : 0.0;
+    }
+    for (int jb = M - 1; jb >= 0; jb -= kPf) {
+#pragma unroll
+        for (int p = 0; p < kPf; ++p) {
+            const int j = jb - p;
+            if (j >= 0) {
+                const double2 dj = bd[p];
+                const double cj = bc[p];
+                if (j - kPf >= 0) {
+                    bd[p] = spec[(int64_t)(j - kPf) * nmodes + m];
+                    bc[p] = cpr[(int64_t)(j - kPf) * nmodes + m];
+                }
+                const double2 xj = make_double2(dj.x - cj * xn.x, dj.y - cj * xn.y);
+                spec[(int64_t)j * nmodes + m] = xj;
+                xn = xj;
+                if (pin) {
+                    sx += xj.x * tb.dn[j];
+                    sy += xj.y * tb.dn[j];
+                    vol += tb.dn[j];
+                }
+            }
         }
     }
     if (pin) {
@@ -261,46 +342,54 @@ __global__ void __launch_bounds__(256) k_thomas_modes(Dims d, Tables tb, double2
     }
 }
 
-inline int pairs_per_block(int nx) { return nx >= 1024 ? 1 : 1024 / nx; }
-inline int modes_per_tile(int nz, int nxh) {
-    int t = nz >= 1024 ? 1 : 1024 / nz;
-    if (t > 16) t = 16;
+inline int pairs_per_block(int nx, int points) { return nx >= points ? 1 : points / nx; }
+inline int modes_per_tile(int nz, int nxh, int points) {
+    int t = nz >= points ? 1 : points / nz;
+    if (t > 32) t = 32;
     if (t > nxh) t = nxh;
     return t;
 }
 
 }  // namespace
 
-hipError_t launch_poisson(nspnp_state *s, int kind, const double *rhs, double *out) {
+// All members of the handle are solved when b.ms is the member stride;
+// caller-owned arrays (b.ms = 0) are solved for member 0 only.
+hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
     const Dims &d = s->d;
+    const int nmem = b.ms ? s->nmem : 1;
     const int64_t nlines = (int64_t)d.M * d.nz;
-    const int ppb = pairs_per_block(d.nx);
+    const int64_t nspec = (int64_t)d.nxh * d.nz * d.M;
+    const int ppb = pairs_per_block(d.nx, s->tiles.fftx);
     const int64_t npairs = (nlines + 1) / 2;
-    const unsigned gx = (unsigned)((npairs + ppb - 1) / ppb);
+    const dim3 gx((unsigned)((npairs + ppb - 1) / ppb), (unsigned)b.nprob, (unsigned)nmem);
     const size_t ldsx = 2 * (size_t)ppb * d.nx * sizeof(double2);
     {
         ProfScope prof_(s, K_FFTX_FWD);
-        k_fft_x_r2c<<<gx, 256, ldsx, s->stream>>>(d, s->planx, s->tb.twx, rhs, s->spec, ppb);
+        if (s->fp64) k_fft_x_r2c<double><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb);
+        else k_fft_x_r2c<float><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb);
     }
-    const int tk = modes_per_tile(d.nz, d.nxh);
-    const unsigned gz = (unsigned)(d.M * ((d.nxh + tk - 1) / tk));
+    const int tk = modes_per_tile(d.nz, d.nxh, s->tiles.fftz);
+    const dim3 gz((unsigned)(d.M * ((d.nxh + tk - 1) / tk)), (unsigned)b.nprob, (unsigned)nmem);
     const size_t ldsz = 2 * (size_t)tk * d.nz * sizeof(double2);
     {
         ProfScope prof_(s, K_FFTZ_FWD);
-        k_fft_z<<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, tk, 0);
+        k_fft_z<<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 0, b.ms);
     }
     const int64_t nmodes = (int64_t)d.nxh * d.nz;
     {
         ProfScope prof_(s, K_THOMAS);
-        k_thomas_modes<<<(unsigned)((nmodes + 255) / 256), 256, 0, s->stream>>>(d, s->tb, s->spec, s->cpr, kind);
+        const int tt = s->tiles.thomas;
+        const dim3 gt((unsigned)((nmodes + tt - 1) / tt), (unsigned)b.nprob, (unsigned)nmem);
+        k_thomas_modes<<<gt, tt, 0, s->stream>>>(d, s->tb, b, s->spec, s->cpr, nspec);
     }
     {
         ProfScope prof_(s, K_FFTZ_INV);
-        k_fft_z<<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, tk, 1);
+        k_fft_z<<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 1, b.ms);
     }
     {
         ProfScope prof_(s, K_FFTX_INV);
-        k_fft_x_c2r<<<gx, 256, ldsx, s->stream>>>(d, s->planx, s->tb.twx, s->spec, out, ppb);
+        if (s->fp64) k_fft_x_c2r<double><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppb);
+        else k_fft_x_c2r<float><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppb);
     }
     return hipGetLastError();
 }

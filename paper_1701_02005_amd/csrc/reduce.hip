@@ -3,6 +3,8 @@
 // Sec. II, ion fluxes through the y-faces of Fig. 1, ion contents, kinetic
 // energy, divergence).  Every reduction runs in a fixed order (fixed launch
 // shape, fixed LDS tree) so results are bitwise reproducible.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace nspnp {
@@ -57,8 +59,10 @@ constexpr int kDtBlocks = 1024;
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads) k_dt_partial(Dims d, Tables tb, const T *u, const T *v,
                                                             const T *w, const T *cp, const T *cm,
-                                                            double *part) {
+                                                            double *part, size_t ms) {
     __shared__ double s_r[kRedThreads], s_c[kRedThreads];
+    u = member_ptr(u, ms); v = member_ptr(v, ms); w = member_ptr(w, ms);
+    cp = member_ptr(cp, ms); cm = member_ptr(cm, ms); part = member_ptr(part, ms);
     double rate = 0.0, cmax = 0.0;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < d.n; q += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(q % d.nx);
@@ -91,9 +95,12 @@ __global__ void __launch_bounds__(kRedThreads) k_dt_partial(Dims d, Tables tb, c
     }
 }
 
-__global__ void __launch_bounds__(kRedThreads) k_dt_final(int nparts, const double *part, Phys ph, Dims d,
-                                                          double *clock) {
+__global__ void __launch_bounds__(kRedThreads) k_dt_final(int nparts, const double *part, const Phys *phys,
+                                                          Dims d, double *clock, size_t ms) {
     __shared__ double s_r[kRedThreads], s_c[kRedThreads];
+    part = member_ptr(part, ms);
+    clock = member_ptr(clock, ms);
+    const Phys ph = *member_ptr(phys, ms);
     double rate = 0.0, cmax = 0.0;
     for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
         rate = fmax(rate, part[2 * b]);
@@ -116,7 +123,7 @@ __global__ void __launch_bounds__(kRedThreads) k_dt_final(int nparts, const doub
         if (s_c[0] > 0.0) dt = fmin(dt, 2.0 * ph.debye * ph.debye * rs / s_c[0]);
         const double nu_min = re < rs ? re : rs;
         dt = fmin(dt, nu_min / (4.0 / (d.dx * d.dx) + 4.0 / (d.dz * d.dz)));
-        clock[1] = dt;
+        if (ph.adaptive != 0.0) clock[1] = dt;
     }
 }
 
@@ -127,10 +134,13 @@ __global__ void __launch_bounds__(kRedThreads) k_dt_final(int nparts, const doub
 constexpr int kPlaneQ = 10;
 
 template <typename T>
-__global__ void __launch_bounds__(kRedThreads) k_plane(Dims d, Phys ph, Tables tb, const T *u, const T *v,
+__global__ void __launch_bounds__(kRedThreads) k_plane(Dims d, const Phys *phys, Tables tb, const T *u, const T *v,
                                                        const T *w, const T *cp, const T *cm, const T *phi,
-                                                       double *out) {
+                                                       double *out, size_t ms) {
     __shared__ double s[kPlaneQ][kRedThreads];
+    u = member_ptr(u, ms); v = member_ptr(v, ms); w = member_ptr(w, ms);
+    cp = member_ptr(cp, ms); cm = member_ptr(cm, ms); phi = member_ptr(phi, ms); out = member_ptr(out, ms);
+    const Phys ph = *member_ptr(phys, ms);
     const int j = blockIdx.x;
     const int64_t pl = d.plane;
     const int64_t base = (int64_t)j * pl;
@@ -181,6 +191,45 @@ __global__ void __launch_bounds__(kRedThreads) k_plane(Dims d, Phys ph, Tables t
     if (threadIdx.x < kPlaneQ) out[(int64_t)j * kPlaneQ + threadIdx.x] = s[threadIdx.x][0];
 }
 
+// time sums (weight alp dt) of the plane means of u, c+ - c- and phi per row
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) k_stats(Dims d, const T *u, const T *cp, const T *cm, const T *phi,
+                                                       const double *clock, double *stats, double alp, size_t ms) {
+    __shared__ double s[3][kRedThreads];
+    u = member_ptr(u, ms); cp = member_ptr(cp, ms); cm = member_ptr(cm, ms); phi = member_ptr(phi, ms);
+    clock = member_ptr(clock, ms);
+    stats = member_ptr(stats, ms);
+    const int j = blockIdx.x;
+    const int64_t base = (int64_t)j * d.plane;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int64_t e = threadIdx.x; e < d.plane; e += blockDim.x) {
+        const int64_t q = base + e;
+        a0 += (double)u[q];
+        a1 += (double)cp[q] - (double)cm[q];
+        a2 += (double)phi[q];
+    }
+    s[0][threadIdx.x] = a0;
+    s[1][threadIdx.x] = a1;
+    s[2][threadIdx.x] = a2;
+    __syncthreads();
+    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int qq = 0; qq < 3; ++qq) s[qq][threadIdx.x] += s[qq][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double wgt = alp * clock[1];
+        const double inv = 1.0 / (double)d.plane;
+        for (int qq = 0; qq < 3; ++qq) stats[3 * j + qq] += wgt * s[qq][0] * inv;
+        if (j == 0) stats[3 * d.M] += wgt;
+    }
+}
+
+__global__ void k_fill(double *p, int64_t n, double v, size_t ms) {
+    p = member_ptr(p, ms);
+    for (int64_t q = threadIdx.x; q < n; q += blockDim.x) p[q] = v;
+}
+
 inline dim3 grid1(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
 
 }  // namespace
@@ -213,27 +262,50 @@ hipError_t launch_shift_conc(nspnp_state *s, double mp, double mm) {
 
 hipError_t launch_dt(nspnp_state *s) {
     ProfScope prof_(s, K_DT);
+    const unsigned nb = (unsigned)std::min<int64_t>(kDtBlocks, (s->d.n + kRedThreads - 1) / kRedThreads);
+    const dim3 g(nb, 1, (unsigned)s->nmem);
     if (s->fp64)
-        k_dt_partial<double><<<kDtBlocks, kRedThreads, 0, s->stream>>>(
+        k_dt_partial<double><<<g, kRedThreads, 0, s->stream>>>(
             s->d, s->tb, (const double *)s->f[0], (const double *)s->f[1], (const double *)s->f[2],
-            (const double *)s->f[3], (const double *)s->f[4], s->red);
+            (const double *)s->f[3], (const double *)s->f[4], s->red, s->mstride);
     else
-        k_dt_partial<float><<<kDtBlocks, kRedThreads, 0, s->stream>>>(
+        k_dt_partial<float><<<g, kRedThreads, 0, s->stream>>>(
             s->d, s->tb, (const float *)s->f[0], (const float *)s->f[1], (const float *)s->f[2],
-            (const float *)s->f[3], (const float *)s->f[4], s->red);
-    k_dt_final<<<1, kRedThreads, 0, s->stream>>>(kDtBlocks, s->red, s->ph, s->d, s->clock);
+            (const float *)s->f[3], (const float *)s->f[4], s->red, s->mstride);
+    k_dt_final<<<dim3(1, 1, (unsigned)s->nmem), kRedThreads, 0, s->stream>>>((int)nb, s->red, s->d_phys, s->d,
+                                                                             s->clock, s->mstride);
     return hipGetLastError();
 }
 
+// per-plane sums of every member (results in each member's dev_out copy)
 hipError_t launch_plane_sums(nspnp_state *s, int /*what*/, double *dev_out) {
+    const dim3 g((unsigned)s->d.M, 1, (unsigned)s->nmem);
     if (s->fp64)
-        k_plane<double><<<s->d.M, kRedThreads, 0, s->stream>>>(
-            s->d, s->ph, s->tb, (const double *)s->f[0], (const double *)s->f[1], (const double *)s->f[2],
-            (const double *)s->f[3], (const double *)s->f[4], (const double *)s->f[5], dev_out);
+        k_plane<double><<<g, kRedThreads, 0, s->stream>>>(
+            s->d, s->d_phys, s->tb, (const double *)s->f[0], (const double *)s->f[1], (const double *)s->f[2],
+            (const double *)s->f[3], (const double *)s->f[4], (const double *)s->f[5], dev_out, s->mstride);
     else
-        k_plane<float><<<s->d.M, kRedThreads, 0, s->stream>>>(
-            s->d, s->ph, s->tb, (const float *)s->f[0], (const float *)s->f[1], (const float *)s->f[2],
-            (const float *)s->f[3], (const float *)s->f[4], (const float *)s->f[5], dev_out);
+        k_plane<float><<<g, kRedThreads, 0, s->stream>>>(
+            s->d, s->d_phys, s->tb, (const float *)s->f[0], (const float *)s->f[1], (const float *)s->f[2],
+            (const float *)s->f[3], (const float *)s->f[4], (const float *)s->f[5], dev_out, s->mstride);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_reset(nspnp_state *s) {
+    k_fill<<<dim3(1, 1, (unsigned)s->nmem), 256, 0, s->stream>>>(s->stats, 3 * (int64_t)s->d.M + 2, 0.0, s->mstride);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_accum(nspnp_state *s, double alp) {
+    const dim3 g((unsigned)s->d.M, 1, (unsigned)s->nmem);
+    if (s->fp64)
+        k_stats<double><<<g, kRedThreads, 0, s->stream>>>(s->d, (const double *)s->f[0], (const double *)s->f[3],
+                                                          (const double *)s->f[4], (const double *)s->f[5], s->clock,
+                                                          s->stats, alp, s->mstride);
+    else
+        k_stats<float><<<g, kRedThreads, 0, s->stream>>>(s->d, (const float *)s->f[0], (const float *)s->f[3],
+                                                         (const float *)s->f[4], (const float *)s->f[5], s->clock,
+                                                         s->stats, alp, s->mstride);
     return hipGetLastError();
 }
 

@@ -36,7 +36,8 @@ __device__ __forceinline__ Idx make_idx(const Dims &d, int64_t q) {
 
 struct ExplicitArgs {
     Dims d;
-    Phys ph;
+    const Phys *phys;
+    size_t ms;
     Tables tb;
     Stage st;
     const void *u, *v, *w, *cp, *cm, *phi, *p;
@@ -47,14 +48,41 @@ struct ExplicitArgs {
     int mode;  // 0: substep (H update + CN right-hand sides); 1: H to dbg only
 };
 
+__device__ __forceinline__ void shift_explicit(ExplicitArgs &a) {
+    const size_t ms = a.ms;
+    a.phys = member_ptr(a.phys, ms);
+    a.u = member_ptr(a.u, ms); a.v = member_ptr(a.v, ms); a.w = member_ptr(a.w, ms);
+    a.cp = member_ptr(a.cp, ms); a.cm = member_ptr(a.cm, ms); a.phi = member_ptr(a.phi, ms); a.p = member_ptr(a.p, ms);
+    for (int f = 0; f < 5; ++f) { a.h[f] = member_ptr(a.h[f], ms); a.r[f] = member_ptr(a.r[f], ms); }
+    a.clock = member_ptr(a.clock, ms);
+}
+
 // Convection, horizontal diffusion, Coulomb force and ion transport at one
 // cell, then the Crank-Nicolson right-hand side
 //   r = dt [gam H^k + zet H^{k-1} - alp G p + alp nu L_y q].
+// Grid: x = 256-cell chunks of one (x, z) plane, y = the cell row j, so the
+// row tables are uniform per block.  Each field's H and r are computed and
+// stored before the next field is started to keep register pressure low.
 template <typename T>
-__global__ void __launch_bounds__(256) k_explicit(ExplicitArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_explicit(ExplicitArgs a) {
+    shift_explicit(a);
+    const Phys ph = *a.phys;
     const Dims &d = a.d;
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= d.n) return;
+    const int nx = d.nx, nz = d.nz, M = d.M;
+    const int pl = (int)d.plane;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= pl) return;
+    const int j = blockIdx.y;
+    const int k = e / nx;
+    const int i = e - k * nx;
+    const int ip = (i + 1 == nx) ? 0 : i + 1, im = (i == 0) ? nx - 1 : i - 1;
+    const int kp = (k + 1 == nz) ? 0 : k + 1, km = (k == 0) ? nz - 1 : k - 1;
+    const int q = j * pl + e;
+    const int xp = q - i + ip, xm = q - i + im;
+    const int zp = q + (kp - k) * nx, zm = q + (km - k) * nx;
+    const bool has_up = (j + 1 < M), has_dn = (j > 0);
+    const int yp = q + pl, ym = q - pl;
+
     const T *__restrict__ u = (const T *)a.u;
     const T *__restrict__ v = (const T *)a.v;
     const T *__restrict__ w = (const T *)a.w;
@@ -62,174 +90,147 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs a) {
     const T *__restrict__ cm = (const T *)a.cm;
     const T *__restrict__ phi = (const T *)a.phi;
     const T *__restrict__ p = (const T *)a.p;
-    const Idx x = make_idx(d, q);
-    const int j = x.j, M = d.M;
-    const int64_t pl = d.plane;
-    const bool has_up = (j + 1 < M), has_dn = (j > 0);
-    const int64_t yp = q + pl, ym = q - pl;
-    const T half = T(0.5);
+
+    const T half = T(0.5), two = T(2);
     const T idx_ = T(1.0 / d.dx), idz_ = T(1.0 / d.dz);
-    const T dnj = T(a.tb.dn[j]);
-    const T idn = T(1) / dnj;
     const T ix2 = idx_ * idx_, iz2 = idz_ * idz_;
+    const T idn = T(a.tb.idn[j]);
+    const T idcb = T(a.tb.idc[j]), idct = T(a.tb.idc[j + 1]);
+    const T kf = T(ph.kf), ire = T(ph.ire), kd = T(ph.kd), e0 = T(ph.e0);
+    const int mode = a.mode;
+    const T dt = T(a.clock[1]);
+    const T gam = T(a.st.gam), zet = T(a.st.zet), alp = T(a.st.alp);
+    const bool use_old = (a.st.k > 0) && mode == 0;
+    const bool keep = (a.st.k < 2) && mode == 0;
+
+    // store H (debug) or H and the Crank-Nicolson right-hand side (substep)
+    auto emit = [&](int f, T hval, T gp, T nu_ly) {
+        if (mode == 1) {
+            a.dbg[f][q] = (double)hval;
+            return;
+        }
+        T *__restrict__ hb = (T *)a.h[f];
+        const T hold = use_old ? hb[q] : T(0);
+        a.r[f][q] = (double)(dt * (gam * hval + zet * hold - alp * gp + alp * nu_ly));
+        if (keep) hb[q] = hval;
+    };
 
     const T uc = u[q], vc = v[q], wc = w[q];
+    const T rho0 = cp[q] - cm[q];
+    const T ph0 = phi[q];
 
     // ---------------- u on the x-face ----------------
-    T hu;
     {
-        const T uxp = u[x.xp], uxm = u[x.xm];
+        const T uxp = u[xp], uxm = u[xm], uzp = u[zp], uzm = u[zm];
         const T a1 = half * (uxp + uc), a2 = half * (uc + uxm);
         const T cx = (a1 * a1 - a2 * a2) * idx_;
-        T cy_t = T(0), cy_b = T(0);
-        if (has_up) cy_t = half * (v[yp] + v[yp - x.i + x.im]) * half * (u[yp] + uc);
-        if (has_dn) cy_b = half * (vc + v[x.xm]) * half * (uc + u[ym]);
-        const T cy = (cy_t - cy_b) * idn;
-        const T wf = half * (w[x.zp] + w[x.zp - x.i + x.im]);
-        const T wb = half * (wc + w[x.xm]);
-        const T cz = (wf * half * (u[x.zp] + uc) - wb * half * (uc + u[x.zm])) * idz_;
-        const T lap = (uxp - T(2) * uc + uxm) * ix2 + (u[x.zp] - T(2) * uc + u[x.zm]) * iz2;
-        const T rho0 = cp[q] - cm[q], rhox = cp[x.xm] - cm[x.xm];
-        const T f = T(a.ph.kf) * half * (rho0 + rhox) * (phi[q] - phi[x.xm]) * idx_;
-        hu = -(cx + cy + cz) + T(a.ph.ire) * lap + f;
+        T flux_t = T(0), flux_b = T(0), ut = T(ph.u_top), ub = T(ph.u_bot);
+        if (has_up) {
+            ut = u[yp];
+            flux_t = half * (v[yp] + v[yp - i + im]) * half * (ut + uc);
+        }
+        if (has_dn) {
+            ub = u[ym];
+            flux_b = half * (vc + v[xm]) * half * (uc + ub);
+        }
+        const T cy = (flux_t - flux_b) * idn;
+        const T wf = half * (w[zp] + w[zp - i + im]);
+        const T wb = half * (wc + w[xm]);
+        const T cz = (wf * half * (uzp + uc) - wb * half * (uc + uzm)) * idz_;
+        const T lap = (uxp - two * uc + uxm) * ix2 + (uzp - two * uc + uzm) * iz2;
+        const T rhox = cp[xm] - cm[xm];
+        const T f = kf * half * (rho0 + rhox) * (ph0 - phi[xm]) * idx_;
+        const T ly = ((ut - uc) * idct - (uc - ub) * idcb) * idn;
+        emit(0, -(cx + cy + cz) + ire * lap + f, (p[q] - p[xm]) * idx_, ire * ly);
     }
     // ---------------- w on the z-face ----------------
-    T hw;
     {
-        const T wzp = w[x.zp], wzm = w[x.zm];
+        const T wzp = w[zp], wzm = w[zm], wxp = w[xp], wxm = w[xm];
         const T a1 = half * (wzp + wc), a2 = half * (wc + wzm);
         const T cz = (a1 * a1 - a2 * a2) * idz_;
-        const T ur = half * (u[x.xp] + u[x.zm - x.i + x.ip]);
-        const T ul = half * (uc + u[x.zm]);
-        const T cx = (ur * half * (w[x.xp] + wc) - ul * half * (wc + w[x.xm])) * idx_;
-        T cy_t = T(0), cy_b = T(0);
-        if (has_up) cy_t = half * (v[yp] + v[yp + (x.km - x.k) * (int64_t)d.nx]) * half * (w[yp] + wc);
-        if (has_dn) cy_b = half * (vc + v[x.zm]) * half * (wc + w[ym]);
-        const T cy = (cy_t - cy_b) * idn;
-        const T lap = (w[x.xp] - T(2) * wc + w[x.xm]) * ix2 + (wzp - T(2) * wc + wzm) * iz2;
-        const T rho0 = cp[q] - cm[q], rhoz = cp[x.zm] - cm[x.zm];
-        const T f = T(a.ph.kf) * half * (rho0 + rhoz) * (phi[q] - phi[x.zm]) * idz_;
-        hw = -(cx + cy + cz) + T(a.ph.ire) * lap + f;
+        const T ur = half * (u[xp] + u[zm - i + ip]);
+        const T ul = half * (uc + u[zm]);
+        const T cx = (ur * half * (wxp + wc) - ul * half * (wc + wxm)) * idx_;
+        T flux_t = T(0), flux_b = T(0), wt = T(0), wb = T(0);
+        if (has_up) {
+            wt = w[yp];
+            flux_t = half * (v[yp] + v[yp + (km - k) * nx]) * half * (wt + wc);
+        }
+        if (has_dn) {
+            wb = w[ym];
+            flux_b = half * (vc + v[zm]) * half * (wc + wb);
+        }
+        const T cy = (flux_t - flux_b) * idn;
+        const T lap = (wxp - two * wc + wxm) * ix2 + (wzp - two * wc + wzm) * iz2;
+        const T rhoz = cp[zm] - cm[zm];
+        const T f = kf * half * (rho0 + rhoz) * (ph0 - phi[zm]) * idz_;
+        const T ly = ((wt - wc) * idct - (wc - wb) * idcb) * idn;
+        emit(2, -(cx + cy + cz) + ire * lap + f, (p[q] - p[zm]) * idz_, ire * ly);
     }
     // ---------------- v on the bottom y-face of row j ----------------
-    T hv = T(0);
     if (has_dn) {
-        const T dcj = T(a.tb.dc[j]);
-        const T idc = T(1) / dcj;
+        const T vwl = T(a.tb.vwl[j]), vwu = T(a.tb.vwu[j]);
+        const T idn_lo = T(a.tb.idn[j - 1]);
         const T vtop = has_up ? v[yp] : T(0);
         const T vbot = (j > 1) ? v[ym] : T(0);
         const T a1 = half * (vtop + vc), a2 = half * (vc + vbot);
-        const T cy = (a1 * a1 - a2 * a2) * idc;
-        const T wl = T(a.tb.dn[j - 1]), wu = dnj;
-        const T i2dc = T(1) / (T(2) * dcj);
-        const T ur = (u[ym - x.i + x.ip] * wl + u[x.xp] * wu) * i2dc;
-        const T ul = (u[ym] * wl + uc * wu) * i2dc;
-        const T cx = (ur * half * (v[x.xp] + vc) - ul * half * (vc + v[x.xm])) * idx_;
-        const T wf = (w[ym + (x.kp - x.k) * (int64_t)d.nx] * wl + w[x.zp] * wu) * i2dc;
-        const T wb = (w[ym] * wl + wc * wu) * i2dc;
-        const T cz = (wf * half * (v[x.zp] + vc) - wb * half * (vc + v[x.zm])) * idz_;
-        const T lap = (v[x.xp] - T(2) * vc + v[x.xm]) * ix2 + (v[x.zp] - T(2) * vc + v[x.zm]) * iz2;
-        const T rho0 = cp[q] - cm[q], rhoy = cp[ym] - cm[ym];
-        const T ey = T(a.ph.e0) + (phi[q] - phi[ym]) * idc;
-        const T f = T(a.ph.kf) * half * (rho0 + rhoy) * ey;
-        hv = -(cx + cy + cz) + T(a.ph.ire) * lap + f;
+        const T cy = (a1 * a1 - a2 * a2) * idcb;
+        const T ur = u[ym - i + ip] * vwl + u[xp] * vwu;
+        const T ul = u[ym] * vwl + uc * vwu;
+        const T vxp = v[xp], vxm = v[xm], vzp = v[zp], vzm = v[zm];
+        const T cx = (ur * half * (vxp + vc) - ul * half * (vc + vxm)) * idx_;
+        const T wf = w[ym + (kp - k) * nx] * vwl + w[zp] * vwu;
+        const T wbk = w[ym] * vwl + wc * vwu;
+        const T cz = (wf * half * (vzp + vc) - wbk * half * (vc + vzm)) * idz_;
+        const T lap = (vxp - two * vc + vxm) * ix2 + (vzp - two * vc + vzm) * iz2;
+        const T rhoy = cp[ym] - cm[ym];
+        const T ey = e0 + (ph0 - phi[ym]) * idcb;
+        const T f = kf * half * (rho0 + rhoy) * ey;
+        const T ly = ((vtop - vc) * idn - (vc - vbot) * idn_lo) * idcb;
+        emit(1, -(cx + cy + cz) + ire * lap + f, (p[q] - p[ym]) * idcb, ire * ly);
+    } else {
+        emit(1, T(0), T(0), T(0));
+        if (mode == 0) a.r[1][q] = 0.0;
     }
     // ---------------- ions at the cell centre ----------------
-    T hc[2];
     {
-        const T kd = T(a.ph.kd), e0 = T(a.ph.e0);
-        const T uxp = u[x.xp], wzp = w[x.zp];
-        const T ph0 = phi[q];
-        const T gx_r = (phi[x.xp] - ph0) * idx_, gx_l = (ph0 - phi[x.xm]) * idx_;
-        const T gz_f = (phi[x.zp] - ph0) * idz_, gz_b = (ph0 - phi[x.zm]) * idz_;
-        T ey_t = T(0), ey_b = T(0);
-        if (has_up) ey_t = e0 + (phi[yp] - ph0) / T(a.tb.dc[j + 1]);
-        if (has_dn) ey_b = e0 + (ph0 - phi[ym]) / T(a.tb.dc[j]);
+        const T uxp = u[xp], wzp = w[zp];
+        const T gx_r = (phi[xp] - ph0) * idx_, gx_l = (ph0 - phi[xm]) * idx_;
+        const T gz_f = (phi[zp] - ph0) * idz_, gz_b = (ph0 - phi[zm]) * idz_;
+        const T ey_t = has_up ? e0 + (phi[yp] - ph0) * idct : T(0);
+        const T ey_b = has_dn ? e0 + (ph0 - phi[ym]) * idcb : T(0);
         const T vt = has_up ? v[yp] : T(0);
 #pragma unroll
         for (int sp = 0; sp < 2; ++sp) {
             const T *__restrict__ c = sp == 0 ? cp : cm;
             const T zs = sp == 0 ? T(1) : T(-1);
-            const T cc = c[q], cxp = c[x.xp], cxm = c[x.xm], czp = c[x.zp], czm = c[x.zm];
+            const T cc = c[q], cxp = c[xp], cxm = c[xm], czp = c[zp], czm = c[zm];
             const T fxr = half * (cxp + cc), fxl = half * (cc + cxm);
             const T fzf = half * (czp + cc), fzb = half * (cc + czm);
             const T ax = (uxp * fxr - uc * fxl) * idx_;
             const T az = (wzp * fzf - wc * fzb) * idz_;
-            T at = T(0), ab = T(0), mt = T(0), mb = T(0);
+            T at = T(0), ab = T(0), mt = T(0), mb = T(0), dft = T(0), dfb = T(0);
             if (has_up) {
-                const T fy = half * (c[yp] + cc);
+                const T cu = c[yp];
+                const T fy = half * (cu + cc);
                 at = vt * fy;
                 mt = fy * ey_t;
+                dft = (cu - cc) * idct;
             }
             if (has_dn) {
-                const T fy = half * (cc + c[ym]);
+                const T cd = c[ym];
+                const T fy = half * (cc + cd);
                 ab = vc * fy;
                 mb = fy * ey_b;
+                dfb = (cc - cd) * idcb;
             }
             const T ay = (at - ab) * idn;
             const T mx = (fxr * gx_r - fxl * gx_l) * idx_;
             const T mz = (fzf * gz_f - fzb * gz_b) * idz_;
             const T my = (mt - mb) * idn;
-            const T dxx = (cxp - T(2) * cc + cxm) * ix2 + (czp - T(2) * cc + czm) * iz2;
-            hc[sp] = -(ax + ay + az) + kd * (dxx + zs * (mx + my + mz));
+            const T dxx = (cxp - two * cc + cxm) * ix2 + (czp - two * cc + czm) * iz2;
+            emit(3 + sp, -(ax + ay + az) + kd * (dxx + zs * (mx + my + mz)), T(0), kd * (dft - dfb) * idn);
         }
-    }
-
-    if (a.mode == 1) {
-        a.dbg[0][q] = (double)hu;
-        a.dbg[1][q] = (double)hv;
-        a.dbg[2][q] = (double)hw;
-        a.dbg[3][q] = (double)hc[0];
-        a.dbg[4][q] = (double)hc[1];
-        return;
-    }
-
-    // ---------------- Crank-Nicolson right-hand sides ----------------
-    const T dt = T(a.clock[1]);
-    const T gam = T(a.st.gam), zet = T(a.st.zet), alp = T(a.st.alp);
-    const bool use_old = (a.st.k > 0);
-    const bool keep = (a.st.k < 2);
-    const T H[5] = {hu, hv, hw, hc[0], hc[1]};
-    // L_y of the current fields
-    T ly[5], gp[5];
-    {
-        const T dcb = T(a.tb.dc[j]), dct = T(a.tb.dc[j + 1]);
-        // u: wall values u_bot, u_top at the half-cell distance
-        const T ub = has_dn ? u[ym] : T(a.ph.u_bot);
-        const T ut = has_up ? u[yp] : T(a.ph.u_top);
-        ly[0] = ((ut - uc) / dct - (uc - ub) / dcb) * idn;
-        const T wb = has_dn ? w[ym] : T(0);
-        const T wt = has_up ? w[yp] : T(0);
-        ly[2] = ((wt - wc) / dct - (wc - wb) / dcb) * idn;
-        for (int sp = 0; sp < 2; ++sp) {
-            const T *__restrict__ c = sp == 0 ? cp : cm;
-            const T cc = c[q];
-            const T ft = has_up ? (c[yp] - cc) / dct : T(0);
-            const T fb = has_dn ? (cc - c[ym]) / dcb : T(0);
-            ly[3 + sp] = (ft - fb) * idn;
-        }
-        if (has_dn) {
-            const T vt = has_up ? v[yp] : T(0);
-            const T vb = (j > 1) ? v[ym] : T(0);
-            ly[1] = ((vt - vc) / dnj - (vc - vb) / T(a.tb.dn[j - 1])) / dcb;
-            gp[1] = (p[q] - p[ym]) / dcb;
-        } else {
-            ly[1] = T(0);
-            gp[1] = T(0);
-        }
-        gp[0] = (p[q] - p[x.xm]) * idx_;
-        gp[2] = (p[q] - p[x.zm]) * idz_;
-        gp[3] = gp[4] = T(0);
-    }
-#pragma unroll
-    for (int f = 0; f < 5; ++f) {
-        T *__restrict__ hb = (T *)a.h[f];
-        const T nu = f < 3 ? T(a.ph.ire) : T(a.ph.kd);
-        const T hold = use_old ? hb[q] : T(0);
-        T val = dt * (gam * H[f] + zet * hold - alp * gp[f] + alp * nu * ly[f]);
-        if (f == 1 && !has_dn) val = T(0);
-        a.r[f][q] = (double)val;
-        if (keep) hb[q] = H[f];
     }
 }
 
@@ -243,13 +244,16 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs a) {
 
 struct CnArgs {
     Dims d;
-    Phys ph;
+    const Phys *phys;
+    size_t ms;
     Tables tb;
     Stage st;
     void *q[5];
     double *r[5];
     const double *clock;
 };
+
+constexpr int kCnPf = 4;  // rows loaded ahead of the elimination
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_cn_solve(CnArgs a) {
@@ -259,94 +263,100 @@ __global__ void __launch_bounds__(256) k_cn_solve(CnArgs a) {
     const int M = d.M;
     const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = col < d.plane;
-    const double dt = a.clock[1];
-    const double nu = (f < 3) ? a.ph.ire : a.ph.kd;
+    const Phys *ph = member_ptr(a.phys, a.ms);
+    const double dt = member_ptr(a.clock, a.ms)[1];
+    const double nu = (f < 3) ? ph->ire : ph->kd;
     const double beta = 0.5 * a.st.alp * dt * nu;
     // system type: 0 Dirichlet centre (u, w), 1 node (v), 2 zero-flux centre (c+-)
     const int sys = (f == 1) ? 1 : (f >= 3 ? 2 : 0);
     const int j0 = (sys == 1) ? 1 : 0;
-    double *__restrict__ r = a.r[f];
-    T *__restrict__ qf = (T *)a.q[f];
+    double *__restrict__ r = member_ptr(a.r[f], a.ms);
+    T *__restrict__ qf = (T *)member_ptr(a.q[f], a.ms);
     const int64_t pl = d.plane;
 
     double cprev = 0.0, dprev = 0.0;
-    for (int j = j0; j < M; ++j) {
-        double lo, up, di;
-        if (sys == 1) {
-            const double aa = a.tb.lyn_lo[j], cc = a.tb.lyn_up[j];
-            lo = (j > 1) ? aa : 0.0;
-            up = (j < M - 1) ? cc : 0.0;
-            di = -(aa + cc);
-        } else {
-            const double aa = a.tb.lyc_lo[j], cc = a.tb.lyc_up[j];
-            lo = (j > 0) ? aa : 0.0;
-            up = (j < M - 1) ? cc : 0.0;
-            di = -(lo + up);
-            if (sys == 0) {
-                if (j == 0) di -= aa;
-                if (j == M - 1) di -= cc;
+    double buf[kCnPf];
+#pragma unroll
+    for (int p = 0; p < kCnPf; ++p) buf[p] = (active && j0 + p < M) ? r[(j0 + p) * pl + col] : 0.0;
+    for (int jb = j0; jb < M; jb += kCnPf) {
+#pragma unroll
+        for (int p = 0; p < kCnPf; ++p) {
+            const int j = jb + p;
+            if (j < M) {
+                const double rj = buf[p];
+                if (active && j + kCnPf < M) buf[p] = r[(j + kCnPf) * pl + col];
+                double lo, up, di;
+                if (sys == 1) {
+                    const double aa = a.tb.lyn_lo[j], cc = a.tb.lyn_up[j];
+                    lo = (j > 1) ? aa : 0.0;
+                    up = (j < M - 1) ? cc : 0.0;
+                    di = -(aa + cc);
+                } else {
+                    const double aa = a.tb.lyc_lo[j], cc = a.tb.lyc_up[j];
+                    lo = (j > 0) ? aa : 0.0;
+                    up = (j < M - 1) ? cc : 0.0;
+                    di = -(lo + up);
+                    if (sys == 0) {
+                        if (j == 0) di -= aa;
+                        if (j == M - 1) di -= cc;
+                    }
+                }
+                const double A = -beta * lo, B = 1.0 - beta * di, C = -beta * up;
+                const double den = B - A * cprev;
+                const double cj = C / den;
+                if (threadIdx.x == 0) s_cp[j] = cj;
+                if (active) {
+                    const double dj = (rj - A * dprev) / den;
+                    r[j * pl + col] = dj;
+                    dprev = dj;
+                }
+                cprev = cj;
             }
         }
-        const double A = -beta * lo, B = 1.0 - beta * di, C = -beta * up;
-        const double den = B - A * cprev;
-        const double cj = C / den;
-        if (threadIdx.x == 0) s_cp[j] = cj;
-        if (active) {
-            const double dj = (r[j * pl + col] - A * dprev) / den;
-            r[j * pl + col] = dj;
-            dprev = dj;
-        }
-        cprev = cj;
     }
     __syncthreads();
     if (!active) return;
     double xn = 0.0;
-    for (int j = M - 1; j >= j0; --j) {
-        const double xj = r[j * pl + col] - s_cp[j] * xn;
-        const int64_t o = j * pl + col;
-        qf[o] = (T)((double)qf[o] + xj);
-        xn = xj;
+    double bd[kCnPf];
+    T bq[kCnPf];
+#pragma unroll
+    for (int p = 0; p < kCnPf; ++p) {
+        const int j = M - 1 - p;
+        bd[p] = (j >= j0) ? r[j * pl + col] : 0.0;
+        bq[p] = (j >= j0) ? qf[j * pl + col] : T(0);
     }
-}
-
-// divergence of the velocity, times scale (1 / (alp dt) from the device
-// clock when scale_by_alpha_dt > 0, else a fixed factor)
-struct DivArgs {
-    Dims d;
-    Tables tb;
-    const void *u, *v, *w;
-    double *out;
-    const double *clock;
-    double alp;
-    double fixed;
-};
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_divergence(DivArgs a) {
-    const Dims &d = a.d;
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= d.n) return;
-    const T *u = (const T *)a.u, *v = (const T *)a.v, *w = (const T *)a.w;
-    const Idx x = make_idx(d, q);
-    const double vt = (x.j + 1 < d.M) ? (double)v[q + d.plane] : 0.0;
-    const double vb = (x.j > 0) ? (double)v[q] : 0.0;
-    const double div = ((double)u[x.xp] - (double)u[q]) / d.dx + (vt - vb) / a.tb.dn[x.j] +
-                       ((double)w[x.zp] - (double)w[q]) / d.dz;
-    const double s = (a.alp > 0.0) ? 1.0 / (a.alp * a.clock[1]) : a.fixed;
-    a.out[q] = div * s;
+    for (int jb = M - 1; jb >= j0; jb -= kCnPf) {
+#pragma unroll
+        for (int p = 0; p < kCnPf; ++p) {
+            const int j = jb - p;
+            if (j >= j0) {
+                const double dj = bd[p];
+                const T qj = bq[p];
+                if (j - kCnPf >= j0) {
+                    bd[p] = r[(j - kCnPf) * pl + col];
+                    bq[p] = qf[(j - kCnPf) * pl + col];
+                }
+                const double xj = dj - s_cp[j] * xn;
+                qf[j * pl + col] = (T)((double)qj + xj);
+                xn = xj;
+            }
+        }
+    }
 }
 
 // projection correction: u -= a G psi;  p += psi - (a / (2 Re)) L_y psi
 struct CorrArgs {
     Dims d;
-    Phys ph;
+    const Phys *phys;
+    size_t ms;
     Tables tb;
     void *u, *v, *w, *p;
     const double *psi;
-    const double *clock;
+    double *clock;
     double alp;
     double fixed;
     int update_p;
+    int advance_clock;
 };
 
 template <typename T>
@@ -354,11 +364,17 @@ __global__ void __launch_bounds__(256) k_correct(CorrArgs a) {
     const Dims &d = a.d;
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= d.n) return;
-    T *u = (T *)a.u, *v = (T *)a.v, *w = (T *)a.w, *p = (T *)a.p;
-    const double *psi = a.psi;
+    const size_t ms = a.ms;
+    double *clock = member_ptr(a.clock, ms);
+    const Phys *ph = member_ptr(a.phys, ms);
+    // substep time t += alp dt (dt is read, never written, by this kernel)
+    if (a.advance_clock && q == 0) clock[0] += a.alp * clock[1];
+    T *u = (T *)member_ptr(a.u, ms), *v = (T *)member_ptr(a.v, ms), *w = (T *)member_ptr(a.w, ms);
+    T *p = (T *)member_ptr(a.p, ms);
+    const double *psi = member_ptr(a.psi, ms);
     const Idx x = make_idx(d, q);
     const int j = x.j;
-    const double sc = (a.alp > 0.0) ? a.alp * a.clock[1] : a.fixed;
+    const double sc = (a.alp > 0.0) ? a.alp * clock[1] : a.fixed;
     const double s0 = psi[q];
     u[q] = (T)((double)u[q] - sc * (s0 - psi[x.xm]) / d.dx);
     w[q] = (T)((double)w[q] - sc * (s0 - psi[x.zm]) / d.dz);
@@ -367,16 +383,8 @@ __global__ void __launch_bounds__(256) k_correct(CorrArgs a) {
         const double ft = (j + 1 < d.M) ? (psi[q + d.plane] - s0) / a.tb.dc[j + 1] : 0.0;
         const double fb = (j > 0) ? (s0 - psi[q - d.plane]) / a.tb.dc[j] : 0.0;
         const double ly = (ft - fb) / a.tb.dn[j];
-        p[q] = (T)((double)p[q] + s0 - 0.5 * sc * a.ph.ire * ly);
+        p[q] = (T)((double)p[q] + s0 - 0.5 * sc * ph->ire * ly);
     }
-}
-
-// right-hand side of the potential equation: -(c+ - c-) / (2 lam^2)
-template <typename T>
-__global__ void __launch_bounds__(256) k_charge(Dims d, double ch, const T *cp, const T *cm, double *out) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= d.n) return;
-    out[q] = ch * ((double)cp[q] - (double)cm[q]);
 }
 
 template <typename Src, typename Dst>
@@ -384,11 +392,6 @@ __global__ void __launch_bounds__(256) k_copy_convert(int64_t n, const Src *in, 
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     out[q] = (Dst)in[q];
-}
-
-template <typename T>
-__global__ void k_advance_clock(double *clock, double alp) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] += alp * clock[1];
 }
 
 inline dim3 grid1(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
@@ -399,30 +402,35 @@ hipError_t launch_explicit(nspnp_state *s, const Stage &st, bool /*write_r*/) {
     ProfScope prof_(s, K_EXPLICIT);
     ExplicitArgs a{};
     a.d = s->d;
-    a.ph = s->ph;
+    a.phys = s->d_phys;
+    a.ms = s->mstride;
     a.tb = s->tb;
     a.st = st;
     a.u = s->f[0]; a.v = s->f[1]; a.w = s->f[2]; a.cp = s->f[3]; a.cm = s->f[4]; a.phi = s->f[5]; a.p = s->f[6];
     for (int q = 0; q < 5; ++q) { a.h[q] = s->h[q]; a.r[q] = s->r[q]; a.dbg[q] = nullptr; }
     a.clock = s->clock;
     a.mode = 0;
-    if (s->fp64) k_explicit<double><<<grid1(s->d.n), 256, 0, s->stream>>>(a);
-    else k_explicit<float><<<grid1(s->d.n), 256, 0, s->stream>>>(a);
+    const int tb = s->tiles.expl;
+    const dim3 g((unsigned)((s->d.plane + tb - 1) / tb), (unsigned)s->d.M, (unsigned)s->nmem);
+    if (s->fp64) k_explicit<double><<<g, tb, 0, s->stream>>>(a);
+    else k_explicit<float><<<g, tb, 0, s->stream>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]) {
     ExplicitArgs a{};
     a.d = s->d;
-    a.ph = s->ph;
+    a.phys = s->d_phys;
+    a.ms = 0;
     a.tb = s->tb;
     a.st = Stage{0, 0, 0, 0};
     a.u = s->f[0]; a.v = s->f[1]; a.w = s->f[2]; a.cp = s->f[3]; a.cm = s->f[4]; a.phi = s->f[5]; a.p = s->f[6];
     for (int q = 0; q < 5; ++q) { a.h[q] = s->h[q]; a.r[q] = s->r[q]; a.dbg[q] = out[q]; }
     a.clock = s->clock;
     a.mode = 1;
-    if (s->fp64) k_explicit<double><<<grid1(s->d.n), 256, 0, s->stream>>>(a);
-    else k_explicit<float><<<grid1(s->d.n), 256, 0, s->stream>>>(a);
+    const dim3 g((unsigned)((s->d.plane + 255) / 256), (unsigned)s->d.M);
+    if (s->fp64) k_explicit<double><<<g, 256, 0, s->stream>>>(a);
+    else k_explicit<float><<<g, 256, 0, s->stream>>>(a);
     return hipGetLastError();
 }
 
@@ -430,38 +438,26 @@ hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
     ProfScope prof_(s, K_CN);
     CnArgs a{};
     a.d = s->d;
-    a.ph = s->ph;
+    a.phys = s->d_phys;
+    a.ms = s->mstride;
     a.tb = s->tb;
     a.st = st;
     for (int q = 0; q < 5; ++q) { a.q[q] = s->f[q]; a.r[q] = s->r[q]; }
     a.clock = s->clock;
-    dim3 g((unsigned)((s->d.plane + 255) / 256), 5);
+    const int tb = s->tiles.cn;
+    dim3 g((unsigned)((s->d.plane + tb - 1) / tb), 5, (unsigned)s->nmem);
     size_t lds = (size_t)s->d.M * sizeof(double);
-    if (s->fp64) k_cn_solve<double><<<g, 256, lds, s->stream>>>(a);
-    else k_cn_solve<float><<<g, 256, lds, s->stream>>>(a);
+    if (s->fp64) k_cn_solve<double><<<g, tb, lds, s->stream>>>(a);
+    else k_cn_solve<float><<<g, tb, lds, s->stream>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_divergence(nspnp_state *s, double fixed, const Stage &st, double *out) {
-    ProfScope prof_(s, K_DIV);
-    DivArgs a{};
-    a.d = s->d;
-    a.tb = s->tb;
-    a.u = s->f[0]; a.v = s->f[1]; a.w = s->f[2];
-    a.out = out;
-    a.clock = s->clock;
-    a.alp = st.alp;
-    a.fixed = fixed;
-    if (s->fp64) k_divergence<double><<<grid1(s->d.n), 256, 0, s->stream>>>(a);
-    else k_divergence<float><<<grid1(s->d.n), 256, 0, s->stream>>>(a);
-    return hipGetLastError();
-}
-
-hipError_t launch_correct(nspnp_state *s, const Stage &st, bool update_p, double fixed) {
+hipError_t launch_correct(nspnp_state *s, const Stage &st, bool update_p, double fixed, bool advance_clock) {
     ProfScope prof_(s, K_CORRECT);
     CorrArgs a{};
     a.d = s->d;
-    a.ph = s->ph;
+    a.phys = s->d_phys;
+    a.ms = s->mstride;
     a.tb = s->tb;
     a.u = s->f[0]; a.v = s->f[1]; a.w = s->f[2]; a.p = s->f[6];
     a.psi = s->psi;
@@ -469,28 +465,11 @@ hipError_t launch_correct(nspnp_state *s, const Stage &st, bool update_p, double
     a.alp = st.alp;
     a.fixed = fixed;
     a.update_p = update_p ? 1 : 0;
-    if (s->fp64) k_correct<double><<<grid1(s->d.n), 256, 0, s->stream>>>(a);
-    else k_correct<float><<<grid1(s->d.n), 256, 0, s->stream>>>(a);
-    return hipGetLastError();
-}
-
-hipError_t launch_charge(nspnp_state *s, double *out) {
-    ProfScope prof_(s, K_CHARGE);
-    if (s->fp64)
-        k_charge<double><<<grid1(s->d.n), 256, 0, s->stream>>>(s->d, s->ph.ch, (const double *)s->f[3],
-                                                              (const double *)s->f[4], out);
-    else
-        k_charge<float><<<grid1(s->d.n), 256, 0, s->stream>>>(s->d, s->ph.ch, (const float *)s->f[3],
-                                                             (const float *)s->f[4], out);
-    return hipGetLastError();
-}
-
-hipError_t launch_store_phi(nspnp_state *s, const double *src) {
-    ProfScope prof_(s, K_STORE_PHI);
-    if (s->fp64)
-        k_copy_convert<double, double><<<grid1(s->d.n), 256, 0, s->stream>>>(s->d.n, src, (double *)s->f[5]);
-    else
-        k_copy_convert<double, float><<<grid1(s->d.n), 256, 0, s->stream>>>(s->d.n, src, (float *)s->f[5]);
+    a.advance_clock = advance_clock ? 1 : 0;
+    const int tb = s->tiles.corr;
+    const dim3 g((unsigned)((s->d.n + tb - 1) / tb), 1, (unsigned)s->nmem);
+    if (s->fp64) k_correct<double><<<g, tb, 0, s->stream>>>(a);
+    else k_correct<float><<<g, tb, 0, s->stream>>>(a);
     return hipGetLastError();
 }
 
@@ -506,12 +485,6 @@ hipError_t launch_convert(nspnp_state *s, int field, const double *in, double *o
         else
             k_copy_convert<float, double><<<grid1(s->d.n), 256, 0, s->stream>>>(s->d.n, (const float *)s->f[field], out);
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_advance_clock(nspnp_state *s, double alp) {
-    ProfScope prof_(s, K_CLOCK);
-    k_advance_clock<double><<<1, 64, 0, s->stream>>>(s->clock, alp);
     return hipGetLastError();
 }
 

@@ -77,7 +77,8 @@ extern "C" {
 
 /*
  * Configuration.  Sizes: nx, nz of the form 2^a 3^b, even, 4..1024; ny (the
- * number of wall-normal NODES, so ny - 1 cell rows) at least 5.  Lengths in
+ * number of wall-normal NODES, so ny - 1 cell rows) within 5..481, and
+ * nx * nz * (ny - 1) below 2^31.  Lengths in
  * units of h.  stretch is the tanh clustering factor g of the y nodes
  * y_j = tanh(g xi_j)/tanh(g), xi_j uniform on [-1, 1] (g = 0: uniform).
  * force_sign sF: -1 is the physical Coulomb force rho E = -rho grad Phi,
@@ -223,12 +224,13 @@ NSPNP_API int nspnp_ensemble_clock(nspnp_ensemble *e, int32_t member, double *t,
 /* Choose the launch shapes of every size class (threads per block of the
  * stencil, Crank-Nicolson, mode-Thomas and correction kernels, points per
  * block of the x and z transforms) by timing trial_substeps substeps (a
- * multiple of 3) per candidate, coordinate by coordinate.  Results are
- * read from / appended to the text cache at cache_path (NULL: no cache),
- * one line per (arch, grid, precision, members) key.  Trials advance the
- * members (the launch shape does not change any result); on return every
- * member has advanced by the same number of substeps.  tiles_out (NULL or
- * 6 ints per class) receives the choice.  Synchronises. */
+ * multiple of 3) per candidate, coordinate by coordinate; also the rows
+ * one block of the stencil kernel marches.  Results are read from /
+ * appended to the text cache at cache_path (NULL: no cache), one line per
+ * (arch, grid, precision, members) key.  Trials advance the members (the
+ * launch shape does not change any result); on return every member has
+ * advanced by the same number of substeps.  tiles_out (NULL or 7 ints per
+ * class) receives the choice.  Synchronises. */
 NSPNP_API int nspnp_ensemble_autotune(nspnp_ensemble *e, const char *cache_path, int32_t trial_substeps,
                                       int32_t *tiles_out);
 /* Number of size classes. */

@@ -288,7 +288,7 @@ class Ensemble:
     null stream cannot be captured into a graph); every call that returns
     data synchronises that stream."""
 
-    TILE_NAMES = ("expl", "cn", "fftx", "fftz", "thomas", "corr")
+    TILE_NAMES = ("expl", "cn", "fftx", "fftz", "thomas", "corr", "slab")
 
     def __init__(self, cfgs, device: str = "cuda:0"):
         if not torch.cuda.is_available():
@@ -366,10 +366,10 @@ class Ensemble:
 
     def autotune(self, cache_path: str | None = None, trial_substeps: int = 6):
         nc = self.classes()
-        out = (ctypes.c_int32 * (6 * nc))()
+        out = (ctypes.c_int32 * (7 * nc))()
         path = cache_path.encode() if cache_path else None
         _check(self.lib.nspnp_ensemble_autotune(self._h, path, int(trial_substeps), out))
-        return [dict(zip(self.TILE_NAMES, list(out)[6 * c: 6 * c + 6])) for c in range(nc)]
+        return [dict(zip(self.TILE_NAMES, list(out)[7 * c: 7 * c + 7])) for c in range(nc)]
 
 
 class Mlp:

@@ -55,7 +55,8 @@ int check_config(const nspnp_config *c) {
         if (n < 4 || n > 1024 || n % 2 != 0 || !smooth_size(n))
             return fail(NSPNP_ERR_SIZE, "nx and nz must be even, of the form 2^a 3^b, and within 4..1024");
     }
-    if (c->ny < 5) return fail(NSPNP_ERR_SIZE, "ny (wall-normal nodes) must be at least 5");
+    if (c->ny < 5 || c->ny > 481)
+        return fail(NSPNP_ERR_SIZE, "ny (wall-normal nodes) must be within 5..481 (cell rows staged in 64 KB of LDS)");
     if ((int64_t)c->nx * c->nz * (c->ny - 1) > 2147483647LL)
         return fail(NSPNP_ERR_SIZE, "nx * nz * (ny - 1) must stay below 2^31 cells (32-bit cell indices)");
     const double pos[] = {c->lx, c->lz, c->re, c->sc, c->debye};
@@ -69,7 +70,8 @@ int check_config(const nspnp_config *c) {
 }
 
 struct Layout {
-    size_t off_f[7], off_h[5], off_r[5], off_psi, off_spec, off_cpr, off_clock, off_phys, off_stats, off_red, off_tab;
+    size_t off_f[7], off_h[5], off_r[5], off_psi, off_spec, off_cpr, off_coef, off_clock, off_phys, off_stats, off_red,
+        off_tab;
     size_t ntab, nred, total;
 };
 
@@ -88,6 +90,7 @@ Layout make_layout(const nspnp_config *c) {
     const int64_t nspec = nxh * c->nz * M;
     L.off_spec = o; o = align256(o + 2 * nspec * 16);
     L.off_cpr = o; o = align256(o + 2 * nspec * 8);
+    L.off_coef = o; o = align256(o + 9 * M * 8);
     L.off_clock = o; o = align256(o + 4 * 8);
     L.off_phys = o; o = align256(o + sizeof(Phys));
     L.off_stats = o; o = align256(o + (3 * M + 2) * 8);
@@ -250,13 +253,14 @@ void setup_handle(nspnp_state *s, const nspnp_config *cfg, char *base, int nmem,
     s->mstride = nmem > 1 ? L.total : 0;
     s->planx = make_plan(cfg->nx);
     s->planz = make_plan(cfg->nz);
-    s->tiles = Tiles{256, 256, 1024, 1024, 64, 256};
+    s->tiles = Tiles{256, 256, 1024, 1024, 64, 256, 16};
     for (int q = 0; q < 7; ++q) s->f[q] = base + L.off_f[q];
     for (int q = 0; q < 5; ++q) s->h[q] = base + L.off_h[q];
     for (int q = 0; q < 5; ++q) s->r[q] = (double *)(base + L.off_r[q]);
     s->psi = (double *)(base + L.off_psi);
     s->spec = (double2 *)(base + L.off_spec);
     s->cpr = (double *)(base + L.off_cpr);
+    s->cn_coef = (double *)(base + L.off_coef);
     s->clock = (double *)(base + L.off_clock);
     s->d_phys = (Phys *)(base + L.off_phys);
     s->stats = (double *)(base + L.off_stats);
@@ -285,6 +289,7 @@ nspnp_state *member_view(const nspnp_state *cls, int m, const nspnp_config *cfg)
     v->psi = sh(cls->psi);
     v->spec = sh(cls->spec);
     v->cpr = sh(cls->cpr);
+    v->cn_coef = sh(cls->cn_coef);
     v->clock = sh(cls->clock);
     v->d_phys = sh(cls->d_phys);
     v->stats = sh(cls->stats);

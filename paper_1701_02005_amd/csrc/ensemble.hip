@@ -122,7 +122,7 @@ bool cache_lookup(const char *path, const std::string &key, Tiles &t) {
         std::istringstream ls(line);
         std::string k;
         Tiles v{};
-        if (ls >> k >> v.expl >> v.cn >> v.fftx >> v.fftz >> v.thomas >> v.corr && k == key) {
+        if (ls >> k >> v.expl >> v.cn >> v.fftx >> v.fftz >> v.thomas >> v.corr >> v.slab && k == key) {
             t = v;
             return true;
         }
@@ -134,7 +134,7 @@ void cache_store(const char *path, const std::string &key, const Tiles &t) {
     if (!path || !*path) return;
     std::ofstream out(path, std::ios::app);
     out << key << " " << t.expl << " " << t.cn << " " << t.fftx << " " << t.fftz << " " << t.thomas << " " << t.corr
-        << "\n";
+        << " " << t.slab << "\n";
 }
 
 // wall time (ms) of `trial` substeps of one class with its current tiles
@@ -307,6 +307,7 @@ int nspnp_ensemble_autotune(nspnp_ensemble *e, const char *cache_path, int32_t t
             const int cand_fft[] = {512, 1024, 2048};
             const int cand_th[] = {32, 64, 128, 256};
             const int cand_corr[] = {128, 256};
+            const int cand_slab[] = {4, 8, 16, 32};
             float base_ms = 0.f;
             if ((rc = time_class(c, trial_substeps, &base_ms))) return rc;  // warm
             if ((rc = time_class(c, trial_substeps, &base_ms))) return rc;
@@ -331,17 +332,19 @@ int nspnp_ensemble_autotune(nspnp_ensemble *e, const char *cache_path, int32_t t
             if ((rc = sweep(&c->tiles.fftz, cand_fft, 3))) return rc;
             if ((rc = sweep(&c->tiles.thomas, cand_th, 4))) return rc;
             if ((rc = sweep(&c->tiles.corr, cand_corr, 2))) return rc;
+            if ((rc = sweep(&c->tiles.slab, cand_slab, 4))) return rc;
             best = c->tiles;
             cache_store(cache_path, key, best);
         }
         c->tiles = best;
         if (tiles_out) {
-            tiles_out[6 * ci + 0] = best.expl;
-            tiles_out[6 * ci + 1] = best.cn;
-            tiles_out[6 * ci + 2] = best.fftx;
-            tiles_out[6 * ci + 3] = best.fftz;
-            tiles_out[6 * ci + 4] = best.thomas;
-            tiles_out[6 * ci + 5] = best.corr;
+            tiles_out[7 * ci + 0] = best.expl;
+            tiles_out[7 * ci + 1] = best.cn;
+            tiles_out[7 * ci + 2] = best.fftx;
+            tiles_out[7 * ci + 3] = best.fftz;
+            tiles_out[7 * ci + 4] = best.thomas;
+            tiles_out[7 * ci + 5] = best.corr;
+            tiles_out[7 * ci + 6] = best.slab;
         }
     }
     // classes may have advanced by different numbers of trial substeps

@@ -62,12 +62,26 @@ struct Phys {
     double adaptive;    // 1: dt from the CFL rule at stage 1; 0: fixed dt
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  This bijection of the linear block id gives XCD x one contiguous range
+// of tiles (the first nblocks % 8 XCDs one tile more), so tiles whose
+// stencils overlap (neighbouring z rows) run in the same L2.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nblocks) {
+    const unsigned x = b & 7u, l = b >> 3;
+    const unsigned q = nblocks >> 3, r = nblocks & 7u;
+    return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
 // Every member of a batch has the same workspace layout; device pointers in
 // kernel arguments refer to member 0 and member blockIdx.z sits stride bytes
 // further per member.
 template <typename P>
 __device__ __forceinline__ P *member_ptr(P *p, size_t stride) {
     return (P *)((char *)p + (size_t)blockIdx.z * stride);
+}
+template <typename P>
+__device__ __forceinline__ P *member_ptr_at(P *p, size_t stride, unsigned member) {
+    return (P *)((char *)p + (size_t)member * stride);
 }
 
 // Runge-Kutta coefficients of one substep.
@@ -105,6 +119,7 @@ struct Tiles {
     int fftz;     // complex points per block of the z transforms
     int thomas;   // threads per block (modes) of the mode Thomas solve
     int corr;     // threads per block of the projection correction
+    int slab;     // rows marched by one block of the explicit kernel
 };
 
 // Kernel classes timed by the optional event profiler.
@@ -153,6 +168,7 @@ struct nspnp_state {
     double *psi;         // pressure increment (n, FP64)
     double2 *spec;       // two half spectra, 2 * nxh * nz * M
     double *cpr;         // their Thomas elimination factors
+    double *cn_coef;     // Crank-Nicolson recurrence coefficients (9 M)
     double *clock;       // device [t, dt]
     double *red;         // reduction scratch
     int64_t nred;
@@ -174,7 +190,7 @@ class ProfScope {
     ProfScope(nspnp_state *s, int id) : s_(s), id_(id) {
         if (s_->prof.on) {
             hipEvent_t e = s_->prof.next();
-            if (e) { hipEventRecord(e, s_->stream); s_->prof.ids.push_back(id_); }
+            if (e) { (void)hipEventRecord(e, s_->stream); s_->prof.ids.push_back(id_); }
             else s_ = nullptr;
         } else {
             s_ = nullptr;
@@ -183,7 +199,7 @@ class ProfScope {
     ~ProfScope() {
         if (s_) {
             hipEvent_t e = s_->prof.next();
-            if (e) hipEventRecord(e, s_->stream);
+            if (e) (void)hipEventRecord(e, s_->stream);
         }
     }
   private:

@@ -4,9 +4,12 @@
 // with zero-flux walls (pressure) or zero wall value (potential).
 //
 // Data flow for one solve, all FP64:
-//   real [j][k][i]  --x R2C-->  half spectrum [j][k][kx] (kx < nx/2+1)
-//   --z C2C--> [j][kz][kx]  --Thomas in j per (kx,kz)-->  --z C2C^-1-->
+//   real [j][k][i]  --x R2C-->  half spectrum [j][kx][k] (kx < nx/2+1)
+//   --z C2C--> [j][kx][kz]  --Thomas in j per (kx,kz)-->  --z C2C^-1-->
 //   --x C2R--> real [j][k][i]
+// The x transforms stage their output / input through LDS so that the
+// spectrum is written and read in runs of consecutive z lines, and every z
+// line is one contiguous run of nz values.
 // The FFTs are self-sorting (Stockham) in LDS with radix 4, 2 and 3 stages;
 // two real x-lines share one complex transform.
 #include "internal.h"
@@ -147,7 +150,7 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
     double2 *out = member_ptr(spec, b.ms) + prob * nspec;
     const int nx = d.nx, nxh = d.nxh;
     const int64_t nlines = (int64_t)d.M * d.nz;
-    double2 *bf[2] = {sm, sm + ppb * nx};
+    double2 *bf[2] = {sm, sm + ppb * (nx + 2)};
     const int64_t pair0 = (int64_t)blockIdx.x * ppb;
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
         const int p = e / nx, i = e - p * nx;
@@ -157,17 +160,27 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
         bf[0][e] = make_double2(re, im);
     }
     __syncthreads();
-    const double2 *z = bf[lds_fft(bf[0], bf[1], nx, ppb, pl, tb.twx, false)];
+    const int w = lds_fft(bf[0], bf[1], nx, ppb, pl, tb.twx, false);
+    const double2 *z = bf[w];
+    double2 *o = bf[1 - w];  // [kk][line] staging for the transposed store
+    const int nl2 = 2 * ppb;
     for (int e = threadIdx.x; e < ppb * nxh; e += blockDim.x) {
         const int p = e / nxh, kk = e - p * nxh;
-        const int64_t la = 2 * (pair0 + p), lb = la + 1;
         const double2 zk = z[p * nx + kk];
         const double2 zc = z[p * nx + (kk == 0 ? 0 : nx - kk)];
         // A = (Z_k + conj(Z_{N-k}))/2, B = (Z_k - conj(Z_{N-k}))/(2i)
-        const double2 A = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y - zc.y));
-        const double2 B = make_double2(0.5 * (zk.y + zc.y), -0.5 * (zk.x - zc.x));
-        if (la < nlines) out[la * nxh + kk] = A;
-        if (lb < nlines) out[lb * nxh + kk] = B;
+        o[kk * nl2 + 2 * p] = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y - zc.y));
+        o[kk * nl2 + 2 * p + 1] = make_double2(0.5 * (zk.y + zc.y), -0.5 * (zk.x - zc.x));
+    }
+    __syncthreads();
+    // spectrum layout [j][kx][kz]: consecutive lines (k) of one kx are contiguous
+    for (int e = threadIdx.x; e < nl2 * nxh; e += blockDim.x) {
+        const int kk = e / nl2, l = e - kk * nl2;
+        const int64_t line = 2 * pair0 + l;
+        if (line < nlines) {
+            const int64_t j = line / d.nz, k = line - j * d.nz;
+            out[(j * nxh + kk) * d.nz + k] = o[e];
+        }
     }
 }
 
@@ -179,15 +192,27 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
     const double2 *in = member_ptr(spec, b.ms) + prob * nspec;
     const int nx = d.nx, nxh = d.nxh;
     const int64_t nlines = (int64_t)d.M * d.nz;
-    double2 *bf[2] = {sm, sm + ppb * nx};
+    double2 *bf[2] = {sm, sm + ppb * (nx + 2)};
     const int64_t pair0 = (int64_t)blockIdx.x * ppb;
+    const int nl2 = 2 * ppb;
+    double2 *o = bf[1];  // [kk][line] staging of the transposed load
+    for (int e = threadIdx.x; e < nl2 * nxh; e += blockDim.x) {
+        const int kk = e / nl2, l = e - kk * nl2;
+        const int64_t line = 2 * pair0 + l;
+        double2 v = make_double2(0.0, 0.0);
+        if (line < nlines) {
+            const int64_t j = line / d.nz, k = line - j * d.nz;
+            v = in[(j * nxh + kk) * d.nz + k];
+        }
+        o[e] = v;
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
         const int p = e / nx, kk = e - p * nx;
-        const int64_t la = 2 * (pair0 + p), lb = la + 1;
         const bool lower = kk < nxh;
         const int src = lower ? kk : nx - kk;
-        double2 A = (la < nlines) ? in[la * nxh + src] : make_double2(0.0, 0.0);
-        double2 B = (lb < nlines) ? in[lb * nxh + src] : make_double2(0.0, 0.0);
+        double2 A = o[src * nl2 + 2 * p];
+        double2 B = o[src * nl2 + 2 * p + 1];
         if (!lower) {  // Hermitian continuation of a real line's spectrum
             A.y = -A.y;
             B.y = -B.y;
@@ -222,20 +247,14 @@ __global__ void __launch_bounds__(256) k_fft_z(Dims d, FftPlan pl, const double2
     const int tiles = (nxh + tk - 1) / tk;
     const int j = blockIdx.x / tiles;
     const int kx0 = (blockIdx.x - j * tiles) * tk;
+    const int nt = (nxh - kx0 < tk) ? nxh - kx0 : tk;  // lines in this tile
     double2 *bf[2] = {sm, sm + tk * nz};
-    double2 *base = data + (int64_t)j * nz * nxh;
-    for (int e = threadIdx.x; e < tk * nz; e += blockDim.x) {
-        const int t = e % tk, k = e / tk;
-        const int kx = kx0 + t;
-        bf[0][t * nz + k] = (kx < nxh) ? base[(int64_t)k * nxh + kx] : make_double2(0.0, 0.0);
-    }
+    // lines (j, kx) are contiguous runs of nz values: the tile is one block of memory
+    double2 *base = data + ((int64_t)j * nxh + kx0) * nz;
+    for (int e = threadIdx.x; e < tk * nz; e += blockDim.x) bf[0][e] = (e < nt * nz) ? base[e] : make_double2(0.0, 0.0);
     __syncthreads();
     const double2 *z = bf[lds_fft(bf[0], bf[1], nz, tk, pl, tw, inverse != 0)];
-    for (int e = threadIdx.x; e < tk * nz; e += blockDim.x) {
-        const int t = e % tk, k = e / tk;
-        const int kx = kx0 + t;
-        if (kx < nxh) base[(int64_t)k * nxh + kx] = z[t * nz + k];
-    }
+    for (int e = threadIdx.x; e < nt * nz; e += blockDim.x) base[e] = z[e];
 }
 
 // ---- y direction: one Thomas solve per (kx, kz) mode ----
@@ -254,7 +273,7 @@ __global__ void __launch_bounds__(256) k_thomas_modes(Dims d, Tables tb, Poisson
     const int64_t nmodes = (int64_t)d.nxh * d.nz;
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= nmodes) return;
-    const int kx = (int)(m % d.nxh), kz = (int)(m / d.nxh);
+    const int kx = (int)(m / d.nz), kz = (int)(m % d.nz);  // spectrum layout [j][kx][kz]
     const int M = d.M;
     const double k2 = tb.kx2[kx] + tb.kz2[kz];
     const double scale = 1.0 / ((double)d.nx * (double)d.nz);
@@ -342,7 +361,14 @@ __global__ void __launch_bounds__(256) k_thomas_modes(Dims d, Tables tb, Poisson
     }
 }
 
-inline int pairs_per_block(int nx, int points) { return nx >= points ? 1 : points / nx; }
+// line pairs per block of the x transforms: about `points` complex values,
+// within 64 KB of LDS for the two staging buffers
+inline int pairs_per_block(int nx, int points) {
+    int p = nx >= points ? 1 : points / nx;
+    const int lds_max = 65536 / (2 * (nx + 2) * (int)sizeof(double2));
+    if (p > lds_max) p = lds_max;
+    return p < 1 ? 1 : p;
+}
 inline int modes_per_tile(int nz, int nxh, int points) {
     int t = nz >= points ? 1 : points / nz;
     if (t > 32) t = 32;
@@ -362,7 +388,7 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
     const int ppb = pairs_per_block(d.nx, s->tiles.fftx);
     const int64_t npairs = (nlines + 1) / 2;
     const dim3 gx((unsigned)((npairs + ppb - 1) / ppb), (unsigned)b.nprob, (unsigned)nmem);
-    const size_t ldsx = 2 * (size_t)ppb * d.nx * sizeof(double2);
+    const size_t ldsx = 2 * (size_t)ppb * (d.nx + 2) * sizeof(double2);
     {
         ProfScope prof_(s, K_FFTX_FWD);
         if (s->fp64) k_fft_x_r2c<double><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb);

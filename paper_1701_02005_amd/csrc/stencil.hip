@@ -46,42 +46,58 @@ struct ExplicitArgs {
     double *dbg[5];
     const double *clock;
     int mode;  // 0: substep (H update + CN right-hand sides); 1: H to dbg only
+    int chunks;     // blocks per (x, z) plane
+    int slabs;      // row slabs per member
+    int slab_rows;  // rows marched by one block
 };
 
-__device__ __forceinline__ void shift_explicit(ExplicitArgs &a) {
+__device__ __forceinline__ void shift_explicit(ExplicitArgs &a, unsigned mem) {
     const size_t ms = a.ms;
-    a.phys = member_ptr(a.phys, ms);
-    a.u = member_ptr(a.u, ms); a.v = member_ptr(a.v, ms); a.w = member_ptr(a.w, ms);
-    a.cp = member_ptr(a.cp, ms); a.cm = member_ptr(a.cm, ms); a.phi = member_ptr(a.phi, ms); a.p = member_ptr(a.p, ms);
-    for (int f = 0; f < 5; ++f) { a.h[f] = member_ptr(a.h[f], ms); a.r[f] = member_ptr(a.r[f], ms); }
-    a.clock = member_ptr(a.clock, ms);
+    a.phys = member_ptr_at(a.phys, ms, mem);
+    a.u = member_ptr_at(a.u, ms, mem); a.v = member_ptr_at(a.v, ms, mem); a.w = member_ptr_at(a.w, ms, mem);
+    a.cp = member_ptr_at(a.cp, ms, mem); a.cm = member_ptr_at(a.cm, ms, mem);
+    a.phi = member_ptr_at(a.phi, ms, mem); a.p = member_ptr_at(a.p, ms, mem);
+    for (int f = 0; f < 5; ++f) { a.h[f] = member_ptr_at(a.h[f], ms, mem); a.r[f] = member_ptr_at(a.r[f], ms, mem); }
+    a.clock = member_ptr_at(a.clock, ms, mem);
 }
 
 // Convection, horizontal diffusion, Coulomb force and ion transport at one
 // cell, then the Crank-Nicolson right-hand side
 //   r = dt [gam H^k + zet H^{k-1} - alp G p + alp nu L_y q].
-// Grid: x = 256-cell chunks of one (x, z) plane, y = the cell row j, so the
-// row tables are uniform per block.  Each field's H and r are computed and
-// stored before the next field is started to keep register pressure low.
+// Each thread owns one (x, z) column and marches through a slab of rows,
+// keeping its own values of rows j-1, j, j+1 in registers (row j+2 is
+// loaded one step ahead); values of neighbouring columns come from the
+// caches, where the neighbouring threads of the block have just loaded them.
+// So every field is read from HBM about once, and each field's H and r are
+// stored as soon as they are known.
 template <typename T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_explicit(ExplicitArgs a) {
-    shift_explicit(a);
+struct Own {  // own-column values at rows j-1 (m), j (c), j+1 (p)
+    T um, uc, up, vm, vc, vp, wm, wc, wp, am, ac, ap, bm, bc, bp, fm, fc, fp, pm, pc;  // a = c+, b = c-, f = phi
+};
+
+// FP64 needs 160 registers without spilling (3 waves per SIMD), FP32 128 (4)
+template <typename T, int kWaves>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) k_explicit(ExplicitArgs a) {
+    const unsigned chunks = (unsigned)a.chunks, slabs = (unsigned)a.slabs;
+    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);  // chunk fastest: z-neighbours share an L2
+    const unsigned chunk = tile % chunks;
+    const unsigned slab = (tile / chunks) % slabs;
+    const unsigned mem = tile / (chunks * slabs);
+    shift_explicit(a, mem);
     const Phys ph = *a.phys;
     const Dims &d = a.d;
     const int nx = d.nx, nz = d.nz, M = d.M;
     const int pl = (int)d.plane;
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = (int)chunk * blockDim.x + threadIdx.x;
     if (e >= pl) return;
-    const int j = blockIdx.y;
     const int k = e / nx;
     const int i = e - k * nx;
     const int ip = (i + 1 == nx) ? 0 : i + 1, im = (i == 0) ? nx - 1 : i - 1;
     const int kp = (k + 1 == nz) ? 0 : k + 1, km = (k == 0) ? nz - 1 : k - 1;
-    const int q = j * pl + e;
-    const int xp = q - i + ip, xm = q - i + im;
-    const int zp = q + (kp - k) * nx, zm = q + (km - k) * nx;
-    const bool has_up = (j + 1 < M), has_dn = (j > 0);
-    const int yp = q + pl, ym = q - pl;
+    // in-plane offsets of the neighbouring columns
+    const int exp_ = e - i + ip, exm = e - i + im;
+    const int ezp = e + (kp - k) * nx, ezm = e + (km - k) * nx;
+    const int e_ip_km = ezm - i + ip, e_im_kp = ezp - i + im;
 
     const T *__restrict__ u = (const T *)a.u;
     const T *__restrict__ v = (const T *)a.v;
@@ -94,8 +110,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
     const T half = T(0.5), two = T(2);
     const T idx_ = T(1.0 / d.dx), idz_ = T(1.0 / d.dz);
     const T ix2 = idx_ * idx_, iz2 = idz_ * idz_;
-    const T idn = T(a.tb.idn[j]);
-    const T idcb = T(a.tb.idc[j]), idct = T(a.tb.idc[j + 1]);
     const T kf = T(ph.kf), ire = T(ph.ire), kd = T(ph.kd), e0 = T(ph.e0);
     const int mode = a.mode;
     const T dt = T(a.clock[1]);
@@ -103,144 +117,174 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
     const bool use_old = (a.st.k > 0) && mode == 0;
     const bool keep = (a.st.k < 2) && mode == 0;
 
-    // store H (debug) or H and the Crank-Nicolson right-hand side (substep)
-    auto emit = [&](int f, T hval, T gp, T nu_ly) {
-        if (mode == 1) {
-            a.dbg[f][q] = (double)hval;
-            return;
-        }
-        T *__restrict__ hb = (T *)a.h[f];
-        const T hold = use_old ? hb[q] : T(0);
-        a.r[f][q] = (double)(dt * (gam * hval + zet * hold - alp * gp + alp * nu_ly));
-        if (keep) hb[q] = hval;
+    const int j0 = (int)slab * a.slab_rows;
+    const int j1 = (j0 + a.slab_rows < M) ? j0 + a.slab_rows : M;
+    Own<T> o;
+    auto load_row = [&](int j, T &uu, T &vv, T &ww, T &aa, T &bb, T &ff) {
+        const int q = j * pl + e;
+        uu = u[q]; vv = v[q]; ww = w[q]; aa = cp[q]; bb = cm[q]; ff = phi[q];
     };
+    const T zero = T(0);
+    o.um = o.vm = o.wm = o.am = o.bm = o.fm = o.pm = zero;
+    o.up = o.vp = o.wp = o.ap = o.bp = o.fp = zero;
+    if (j0 > 0) {
+        load_row(j0 - 1, o.um, o.vm, o.wm, o.am, o.bm, o.fm);
+        o.pm = p[(j0 - 1) * pl + e];
+    }
+    load_row(j0, o.uc, o.vc, o.wc, o.ac, o.bc, o.fc);
+    o.pc = p[j0 * pl + e];
+    if (j0 + 1 < M) load_row(j0 + 1, o.up, o.vp, o.wp, o.ap, o.bp, o.fp);
 
-    const T uc = u[q], vc = v[q], wc = w[q];
-    const T rho0 = cp[q] - cm[q];
-    const T ph0 = phi[q];
+    for (int j = j0; j < j1; ++j) {
+        const int q = j * pl + e;
+        const int xp = j * pl + exp_, xm = j * pl + exm, zp = j * pl + ezp, zm = j * pl + ezm;
+        const bool has_up = (j + 1 < M), has_dn = (j > 0);
+        const T idn = T(a.tb.idn[j]);
+        const T idcb = T(a.tb.idc[j]), idct = T(a.tb.idc[j + 1]);
+        const T uc = o.uc, vc = o.vc, wc = o.wc;
+        const T rho0 = o.ac - o.bc;
+        const T ph0 = o.fc;
 
-    // ---------------- u on the x-face ----------------
-    {
-        const T uxp = u[xp], uxm = u[xm], uzp = u[zp], uzm = u[zm];
-        const T a1 = half * (uxp + uc), a2 = half * (uc + uxm);
-        const T cx = (a1 * a1 - a2 * a2) * idx_;
-        T flux_t = T(0), flux_b = T(0), ut = T(ph.u_top), ub = T(ph.u_bot);
-        if (has_up) {
-            ut = u[yp];
-            flux_t = half * (v[yp] + v[yp - i + im]) * half * (ut + uc);
-        }
-        if (has_dn) {
-            ub = u[ym];
-            flux_b = half * (vc + v[xm]) * half * (uc + ub);
-        }
-        const T cy = (flux_t - flux_b) * idn;
-        const T wf = half * (w[zp] + w[zp - i + im]);
-        const T wb = half * (wc + w[xm]);
-        const T cz = (wf * half * (uzp + uc) - wb * half * (uc + uzm)) * idz_;
-        const T lap = (uxp - two * uc + uxm) * ix2 + (uzp - two * uc + uzm) * iz2;
-        const T rhox = cp[xm] - cm[xm];
-        const T f = kf * half * (rho0 + rhox) * (ph0 - phi[xm]) * idx_;
-        const T ly = ((ut - uc) * idct - (uc - ub) * idcb) * idn;
-        emit(0, -(cx + cy + cz) + ire * lap + f, (p[q] - p[xm]) * idx_, ire * ly);
-    }
-    // ---------------- w on the z-face ----------------
-    {
-        const T wzp = w[zp], wzm = w[zm], wxp = w[xp], wxm = w[xm];
-        const T a1 = half * (wzp + wc), a2 = half * (wc + wzm);
-        const T cz = (a1 * a1 - a2 * a2) * idz_;
-        const T ur = half * (u[xp] + u[zm - i + ip]);
-        const T ul = half * (uc + u[zm]);
-        const T cx = (ur * half * (wxp + wc) - ul * half * (wc + wxm)) * idx_;
-        T flux_t = T(0), flux_b = T(0), wt = T(0), wb = T(0);
-        if (has_up) {
-            wt = w[yp];
-            flux_t = half * (v[yp] + v[yp + (km - k) * nx]) * half * (wt + wc);
-        }
-        if (has_dn) {
-            wb = w[ym];
-            flux_b = half * (vc + v[zm]) * half * (wc + wb);
-        }
-        const T cy = (flux_t - flux_b) * idn;
-        const T lap = (wxp - two * wc + wxm) * ix2 + (wzp - two * wc + wzm) * iz2;
-        const T rhoz = cp[zm] - cm[zm];
-        const T f = kf * half * (rho0 + rhoz) * (ph0 - phi[zm]) * idz_;
-        const T ly = ((wt - wc) * idct - (wc - wb) * idcb) * idn;
-        emit(2, -(cx + cy + cz) + ire * lap + f, (p[q] - p[zm]) * idz_, ire * ly);
-    }
-    // ---------------- v on the bottom y-face of row j ----------------
-    if (has_dn) {
-        const T vwl = T(a.tb.vwl[j]), vwu = T(a.tb.vwu[j]);
-        const T idn_lo = T(a.tb.idn[j - 1]);
-        const T vtop = has_up ? v[yp] : T(0);
-        const T vbot = (j > 1) ? v[ym] : T(0);
-        const T a1 = half * (vtop + vc), a2 = half * (vc + vbot);
-        const T cy = (a1 * a1 - a2 * a2) * idcb;
-        const T ur = u[ym - i + ip] * vwl + u[xp] * vwu;
-        const T ul = u[ym] * vwl + uc * vwu;
-        const T vxp = v[xp], vxm = v[xm], vzp = v[zp], vzm = v[zm];
-        const T cx = (ur * half * (vxp + vc) - ul * half * (vc + vxm)) * idx_;
-        const T wf = w[ym + (kp - k) * nx] * vwl + w[zp] * vwu;
-        const T wbk = w[ym] * vwl + wc * vwu;
-        const T cz = (wf * half * (vzp + vc) - wbk * half * (vc + vzm)) * idz_;
-        const T lap = (vxp - two * vc + vxm) * ix2 + (vzp - two * vc + vzm) * iz2;
-        const T rhoy = cp[ym] - cm[ym];
-        const T ey = e0 + (ph0 - phi[ym]) * idcb;
-        const T f = kf * half * (rho0 + rhoy) * ey;
-        const T ly = ((vtop - vc) * idn - (vc - vbot) * idn_lo) * idcb;
-        emit(1, -(cx + cy + cz) + ire * lap + f, (p[q] - p[ym]) * idcb, ire * ly);
-    } else {
-        emit(1, T(0), T(0), T(0));
-        if (mode == 0) a.r[1][q] = 0.0;
-    }
-    // ---------------- ions at the cell centre ----------------
-    {
-        const T uxp = u[xp], wzp = w[zp];
-        const T gx_r = (phi[xp] - ph0) * idx_, gx_l = (ph0 - phi[xm]) * idx_;
-        const T gz_f = (phi[zp] - ph0) * idz_, gz_b = (ph0 - phi[zm]) * idz_;
-        const T ey_t = has_up ? e0 + (phi[yp] - ph0) * idct : T(0);
-        const T ey_b = has_dn ? e0 + (ph0 - phi[ym]) * idcb : T(0);
-        const T vt = has_up ? v[yp] : T(0);
-#pragma unroll
-        for (int sp = 0; sp < 2; ++sp) {
-            const T *__restrict__ c = sp == 0 ? cp : cm;
-            const T zs = sp == 0 ? T(1) : T(-1);
-            const T cc = c[q], cxp = c[xp], cxm = c[xm], czp = c[zp], czm = c[zm];
-            const T fxr = half * (cxp + cc), fxl = half * (cc + cxm);
-            const T fzf = half * (czp + cc), fzb = half * (cc + czm);
-            const T ax = (uxp * fxr - uc * fxl) * idx_;
-            const T az = (wzp * fzf - wc * fzb) * idz_;
-            T at = T(0), ab = T(0), mt = T(0), mb = T(0), dft = T(0), dfb = T(0);
+        auto emit = [&](int f, T hval, T gp, T nu_ly) {
+            if (mode == 1) {
+                a.dbg[f][q] = (double)hval;
+                return;
+            }
+            T *__restrict__ hb = (T *)a.h[f];
+            const T hold = use_old ? hb[q] : T(0);
+            a.r[f][q] = (double)(dt * (gam * hval + zet * hold - alp * gp + alp * nu_ly));
+            if (keep) hb[q] = hval;
+        };
+
+        // ---------------- u on the x-face ----------------
+        {
+            const T uxp = u[xp], uxm = u[xm], uzp = u[zp], uzm = u[zm];
+            const T a1 = half * (uxp + uc), a2 = half * (uc + uxm);
+            const T cx = (a1 * a1 - a2 * a2) * idx_;
+            T flux_t = T(0), flux_b = T(0), ut = T(ph.u_top), ub = T(ph.u_bot);
             if (has_up) {
-                const T cu = c[yp];
-                const T fy = half * (cu + cc);
-                at = vt * fy;
-                mt = fy * ey_t;
-                dft = (cu - cc) * idct;
+                ut = o.up;
+                flux_t = half * (o.vp + v[(j + 1) * pl + exm]) * half * (ut + uc);
             }
             if (has_dn) {
-                const T cd = c[ym];
-                const T fy = half * (cc + cd);
-                ab = vc * fy;
-                mb = fy * ey_b;
-                dfb = (cc - cd) * idcb;
+                ub = o.um;
+                flux_b = half * (vc + v[xm]) * half * (uc + ub);
             }
-            const T ay = (at - ab) * idn;
-            const T mx = (fxr * gx_r - fxl * gx_l) * idx_;
-            const T mz = (fzf * gz_f - fzb * gz_b) * idz_;
-            const T my = (mt - mb) * idn;
-            const T dxx = (cxp - two * cc + cxm) * ix2 + (czp - two * cc + czm) * iz2;
-            emit(3 + sp, -(ax + ay + az) + kd * (dxx + zs * (mx + my + mz)), T(0), kd * (dft - dfb) * idn);
+            const T cy = (flux_t - flux_b) * idn;
+            const T wf = half * (w[zp] + w[j * pl + e_im_kp]);
+            const T wb = half * (wc + w[xm]);
+            const T cz = (wf * half * (uzp + uc) - wb * half * (uc + uzm)) * idz_;
+            const T lap = (uxp - two * uc + uxm) * ix2 + (uzp - two * uc + uzm) * iz2;
+            const T rhox = cp[xm] - cm[xm];
+            const T f = kf * half * (rho0 + rhox) * (ph0 - phi[xm]) * idx_;
+            const T ly = ((ut - uc) * idct - (uc - ub) * idcb) * idn;
+            emit(0, -(cx + cy + cz) + ire * lap + f, (o.pc - p[xm]) * idx_, ire * ly);
+        }
+        // ---------------- w on the z-face ----------------
+        {
+            const T wzp = w[zp], wzm = w[zm], wxp = w[xp], wxm = w[xm];
+            const T a1 = half * (wzp + wc), a2 = half * (wc + wzm);
+            const T cz = (a1 * a1 - a2 * a2) * idz_;
+            const T ur = half * (u[xp] + u[j * pl + e_ip_km]);
+            const T ul = half * (uc + u[zm]);
+            const T cx = (ur * half * (wxp + wc) - ul * half * (wc + wxm)) * idx_;
+            T flux_t = T(0), flux_b = T(0), wt = T(0), wb = T(0);
+            if (has_up) {
+                wt = o.wp;
+                flux_t = half * (o.vp + v[(j + 1) * pl + ezm]) * half * (wt + wc);
+            }
+            if (has_dn) {
+                wb = o.wm;
+                flux_b = half * (vc + v[zm]) * half * (wc + wb);
+            }
+            const T cy = (flux_t - flux_b) * idn;
+            const T lap = (wxp - two * wc + wxm) * ix2 + (wzp - two * wc + wzm) * iz2;
+            const T rhoz = cp[zm] - cm[zm];
+            const T f = kf * half * (rho0 + rhoz) * (ph0 - phi[zm]) * idz_;
+            const T ly = ((wt - wc) * idct - (wc - wb) * idcb) * idn;
+            emit(2, -(cx + cy + cz) + ire * lap + f, (o.pc - p[zm]) * idz_, ire * ly);
+        }
+        // ---------------- v on the bottom y-face of row j ----------------
+        if (has_dn) {
+            const T vwl = T(a.tb.vwl[j]), vwu = T(a.tb.vwu[j]);
+            const T idn_lo = T(a.tb.idn[j - 1]);
+            const T vtop = has_up ? o.vp : T(0);
+            const T vbot = (j > 1) ? o.vm : T(0);
+            const T a1 = half * (vtop + vc), a2 = half * (vc + vbot);
+            const T cy = (a1 * a1 - a2 * a2) * idcb;
+            const T ur = u[(j - 1) * pl + exp_] * vwl + u[xp] * vwu;
+            const T ul = o.um * vwl + uc * vwu;
+            const T vxp = v[xp], vxm = v[xm], vzp = v[zp], vzm = v[zm];
+            const T cx = (ur * half * (vxp + vc) - ul * half * (vc + vxm)) * idx_;
+            const T wf = w[(j - 1) * pl + ezp] * vwl + w[zp] * vwu;
+            const T wbk = o.wm * vwl + wc * vwu;
+            const T cz = (wf * half * (vzp + vc) - wbk * half * (vc + vzm)) * idz_;
+            const T lap = (vxp - two * vc + vxm) * ix2 + (vzp - two * vc + vzm) * iz2;
+            const T rhoy = o.am - o.bm;
+            const T ey = e0 + (ph0 - o.fm) * idcb;
+            const T f = kf * half * (rho0 + rhoy) * ey;
+            const T ly = ((vtop - vc) * idn - (vc - vbot) * idn_lo) * idcb;
+            emit(1, -(cx + cy + cz) + ire * lap + f, (o.pc - o.pm) * idcb, ire * ly);
+        } else {
+            emit(1, T(0), T(0), T(0));
+            if (mode == 0) a.r[1][q] = 0.0;
+        }
+        // ---------------- ions at the cell centre ----------------
+        {
+            const T uxp = u[xp], wzp = w[zp];
+            const T gx_r = (phi[xp] - ph0) * idx_, gx_l = (ph0 - phi[xm]) * idx_;
+            const T gz_f = (phi[zp] - ph0) * idz_, gz_b = (ph0 - phi[zm]) * idz_;
+            const T ey_t = has_up ? e0 + (o.fp - ph0) * idct : T(0);
+            const T ey_b = has_dn ? e0 + (ph0 - o.fm) * idcb : T(0);
+            const T vt = has_up ? o.vp : T(0);
+#pragma unroll
+            for (int sp = 0; sp < 2; ++sp) {
+                const T *__restrict__ c = sp == 0 ? cp : cm;
+                const T zs = sp == 0 ? T(1) : T(-1);
+                const T cc = sp == 0 ? o.ac : o.bc;
+                const T cu = sp == 0 ? o.ap : o.bp;
+                const T cd = sp == 0 ? o.am : o.bm;
+                const T cxp = c[xp], cxm = c[xm], czp = c[zp], czm = c[zm];
+                const T fxr = half * (cxp + cc), fxl = half * (cc + cxm);
+                const T fzf = half * (czp + cc), fzb = half * (cc + czm);
+                const T ax = (uxp * fxr - uc * fxl) * idx_;
+                const T az = (wzp * fzf - wc * fzb) * idz_;
+                T at = T(0), ab = T(0), mt = T(0), mb = T(0), dft = T(0), dfb = T(0);
+                if (has_up) {
+                    const T fy = half * (cu + cc);
+                    at = vt * fy;
+                    mt = fy * ey_t;
+                    dft = (cu - cc) * idct;
+                }
+                if (has_dn) {
+                    const T fy = half * (cc + cd);
+                    ab = vc * fy;
+                    mb = fy * ey_b;
+                    dfb = (cc - cd) * idcb;
+                }
+                const T ay = (at - ab) * idn;
+                const T mx = (fxr * gx_r - fxl * gx_l) * idx_;
+                const T mz = (fzf * gz_f - fzb * gz_b) * idz_;
+                const T my = (mt - mb) * idn;
+                const T dxx = (cxp - two * cc + cxm) * ix2 + (czp - two * cc + czm) * iz2;
+                emit(3 + sp, -(ax + ay + az) + kd * (dxx + zs * (mx + my + mz)), T(0), kd * (dft - dfb) * idn);
+            }
+        }
+        // rotate the own-column window and load row j + 2 into the freed slot
+        if (j + 1 < j1) {
+            o.um = o.uc; o.uc = o.up;
+            o.vm = o.vc; o.vc = o.vp;
+            o.wm = o.wc; o.wc = o.wp;
+            o.am = o.ac; o.ac = o.ap;
+            o.bm = o.bc; o.bc = o.bp;
+            o.fm = o.fc; o.fc = o.fp;
+            o.pm = o.pc;
+            o.pc = p[(j + 1) * pl + e];
+            if (j + 2 < M) load_row(j + 2, o.up, o.vp, o.wp, o.ap, o.bp, o.fp);
+            else o.up = o.vp = o.wp = o.ap = o.bp = o.fp = zero;
         }
     }
 }
-
-// ---------------------------------------------------------------------------
-// Crank-Nicolson wall-normal solves (I - alp dt nu / 2 L_y) delta = r, one
-// thread per (x, z) column, q += delta.  The tridiagonal matrix is the same
-// for every column of a field, so its elimination factors c'_j are computed
-// by the block (identically in every thread) and kept in LDS for the back
-// substitution; only d'_j goes through memory (in place in r).
-// ---------------------------------------------------------------------------
 
 struct CnArgs {
     Dims d;
@@ -251,95 +295,175 @@ struct CnArgs {
     void *q[5];
     double *r[5];
     const double *clock;
+    double *coef;  // [3 systems][g, m, n][M] recurrence coefficients of this substep
 };
 
-constexpr int kCnPf = 4;  // rows loaded ahead of the elimination
+// Row coefficients of the Crank-Nicolson matrix (I - beta L_y) of system
+// sys: 0 = cell rows with wall values (u, w), 1 = interior nodes (v),
+// 2 = cell rows with zero-flux walls (c+, c-).
+__device__ __forceinline__ void cn_row(const Tables &tb, int sys, int M, int j, double beta, double &A, double &B,
+                                       double &C) {
+    double lo, up, di;
+    if (sys == 1) {
+        const double aa = tb.lyn_lo[j], cc = tb.lyn_up[j];
+        lo = (j > 1) ? aa : 0.0;
+        up = (j < M - 1) ? cc : 0.0;
+        di = -(aa + cc);
+    } else {
+        const double aa = tb.lyc_lo[j], cc = tb.lyc_up[j];
+        lo = (j > 0) ? aa : 0.0;
+        up = (j < M - 1) ? cc : 0.0;
+        di = -(lo + up);
+        if (sys == 0) {
+            if (j == 0) di -= aa;
+            if (j == M - 1) di -= cc;
+        }
+    }
+    A = -beta * lo;
+    B = 1.0 - beta * di;
+    C = -beta * up;
+}
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_cn_solve(CnArgs a) {
-    extern __shared__ double s_cp[];
-    const int f = blockIdx.y;
-    const Dims &d = a.d;
+// The matrix is the same for every (x, z) column, so Thomas elimination
+// reduces to two linear recurrences with column-independent coefficients:
+//   d'_j = g_j r_j + m_j d'_{j-1},   x_j = d'_j + n_j x_{j+1}
+// with g = 1/den, m = -A/den, n = -c' (den, c' of the Thomas forward pass).
+// One thread per system and member computes them for this substep.
+__global__ void k_cn_coef(Dims d, Tables tb, const Phys *phys, const double *clock, double *coef, double alp,
+                          size_t ms) {
+    const int sys = threadIdx.x;
+    if (sys >= 3) return;
+    phys = member_ptr(phys, ms);
+    clock = member_ptr(clock, ms);
+    coef = member_ptr(coef, ms);
     const int M = d.M;
-    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = col < d.plane;
-    const Phys *ph = member_ptr(a.phys, a.ms);
-    const double dt = member_ptr(a.clock, a.ms)[1];
-    const double nu = (f < 3) ? ph->ire : ph->kd;
-    const double beta = 0.5 * a.st.alp * dt * nu;
-    // system type: 0 Dirichlet centre (u, w), 1 node (v), 2 zero-flux centre (c+-)
+    const double nu = (sys == 2) ? phys->kd : phys->ire;
+    const double beta = 0.5 * alp * clock[1] * nu;
+    double *g = coef + (size_t)sys * 3 * M, *m = g + M, *n = m + M;
+    const int j0 = (sys == 1) ? 1 : 0;
+    double cprev = 0.0;
+    for (int j = j0; j < M; ++j) {
+        double A, B, C;
+        cn_row(tb, sys, M, j, beta, A, B, C);
+        const double den = B - A * cprev;
+        const double cj = C / den;
+        g[j] = 1.0 / den;
+        m[j] = -A / den;
+        n[j] = -cj;
+        cprev = cj;
+    }
+}
+
+constexpr int kCnTx = 16;  // columns staged per block
+
+// Crank-Nicolson solve of one tile of kCnTx columns: the rows of r are staged
+// in LDS with coalesced loads; each wave then solves one column at a time
+// with its rows split into 64 contiguous lane segments.  Each recurrence is
+// a local sweep per lane followed by a 6-step scan of affine maps across the
+// wave (x -> T + Q x composed lane by lane) and a second local sweep from the
+// correct incoming value.  Finally q += x with coalesced stores.
+template <typename T, int kCnMaxR>
+__global__ void __launch_bounds__(256) k_cn_scan(CnArgs a) {
+    extern __shared__ double s_r[];
+    const int f = blockIdx.y;
+    const size_t ms = a.ms;
     const int sys = (f == 1) ? 1 : (f >= 3 ? 2 : 0);
     const int j0 = (sys == 1) ? 1 : 0;
-    double *__restrict__ r = member_ptr(a.r[f], a.ms);
-    T *__restrict__ qf = (T *)member_ptr(a.q[f], a.ms);
-    const int64_t pl = d.plane;
-
-    double cprev = 0.0, dprev = 0.0;
-    double buf[kCnPf];
+    const int M = a.d.M;
+    const int64_t pl = a.d.plane;
+    const int64_t c0 = (int64_t)blockIdx.x * kCnTx;
+    const int ncol = (int)((pl - c0) < kCnTx ? (pl - c0) : kCnTx);
+    const double *__restrict__ r = member_ptr(a.r[f], ms);
+    T *__restrict__ q = (T *)member_ptr(a.q[f], ms);
+    const double *__restrict__ coef = member_ptr(a.coef, ms) + (size_t)sys * 3 * M;
+    const double *__restrict__ cg = coef, *__restrict__ cm = coef + M, *__restrict__ cn = coef + 2 * M;
+    constexpr int LD = kCnTx + 1;
+    const int nrow = M - j0;
+    for (int e = threadIdx.x; e < nrow * kCnTx; e += blockDim.x) {
+        const int jj = j0 + e / kCnTx, c = e % kCnTx;
+        s_r[jj * LD + c] = (c < ncol) ? r[(int64_t)jj * pl + c0 + c] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int R = kCnMaxR;  // rows per lane (the launcher picks ceil(rows / 64))
+    const int js = j0 + lane * R;
+    // this lane's recurrence coefficients (the same for every column)
+    double g[kCnMaxR], mm[kCnMaxR], nn[kCnMaxR];
+    double Qs = 1.0, Ss = 1.0;
 #pragma unroll
-    for (int p = 0; p < kCnPf; ++p) buf[p] = (active && j0 + p < M) ? r[(j0 + p) * pl + col] : 0.0;
-    for (int jb = j0; jb < M; jb += kCnPf) {
+    for (int t = 0; t < kCnMaxR; ++t) {
+        const int j = js + t;
+        const bool in = (t < R) && (j < M);
+        g[t] = in ? cg[j] : 0.0;
+        mm[t] = in ? cm[j] : 1.0;
+        nn[t] = in ? cn[j] : 1.0;
+        Qs *= mm[t];
+        Ss *= nn[t];
+    }
+    // multipliers of the scans of the affine maps x -> T + Q x across lanes
+    // (forward, from lane 0 up) and x -> U + S x (backward, from lane 63 down)
+    double qm[6], sm[6];
 #pragma unroll
-        for (int p = 0; p < kCnPf; ++p) {
-            const int j = jb + p;
-            if (j < M) {
-                const double rj = buf[p];
-                if (active && j + kCnPf < M) buf[p] = r[(j + kCnPf) * pl + col];
-                double lo, up, di;
-                if (sys == 1) {
-                    const double aa = a.tb.lyn_lo[j], cc = a.tb.lyn_up[j];
-                    lo = (j > 1) ? aa : 0.0;
-                    up = (j < M - 1) ? cc : 0.0;
-                    di = -(aa + cc);
-                } else {
-                    const double aa = a.tb.lyc_lo[j], cc = a.tb.lyc_up[j];
-                    lo = (j > 0) ? aa : 0.0;
-                    up = (j < M - 1) ? cc : 0.0;
-                    di = -(lo + up);
-                    if (sys == 0) {
-                        if (j == 0) di -= aa;
-                        if (j == M - 1) di -= cc;
-                    }
-                }
-                const double A = -beta * lo, B = 1.0 - beta * di, C = -beta * up;
-                const double den = B - A * cprev;
-                const double cj = C / den;
-                if (threadIdx.x == 0) s_cp[j] = cj;
-                if (active) {
-                    const double dj = (rj - A * dprev) / den;
-                    r[j * pl + col] = dj;
-                    dprev = dj;
-                }
-                cprev = cj;
-            }
+    for (int st = 0; st < 6; ++st) {
+        const int sft = 1 << st;
+        qm[st] = Qs;
+        sm[st] = Ss;
+        const double Qp = __shfl_up(Qs, sft, 64), Sp = __shfl_down(Ss, sft, 64);
+        if (lane >= sft) Qs *= Qp;
+        if (lane + sft < 64) Ss *= Sp;
+    }
+    for (int c = wave; c < ncol; c += nwave) {
+        double *col = s_r + c;
+        double x[kCnMaxR];
+#pragma unroll
+        for (int t = 0; t < kCnMaxR; ++t) {
+            const int j = js + t;
+            x[t] = (t < R && j < M) ? col[j * LD] : 0.0;
+        }
+        // forward d'_j = g_j r_j + m_j d'_{j-1}: local sweep, scan, sweep
+        double Tf = 0.0;
+#pragma unroll
+        for (int t = 0; t < kCnMaxR; ++t) Tf = g[t] * x[t] + mm[t] * Tf;
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+            const double Tp = __shfl_up(Tf, 1 << st, 64);
+            if (lane >= (1 << st)) Tf += qm[st] * Tp;
+        }
+        double din = __shfl_up(Tf, 1, 64);
+        if (lane == 0) din = 0.0;
+#pragma unroll
+        for (int t = 0; t < kCnMaxR; ++t) {
+            din = g[t] * x[t] + mm[t] * din;
+            x[t] = din;
+        }
+        // backward x_j = d'_j + n_j x_{j+1}
+        double U = 0.0;
+#pragma unroll
+        for (int t = kCnMaxR - 1; t >= 0; --t) U = (g[t] != 0.0 ? x[t] : 0.0) + nn[t] * U;
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+            const double Up = __shfl_down(U, 1 << st, 64);
+            if (lane + (1 << st) < 64) U += sm[st] * Up;
+        }
+        double xin = __shfl_down(U, 1, 64);
+        if (lane == 63) xin = 0.0;
+#pragma unroll
+        for (int t = kCnMaxR - 1; t >= 0; --t) {
+            xin = (g[t] != 0.0 ? x[t] : 0.0) + nn[t] * xin;
+            x[t] = xin;
+        }
+#pragma unroll
+        for (int t = 0; t < kCnMaxR; ++t) {
+            const int j = js + t;
+            if (t < R && j < M) col[j * LD] = x[t];
         }
     }
     __syncthreads();
-    if (!active) return;
-    double xn = 0.0;
-    double bd[kCnPf];
-    T bq[kCnPf];
-#pragma unroll
-    for (int p = 0; p < kCnPf; ++p) {
-        const int j = M - 1 - p;
-        bd[p] = (j >= j0) ? r[j * pl + col] : 0.0;
-        bq[p] = (j >= j0) ? qf[j * pl + col] : T(0);
-    }
-    for (int jb = M - 1; jb >= j0; jb -= kCnPf) {
-#pragma unroll
-        for (int p = 0; p < kCnPf; ++p) {
-            const int j = jb - p;
-            if (j >= j0) {
-                const double dj = bd[p];
-                const T qj = bq[p];
-                if (j - kCnPf >= j0) {
-                    bd[p] = r[(j - kCnPf) * pl + col];
-                    bq[p] = qf[(j - kCnPf) * pl + col];
-                }
-                const double xj = dj - s_cp[j] * xn;
-                qf[j * pl + col] = (T)((double)qj + xj);
-                xn = xj;
-            }
+    for (int e = threadIdx.x; e < nrow * kCnTx; e += blockDim.x) {
+        const int jj = j0 + e / kCnTx, c = e % kCnTx;
+        if (c < ncol) {
+            const int64_t o = (int64_t)jj * pl + c0 + c;
+            q[o] = (T)((double)q[o] + s_r[jj * LD + c]);
         }
     }
 }
@@ -357,21 +481,25 @@ struct CorrArgs {
     double fixed;
     int update_p;
     int advance_clock;
+    int blocks_per_member;
 };
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_correct(CorrArgs a) {
     const Dims &d = a.d;
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+    const unsigned per = (unsigned)a.blocks_per_member;
+    const unsigned mem = tile / per;
+    int64_t q = (int64_t)(tile - mem * per) * blockDim.x + threadIdx.x;
     if (q >= d.n) return;
     const size_t ms = a.ms;
-    double *clock = member_ptr(a.clock, ms);
-    const Phys *ph = member_ptr(a.phys, ms);
+    double *clock = member_ptr_at(a.clock, ms, mem);
+    const Phys *ph = member_ptr_at(a.phys, ms, mem);
     // substep time t += alp dt (dt is read, never written, by this kernel)
     if (a.advance_clock && q == 0) clock[0] += a.alp * clock[1];
-    T *u = (T *)member_ptr(a.u, ms), *v = (T *)member_ptr(a.v, ms), *w = (T *)member_ptr(a.w, ms);
-    T *p = (T *)member_ptr(a.p, ms);
-    const double *psi = member_ptr(a.psi, ms);
+    T *u = (T *)member_ptr_at(a.u, ms, mem), *v = (T *)member_ptr_at(a.v, ms, mem);
+    T *w = (T *)member_ptr_at(a.w, ms, mem), *p = (T *)member_ptr_at(a.p, ms, mem);
+    const double *psi = member_ptr_at(a.psi, ms, mem);
     const Idx x = make_idx(d, q);
     const int j = x.j;
     const double sc = (a.alp > 0.0) ? a.alp * clock[1] : a.fixed;
@@ -411,9 +539,12 @@ hipError_t launch_explicit(nspnp_state *s, const Stage &st, bool /*write_r*/) {
     a.clock = s->clock;
     a.mode = 0;
     const int tb = s->tiles.expl;
-    const dim3 g((unsigned)((s->d.plane + tb - 1) / tb), (unsigned)s->d.M, (unsigned)s->nmem);
-    if (s->fp64) k_explicit<double><<<g, tb, 0, s->stream>>>(a);
-    else k_explicit<float><<<g, tb, 0, s->stream>>>(a);
+    a.chunks = (int)((s->d.plane + tb - 1) / tb);
+    a.slab_rows = s->tiles.slab;
+    a.slabs = (s->d.M + a.slab_rows - 1) / a.slab_rows;
+    const dim3 g((unsigned)((int64_t)a.chunks * a.slabs * s->nmem));
+    if (s->fp64) k_explicit<double, 3><<<g, tb, 0, s->stream>>>(a);
+    else k_explicit<float, 4><<<g, tb, 0, s->stream>>>(a);
     return hipGetLastError();
 }
 
@@ -428,9 +559,12 @@ hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]) {
     for (int q = 0; q < 5; ++q) { a.h[q] = s->h[q]; a.r[q] = s->r[q]; a.dbg[q] = out[q]; }
     a.clock = s->clock;
     a.mode = 1;
-    const dim3 g((unsigned)((s->d.plane + 255) / 256), (unsigned)s->d.M);
-    if (s->fp64) k_explicit<double><<<g, 256, 0, s->stream>>>(a);
-    else k_explicit<float><<<g, 256, 0, s->stream>>>(a);
+    a.chunks = (int)((s->d.plane + 255) / 256);
+    a.slab_rows = s->tiles.slab;
+    a.slabs = (s->d.M + a.slab_rows - 1) / a.slab_rows;
+    const dim3 g((unsigned)((int64_t)a.chunks * a.slabs));
+    if (s->fp64) k_explicit<double, 3><<<g, 256, 0, s->stream>>>(a);
+    else k_explicit<float, 4><<<g, 256, 0, s->stream>>>(a);
     return hipGetLastError();
 }
 
@@ -444,11 +578,31 @@ hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
     a.st = st;
     for (int q = 0; q < 5; ++q) { a.q[q] = s->f[q]; a.r[q] = s->r[q]; }
     a.clock = s->clock;
+    a.coef = s->cn_coef;
+    k_cn_coef<<<dim3(1, 1, (unsigned)s->nmem), 64, 0, s->stream>>>(s->d, s->tb, s->d_phys, s->clock, s->cn_coef,
+                                                                  st.alp, s->mstride);
+    const dim3 g((unsigned)((s->d.plane + kCnTx - 1) / kCnTx), 5, (unsigned)s->nmem);
+    const size_t lds = (size_t)s->d.M * (kCnTx + 1) * sizeof(double);
     const int tb = s->tiles.cn;
-    dim3 g((unsigned)((s->d.plane + tb - 1) / tb), 5, (unsigned)s->nmem);
-    size_t lds = (size_t)s->d.M * sizeof(double);
-    if (s->fp64) k_cn_solve<double><<<g, tb, lds, s->stream>>>(a);
-    else k_cn_solve<float><<<g, tb, lds, s->stream>>>(a);
+    const int rpl = (s->d.M + 63) / 64;  // rows per lane (M <= 480: at most 8)
+#define NSPNP_CN_CASE(RR)                                                              \
+    case RR:                                                                           \
+        if (s->fp64) k_cn_scan<double, RR><<<g, tb, lds, s->stream>>>(a);              \
+        else k_cn_scan<float, RR><<<g, tb, lds, s->stream>>>(a);                       \
+        break;
+    switch (rpl) {
+        NSPNP_CN_CASE(1)
+        NSPNP_CN_CASE(2)
+        NSPNP_CN_CASE(3)
+        NSPNP_CN_CASE(4)
+        NSPNP_CN_CASE(5)
+        NSPNP_CN_CASE(6)
+        NSPNP_CN_CASE(7)
+        NSPNP_CN_CASE(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef NSPNP_CN_CASE
     return hipGetLastError();
 }
 
@@ -467,7 +621,8 @@ hipError_t launch_correct(nspnp_state *s, const Stage &st, bool update_p, double
     a.update_p = update_p ? 1 : 0;
     a.advance_clock = advance_clock ? 1 : 0;
     const int tb = s->tiles.corr;
-    const dim3 g((unsigned)((s->d.n + tb - 1) / tb), 1, (unsigned)s->nmem);
+    a.blocks_per_member = (int)((s->d.n + tb - 1) / tb);
+    const dim3 g((unsigned)((int64_t)a.blocks_per_member * s->nmem));
     if (s->fp64) k_correct<double><<<g, tb, 0, s->stream>>>(a);
     else k_correct<float><<<g, tb, 0, s->stream>>>(a);
     return hipGetLastError();

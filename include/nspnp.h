@@ -117,6 +117,10 @@ NSPNP_API size_t nspnp_workspace_bytes(const nspnp_config *cfg);
 NSPNP_API int nspnp_init_state(const nspnp_config *cfg, void *dev_workspace, size_t bytes, void *hip_stream,
                      nspnp_state **out);
 
+/* Host-only: the ny wall-normal node coordinates yn and the ny-1 cell-centre
+ * coordinates yc of this configuration (caller-owned host arrays). */
+NSPNP_API int nspnp_grid(const nspnp_config *cfg, double *yn, double *yc);
+
 /* Advance n_substeps Runge-Kutta substeps (stage = substep count mod 3, three
  * substeps make one full step dt).  Asynchronous. */
 NSPNP_API int nspnp_step(nspnp_state *s, int32_t n_substeps);
@@ -216,6 +220,9 @@ NSPNP_API int nspnp_ensemble_profiles(nspnp_ensemble *e, int32_t member, double 
                                       double *time_weight);
 /* Single-run diagnostics of one member (see the single-run calls). */
 NSPNP_API int nspnp_ensemble_get_field(nspnp_ensemble *e, int32_t member, int32_t field, double *dev_out);
+NSPNP_API int nspnp_ensemble_set_field(nspnp_ensemble *e, int32_t member, int32_t field, const double *dev_in);
+NSPNP_API int nspnp_ensemble_refresh_potential(nspnp_ensemble *e, int32_t member);
+NSPNP_API int nspnp_ensemble_diagnostics(nspnp_ensemble *e, int32_t member, double out[5]);
 NSPNP_API int nspnp_ensemble_wall_shear_stress(nspnp_ensemble *e, int32_t member, double *tau_bottom,
                                                double *tau_top);
 NSPNP_API int nspnp_ensemble_ion_flux(nspnp_ensemble *e, int32_t member, double *jy_plus, double *jy_minus,

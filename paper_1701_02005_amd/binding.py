@@ -109,6 +109,7 @@ def load_library() -> ctypes.CDLL:
         "nspnp_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(_CConfig)]),
         "nspnp_init_state": (_I, [ctypes.POINTER(_CConfig), _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
         "nspnp_step": (_I, [_P, ctypes.c_int32]),
+        "nspnp_grid": (_I, [ctypes.POINTER(_CConfig), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
         "nspnp_poisson_solve": (_I, [_P, ctypes.c_int32, _P, _P]),
         "nspnp_wall_shear_stress": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
         "nspnp_ion_flux": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D),
@@ -136,6 +137,9 @@ def load_library() -> ctypes.CDLL:
         "nspnp_ensemble_profiles": (_I, [_P, ctypes.c_int32, ctypes.POINTER(_D), ctypes.POINTER(_D),
                                          ctypes.POINTER(_D), ctypes.POINTER(_D)]),
         "nspnp_ensemble_get_field": (_I, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
+        "nspnp_ensemble_set_field": (_I, [_P, ctypes.c_int32, ctypes.c_int32, _P]),
+        "nspnp_ensemble_refresh_potential": (_I, [_P, ctypes.c_int32]),
+        "nspnp_ensemble_diagnostics": (_I, [_P, ctypes.c_int32, ctypes.POINTER(_D)]),
         "nspnp_ensemble_wall_shear_stress": (_I, [_P, ctypes.c_int32, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
         "nspnp_ensemble_ion_flux": (_I, [_P, ctypes.c_int32, ctypes.POINTER(_D), ctypes.POINTER(_D),
                                          ctypes.POINTER(_D), ctypes.POINTER(_D)]),
@@ -166,6 +170,14 @@ def load_library() -> ctypes.CDLL:
 def _check(rc: int):
     if rc != NSPNP_OK:
         raise NsPnpError(rc, load_library().nspnp_last_error().decode())
+
+
+def grid(cfg: Config):
+    """(node coordinates [ny], cell-centre coordinates [ny-1]) of the wall-normal grid."""
+    c = cfg.to_c()
+    yn, yc = (_D * cfg.ny)(), (_D * (cfg.ny - 1))()
+    _check(load_library().nspnp_grid(ctypes.byref(c), yn, yc))
+    return list(yn), list(yc)
 
 
 def workspace_bytes(cfg: Config) -> int:
@@ -343,6 +355,23 @@ class Ensemble:
         _check(self.lib.nspnp_ensemble_get_field(self._h, member, FIELDS[name], ctypes.c_void_p(out.data_ptr())))
         self.sync()
         return out
+
+    def set_field(self, member: int, name: str, value: torch.Tensor):
+        c = self.cfgs[member]
+        if value.dtype != torch.float64 or not value.is_contiguous() or value.numel() != c.cells:
+            raise ValueError("expected a contiguous float64 tensor of nx*nz*(ny-1) values")
+        torch.cuda.synchronize(self.device)
+        _check(self.lib.nspnp_ensemble_set_field(self._h, member, FIELDS[name], ctypes.c_void_p(value.data_ptr())))
+        self.sync()
+
+    def diagnostics(self, member: int) -> Dict[str, float]:
+        """Raises NsPnpError(-4) when the member's state is not finite."""
+        out = (_D * 5)()
+        _check(self.lib.nspnp_ensemble_diagnostics(self._h, member, out))
+        return dict(zip(("ke", "max_div", "min_cp", "min_cm", "max_csum"), list(out)))
+
+    def refresh_potential(self, member: int):
+        _check(self.lib.nspnp_ensemble_refresh_potential(self._h, member))
 
     def wall_shear_stress(self, member: int):
         tb, tt = _D(), _D()

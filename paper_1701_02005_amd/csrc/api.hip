@@ -445,6 +445,29 @@ int nspnp_init_state(const nspnp_config *cfg, void *dev_workspace, size_t bytes,
     return NSPNP_OK;
 }
 
+int nspnp_grid(const nspnp_config *cfg, double *yn, double *yc) {
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    if (!yn || !yc) return fail(NSPNP_ERR_INVALID, "grid: NULL output");
+    nspnp_state tmp;
+    tmp.cfg = *cfg;
+    tmp.d.M = cfg->ny - 1;
+    tmp.d.nxh = cfg->nx / 2 + 1;
+    tmp.d.dx = cfg->lx / cfg->nx;
+    tmp.d.dz = cfg->lz / cfg->nz;
+    std::vector<double> dev_dummy(table_count(tmp.d.M, cfg->nx, cfg->nz));
+    build_tables(&tmp, dev_dummy.data());
+    const int M = tmp.d.M;
+    const double *hyc = tmp.host_tables.data(), *hdn = hyc + M;
+    yn[0] = -1.0;
+    for (int j = 0; j < M; ++j) {
+        yc[j] = hyc[j];
+        yn[j + 1] = yn[j] + hdn[j];
+    }
+    yn[M] = 1.0;
+    return NSPNP_OK;
+}
+
 int nspnp_step(nspnp_state *s, int32_t n_substeps) {
     if (!s || n_substeps < 0) return fail(NSPNP_ERR_INVALID, "bad state or substep count");
     return step_handle(s, n_substeps);

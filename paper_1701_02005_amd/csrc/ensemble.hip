@@ -278,6 +278,18 @@ int nspnp_ensemble_get_field(nspnp_ensemble *e, int32_t member, int32_t field, d
     WITH_VIEW(e, member, nspnp_get_field(v_, field, dev_out));
 }
 
+int nspnp_ensemble_set_field(nspnp_ensemble *e, int32_t member, int32_t field, const double *dev_in) {
+    WITH_VIEW(e, member, nspnp_set_field(v_, field, dev_in));
+}
+
+int nspnp_ensemble_diagnostics(nspnp_ensemble *e, int32_t member, double out[5]) {
+    WITH_VIEW(e, member, nspnp_diagnostics(v_, out));
+}
+
+int nspnp_ensemble_refresh_potential(nspnp_ensemble *e, int32_t member) {
+    WITH_VIEW(e, member, nspnp_refresh_potential(v_));
+}
+
 int nspnp_ensemble_wall_shear_stress(nspnp_ensemble *e, int32_t member, double *tau_bottom, double *tau_top) {
     WITH_VIEW(e, member, nspnp_wall_shear_stress(v_, tau_bottom, tau_top));
 }

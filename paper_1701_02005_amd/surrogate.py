@@ -1,0 +1,359 @@
+"""Learned warm start for new runs.
+
+Pipeline (all GPU work through the HIP library):
+
+1. an ensemble of independent runs over (Re, vhat, Debye length) is advanced
+   together and its time-mean plane profiles of u, rho = c+ - c- and Phi are
+   recorded over the second half of every run;
+2. the profiles are sampled at each run's wall-normal nodes (wall values from
+   the boundary conditions: u = u_bot / u_top, Phi = -+vhat/2, rho linearly
+   extrapolated) and interpolated onto the nodes of the target grid;
+3. a GELU network (BF16 matrix-core kernels, Adam) learns the map from the
+   scaled control parameters to the encoded profiles (u as is, asinh(rho),
+   Phi / (vhat/2 + 1e-6), each standardised);
+4. new runs are initialised from its predictions: u = predicted mean profile
+   plus the same seeded noise as the plain start, c+- rebuilt from rho with
+   c+ c- = A^2 and both ion contents fixed, phi re-solved;
+5. warm and plain starts are advanced side by side and the times after which
+   the mean wall shear stress (and the charge of the lower half gap, the
+   quantity the double layer sets) stay within 1 % of their stationary values
+   are compared.
+
+The stationarity rule: the reference is the mean over the second half of
+the plain run; t* is the first time after which the average over a window
+of `window` time units stays within `tol` of the reference to the end of
+the run (censored at the end when it never does).
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import math
+import time
+from pathlib import Path
+
+import numpy as np
+
+from . import configs
+from .binding import Config, Ensemble, Mlp, grid
+
+SIZES = (3, 256, 256, 256, 256, 579)
+RANGES = {"re": (500.0, 3000.0), "vhat": (0.0, 20.0), "lnlam": (math.log(0.02), math.log(0.2))}
+
+
+# ---------------------------------------------------------------- features
+def scale_inputs(re, vhat, lam) -> np.ndarray:
+    """(Re, vhat, ln lam) mapped linearly onto [-1, 1] over the ensemble ranges."""
+    cols = []
+    for val, key in ((np.asarray(re, float), "re"), (np.asarray(vhat, float), "vhat"),
+                     (np.log(np.asarray(lam, float)), "lnlam")):
+        lo, hi = RANGES[key]
+        cols.append(2.0 * (val - lo) / (hi - lo) - 1.0)
+    return np.stack(cols, axis=-1)
+
+
+def node_profiles(cfg: Config, u_c, rho_c, phi_c):
+    """Cell-row means -> node values including the walls (see module doc)."""
+    yn, yc = (np.asarray(a) for a in grid(cfg))
+    u_c, rho_c, phi_c = (np.asarray(a, float) for a in (u_c, rho_c, phi_c))
+    Phi_c = 0.5 * cfg.vhat * yc + phi_c
+    inner = yn[1:-1]
+    u = np.concatenate([[cfg.u_bot], np.interp(inner, yc, u_c), [cfg.u_top]])
+    Phi = np.concatenate([[-0.5 * cfg.vhat], np.interp(inner, yc, Phi_c), [0.5 * cfg.vhat]])
+    r0 = rho_c[0] + (rho_c[1] - rho_c[0]) * (yn[0] - yc[0]) / (yc[1] - yc[0])
+    r1 = rho_c[-1] + (rho_c[-1] - rho_c[-2]) * (yn[-1] - yc[-1]) / (yc[-1] - yc[-2])
+    rho = np.concatenate([[r0], np.interp(inner, yc, rho_c), [r1]])
+    return yn, u, rho, Phi
+
+
+def encode(u, rho, Phi, vhat) -> np.ndarray:
+    return np.concatenate([u, np.arcsinh(rho), Phi / (0.5 * vhat + 1e-6)])
+
+
+def decode(vec, vhat, n):
+    u = vec[:n]
+    rho = np.sinh(vec[n:2 * n])
+    Phi = vec[2 * n:3 * n] * (0.5 * vhat + 1e-6)
+    return u, rho, Phi
+
+
+@dataclasses.dataclass
+class Standardizer:
+    mean: np.ndarray
+    std: np.ndarray
+
+    @classmethod
+    def fit(cls, Y):
+        return cls(Y.mean(axis=0), np.maximum(Y.std(axis=0), 1e-6))
+
+    def fwd(self, Y):
+        return (Y - self.mean) / self.std
+
+    def inv(self, Z):
+        return Z * self.std + self.mean
+
+
+def ions_from_charge(rho_c, dn):
+    """c+- = (sqrt(rho^2 + 4 A^2) +- rho) / 2 (Boltzmann product c+ c- = A^2),
+    rho shifted to zero net charge, A fixed so that sum(c+- dy) = 2."""
+    rho = np.asarray(rho_c, float)
+    dn = np.asarray(dn, float)
+    rho = rho - np.sum(rho * dn) / np.sum(dn)
+    target = 2.0 * np.sum(dn)  # sum(c+ + c-) dy = 4 over the gap of 2
+
+    def total(A):
+        return np.sum(np.sqrt(rho * rho + 4 * A * A) * dn)
+
+    lo, hi = 0.0, 1.0
+    while total(hi) < target:
+        hi *= 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if total(mid) < target:
+            lo = mid
+        else:
+            hi = mid
+    A = 0.5 * (lo + hi)
+    s = np.sqrt(rho * rho + 4 * A * A)
+    return 0.5 * (s + rho), 0.5 * (s - rho), A
+
+
+def stationary_time(t, series, ref, window, tol):
+    """First time after which the trailing-window average stays within tol*|ref|."""
+    t = np.asarray(t, float)
+    s = np.asarray(series, float)
+    ok = np.zeros(len(t), bool)
+    for q in range(len(t)):
+        sel = (t > t[q] - window) & (t <= t[q])
+        avg = s[sel].mean()
+        ok[q] = abs(avg - ref) <= tol * abs(ref) and t[q] - t[0] >= min(window, t[-1] - t[0])
+    bad = np.nonzero(~ok)[0]
+    if len(bad) == 0:
+        return float(t[0]), False
+    last_bad = bad[-1]
+    if last_bad == len(t) - 1:
+        return float(t[-1]), True  # censored
+    return float(t[last_bad + 1]), False
+
+
+# ---------------------------------------------------------------- stages
+def ensemble_data(seed: int, substeps: int, stats_from: int, target_ny: int, log=print, tune_cache=None):
+    members = configs.ensemble_members(seed)
+    t0 = time.perf_counter()
+    ens = Ensemble(members)
+    tiles = ens.autotune(tune_cache, 6)
+    done = ens.clock(0)[2]
+    first = (max(stats_from, done) - done) // 30 * 30
+    ens.capture(30)
+    ens.step(first)
+    ens.stats(True)          # statistics over the rest of the run
+    ens.capture(30)          # the replayed graph now includes the statistics kernel
+    ens.step(substeps - done - first)
+    ens.sync()
+    wall = time.perf_counter() - t0
+    tgt = dataclasses.replace(configs.couette_turbulent(), ny=target_ny)
+    y_t, _ = grid(tgt)
+    X, Y, meta = [], [], []
+    for m, c in enumerate(members):
+        u_c, rho_c, phi_c, wt = ens.profiles(m)
+        yn, u, rho, Phi = node_profiles(c, u_c, rho_c, phi_c)
+        ui, ri, Pi = (np.interp(y_t, yn, f) for f in (u, rho, Phi))
+        X.append((c.re, c.vhat, c.debye))
+        Y.append(encode(ui, ri, Pi, c.vhat))
+        t_m, dt_m, _ = ens.clock(m)
+        try:
+            dg = ens.diagnostics(m)
+        except Exception as exc:  # non-finite member
+            dg = {"error": str(exc)}
+        meta.append({"re": c.re, "vhat": c.vhat, "debye": c.debye, "grid": f"{c.nx}x{c.ny}x{c.nz}",
+                     "time_averaged": wt, "t_end": t_m, "dt_end": dt_m, "diagnostics": dg})
+    points = sum(c.points for c in members) * substeps
+    log(f"ensemble: {len(members)} runs, {substeps} substeps in {wall:.1f} s "
+        f"({points / wall / 1e6:.0f} Mpoint-substeps/s incl. autotune and capture)")
+    info = {"members": len(members), "substeps": substeps, "stats_from": stats_from, "wall_s": wall,
+            "mpoint_substeps_per_s": points / wall / 1e6, "tiles": tiles, "runs": meta}
+    return np.array(X), np.array(Y), np.asarray(y_t), info
+
+
+def init_params(sizes, seed):
+    """He-style uniform initialisation (W [in, out], zero biases), flattened."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for fin, fout in zip(sizes[:-1], sizes[1:]):
+        b = math.sqrt(6.0 / fin)
+        out.append(rng.uniform(-b, b, (fin, fout)).ravel())
+        out.append(np.zeros(fout))
+    return np.concatenate(out).astype(np.float32)
+
+
+def train_network(X, Y, steps: int, lr: float, seed: int, log=print):
+    import torch
+    xs = scale_inputs(X[:, 0], X[:, 1], X[:, 2]).astype(np.float32)
+    std = Standardizer.fit(Y)
+    ys = std.fwd(Y).astype(np.float32)
+    net = Mlp(SIZES, max(64, len(xs)), init_params(SIZES, seed))
+    xt = torch.tensor(xs, device=net.device)
+    yt = torch.tensor(ys, device=net.device)
+    losses = []
+    t0 = time.perf_counter()
+    for it in range(steps):
+        lt = net.train_step(xt, yt, lr)
+        if it % 250 == 0 or it == steps - 1:
+            losses.append((it, float(lt.item())))
+    net.sync()
+    wall = time.perf_counter() - t0
+    final = net.gradients(xt, yt)
+    log(f"training: {steps} Adam steps in {wall:.2f} s, loss {losses[0][1]:.3e} -> {final:.3e}")
+    return net, std, {"steps": steps, "lr": lr, "wall_s": wall, "loss_curve": losses, "final_loss": final}
+
+
+def predict(net, std, X):
+    import torch
+    xs = torch.tensor(scale_inputs(X[:, 0], X[:, 1], X[:, 2]).astype(np.float32), device=net.device)
+    out = net.forward(xs).cpu().numpy().astype(np.float64)
+    return std.inv(out)
+
+
+def test_members(seed: int, n: int, precision: str):
+    """Unseen parameter points (same sampler, another seed) on the 256x193x256 grid."""
+    base = configs.couette_turbulent(precision=precision)
+    pts = configs.ensemble_members(seed, n_large=n, n_small=0)
+    return [dataclasses.replace(base, re=p.re, vhat=p.vhat, debye=p.debye, seed=base.seed + 7 * q)
+            for q, p in enumerate(pts)]
+
+
+def warm_start(ens: Ensemble, members, preds, y_t, log=print):
+    import torch
+    for m, (c, vec) in enumerate(zip(members, preds)):
+        u_t, rho_t, Phi_t = decode(vec, c.vhat, len(y_t))
+        yn, yc = (np.asarray(a) for a in grid(c))
+        dn = np.diff(yn)
+        u_new = np.interp(yc, y_t, u_t)
+        u_lin = 0.5 * (c.u_top + c.u_bot) + 0.5 * (c.u_top - c.u_bot) * yc
+        cp_new, cm_new, _ = ions_from_charge(np.interp(yc, y_t, rho_t), dn)
+        shape = (c.ny - 1, c.nz, c.nx)
+        u = ens.get_field(m, "u") + torch.tensor(u_new - u_lin, device=ens.device).view(-1, 1, 1)
+        cp = ens.get_field(m, "cp") - 1.0 + torch.tensor(cp_new, device=ens.device).view(-1, 1, 1)
+        cm = ens.get_field(m, "cm") - 1.0 + torch.tensor(cm_new, device=ens.device).view(-1, 1, 1)
+        for name, val in (("u", u), ("cp", cp), ("cm", cm)):
+            ens.set_field(m, name, val.reshape(shape).contiguous())
+        ens.refresh_potential(m)
+    ens.sync()
+
+
+def monitor(ens: Ensemble, members, chunk: int, t_end: float, log=print):
+    """Advance until every member reaches t_end; per chunk record the
+    chunk-mean wall shear stress and lower-half charge of every member."""
+    out = [{"t": [], "tau": [], "q": []} for _ in members]
+    geo = []
+    for c in members:
+        yn, yc = (np.asarray(a) for a in grid(c))
+        geo.append((yn, yc, np.diff(yn)))
+    t0 = time.perf_counter()
+    nsub = 0
+    while True:
+        ens.stats(True)
+        ens.step(chunk)
+        nsub += chunk
+        tmin = math.inf
+        for m, c in enumerate(members):
+            u, rho, phi, wt = ens.profiles(m)
+            yn, yc, dn = geo[m]
+            t = ens.clock(m)[0]
+            tb = (u[0] - c.u_bot) / (c.re * (yc[0] - yn[0]))
+            tt = (c.u_top - u[-1]) / (c.re * (yn[-1] - yc[-1]))
+            lower = yc < 0
+            out[m]["t"].append(t)
+            out[m]["tau"].append(0.5 * (tb + tt))
+            out[m]["q"].append(float(np.sum(np.asarray(rho)[lower] * dn[lower])))
+            out[m].setdefault("prof", []).append((wt, u, rho, phi))
+            tmin = min(tmin, t)
+        if tmin >= t_end:
+            break
+    ens.sync()
+    wall = time.perf_counter() - t0
+    return out, nsub, wall
+
+
+def run(out_path: str, seed: int = 0, ens_substeps: int = 5000, stats_from: int = 2500, train_steps: int = 3000,
+        lr: float = 1e-3, n_test: int = 8, t_end: float = 30.0, chunk: int = 60, window: float = 5.0,
+        tol: float = 0.01, precision: str = "mixed", log=print):
+    report = {"seed": seed}
+    X, Y, y_t, report["ensemble"] = ensemble_data(seed, ens_substeps, stats_from, 193, log)
+    net, std, report["training"] = train_network(X, Y, train_steps, lr, seed, log)
+    members = test_members(seed + 1, n_test, precision)
+    Xt = np.array([(c.re, c.vhat, c.debye) for c in members])
+    preds = predict(net, std, Xt)
+    log(f"test points: {[(round(c.re), round(c.vhat, 2), round(c.debye, 4)) for c in members]}")
+    results = {}
+    for label in ("plain", "warm"):
+        ens = Ensemble(members)
+        if label == "warm":
+            t0 = time.perf_counter()
+            warm_start(ens, members, preds, y_t, log)
+            results["warm_init_s"] = time.perf_counter() - t0
+        ens.stats(True)
+        ens.capture(chunk)
+        series, nsub, wall = monitor(ens, members, chunk, t_end, log)
+        results[label] = (series, nsub, wall)
+        log(f"{label}: {nsub} substeps per run to t >= {t_end} in {wall:.1f} s")
+        del ens
+    plain, _, wall_p = results["plain"]
+    warm, _, wall_w = results["warm"]
+    per = []
+    for m, c in enumerate(members):
+        ps, ws = plain[m], warm[m]
+        tp = np.array(ps["t"])
+        half = tp >= 0.5 * tp[-1]
+        rec = {"re": c.re, "vhat": c.vhat, "debye": c.debye}
+        for key in ("tau", "q"):
+            ref = float(np.mean(np.array(ps[key])[half]))
+            t_p, cen_p = stationary_time(ps["t"], ps[key], ref, window, tol)
+            t_w, cen_w = stationary_time(ws["t"], ws[key], ref, window, tol)
+            n_p = int(np.searchsorted(tp, t_p)) * chunk
+            n_w = int(np.searchsorted(np.array(ws["t"]), t_w)) * chunk
+            rec[key] = {"ref": ref, "t_plain": t_p, "t_warm": t_w, "censored_plain": cen_p, "censored_warm": cen_w,
+                        "substeps_plain": n_p, "substeps_warm": n_w,
+                        "wall_plain_s": wall_p * n_p / max(1, len(tp) * chunk),
+                        "wall_warm_s": wall_w * n_w / max(1, len(ws["t"]) * chunk)}
+        # profile error of the prediction against the plain run's late-time mean
+        late = [p for p, h in zip(ps["prof"], half) if h]
+        wts = np.array([p[0] for p in late])
+        prof = [np.sum([w * np.asarray(p[i]) for w, p in zip(wts, late)], axis=0) / wts.sum() for i in (1, 2, 3)]
+        yn, u, rho, Phi = node_profiles(c, *prof)
+        truth = [np.interp(y_t, yn, f) for f in (u, rho, Phi)]
+        pu, pr, pP = decode(preds[m], c.vhat, len(y_t))
+        rec["profile_rel_l2"] = {k: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+                                 for k, a, b in (("u", pu, truth[0]), ("rho", pr, truth[1]), ("Phi", pP, truth[2]))}
+        per.append(rec)
+        log(f"point {m}: Re={c.re:.0f} vhat={c.vhat:.2f} lam={c.debye:.4f}  "
+            f"drag t*: plain {rec['tau']['t_plain']:.2f} warm {rec['tau']['t_warm']:.2f} | "
+            f"charge t*: plain {rec['q']['t_plain']:.2f}{'(c)' if rec['q']['censored_plain'] else ''} "
+            f"warm {rec['q']['t_warm']:.2f}{'(c)' if rec['q']['censored_warm'] else ''} | "
+            f"L2 u {rec['profile_rel_l2']['u']:.2e} rho {rec['profile_rel_l2']['rho']:.2e} "
+            f"Phi {rec['profile_rel_l2']['Phi']:.2e}")
+    report["test"] = {"points": per, "t_end": t_end, "window": window, "tol": tol, "chunk": chunk,
+                      "wall_plain_s": wall_p, "wall_warm_s": wall_w, "warm_init_s": results.get("warm_init_s")}
+    Path(out_path).parent.mkdir(parents=True, exist_ok=True)
+    Path(out_path).write_text(json.dumps(report, indent=1, default=float))
+    return report
+
+
+def main():
+    ap = argparse.ArgumentParser(description="ensemble -> surrogate network -> warm-started runs")
+    ap.add_argument("--out", default="gpurun_out/surrogate_report.json")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--ens-substeps", type=int, default=5000)
+    ap.add_argument("--stats-from", type=int, default=2500)
+    ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--n-test", type=int, default=8)
+    ap.add_argument("--t-end", type=float, default=30.0)
+    args = ap.parse_args()
+    run(args.out, seed=args.seed, ens_substeps=args.ens_substeps, stats_from=args.stats_from,
+        train_steps=args.train_steps, n_test=args.n_test, t_end=args.t_end,
+        log=lambda s: print(s, flush=True))
+
+
+if __name__ == "__main__":
+    main()

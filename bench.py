@@ -39,7 +39,8 @@ def kernel_bytes(cfg, name: str, launches: int, substeps: int) -> float:
     (divergence) and c+, c- (charge) and writes two half spectra; fft_z_*
     and thomas_modes read and write both half spectra once; fft_x_c2r reads
     them and writes psi (FP64) and phi (state); correct reads psi and
-    updates u, v, w, p; dt reads u, v, w, c+, c- once per three substeps.
+    updates u, v, w, p; dt (with the health check) reads u, v, w, c+, c-, phi
+    once per three substeps.
     """
     w = 8 if cfg.precision == "fp64" else 4
     n = cfg.nx * cfg.nz * (cfg.ny - 1)
@@ -53,12 +54,12 @@ def kernel_bytes(cfg, name: str, launches: int, substeps: int) -> float:
         "fft_z_inv": 4 * sp,
         "fft_x_c2r": 2 * sp + 8 + w,
         "correct": 8 + 8 * w,
-        "dt": 5 * w,
+        "dt": 6 * w,
     }.get(name, 0.0)
     return per * n * launches
 
 
-def cpu_baseline(cfg, nsub: int = 3) -> dict:
+def cpu_baseline(cfg, nsub: int = 12) -> dict:
     """The FP64 oracle as it stands, on all host cores, on a bounded sample."""
     from oracle import oracle as O
     threads = os.cpu_count() or 1
@@ -70,7 +71,7 @@ def cpu_baseline(cfg, nsub: int = 3) -> dict:
     el = time.perf_counter() - t0
     return {"value": cfg.points * nsub / el / 1e6, "unit": "Mpoint-substeps/s", "cores": O.num_threads(),
             "kind": "oracle",
-            "sample": f"{nsub} substeps (one full RK3 step) of the {cfg.nx}x{cfg.ny}x{cfg.nz} case from its "
+            "sample": f"{nsub} substeps ({nsub // 3} full RK3 steps) of the {cfg.nx}x{cfg.ny}x{cfg.nz} case from its "
                       f"seeded initial state, FP64, {el:.1f} s"}
 
 
@@ -152,14 +153,18 @@ def main():
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     per_launch_bytes = dom_bytes / dom_cnt
 
+    # HBM bytes per launch from the rocprofv3 counter runs, while the kernel
+    # source they were taken from is unchanged
     traffic = None
     tr_file = ROOT / "profiles" / "traffic.json"
     if tr_file.exists():
         try:
-            tr = json.loads(tr_file.read_text())
-            key = f"{args.workload}/{args.precision}/{dom}"
-            traffic = tr.get(key)
-        except (ValueError, OSError):
+            from paper_1701_02005_amd import pmc_traffic
+            ent = json.loads(tr_file.read_text()).get(f"{args.workload}/{args.precision}/{dom}")
+            src = Path(ent["source"]).name if ent else None
+            if ent and ent.get("source_sha256") == pmc_traffic.source_hash(src):
+                traffic = ent["bytes_per_launch"]
+        except (ValueError, OSError, KeyError):
             traffic = None
 
     value = cfg.points * args.steps / (ms * 1e-3) / 1e6
@@ -181,7 +186,7 @@ def main():
                    "points": cfg.points, "cells": cfg.cells, "precision": args.precision,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes/launch",
                      "algorithmic_bytes_per_launch": per_launch_bytes,
                      "avg_launch_ms": dom_ms / dom_cnt},
         "substep_roofline": {"algorithmic_GBs": total_bytes / (ms_prof * 1e-3) / 1e9,

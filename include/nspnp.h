@@ -122,7 +122,17 @@ NSPNP_API int nspnp_init_state(const nspnp_config *cfg, void *dev_workspace, siz
 NSPNP_API int nspnp_grid(const nspnp_config *cfg, double *yn, double *yc);
 
 /* Advance n_substeps Runge-Kutta substeps (stage = substep count mod 3, three
- * substeps make one full step dt).  Asynchronous. */
+ * substeps make one full step dt).  Asynchronous.
+ * Health check: at the first stage of every step a device reduction (the
+ * one that also evaluates the adaptive dt rule) looks at every cell and sets
+ * a sticky flag when a field value or the step is not finite or a
+ * concentration is negative.  The flag is copied back behind the queued
+ * work; nspnp_step returns NSPNP_ERR_NONFINITE, with a message naming the
+ * fault, from the first call that starts after the copy has landed, and
+ * nspnp_sync, which waits for the copy, from its next call.  The run stays
+ * flagged until
+ * nspnp_set_clock (or a new init).  The same check records the largest
+ * potential difference across one cell face (nspnp_diagnostics out[5]). */
 NSPNP_API int nspnp_step(nspnp_state *s, int32_t n_substeps);
 
 /* Solve the elliptic problem of the pressure projection (kind 0) or of the
@@ -165,14 +175,31 @@ NSPNP_API int nspnp_explicit_terms(nspnp_state *s, double *const dev_out[5]);
 
 /* Scalar diagnostics, FP64, synchronising: out[0] kinetic energy
  * 1/2 sum(|u|^2 Omega), out[1] max |div u| over the cells, out[2] min c+,
- * out[3] min c-, out[4] max(c+ + c-).  Returns NSPNP_ERR_NONFINITE if any
- * is not finite. */
-NSPNP_API int nspnp_diagnostics(nspnp_state *s, double out[5]);
+ * out[3] min c-, out[4] max(c+ + c-), out[5] the largest difference of the
+ * total potential Phi across an interior cell face (x, z or y).  out[5] is
+ * the cell Peclet number of migration: the central face value of c in the
+ * migration flux (Sec. II) keeps concentrations positive at equilibrium only
+ * while it stays below 2.  Returns NSPNP_ERR_NONFINITE if any is not
+ * finite. */
+NSPNP_API int nspnp_diagnostics(nspnp_state *s, double out[6]);
 
 /* Simulation clock: time, current full step dt, next stage (0..2), substeps
- * taken.  get synchronises; set is used to restart from saved fields. */
+ * taken.  get synchronises; set is used to restart from saved fields and
+ * clears the health flag (see nspnp_step). */
 NSPNP_API int nspnp_get_clock(nspnp_state *s, double *t, double *dt, int32_t *stage, int64_t *substeps);
 NSPNP_API int nspnp_set_clock(nspnp_state *s, double t, double dt, int32_t stage, int64_t substeps);
+
+/* Checkpoint of a run: the seven fields and the five explicit-term buffers
+ * H (kept between the stages of a Runge-Kutta step) in the storage type,
+ * the clock and the substep count, written to the file at path as a small
+ * header followed by raw little-endian arrays.  nspnp_load restores it into
+ * a handle initialised with the same configuration (seed and noise
+ * amplitudes may differ); the run then continues bit for bit as the saved
+ * one would have.  Time statistics of ensembles are not part of it.  Both
+ * synchronise; NSPNP_ERR_INVALID for an unreadable, foreign or mismatching
+ * file. */
+NSPNP_API int nspnp_save(nspnp_state *s, const char *path);
+NSPNP_API int nspnp_load(nspnp_state *s, const char *path);
 
 /* Kernel timing with HIP events recorded on the solver's stream around every
  * kernel launch (off by default).  enable(1) clears the totals and starts
@@ -203,8 +230,13 @@ NSPNP_API size_t nspnp_ensemble_workspace_bytes(const nspnp_config *cfgs, int32_
 NSPNP_API int nspnp_ensemble_init(const nspnp_config *cfgs, int32_t n, void *dev_workspace, size_t bytes,
                                   void *hip_stream, nspnp_ensemble **out);
 /* Advance every member n_substeps substeps (replaying the captured graph for
- * whole multiples of its length when one exists).  Asynchronous. */
+ * whole multiples of its length when one exists).  Asynchronous.  Health
+ * checks as for nspnp_step; the message names the first flagged member.
+ * A flagged ensemble stays flagged. */
 NSPNP_API int nspnp_ensemble_step(nspnp_ensemble *e, int32_t n_substeps);
+/* Wait for the queued work of every member; NSPNP_ERR_NONFINITE if a health
+ * check has flagged a member. */
+NSPNP_API int nspnp_ensemble_sync(nspnp_ensemble *e);
 /* Capture substeps_per_replay substeps (a multiple of 3, from the start of a
  * Runge-Kutta step) of all members into one hipGraph, replayed by step().
  * Nothing is executed by the capture itself. */
@@ -222,7 +254,7 @@ NSPNP_API int nspnp_ensemble_profiles(nspnp_ensemble *e, int32_t member, double 
 NSPNP_API int nspnp_ensemble_get_field(nspnp_ensemble *e, int32_t member, int32_t field, double *dev_out);
 NSPNP_API int nspnp_ensemble_set_field(nspnp_ensemble *e, int32_t member, int32_t field, const double *dev_in);
 NSPNP_API int nspnp_ensemble_refresh_potential(nspnp_ensemble *e, int32_t member);
-NSPNP_API int nspnp_ensemble_diagnostics(nspnp_ensemble *e, int32_t member, double out[5]);
+NSPNP_API int nspnp_ensemble_diagnostics(nspnp_ensemble *e, int32_t member, double out[6]);
 NSPNP_API int nspnp_ensemble_wall_shear_stress(nspnp_ensemble *e, int32_t member, double *tau_bottom,
                                                double *tau_top);
 NSPNP_API int nspnp_ensemble_ion_flux(nspnp_ensemble *e, int32_t member, double *jy_plus, double *jy_minus,

@@ -123,6 +123,8 @@ def load_library() -> ctypes.CDLL:
                                  ctypes.POINTER(ctypes.c_int64)]),
         "nspnp_set_clock": (_I, [_P, _D, _D, ctypes.c_int32, ctypes.c_int64]),
         "nspnp_sync": (_I, [_P]),
+        "nspnp_save": (_I, [_P, ctypes.c_char_p]),
+        "nspnp_load": (_I, [_P, ctypes.c_char_p]),
         "nspnp_profile_enable": (_I, [_P, ctypes.c_int32]),
         "nspnp_profile_read": (_I, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_char_p),
                                     ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_int64)]),
@@ -132,6 +134,7 @@ def load_library() -> ctypes.CDLL:
         "nspnp_ensemble_init": (_I, [ctypes.POINTER(_CConfig), ctypes.c_int32, _P, ctypes.c_size_t, _P,
                                      ctypes.POINTER(_P)]),
         "nspnp_ensemble_step": (_I, [_P, ctypes.c_int32]),
+        "nspnp_ensemble_sync": (_I, [_P]),
         "nspnp_ensemble_capture": (_I, [_P, ctypes.c_int32]),
         "nspnp_ensemble_stats": (_I, [_P, ctypes.c_int32]),
         "nspnp_ensemble_profiles": (_I, [_P, ctypes.c_int32, ctypes.POINTER(_D), ctypes.POINTER(_D),
@@ -165,6 +168,9 @@ def load_library() -> ctypes.CDLL:
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+DIAGNOSTIC_NAMES = ("ke", "max_div", "min_cp", "min_cm", "max_csum", "max_dphi")
 
 
 def _check(rc: int):
@@ -264,9 +270,11 @@ class Solver:
         return dict(zip(("u", "v", "w", "cp", "cm"), outs))
 
     def diagnostics(self) -> Dict[str, float]:
-        out = (_D * 5)()
+        """Kinetic energy, max |div u|, min c+, min c-, max(c+ + c-) and the
+        largest potential difference across one cell face (max_dphi)."""
+        out = (_D * 6)()
         _check(self.lib.nspnp_diagnostics(self._h, out))
-        return dict(zip(("ke", "max_div", "min_cp", "min_cm", "max_csum"), list(out)))
+        return dict(zip(DIAGNOSTIC_NAMES, list(out)))
 
     def clock(self):
         t, dt, st, ns = _D(), _D(), ctypes.c_int32(), ctypes.c_int64()
@@ -278,7 +286,17 @@ class Solver:
         _check(self.lib.nspnp_set_clock(self._h, t, dt, int(stage), int(substeps)))
 
     def sync(self):
+        """Waits for the queued work; NsPnpError(-4) once a health check has
+        flagged the run."""
         _check(self.lib.nspnp_sync(self._h))
+
+    def save(self, path: str):
+        """Checkpoint (fields, H buffers, clock) to a file."""
+        _check(self.lib.nspnp_save(self._h, str(path).encode()))
+
+    def load(self, path: str):
+        """Restore a checkpoint written for the same configuration."""
+        _check(self.lib.nspnp_load(self._h, str(path).encode()))
 
     def profile_enable(self, on: bool = True):
         _check(self.lib.nspnp_profile_enable(self._h, 1 if on else 0))
@@ -330,7 +348,9 @@ class Ensemble:
         return len(self.cfgs)
 
     def sync(self):
-        self.stream.synchronize()
+        """Waits for every member; NsPnpError(-4) once a health check has
+        flagged a member."""
+        _check(self.lib.nspnp_ensemble_sync(self._h))
 
     def step(self, n_substeps: int):
         _check(self.lib.nspnp_ensemble_step(self._h, int(n_substeps)))
@@ -366,9 +386,9 @@ class Ensemble:
 
     def diagnostics(self, member: int) -> Dict[str, float]:
         """Raises NsPnpError(-4) when the member's state is not finite."""
-        out = (_D * 5)()
+        out = (_D * 6)()
         _check(self.lib.nspnp_ensemble_diagnostics(self._h, member, out))
-        return dict(zip(("ke", "max_div", "min_cp", "min_cm", "max_csum"), list(out)))
+        return dict(zip(DIAGNOSTIC_NAMES, list(out)))
 
     def refresh_potential(self, member: int):
         _check(self.lib.nspnp_ensemble_refresh_potential(self._h, member))

@@ -91,10 +91,10 @@ Layout make_layout(const nspnp_config *c) {
     L.off_spec = o; o = align256(o + 2 * nspec * 16);
     L.off_cpr = o; o = align256(o + 2 * nspec * 8);
     L.off_coef = o; o = align256(o + 9 * M * 8);
-    L.off_clock = o; o = align256(o + 4 * 8);
+    L.off_clock = o; o = align256(o + kClockSlots * 8);
     L.off_phys = o; o = align256(o + sizeof(Phys));
     L.off_stats = o; o = align256(o + (3 * M + 2) * 8);
-    L.nred = std::max<int64_t>(2 * 1024, M * 10);
+    L.nred = std::max<int64_t>(kDtParts * kDtMaxBlocks, M * kPlaneQ);
     L.off_red = o; o = align256(o + L.nred * 8);
     L.ntab = 11 * M + 2 + nxh + c->nz + 2 * c->nx + 2 * c->nz;
     L.off_tab = o; o = align256(o + L.ntab * 8);
@@ -172,7 +172,7 @@ const double *host_dc(const nspnp_state *s) { return s->host_tables.data() + 2 *
 
 int plane_reduce(nspnp_state *s, std::vector<double> &host) {
     HIP_TRY(launch_plane_sums(s, 0, s->red));
-    host.resize((size_t)s->d.M * 10);
+    host.resize((size_t)s->d.M * kPlaneQ);
     HIP_TRY(hipMemcpyAsync(host.data(), s->red, host.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     return NSPNP_OK;
@@ -296,6 +296,8 @@ nspnp_state *member_view(const nspnp_state *cls, int m, const nspnp_config *cfg)
     v->red = sh(cls->red);
     v->nmem = 1;
     v->mstride = 0;
+    v->host_health = cls->host_health ? cls->host_health + 2 * (size_t)m : nullptr;
+    v->owns_host_health = false;
     if (cfg) {
         v->cfg = *cfg;
         v->ph = make_phys(cfg);
@@ -307,7 +309,7 @@ nspnp_state *member_view(const nspnp_state *cls, int m, const nspnp_config *cfg)
 // boundary conditions; noise recipe in include/nspnp.h).
 int init_member(nspnp_state *s) {
     const Dims &d = s->d;
-    const double clock0[4] = {0.0, s->cfg.dt > 0.0 ? s->cfg.dt : 0.0, 0.0, 0.0};
+    const double clock0[kClockSlots] = {0.0, s->cfg.dt > 0.0 ? s->cfg.dt : 0.0, 0.0, 0.0};
     HIP_TRY(hipMemcpyAsync(s->clock, clock0, sizeof(clock0), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(s->d_phys, &s->ph, sizeof(Phys), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(launch_init_fields(s));
@@ -318,8 +320,8 @@ int init_member(nspnp_state *s) {
     double sp = 0.0, sm = 0.0, vol = 0.0;
     for (int j = 0; j < d.M; ++j) {
         const double dn = host_dn(s)[j];
-        sp += ps[j * 10 + 1] * dn;
-        sm += ps[j * 10 + 2] * dn;
+        sp += ps[j * kPlaneQ + PQ_SUM_CP] * dn;
+        sm += ps[j * kPlaneQ + PQ_SUM_CM] * dn;
         vol += dn * (double)d.plane;
     }
     HIP_TRY(launch_shift_conc(s, sp / vol, sm / vol));
@@ -337,11 +339,10 @@ int init_member(nspnp_state *s) {
 
 // n Runge-Kutta substeps of every member of the handle.
 int step_handle(nspnp_state *s, int n) {
-    const bool adaptive = s->cfg.dt <= 0.0;
     for (int it = 0; it < n; ++it) {
         const int k = (int)(s->substeps % 3);
         const Stage st{kGam[k], kZet[k], kGam[k] + kZet[k], k};
-        if (k == 0 && adaptive) HIP_TRY(launch_dt(s));
+        if (k == 0) HIP_TRY(launch_dt(s));  // dt rule (adaptive runs) and health check
         HIP_TRY(launch_explicit(s, st, true));
         HIP_TRY(launch_cn_solve(s, st));
         // pressure projection and potential depend only on the updated
@@ -364,10 +365,48 @@ int step_handle(nspnp_state *s, int n) {
     return NSPNP_OK;
 }
 
+int health_error(int bits, int member) {
+    std::string m = "run";
+    if (member >= 0) m += " (ensemble member " + std::to_string(member) + ")";
+    if (bits & kHealthNonFinite) m += " produced a non-finite value";
+    if (bits & kHealthNegative) m += std::string((bits & kHealthNonFinite) ? " and" : "") + " a negative concentration";
+    return fail(NSPNP_ERR_NONFINITE, m + "; the state is invalid until it is reset (nspnp_set_clock or a new init)");
+}
+
+// Pinned host mirror of the health slots of every member of a handle.
+int alloc_host_health(nspnp_state *s) {
+    void *p = nullptr;
+    HIP_TRY(hipHostMalloc(&p, 2 * sizeof(double) * (size_t)s->nmem, hipHostMallocDefault));
+    s->host_health = (double *)p;
+    s->owns_host_health = true;
+    for (int q = 0; q < 2 * s->nmem; ++q) s->host_health[q] = 0.0;
+    return NSPNP_OK;
+}
+
+// Health of the last check whose copy has landed (member ids from first_id).
+int check_health(const nspnp_state *s, int first_id) {
+    if (!s->host_health) return NSPNP_OK;
+    for (int m = 0; m < s->nmem; ++m) {
+        const int bits = (int)s->host_health[2 * m];
+        if (bits) return health_error(bits, first_id < 0 ? -1 : first_id + m);
+    }
+    return NSPNP_OK;
+}
+
+// Queue the copy of every member's [health, max |dPhi|] to the host mirror.
+int queue_health_copy(nspnp_state *s) {
+    if (!s->host_health) return NSPNP_OK;
+    const size_t w = 2 * sizeof(double);
+    HIP_TRY(hipMemcpy2DAsync(s->host_health, w, s->clock + 2, s->nmem > 1 ? s->mstride : w, w, (size_t)s->nmem,
+                             hipMemcpyDeviceToHost, s->stream));
+    return NSPNP_OK;
+}
+
 }  // namespace nspnp
 
 nspnp_state::~nspnp_state() {
     for (hipEvent_t e : prof.ev) hipEventDestroy(e);
+    if (owns_host_health && host_health) (void)hipHostFree(host_health);
 }
 
 namespace {
@@ -432,7 +471,7 @@ int nspnp_init_state(const nspnp_config *cfg, void *dev_workspace, size_t bytes,
     if (((uintptr_t)dev_workspace & 255) != 0) return fail(NSPNP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     nspnp_state *s = new nspnp_state();
     setup_handle(s, cfg, (char *)dev_workspace, 1, (hipStream_t)hip_stream);
-    if ((rc = upload_tables(s)) || (rc = init_member(s))) {
+    if ((rc = alloc_host_health(s)) || (rc = upload_tables(s)) || (rc = init_member(s))) {
         delete s;
         return rc;
     }
@@ -470,7 +509,13 @@ int nspnp_grid(const nspnp_config *cfg, double *yn, double *yc) {
 
 int nspnp_step(nspnp_state *s, int32_t n_substeps) {
     if (!s || n_substeps < 0) return fail(NSPNP_ERR_INVALID, "bad state or substep count");
-    return step_handle(s, n_substeps);
+    int rc = check_health(s, -1);
+    if (rc) return rc;
+    // a check runs at every substep of stage 0 among the ones queued here
+    const int r = (int)(s->substeps % 3);
+    const bool checks = n_substeps > 0 && (r == 0 || r + n_substeps > 3);
+    if ((rc = step_handle(s, n_substeps))) return rc;
+    return checks ? queue_health_copy(s) : NSPNP_OK;
 }
 
 int nspnp_poisson_solve(nspnp_state *s, int32_t kind, const double *dev_rhs, double *dev_out) {
@@ -493,8 +538,8 @@ int nspnp_wall_shear_stress(nspnp_state *s, double *tau_bottom, double *tau_top)
     const int M = s->d.M;
     const double pl = (double)s->d.plane;
     const double *dc = host_dc(s);
-    *tau_bottom = s->ph.ire * (ps[0] / pl - s->cfg.u_bot) / dc[0];
-    *tau_top = s->ph.ire * (s->cfg.u_top - ps[(M - 1) * 10] / pl) / dc[M];
+    *tau_bottom = s->ph.ire * (ps[PQ_SUM_U] / pl - s->cfg.u_bot) / dc[0];
+    *tau_top = s->ph.ire * (s->cfg.u_top - ps[(M - 1) * kPlaneQ + PQ_SUM_U] / pl) / dc[M];
     if (!std::isfinite(*tau_bottom) || !std::isfinite(*tau_top)) return fail(NSPNP_ERR_NONFINITE, "non-finite wall stress");
     return NSPNP_OK;
 }
@@ -509,13 +554,13 @@ int nspnp_ion_flux(nspnp_state *s, double *jp, double *jm, double *mass_p, doubl
     const double *dn = host_dn(s);
     jp[0] = jm[0] = jp[M] = jm[M] = 0.0;
     for (int j = 1; j < M; ++j) {
-        jp[j] = ps[j * 10 + 3] / pl;
-        jm[j] = ps[j * 10 + 4] / pl;
+        jp[j] = ps[j * kPlaneQ + PQ_FLUX_P] / pl;
+        jm[j] = ps[j * kPlaneQ + PQ_FLUX_M] / pl;
     }
     double a = 0.0, b = 0.0;
     for (int j = 0; j < M; ++j) {
-        a += ps[j * 10 + 1] * s->d.dx * dn[j] * s->d.dz;
-        b += ps[j * 10 + 2] * s->d.dx * dn[j] * s->d.dz;
+        a += ps[j * kPlaneQ + PQ_SUM_CP] * s->d.dx * dn[j] * s->d.dz;
+        b += ps[j * kPlaneQ + PQ_SUM_CM] * s->d.dx * dn[j] * s->d.dz;
     }
     *mass_p = a;
     *mass_m = b;
@@ -548,25 +593,28 @@ int nspnp_explicit_terms(nspnp_state *s, double *const dev_out[5]) {
     return NSPNP_OK;
 }
 
-int nspnp_diagnostics(nspnp_state *s, double out[5]) {
+int nspnp_diagnostics(nspnp_state *s, double out[6]) {
     if (!s || !out) return fail(NSPNP_ERR_INVALID, "bad diagnostics arguments");
     std::vector<double> ps;
     int rc = plane_reduce(s, ps);
     if (rc) return rc;
-    double ke = 0.0, dv = 0.0, mp = 1e300, mm = 1e300, cs = 0.0;
+    double ke = 0.0, dv = 0.0, mp = 1e300, mm = 1e300, cs = 0.0, pe = 0.0;
     for (int j = 0; j < s->d.M; ++j) {
-        ke += ps[j * 10 + 5];
-        dv = std::fmax(dv, ps[j * 10 + 6]);
-        mp = std::fmin(mp, ps[j * 10 + 7]);
-        mm = std::fmin(mm, ps[j * 10 + 8]);
-        cs = std::fmax(cs, ps[j * 10 + 9]);
+        const double *r = &ps[(size_t)j * kPlaneQ];
+        ke += r[PQ_KE];
+        dv = std::fmax(dv, r[PQ_MAX_DIV]);
+        mp = std::fmin(mp, r[PQ_MIN_CP]);
+        mm = std::fmin(mm, r[PQ_MIN_CM]);
+        cs = std::fmax(cs, r[PQ_MAX_CSUM]);
+        pe = std::fmax(pe, r[PQ_MAX_DPHI]);
     }
     out[0] = ke;
     out[1] = dv;
     out[2] = mp;
     out[3] = mm;
     out[4] = cs;
-    for (int q = 0; q < 5; ++q)
+    out[5] = pe;
+    for (int q = 0; q < 6; ++q)
         if (!std::isfinite(out[q])) return fail(NSPNP_ERR_NONFINITE, "non-finite diagnostics");
     return NSPNP_OK;
 }
@@ -586,9 +634,10 @@ int nspnp_get_clock(nspnp_state *s, double *t, double *dt, int32_t *stage, int64
 int nspnp_set_clock(nspnp_state *s, double t, double dt, int32_t stage, int64_t substeps) {
     if (!s || stage < 0 || stage > 2 || substeps < 0 || substeps % 3 != stage)
         return fail(NSPNP_ERR_INVALID, "bad set_clock arguments (stage must equal substeps mod 3)");
-    double c[2] = {t, dt};
+    const double c[kClockSlots] = {t, dt, 0.0, 0.0};  // also clears the health word
     HIP_TRY(hipMemcpyAsync(s->clock, c, sizeof(c), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
+    if (s->host_health) s->host_health[0] = s->host_health[1] = 0.0;
     s->substeps = substeps;
     return NSPNP_OK;
 }
@@ -596,6 +645,89 @@ int nspnp_set_clock(nspnp_state *s, double t, double dt, int32_t stage, int64_t 
 int nspnp_sync(nspnp_state *s) {
     if (!s) return fail(NSPNP_ERR_INVALID, "state is NULL");
     HIP_TRY(hipStreamSynchronize(s->stream));
+    return check_health(s, -1);
+}
+
+// ---- checkpoints --------------------------------------------------------
+
+namespace {
+struct CkptHeader {
+    char magic[8];     // "NSPNPCK1"
+    uint32_t version;  // 1
+    uint32_t word;     // bytes per stored value: 8 (FP64) or 4 (mixed)
+    nspnp_config cfg;
+    double clock[kClockSlots];
+    int64_t substeps;
+    int64_t cells;
+};
+const char kCkptMagic[8] = {'N', 'S', 'P', 'N', 'P', 'C', 'K', '1'};
+
+// Every configuration value that the continuation depends on (seed and noise
+// amplitudes only shape the initial state).
+bool same_run(const nspnp_config &a, const nspnp_config &b) {
+    return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.precision == b.precision && a.lx == b.lx &&
+           a.lz == b.lz && a.stretch == b.stretch && a.re == b.re && a.sc == b.sc && a.beta == b.beta &&
+           a.debye == b.debye && a.vhat == b.vhat && a.u_top == b.u_top && a.u_bot == b.u_bot &&
+           a.force_sign == b.force_sign && a.dt == b.dt && a.cfl == b.cfl;
+}
+
+struct FileCloser {
+    FILE *f;
+    ~FileCloser() { if (f) std::fclose(f); }
+};
+}  // namespace
+
+int nspnp_save(nspnp_state *s, const char *path) {
+    if (!s || !path) return fail(NSPNP_ERR_INVALID, "bad save arguments");
+    CkptHeader h{};
+    std::memcpy(h.magic, kCkptMagic, 8);
+    h.version = 1;
+    h.word = (uint32_t)s->wsize;
+    h.cfg = s->cfg;
+    h.substeps = s->substeps;
+    h.cells = s->d.n;
+    HIP_TRY(hipMemcpyAsync(h.clock, s->clock, sizeof(h.clock), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    FileCloser fc{std::fopen(path, "wb")};
+    if (!fc.f) return fail(NSPNP_ERR_INVALID, std::string("save: cannot open ") + path);
+    if (std::fwrite(&h, sizeof(h), 1, fc.f) != 1) return fail(NSPNP_ERR_INVALID, "save: write failed");
+    const size_t bytes = (size_t)s->d.n * s->wsize;
+    std::vector<char> buf(bytes);
+    for (int a = 0; a < 12; ++a) {
+        const void *src = a < 7 ? s->f[a] : s->h[a - 7];
+        HIP_TRY(hipMemcpyAsync(buf.data(), src, bytes, hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        if (std::fwrite(buf.data(), 1, bytes, fc.f) != bytes) return fail(NSPNP_ERR_INVALID, "save: write failed");
+    }
+    if (std::fflush(fc.f) != 0) return fail(NSPNP_ERR_INVALID, "save: flush failed");
+    return NSPNP_OK;
+}
+
+int nspnp_load(nspnp_state *s, const char *path) {
+    if (!s || !path) return fail(NSPNP_ERR_INVALID, "bad load arguments");
+    FileCloser fc{std::fopen(path, "rb")};
+    if (!fc.f) return fail(NSPNP_ERR_INVALID, std::string("load: cannot open ") + path);
+    CkptHeader h{};
+    if (std::fread(&h, sizeof(h), 1, fc.f) != 1 || std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1)
+        return fail(NSPNP_ERR_INVALID, "load: not a checkpoint of this library");
+    if (h.word != s->wsize || h.cells != s->d.n || !same_run(h.cfg, s->cfg))
+        return fail(NSPNP_ERR_INVALID, "load: the checkpoint was written for a different configuration");
+    if (h.substeps < 0) return fail(NSPNP_ERR_INVALID, "load: bad substep count");
+    const size_t bytes = (size_t)s->d.n * s->wsize;
+    std::vector<char> buf(bytes);
+    for (int a = 0; a < 12; ++a) {
+        if (std::fread(buf.data(), 1, bytes, fc.f) != bytes) return fail(NSPNP_ERR_INVALID, "load: truncated file");
+        void *dst = a < 7 ? s->f[a] : s->h[a - 7];
+        HIP_TRY(hipMemcpyAsync(dst, buf.data(), bytes, hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(s->clock, h.clock, sizeof(h.clock), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->substeps = h.substeps;
+    if (s->host_health) {
+        s->host_health[0] = h.clock[2];
+        s->host_health[1] = h.clock[3];
+    }
     return NSPNP_OK;
 }
 

@@ -106,6 +106,16 @@ int capture(nspnp_ensemble *e, int nsub) {
 
 bool valid_member(const nspnp_ensemble *e, int m) { return e && m >= 0 && m < (int)e->cfgs.size(); }
 
+// Health of every member from the last landed copy of the device checks.
+int check_members(const nspnp_ensemble *e) {
+    for (size_t m = 0; m < e->cfgs.size(); ++m) {
+        const nspnp_state *c = e->classes[e->cls_of[m]];
+        const int bits = c->host_health ? (int)c->host_health[2 * e->idx_in[m]] : 0;
+        if (bits) return health_error(bits, (int)m);
+    }
+    return NSPNP_OK;
+}
+
 // ---- autotuner ----------------------------------------------------------
 std::string tune_key(const nspnp_state *c) {
     std::ostringstream k;
@@ -152,6 +162,8 @@ int time_class(nspnp_state *c, int trial, float *ms) {
     return rc;
 }
 
+int ensemble_advance(nspnp_ensemble *e, int32_t n_substeps);
+
 }  // namespace
 
 extern "C" {
@@ -192,7 +204,8 @@ int nspnp_ensemble_init(const nspnp_config *cfgs, int32_t n, void *dev_workspace
         setup_handle(h, &cfgs[first[c]], base, count[c], e->stream);
         e->classes.push_back(h);
         base += (size_t)count[c] * layout_bytes(&cfgs[first[c]]);
-        int rc = upload_tables(h);
+        int rc = alloc_host_health(h);
+        if (!rc) rc = upload_tables(h);
         if (rc) { delete e; return rc; }
     }
     for (int m = 0; m < n; ++m) {
@@ -212,6 +225,25 @@ int nspnp_ensemble_init(const nspnp_config *cfgs, int32_t n, void *dev_workspace
 
 int nspnp_ensemble_step(nspnp_ensemble *e, int32_t n_substeps) {
     if (!e || n_substeps < 0) return fail_code(NSPNP_ERR_INVALID, "bad ensemble step arguments");
+    int rc0 = check_members(e);
+    if (rc0) return rc0;
+    rc0 = ensemble_advance(e, n_substeps);
+    if (rc0 || n_substeps == 0) return rc0;
+    for (nspnp_state *c : e->classes)
+        if ((rc0 = queue_health_copy(c))) return rc0;
+    return NSPNP_OK;
+}
+
+int nspnp_ensemble_sync(nspnp_ensemble *e) {
+    if (!e) return fail_code(NSPNP_ERR_INVALID, "ensemble is NULL");
+    E_TRY(hipStreamSynchronize(e->stream));
+    return check_members(e);
+}
+
+}  // extern "C"
+
+namespace {
+int ensemble_advance(nspnp_ensemble *e, int32_t n_substeps) {
     int left = n_substeps;
     const bool stats = e->classes[0]->stats_on;
     if (e->graph && e->graph_stats != stats) {
@@ -226,6 +258,9 @@ int nspnp_ensemble_step(nspnp_ensemble *e, int32_t n_substeps) {
     }
     return step_all(e, left);
 }
+}  // namespace
+
+extern "C" {
 
 int nspnp_ensemble_capture(nspnp_ensemble *e, int32_t substeps_per_replay) {
     if (!e || substeps_per_replay <= 0 || substeps_per_replay % 3 != 0)
@@ -282,7 +317,7 @@ int nspnp_ensemble_set_field(nspnp_ensemble *e, int32_t member, int32_t field, c
     WITH_VIEW(e, member, nspnp_set_field(v_, field, dev_in));
 }
 
-int nspnp_ensemble_diagnostics(nspnp_ensemble *e, int32_t member, double out[5]) {
+int nspnp_ensemble_diagnostics(nspnp_ensemble *e, int32_t member, double out[6]) {
     WITH_VIEW(e, member, nspnp_diagnostics(v_, out));
 }
 

@@ -84,6 +84,26 @@ __device__ __forceinline__ P *member_ptr_at(P *p, size_t stride, unsigned member
     return (P *)((char *)p + (size_t)member * stride);
 }
 
+// Per-row quantities of the plane reduction (k_plane), kPlaneQ per row.
+enum PlaneQ {
+    PQ_SUM_U = 0, PQ_SUM_CP, PQ_SUM_CM,  // plane sums of u, c+, c-
+    PQ_FLUX_P, PQ_FLUX_M,                // total wall-normal ion fluxes at node j (sums)
+    PQ_KE,                               // kinetic energy of the row
+    PQ_MAX_DIV, PQ_MIN_CP, PQ_MIN_CM, PQ_MAX_CSUM,
+    PQ_MAX_DPHI,                         // max |Phi difference| across the row's faces
+    kPlaneQ
+};
+
+// Health word of a run (device clock slot 2), sticky until the clock is set:
+// bit 0 a non-finite field value or step, bit 1 a negative concentration.
+// Slot 3 holds the largest potential difference across one cell face at the
+// last check (the migration cell Peclet number).
+constexpr int kHealthNonFinite = 1, kHealthNegative = 2;
+constexpr int kClockSlots = 4;  // t, dt, health, max |dPhi|
+// Partial results of the once-per-step check (dt rule and health): values
+// per block and the largest number of blocks per member.
+constexpr int kDtParts = 5, kDtMaxBlocks = 1024;
+
 // Runge-Kutta coefficients of one substep.
 struct Stage {
     double gam, zet, alp;
@@ -169,7 +189,9 @@ struct nspnp_state {
     double2 *spec;       // two half spectra, 2 * nxh * nz * M
     double *cpr;         // their Thomas elimination factors
     double *cn_coef;     // Crank-Nicolson recurrence coefficients (9 M)
-    double *clock;       // device [t, dt]
+    double *clock;       // device [t, dt, health, max |dPhi|]
+    double *host_health = nullptr;  // pinned host mirror of each member's [health, max |dPhi|]
+    bool owns_host_health = false;
     double *red;         // reduction scratch
     int64_t nred;
     double *stats;       // time sums of the plane means of u, c+ - c-, phi (3 per row) and the time
@@ -231,5 +253,9 @@ int upload_tables(nspnp_state *s);
 nspnp_state *member_view(const nspnp_state *cls, int m, const nspnp_config *cfg);
 int init_member(nspnp_state *s);
 int step_handle(nspnp_state *s, int n);
+int health_error(int bits, int member);
+int alloc_host_health(nspnp_state *s);
+int check_health(const nspnp_state *s, int first_id);
+int queue_health_copy(nspnp_state *s);
 
 }  // namespace nspnp

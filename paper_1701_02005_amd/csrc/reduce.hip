@@ -53,17 +53,22 @@ __global__ void __launch_bounds__(256) k_shift_conc(Dims d, double mp, double mm
 }
 
 constexpr int kRedThreads = 256;
-constexpr int kDtBlocks = 1024;
 
 // ---- adaptive time step: max of the advective rate and of c+ + c- ----
+// Once per Runge-Kutta step: the quantities of the adaptive dt rule and the
+// health check of every cell.  Per block: [0] max CFL rate, [1] max(c+ + c-),
+// [2] min(c+, c-), [3] 1 if any value is not finite, [4] max |dPhi| across
+// the cell's x, z and upper y faces.
 template <typename T>
-__global__ void __launch_bounds__(kRedThreads) k_dt_partial(Dims d, Tables tb, const T *u, const T *v,
-                                                            const T *w, const T *cp, const T *cm,
-                                                            double *part, size_t ms) {
-    __shared__ double s_r[kRedThreads], s_c[kRedThreads];
+__global__ void __launch_bounds__(kRedThreads) k_dt_partial(Dims d, Tables tb, const Phys *phys, const T *u,
+                                                            const T *v, const T *w, const T *cp, const T *cm,
+                                                            const T *phi, double *part, size_t ms) {
+    __shared__ double s[kDtParts][kRedThreads];
     u = member_ptr(u, ms); v = member_ptr(v, ms); w = member_ptr(w, ms);
-    cp = member_ptr(cp, ms); cm = member_ptr(cm, ms); part = member_ptr(part, ms);
-    double rate = 0.0, cmax = 0.0;
+    cp = member_ptr(cp, ms); cm = member_ptr(cm, ms); phi = member_ptr(phi, ms); part = member_ptr(part, ms);
+    const double e0 = member_ptr(phys, ms)->e0;
+    double rate = 0.0, cmax = 0.0, cmin = 1e300, pe = 0.0;
+    bool bad = false;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < d.n; q += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(q % d.nx);
         const int64_t r = q / d.nx;
@@ -71,67 +76,93 @@ __global__ void __launch_bounds__(kRedThreads) k_dt_partial(Dims d, Tables tb, c
         const int j = (int)(r / d.nz);
         const int64_t xp = q - i + ((i + 1 == d.nx) ? 0 : i + 1);
         const int64_t zp = q + (int64_t)(((k + 1 == d.nz) ? 0 : k + 1) - k) * d.nx;
-        const double uc = 0.5 * ((double)u[q] + (double)u[xp]);
-        const double vt = (j + 1 < d.M) ? (double)v[q + d.plane] : 0.0;
-        const double vc = 0.5 * ((double)v[q] + vt);
-        const double wc = 0.5 * ((double)w[q] + (double)w[zp]);
-        const double rr = fabs(uc) / d.dx + fabs(vc) / tb.dn[j] + fabs(wc) / d.dz;
-        rate = fmax(rate, rr);
-        cmax = fmax(cmax, (double)cp[q] + (double)cm[q]);
+        const double u0 = (double)u[q], v0 = (double)v[q], w0 = (double)w[q];
+        const double c1 = (double)cp[q], c2 = (double)cm[q], f0 = (double)phi[q];
+        const bool top = j + 1 < d.M;
+        const double uc = 0.5 * (u0 + (double)u[xp]);
+        const double vt = top ? (double)v[q + d.plane] : 0.0;
+        const double vc = 0.5 * (v0 + vt);
+        const double wc = 0.5 * (w0 + (double)w[zp]);
+        rate = fmax(rate, fabs(uc) / d.dx + fabs(vc) / tb.dn[j] + fabs(wc) / d.dz);
+        cmax = fmax(cmax, c1 + c2);
+        cmin = fmin(cmin, fmin(c1, c2));
+        bad = bad || !__builtin_isfinite(u0) || !__builtin_isfinite(v0) || !__builtin_isfinite(w0) ||
+              !__builtin_isfinite(c1) || !__builtin_isfinite(c2) || !__builtin_isfinite(f0);
+        double dphi = fmax(fabs((double)phi[xp] - f0), fabs((double)phi[zp] - f0));
+        if (top) dphi = fmax(dphi, fabs((double)phi[q + d.plane] - f0 + e0 * tb.dc[j + 1]));
+        pe = fmax(pe, dphi);
     }
-    s_r[threadIdx.x] = rate;
-    s_c[threadIdx.x] = cmax;
+    s[0][threadIdx.x] = rate;
+    s[1][threadIdx.x] = cmax;
+    s[2][threadIdx.x] = cmin;
+    s[3][threadIdx.x] = bad ? 1.0 : 0.0;
+    s[4][threadIdx.x] = pe;
     __syncthreads();
     for (int o = kRedThreads / 2; o > 0; o >>= 1) {
         if (threadIdx.x < o) {
-            s_r[threadIdx.x] = fmax(s_r[threadIdx.x], s_r[threadIdx.x + o]);
-            s_c[threadIdx.x] = fmax(s_c[threadIdx.x], s_c[threadIdx.x + o]);
+            s[0][threadIdx.x] = fmax(s[0][threadIdx.x], s[0][threadIdx.x + o]);
+            s[1][threadIdx.x] = fmax(s[1][threadIdx.x], s[1][threadIdx.x + o]);
+            s[2][threadIdx.x] = fmin(s[2][threadIdx.x], s[2][threadIdx.x + o]);
+            s[3][threadIdx.x] = fmax(s[3][threadIdx.x], s[3][threadIdx.x + o]);
+            s[4][threadIdx.x] = fmax(s[4][threadIdx.x], s[4][threadIdx.x + o]);
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = s_r[0];
-        part[2 * blockIdx.x + 1] = s_c[0];
-    }
+    if (threadIdx.x < kDtParts) part[kDtParts * blockIdx.x + threadIdx.x] = s[threadIdx.x][0];
 }
 
+// Combines the partials: the step dt (adaptive runs only, Sec. II time
+// stepping with the limits of include/nspnp.h) and the sticky health word.
 __global__ void __launch_bounds__(kRedThreads) k_dt_final(int nparts, const double *part, const Phys *phys,
                                                           Dims d, double *clock, size_t ms) {
-    __shared__ double s_r[kRedThreads], s_c[kRedThreads];
+    __shared__ double s[kDtParts][kRedThreads];
     part = member_ptr(part, ms);
     clock = member_ptr(clock, ms);
     const Phys ph = *member_ptr(phys, ms);
-    double rate = 0.0, cmax = 0.0;
+    double acc[kDtParts] = {0.0, 0.0, 1e300, 0.0, 0.0};
     for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
-        rate = fmax(rate, part[2 * b]);
-        cmax = fmax(cmax, part[2 * b + 1]);
+        acc[0] = fmax(acc[0], part[kDtParts * b + 0]);
+        acc[1] = fmax(acc[1], part[kDtParts * b + 1]);
+        acc[2] = fmin(acc[2], part[kDtParts * b + 2]);
+        acc[3] = fmax(acc[3], part[kDtParts * b + 3]);
+        acc[4] = fmax(acc[4], part[kDtParts * b + 4]);
     }
-    s_r[threadIdx.x] = rate;
-    s_c[threadIdx.x] = cmax;
+#pragma unroll
+    for (int q = 0; q < kDtParts; ++q) s[q][threadIdx.x] = acc[q];
     __syncthreads();
     for (int o = kRedThreads / 2; o > 0; o >>= 1) {
         if (threadIdx.x < o) {
-            s_r[threadIdx.x] = fmax(s_r[threadIdx.x], s_r[threadIdx.x + o]);
-            s_c[threadIdx.x] = fmax(s_c[threadIdx.x], s_c[threadIdx.x + o]);
+            s[0][threadIdx.x] = fmax(s[0][threadIdx.x], s[0][threadIdx.x + o]);
+            s[1][threadIdx.x] = fmax(s[1][threadIdx.x], s[1][threadIdx.x + o]);
+            s[2][threadIdx.x] = fmin(s[2][threadIdx.x], s[2][threadIdx.x + o]);
+            s[3][threadIdx.x] = fmax(s[3][threadIdx.x], s[3][threadIdx.x + o]);
+            s[4][threadIdx.x] = fmax(s[4][threadIdx.x], s[4][threadIdx.x + o]);
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         const double re = ph.re, rs = 1.0 / ph.kd;
         double dt = 1e30;
-        if (s_r[0] > 0.0) dt = ph.cfl / s_r[0];
-        if (s_c[0] > 0.0) dt = fmin(dt, 2.0 * ph.debye * ph.debye * rs / s_c[0]);
+        if (s[0][0] > 0.0) dt = ph.cfl / s[0][0];
+        if (s[1][0] > 0.0) dt = fmin(dt, 2.0 * ph.debye * ph.debye * rs / s[1][0]);
         const double nu_min = re < rs ? re : rs;
         dt = fmin(dt, nu_min / (4.0 / (d.dx * d.dx) + 4.0 / (d.dz * d.dz)));
-        if (ph.adaptive != 0.0) clock[1] = dt;
+        int bits = (int)clock[2];
+        if (s[3][0] != 0.0) bits |= kHealthNonFinite;
+        if (s[2][0] < 0.0) bits |= kHealthNegative;
+        if (ph.adaptive != 0.0) {
+            if (!(dt > 0.0) || !__builtin_isfinite(dt)) bits |= kHealthNonFinite;
+            else clock[1] = dt;
+        }
+        clock[2] = (double)bits;
+        clock[3] = s[4][0];
     }
 }
 
 // ---- per-plane sums for diagnostics ----
-// out[j * kPlaneQ + q]:
-//   0 sum u, 1 sum c+, 2 sum c-, 3 flux+ at node j, 4 flux- at node j,
-//   5 kinetic energy of row j, 6 max |div u|, 7 min c+, 8 min c-, 9 max (c+ + c-)
-constexpr int kPlaneQ = 10;
+// out[j * kPlaneQ + q], q as in PlaneQ: sums of u, c+, c-; total ion fluxes
+// at node j; kinetic energy of row j; max |div u|; min c+, min c-,
+// max (c+ + c-); max |dPhi| across the x, z and lower y faces of row j.
 
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads) k_plane(Dims d, const Phys *phys, Tables tb, const T *u, const T *v,
@@ -144,7 +175,8 @@ __global__ void __launch_bounds__(kRedThreads) k_plane(Dims d, const Phys *phys,
     const int j = blockIdx.x;
     const int64_t pl = d.plane;
     const int64_t base = (int64_t)j * pl;
-    double acc[kPlaneQ] = {0, 0, 0, 0, 0, 0, 0, 1e300, 1e300, 0};
+    double acc[kPlaneQ] = {0, 0, 0, 0, 0, 0, 0, 1e300, 1e300, 0, 0};
+    static_assert(kPlaneQ == 11, "plane quantities");
     const double dn = tb.dn[j];
     const double dcj = tb.dc[j];
     for (int64_t e = threadIdx.x; e < pl; e += blockDim.x) {
@@ -165,7 +197,10 @@ __global__ void __launch_bounds__(kRedThreads) k_plane(Dims d, const Phys *phys,
             acc[3] += vv * f1 - ph.kd * ((c1 - (double)cp[qd]) / dcj + f1 * e_y);
             acc[4] += vv * f2 - ph.kd * ((c2 - (double)cm[qd]) / dcj - f2 * e_y);
             acc[5] += 0.5 * vv * vv * d.dx * dcj * d.dz;
+            acc[10] = fmax(acc[10], fabs((double)phi[q] - (double)phi[qd] + ph.e0 * dcj));
         }
+        const double f0 = (double)phi[q];
+        acc[10] = fmax(acc[10], fmax(fabs((double)phi[xp] - f0), fabs((double)phi[zp] - f0)));
         acc[5] += 0.5 * (uu * uu + ww * ww) * d.dx * dn * d.dz;
         const double vt = (j + 1 < d.M) ? (double)v[q + pl] : 0.0;
         const double vb = (j > 0) ? vv : 0.0;
@@ -185,6 +220,7 @@ __global__ void __launch_bounds__(kRedThreads) k_plane(Dims d, const Phys *phys,
             s[7][threadIdx.x] = fmin(s[7][threadIdx.x], s[7][threadIdx.x + o]);
             s[8][threadIdx.x] = fmin(s[8][threadIdx.x], s[8][threadIdx.x + o]);
             s[9][threadIdx.x] = fmax(s[9][threadIdx.x], s[9][threadIdx.x + o]);
+            s[10][threadIdx.x] = fmax(s[10][threadIdx.x], s[10][threadIdx.x + o]);
         }
         __syncthreads();
     }
@@ -262,16 +298,16 @@ hipError_t launch_shift_conc(nspnp_state *s, double mp, double mm) {
 
 hipError_t launch_dt(nspnp_state *s) {
     ProfScope prof_(s, K_DT);
-    const unsigned nb = (unsigned)std::min<int64_t>(kDtBlocks, (s->d.n + kRedThreads - 1) / kRedThreads);
+    const unsigned nb = (unsigned)std::min<int64_t>(kDtMaxBlocks, (s->d.n + kRedThreads - 1) / kRedThreads);
     const dim3 g(nb, 1, (unsigned)s->nmem);
     if (s->fp64)
         k_dt_partial<double><<<g, kRedThreads, 0, s->stream>>>(
-            s->d, s->tb, (const double *)s->f[0], (const double *)s->f[1], (const double *)s->f[2],
-            (const double *)s->f[3], (const double *)s->f[4], s->red, s->mstride);
+            s->d, s->tb, s->d_phys, (const double *)s->f[0], (const double *)s->f[1], (const double *)s->f[2],
+            (const double *)s->f[3], (const double *)s->f[4], (const double *)s->f[5], s->red, s->mstride);
     else
         k_dt_partial<float><<<g, kRedThreads, 0, s->stream>>>(
-            s->d, s->tb, (const float *)s->f[0], (const float *)s->f[1], (const float *)s->f[2],
-            (const float *)s->f[3], (const float *)s->f[4], s->red, s->mstride);
+            s->d, s->tb, s->d_phys, (const float *)s->f[0], (const float *)s->f[1], (const float *)s->f[2],
+            (const float *)s->f[3], (const float *)s->f[4], (const float *)s->f[5], s->red, s->mstride);
     k_dt_final<<<dim3(1, 1, (unsigned)s->nmem), kRedThreads, 0, s->stream>>>((int)nb, s->red, s->d_phys, s->d,
                                                                              s->clock, s->mstride);
     return hipGetLastError();

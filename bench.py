@@ -30,11 +30,12 @@ def kernel_bytes(cfg, name: str, launches: int, substeps: int) -> float:
     """Algorithmic (compulsory) HBM bytes of all launches of one kernel class
     inside the substep loop.
 
-    w = state word (8 FP64, 4 mixed); spectral and scratch buffers are FP64;
+    w = state word (8 FP64, 4 mixed); spectral buffers and psi are FP64;
     s = 16 (nx/2+1)/nx bytes of half spectrum per cell.  Per cell and launch:
     explicit_rhs reads the 7 state fields, reads H^{k-1} on stages 2 and 3,
     writes H^k on stages 1 and 2 and the 5 Crank-Nicolson right-hand sides
-    (FP64); cn_tridiag reads r and the field and writes the field, 5 fields.
+    (state type); cn_tridiag reads r and the field and writes the field, 5
+    fields.
     The pressure and potential solves run batched: fft_x_r2c reads u, v, w
     (divergence) and c+, c- (charge) and writes two half spectra; fft_z_*
     and thomas_modes read and write both half spectra once; fft_x_c2r reads
@@ -46,8 +47,8 @@ def kernel_bytes(cfg, name: str, launches: int, substeps: int) -> float:
     n = cfg.nx * cfg.nz * (cfg.ny - 1)
     sp = 16.0 * (cfg.nx // 2 + 1) / cfg.nx
     per = {
-        "explicit_rhs": 7 * w + 40 + 5 * w * (2.0 / 3.0) + 5 * w * (2.0 / 3.0),
-        "cn_tridiag": 5 * (8 + 2 * w),
+        "explicit_rhs": 7 * w + 5 * w + 5 * w * (2.0 / 3.0) + 5 * w * (2.0 / 3.0),
+        "cn_tridiag": 5 * 3 * w,
         "fft_x_r2c": 5 * w + 2 * sp,
         "fft_z_fwd": 4 * sp,
         "thomas_modes": 4 * sp,

@@ -26,8 +26,6 @@ int fail(int code, const std::string &msg) {
     } while (0)
 
 // Low-storage three-stage Runge-Kutta (Sec. II): gamma, zeta, alpha = gamma + zeta
-constexpr double kGam[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
-constexpr double kZet[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
 
 bool smooth_size(int n) {
     if (n < 1) return false;
@@ -70,7 +68,7 @@ int check_config(const nspnp_config *c) {
 }
 
 struct Layout {
-    size_t off_f[7], off_h[5], off_r[5], off_psi, off_spec, off_cpr, off_coef, off_clock, off_phys, off_stats, off_red,
+    size_t off_f[7], off_h[5], off_r[5], off_psi, off_spec, off_fac, off_coef, off_clock, off_phys, off_stats, off_red,
         off_tab;
     size_t ntab, nred, total;
 };
@@ -85,16 +83,16 @@ Layout make_layout(const nspnp_config *c) {
     size_t o = 0;
     for (int q = 0; q < 7; ++q) { L.off_f[q] = o; o = align256(o + n * ws); }
     for (int q = 0; q < 5; ++q) { L.off_h[q] = o; o = align256(o + n * ws); }
-    for (int q = 0; q < 5; ++q) { L.off_r[q] = o; o = align256(o + n * 8); }
+    for (int q = 0; q < 5; ++q) { L.off_r[q] = o; o = align256(o + n * ws); }
     L.off_psi = o; o = align256(o + n * 8);
     const int64_t nspec = nxh * c->nz * M;
     L.off_spec = o; o = align256(o + 2 * nspec * 16);
-    L.off_cpr = o; o = align256(o + 2 * nspec * 8);
-    L.off_coef = o; o = align256(o + 9 * M * 8);
+    L.off_fac = o; o = align256(o + 2 * nspec * 16);  // [kind][mode][row] pivots
+    L.off_coef = o; o = align256(o + 27 * M * 8);  // 3 stages x 3 systems x (g, m, n)
     L.off_clock = o; o = align256(o + kClockSlots * 8);
     L.off_phys = o; o = align256(o + sizeof(Phys));
     L.off_stats = o; o = align256(o + (3 * M + 2) * 8);
-    L.nred = std::max<int64_t>(kDtParts * kDtMaxBlocks, M * kPlaneQ);
+    L.nred = std::max<int64_t>((int64_t)kDtParts * dt_max_blocks((int64_t)c->nx * c->nz), M * kPlaneQ);
     L.off_red = o; o = align256(o + L.nred * 8);
     L.ntab = 11 * M + 2 + nxh + c->nz + 2 * c->nx + 2 * c->nz;
     L.off_tab = o; o = align256(o + L.ntab * 8);
@@ -253,13 +251,13 @@ void setup_handle(nspnp_state *s, const nspnp_config *cfg, char *base, int nmem,
     s->mstride = nmem > 1 ? L.total : 0;
     s->planx = make_plan(cfg->nx);
     s->planz = make_plan(cfg->nz);
-    s->tiles = Tiles{256, 256, 1024, 1024, 64, 256, 16};
+    s->tiles = Tiles{256, 256, 512, 512, 8, 128, 32};  // the tuner's choice at 256 x 193 x 256
     for (int q = 0; q < 7; ++q) s->f[q] = base + L.off_f[q];
     for (int q = 0; q < 5; ++q) s->h[q] = base + L.off_h[q];
-    for (int q = 0; q < 5; ++q) s->r[q] = (double *)(base + L.off_r[q]);
+    for (int q = 0; q < 5; ++q) s->r[q] = base + L.off_r[q];
     s->psi = (double *)(base + L.off_psi);
     s->spec = (double2 *)(base + L.off_spec);
-    s->cpr = (double *)(base + L.off_cpr);
+    s->fac = (double2 *)(base + L.off_fac);
     s->cn_coef = (double *)(base + L.off_coef);
     s->clock = (double *)(base + L.off_clock);
     s->d_phys = (Phys *)(base + L.off_phys);
@@ -288,7 +286,7 @@ nspnp_state *member_view(const nspnp_state *cls, int m, const nspnp_config *cfg)
     for (int q = 0; q < 5; ++q) { v->h[q] = sh(cls->h[q]); v->r[q] = sh(cls->r[q]); }
     v->psi = sh(cls->psi);
     v->spec = sh(cls->spec);
-    v->cpr = sh(cls->cpr);
+    v->fac = sh(cls->fac);
     v->cn_coef = sh(cls->cn_coef);
     v->clock = sh(cls->clock);
     v->d_phys = sh(cls->d_phys);
@@ -325,6 +323,7 @@ int init_member(nspnp_state *s) {
         vol += dn * (double)d.plane;
     }
     HIP_TRY(launch_shift_conc(s, sp / vol, sm / vol));
+    HIP_TRY(launch_thomas_factors(s));
     // project the initial velocity (no pressure), then the initial potential
     PoissonBatch b = make_batch(s, true);
     b.nprob = 1;
@@ -341,7 +340,7 @@ int init_member(nspnp_state *s) {
 int step_handle(nspnp_state *s, int n) {
     for (int it = 0; it < n; ++it) {
         const int k = (int)(s->substeps % 3);
-        const Stage st{kGam[k], kZet[k], kGam[k] + kZet[k], k};
+        const Stage st{kRkGam[k], kRkZet[k], kRkAlp[k], k};
         if (k == 0) HIP_TRY(launch_dt(s));  // dt rule (adaptive runs) and health check
         HIP_TRY(launch_explicit(s, st, true));
         HIP_TRY(launch_cn_solve(s, st));
@@ -639,6 +638,7 @@ int nspnp_set_clock(nspnp_state *s, double t, double dt, int32_t stage, int64_t 
     HIP_TRY(hipStreamSynchronize(s->stream));
     if (s->host_health) s->host_health[0] = s->host_health[1] = 0.0;
     s->substeps = substeps;
+    s->cn_fresh = false;  // dt may have changed
     return NSPNP_OK;
 }
 
@@ -724,6 +724,7 @@ int nspnp_load(nspnp_state *s, const char *path) {
     HIP_TRY(hipMemcpyAsync(s->clock, h.clock, sizeof(h.clock), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->substeps = h.substeps;
+    s->cn_fresh = false;
     if (s->host_health) {
         s->host_health[0] = h.clock[2];
         s->host_health[1] = h.clock[3];

@@ -352,7 +352,7 @@ int nspnp_ensemble_autotune(nspnp_ensemble *e, const char *cache_path, int32_t t
             const int cand_expl[] = {64, 128, 256};
             const int cand_cn[] = {64, 128, 256};
             const int cand_fft[] = {512, 1024, 2048};
-            const int cand_th[] = {32, 64, 128, 256};
+            const int cand_th[] = {4, 8, 16, 32};
             const int cand_corr[] = {128, 256};
             const int cand_slab[] = {4, 8, 16, 32};
             float base_ms = 0.f;

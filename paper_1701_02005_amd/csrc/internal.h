@@ -101,8 +101,17 @@ enum PlaneQ {
 constexpr int kHealthNonFinite = 1, kHealthNegative = 2;
 constexpr int kClockSlots = 4;  // t, dt, health, max |dPhi|
 // Partial results of the once-per-step check (dt rule and health): values
-// per block and the largest number of blocks per member.
-constexpr int kDtParts = 5, kDtMaxBlocks = 1024;
+// per block, threads per block, and the block budget per member (more only
+// when one block per kDtThreads columns already exceeds it).
+constexpr int kDtParts = 5, kDtThreads = 256, kDtMaxBlocks = 1024;
+inline int dt_chunks(int64_t plane) { return (int)((plane + kDtThreads - 1) / kDtThreads); }
+inline int dt_max_blocks(int64_t plane) { return dt_chunks(plane) > kDtMaxBlocks ? dt_chunks(plane) : kDtMaxBlocks; }
+
+// Low-storage third-order Runge-Kutta coefficients of the three stages:
+// gamma, zeta and alpha = gamma + zeta.
+constexpr double kRkGam[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+constexpr double kRkZet[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+constexpr double kRkAlp[3] = {8.0 / 15.0 + 0.0, 5.0 / 12.0 - 17.0 / 60.0, 3.0 / 4.0 - 5.0 / 12.0};
 
 // Runge-Kutta coefficients of one substep.
 struct Stage {
@@ -137,7 +146,7 @@ struct Tiles {
     int cn;       // threads per block (columns) of the Crank-Nicolson solve
     int fftx;     // complex points per block of the x transforms
     int fftz;     // complex points per block of the z transforms
-    int thomas;   // threads per block (modes) of the mode Thomas solve
+    int thomas;   // modes per tile of the y solve of the elliptic problems (capped by LDS)
     int corr;     // threads per block of the projection correction
     int slab;     // rows marched by one block of the explicit kernel
 };
@@ -184,11 +193,12 @@ struct nspnp_state {
     size_t wsize;        // bytes of one state-type element
     void *f[7];          // u v w c+ c- phi p, state type
     void *h[5];          // H^{k-1} -> H^k, state type
-    double *r[5];        // Crank-Nicolson right-hand sides / Thomas scratch
+    void *r[5];          // Crank-Nicolson right-hand sides, state type
     double *psi;         // pressure increment (n, FP64)
     double2 *spec;       // two half spectra, 2 * nxh * nz * M
-    double *cpr;         // their Thomas elimination factors
-    double *cn_coef;     // Crank-Nicolson recurrence coefficients (9 M)
+    double2 *fac;        // Thomas pivots (1/den, c') of both elliptic operators, [kind][mode][row]
+    double *cn_coef;     // Crank-Nicolson recurrence coefficients, 9 M per stage
+    bool cn_fresh = false;  // cn_coef matches the device dt of the current step
     double *clock;       // device [t, dt, health, max |dPhi|]
     double *host_health = nullptr;  // pinned host mirror of each member's [health, max |dPhi|]
     bool owns_host_health = false;
@@ -235,6 +245,7 @@ hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]);
 hipError_t launch_cn_solve(nspnp_state *s, const Stage &st);
 hipError_t launch_correct(nspnp_state *s, const Stage &st, bool update_p, double fixed_scale, bool advance_clock);
 hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b);
+hipError_t launch_thomas_factors(nspnp_state *s);
 hipError_t launch_dt(nspnp_state *s);
 hipError_t launch_init_fields(nspnp_state *s);
 hipError_t launch_plane_sums(nspnp_state *s, int what, double *dev_out);

@@ -257,108 +257,210 @@ __global__ void __launch_bounds__(256) k_fft_z(Dims d, FftPlan pl, const double2
     for (int e = threadIdx.x; e < nt * nz; e += blockDim.x) base[e] = z[e];
 }
 
-// ---- y direction: one Thomas solve per (kx, kz) mode ----
+// ---- y direction: one tridiagonal solve per (kx, kz) mode ----
 // (lo_j psi_{j-1} + (di_j - kx^2 - kz^2) psi_j + up_j psi_{j+1}) = rhs_j / (nx nz)
 // kind 0: zero-flux walls, mode (0,0) pinned at row 0 then shifted to zero
-// volume mean; kind 1: zero wall value at the half-cell distance.  Rows are
-// prefetched kPf ahead so the elimination chain does not wait on memory.
-constexpr int kPf = 4;
+// volume mean; kind 1: zero wall value at the half-cell distance.
+//
+// The matrices do not change in time, so the Thomas pivots of every mode are
+// computed once (k_thomas_factors) and stored as fac[kind][mode][row] =
+// (g, c') with g = 1/den.  Each solve is then two linear recurrences
+//   d'_j = g_j r_j + m_j d'_{j-1}  (m_j = -lo_j g_j),   x_j = d'_j - c'_j x_{j+1}.
 
-__global__ void __launch_bounds__(256) k_thomas_modes(Dims d, Tables tb, PoissonBatch b, double2 *spec_all,
-                                                     double *cpr_all, int64_t nspec) {
-    const int prob = blockIdx.y;
-    const int kind = b.kind[prob];
-    double2 *spec = member_ptr(spec_all, b.ms) + prob * nspec;
-    double *cpr = member_ptr(cpr_all, b.ms) + prob * nspec;
+// One thread per (kind, mode): the forward pass of Thomas' algorithm on the
+// matrix only.
+__global__ void __launch_bounds__(256) k_thomas_factors(Dims d, Tables tb, double2 *fac_all, size_t ms) {
+    const int kind = blockIdx.y;
     const int64_t nmodes = (int64_t)d.nxh * d.nz;
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= nmodes) return;
-    const int kx = (int)(m / d.nz), kz = (int)(m % d.nz);  // spectrum layout [j][kx][kz]
     const int M = d.M;
+    double2 *fac = member_ptr(fac_all, ms) + ((int64_t)kind * nmodes + m) * M;
+    const int kx = (int)(m / d.nz), kz = (int)(m % d.nz);  // spectrum layout [j][kx][kz]
     const double k2 = tb.kx2[kx] + tb.kz2[kz];
-    const double scale = 1.0 / ((double)d.nx * (double)d.nz);
-    const bool pin = (kind == 0 && kx == 0 && kz == 0);
+    const bool pin = (kind == 0 && m == 0);
     double cprev = 0.0;
-    double2 dprev = make_double2(0.0, 0.0);
-    double2 buf[kPf];
+    for (int j = 0; j < M; ++j) {
+        const double aa = tb.lyc_lo[j], cc = tb.lyc_up[j];
+        const double lo = (j > 0) ? aa : 0.0;
+        double up = (j < M - 1) ? cc : 0.0;
+        double di = -(lo + up);
+        if (kind == 1) {
+            if (j == 0) di -= aa;
+            if (j == M - 1) di -= cc;
+        }
+        double B = di - k2;
+        if (pin && j == 0) {
+            B = 1.0;
+            up = 0.0;
+        }
+        const double den = B - lo * cprev;
+        const double cj = up / den;
+        fac[j] = make_double2(1.0 / den, cj);
+        cprev = cj;
+    }
+}
+
+// Solve of one tile of tm consecutive modes of one problem: the tile's rows
+// are staged in LDS with coalesced loads; each wave then solves one mode at
+// a time with its rows split into 64 contiguous lane segments of R rows (the
+// mode's pivots are one contiguous read per wave).  Each recurrence is a
+// local sweep per lane, a 6-step scan of affine maps across the wave and a
+// second sweep from the correct incoming value.  The tile is written back
+// with coalesced stores.
+template <int R>
+__global__ void __launch_bounds__(256) k_thomas_tile(Dims d, Tables tb, PoissonBatch b, double2 *spec_all,
+                                                     const double2 *fac_all, int64_t nspec, int tm) {
+    extern __shared__ double2 s_x[];
+    const int prob = blockIdx.y;
+    const int kind = b.kind[prob];
+    const int64_t nmodes = (int64_t)d.nxh * d.nz;
+    const int M = d.M;
+    double2 *spec = member_ptr(spec_all, b.ms) + prob * nspec;
+    const double2 *fac = member_ptr(fac_all, b.ms) + (int64_t)kind * nmodes * M;
+    const int64_t m0 = (int64_t)blockIdx.x * tm;
+    const int ncol = (int)((nmodes - m0) < tm ? (nmodes - m0) : tm);
+    const int LD = tm + 1;
+    for (int e = threadIdx.x; e < M * tm; e += blockDim.x) {
+        const int j = e / tm, c = e - j * tm;
+        s_x[j * LD + c] = (c < ncol) ? spec[(int64_t)j * nmodes + m0 + c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int js = lane * R;
+    const double scale = 1.0 / ((double)d.nx * (double)d.nz);
+    double lo[R];
 #pragma unroll
-    for (int p = 0; p < kPf; ++p) buf[p] = (p < M) ? spec[p * nmodes + m] : make_double2(0.0, 0.0);
-    for (int jb = 0; jb < M; jb += kPf) {
+    for (int t = 0; t < R; ++t) {
+        const int j = js + t;
+        lo[t] = (j > 0 && j < M) ? tb.lyc_lo[j] : 0.0;
+    }
+    for (int c = wave; c < ncol; c += nwave) {
+        const int64_t m = m0 + c;
+        const bool pin = (kind == 0 && m == 0);
+        const double2 *fm = fac + m * M;
+        double g[R], mm[R], nn[R];
+        double2 x[R];
+        double Qs = 1.0, Ss = 1.0;
 #pragma unroll
-        for (int p = 0; p < kPf; ++p) {
-            const int j = jb + p;
+        for (int t = 0; t < R; ++t) {
+            const int j = js + t;
             if (j < M) {
-                double2 rhs = buf[p];
-                if (j + kPf < M) buf[p] = spec[(int64_t)(j + kPf) * nmodes + m];
-                const double aa = tb.lyc_lo[j], cc = tb.lyc_up[j];
-                double lo = (j > 0) ? aa : 0.0;
-                double up = (j < M - 1) ? cc : 0.0;
-                double di = -(lo + up);
-                if (kind == 1) {
-                    if (j == 0) di -= aa;
-                    if (j == M - 1) di -= cc;
-                }
-                double B = di - k2;
-                rhs.x *= scale;
-                rhs.y *= scale;
-                if (pin && j == 0) {
-                    B = 1.0;
-                    up = 0.0;
-                    rhs = make_double2(0.0, 0.0);
-                }
-                const double den = B - lo * cprev;
-                const double cj = up / den;
-                const double2 dj = make_double2((rhs.x - lo * dprev.x) / den, (rhs.y - lo * dprev.y) / den);
-                const int64_t o = (int64_t)j * nmodes + m;
-                spec[o] = dj;
-                cpr[o] = cj;
-                cprev = cj;
-                dprev = dj;
+                const double2 f = fm[j];
+                g[t] = f.x;
+                mm[t] = -lo[t] * f.x;
+                nn[t] = -f.y;
+                const double2 r = s_x[j * LD + c];
+                x[t] = (pin && j == 0) ? make_double2(0.0, 0.0) : make_double2(r.x * scale, r.y * scale);
+            } else {  // padding rows pass values through
+                g[t] = 0.0;
+                mm[t] = 1.0;
+                nn[t] = 1.0;
+                x[t] = make_double2(0.0, 0.0);
+            }
+            Qs *= mm[t];
+            Ss *= nn[t];
+        }
+        // multipliers of the scans of x -> T + Q x (forward, from lane 0 up)
+        // and x -> U + S x (backward, from lane 63 down)
+        double qm[6], sm[6];
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+            const int sft = 1 << st;
+            qm[st] = Qs;
+            sm[st] = Ss;
+            const double Qp = __shfl_up(Qs, sft, 64), Sp = __shfl_down(Ss, sft, 64);
+            if (lane >= sft) Qs *= Qp;
+            if (lane + sft < 64) Ss *= Sp;
+        }
+        // forward sweep
+        double tx = 0.0, ty = 0.0;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            tx = g[t] * x[t].x + mm[t] * tx;
+            ty = g[t] * x[t].y + mm[t] * ty;
+        }
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+            const double px = __shfl_up(tx, 1 << st, 64), py = __shfl_up(ty, 1 << st, 64);
+            if (lane >= (1 << st)) {
+                tx += qm[st] * px;
+                ty += qm[st] * py;
             }
         }
-    }
-    double2 xn = make_double2(0.0, 0.0);
-    double sx = 0.0, sy = 0.0, vol = 0.0;
-    double2 bd[kPf];
-    double bc[kPf];
+        double dx_ = __shfl_up(tx, 1, 64), dy_ = __shfl_up(ty, 1, 64);
+        if (lane == 0) dx_ = dy_ = 0.0;
 #pragma unroll
-    for (int p = 0; p < kPf; ++p) {
-        const int j = M - 1 - p;
-        bd[p] = (j >= 0) ? spec[(int64_t)j * nmodes + m] : make_double2(0.0, 0.0);
-        bc[p] = (j >= 0) ? cpr[(int64_t)j * nmodes + m] : 0.0;
-    }
-    for (int jb = M - 1; jb >= 0; jb -= kPf) {
+        for (int t = 0; t < R; ++t) {
+            dx_ = g[t] * x[t].x + mm[t] * dx_;
+            dy_ = g[t] * x[t].y + mm[t] * dy_;
+            x[t] = make_double2(dx_, dy_);
+        }
+        // backward sweep
+        double ux = 0.0, uy = 0.0;
 #pragma unroll
-        for (int p = 0; p < kPf; ++p) {
-            const int j = jb - p;
-            if (j >= 0) {
-                const double2 dj = bd[p];
-                const double cj = bc[p];
-                if (j - kPf >= 0) {
-                    bd[p] = spec[(int64_t)(j - kPf) * nmodes + m];
-                    bc[p] = cpr[(int64_t)(j - kPf) * nmodes + m];
-                }
-                const double2 xj = make_double2(dj.x - cj * xn.x, dj.y - cj * xn.y);
-                spec[(int64_t)j * nmodes + m] = xj;
-                xn = xj;
-                if (pin) {
-                    sx += xj.x * tb.dn[j];
-                    sy += xj.y * tb.dn[j];
-                    vol += tb.dn[j];
-                }
+        for (int t = R - 1; t >= 0; --t) {
+            const bool in = g[t] != 0.0;
+            ux = (in ? x[t].x : 0.0) + nn[t] * ux;
+            uy = (in ? x[t].y : 0.0) + nn[t] * uy;
+        }
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+            const double px = __shfl_down(ux, 1 << st, 64), py = __shfl_down(uy, 1 << st, 64);
+            if (lane + (1 << st) < 64) {
+                ux += sm[st] * px;
+                uy += sm[st] * py;
             }
         }
-    }
-    if (pin) {
-        const double mx = sx / vol, my = sy / vol;
-        for (int j = 0; j < M; ++j) {
-            const int64_t o = (int64_t)j * nmodes + m;
-            double2 x = spec[o];
-            x.x -= mx;
-            x.y -= my;
-            spec[o] = x;
+        double xx = __shfl_down(ux, 1, 64), xy = __shfl_down(uy, 1, 64);
+        if (lane == 63) xx = xy = 0.0;
+#pragma unroll
+        for (int t = R - 1; t >= 0; --t) {
+            const bool in = g[t] != 0.0;
+            xx = (in ? x[t].x : 0.0) + nn[t] * xx;
+            xy = (in ? x[t].y : 0.0) + nn[t] * xy;
+            x[t] = make_double2(xx, xy);
+        }
+        if (pin) {  // zero volume mean of the pressure-type solution
+            double sx = 0.0, sy = 0.0, vol = 0.0;
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                const int j = js + t;
+                if (j < M) {
+                    const double h = tb.dn[j];
+                    sx += x[t].x * h;
+                    sy += x[t].y * h;
+                    vol += h;
+                }
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                sx += __shfl_xor(sx, o, 64);
+                sy += __shfl_xor(sy, o, 64);
+                vol += __shfl_xor(vol, o, 64);
+            }
+            const double mx = sx / vol, my = sy / vol;
+#pragma unroll
+            for (int t = 0; t < R; ++t) x[t] = make_double2(x[t].x - mx, x[t].y - my);
+        }
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int j = js + t;
+            if (j < M) s_x[j * LD + c] = x[t];
         }
     }
+    __syncthreads();
+    for (int e = threadIdx.x; e < M * tm; e += blockDim.x) {
+        const int j = e / tm, c = e - j * tm;
+        if (c < ncol) spec[(int64_t)j * nmodes + m0 + c] = s_x[j * LD + c];
+    }
+}
+
+// modes per tile of the y solve: at most `want`, within 64 KB of LDS
+inline int thomas_tile_modes(int M, int want) {
+    int tm = 65536 / (M * (int)sizeof(double2)) - 1;
+    if (tm > want) tm = want;
+    return tm < 1 ? 1 : tm;
 }
 
 // line pairs per block of the x transforms: about `points` complex values,
@@ -404,9 +506,27 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
     const int64_t nmodes = (int64_t)d.nxh * d.nz;
     {
         ProfScope prof_(s, K_THOMAS);
-        const int tt = s->tiles.thomas;
-        const dim3 gt((unsigned)((nmodes + tt - 1) / tt), (unsigned)b.nprob, (unsigned)nmem);
-        k_thomas_modes<<<gt, tt, 0, s->stream>>>(d, s->tb, b, s->spec, s->cpr, nspec);
+        const int tm = thomas_tile_modes(d.M, s->tiles.thomas);
+        const dim3 gt((unsigned)((nmodes + tm - 1) / tm), (unsigned)b.nprob, (unsigned)nmem);
+        const size_t ldst = (size_t)d.M * (tm + 1) * sizeof(double2);
+        const int rpl = (d.M + 63) / 64;  // rows per lane (M <= 480: at most 8)
+#define NSPNP_TH_CASE(RR)                                                                                \
+    case RR:                                                                                             \
+        k_thomas_tile<RR><<<gt, 256, ldst, s->stream>>>(d, s->tb, b, s->spec, s->fac, nspec, tm);        \
+        break;
+        switch (rpl) {
+            NSPNP_TH_CASE(1)
+            NSPNP_TH_CASE(2)
+            NSPNP_TH_CASE(3)
+            NSPNP_TH_CASE(4)
+            NSPNP_TH_CASE(5)
+            NSPNP_TH_CASE(6)
+            NSPNP_TH_CASE(7)
+            NSPNP_TH_CASE(8)
+            default:
+                return hipErrorInvalidValue;
+        }
+#undef NSPNP_TH_CASE
     }
     {
         ProfScope prof_(s, K_FFTZ_INV);
@@ -417,6 +537,15 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
         if (s->fp64) k_fft_x_c2r<double><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppb);
         else k_fft_x_c2r<float><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppb);
     }
+    return hipGetLastError();
+}
+
+// Thomas pivots of both elliptic operators for every member of the handle
+// (once, at init: they depend on the grid only).
+hipError_t launch_thomas_factors(nspnp_state *s) {
+    const int64_t nmodes = (int64_t)s->d.nxh * s->d.nz;
+    const dim3 g((unsigned)((nmodes + 255) / 256), 2, (unsigned)s->nmem);
+    k_thomas_factors<<<g, 256, 0, s->stream>>>(s->d, s->tb, s->fac, s->mstride);
     return hipGetLastError();
 }
 

@@ -56,41 +56,54 @@ constexpr int kRedThreads = 256;
 
 // ---- adaptive time step: max of the advective rate and of c+ + c- ----
 // Once per Runge-Kutta step: the quantities of the adaptive dt rule and the
-// health check of every cell.  Per block: [0] max CFL rate, [1] max(c+ + c-),
-// [2] min(c+, c-), [3] 1 if any value is not finite, [4] max |dPhi| across
-// the cell's x, z and upper y faces.
+// health check of every cell.  Each thread owns one (x, z) column and marches
+// a slab of rows, carrying the next row's v and phi (the top-face values of
+// the current row) so that every field is read about once.  Per block:
+// [0] max CFL rate, [1] max(c+ + c-), [2] min(c+, c-), [3] 1 if any value is
+// not finite, [4] max |dPhi| across the cell's x, z and upper y faces.  All
+// five are maxima or minima, so the result does not depend on the order.
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads) k_dt_partial(Dims d, Tables tb, const Phys *phys, const T *u,
                                                             const T *v, const T *w, const T *cp, const T *cm,
-                                                            const T *phi, double *part, size_t ms) {
+                                                            const T *phi, double *part, int chunks,
+                                                            int slab_rows, size_t ms) {
     __shared__ double s[kDtParts][kRedThreads];
     u = member_ptr(u, ms); v = member_ptr(v, ms); w = member_ptr(w, ms);
     cp = member_ptr(cp, ms); cm = member_ptr(cm, ms); phi = member_ptr(phi, ms); part = member_ptr(part, ms);
     const double e0 = member_ptr(phys, ms)->e0;
     double rate = 0.0, cmax = 0.0, cmin = 1e300, pe = 0.0;
     bool bad = false;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < d.n; q += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(q % d.nx);
-        const int64_t r = q / d.nx;
-        const int k = (int)(r % d.nz);
-        const int j = (int)(r / d.nz);
-        const int64_t xp = q - i + ((i + 1 == d.nx) ? 0 : i + 1);
-        const int64_t zp = q + (int64_t)(((k + 1 == d.nz) ? 0 : k + 1) - k) * d.nx;
-        const double u0 = (double)u[q], v0 = (double)v[q], w0 = (double)w[q];
-        const double c1 = (double)cp[q], c2 = (double)cm[q], f0 = (double)phi[q];
-        const bool top = j + 1 < d.M;
-        const double uc = 0.5 * (u0 + (double)u[xp]);
-        const double vt = top ? (double)v[q + d.plane] : 0.0;
-        const double vc = 0.5 * (v0 + vt);
-        const double wc = 0.5 * (w0 + (double)w[zp]);
-        rate = fmax(rate, fabs(uc) / d.dx + fabs(vc) / tb.dn[j] + fabs(wc) / d.dz);
-        cmax = fmax(cmax, c1 + c2);
-        cmin = fmin(cmin, fmin(c1, c2));
-        bad = bad || !__builtin_isfinite(u0) || !__builtin_isfinite(v0) || !__builtin_isfinite(w0) ||
-              !__builtin_isfinite(c1) || !__builtin_isfinite(c2) || !__builtin_isfinite(f0);
-        double dphi = fmax(fabs((double)phi[xp] - f0), fabs((double)phi[zp] - f0));
-        if (top) dphi = fmax(dphi, fabs((double)phi[q + d.plane] - f0 + e0 * tb.dc[j + 1]));
-        pe = fmax(pe, dphi);
+    const int chunk = (int)(blockIdx.x % (unsigned)chunks), slab = (int)(blockIdx.x / (unsigned)chunks);
+    const int64_t pl = d.plane;
+    const int64_t e = (int64_t)chunk * blockDim.x + threadIdx.x;
+    const int j0 = slab * slab_rows;
+    const int j1 = (j0 + slab_rows < d.M) ? j0 + slab_rows : d.M;
+    if (e < pl && j0 < j1) {
+        const int i = (int)(e % d.nx), k = (int)(e / d.nx);
+        const int64_t exp_ = e - i + ((i + 1 == d.nx) ? 0 : i + 1);
+        const int64_t ezp = e + (int64_t)(((k + 1 == d.nz) ? 0 : k + 1) - k) * d.nx;
+        double v0 = (double)v[(int64_t)j0 * pl + e], f0 = (double)phi[(int64_t)j0 * pl + e];
+        for (int j = j0; j < j1; ++j) {
+            const int64_t q = (int64_t)j * pl + e, row = (int64_t)j * pl;
+            const bool top = j + 1 < d.M;
+            const double v1 = top ? (double)v[q + pl] : 0.0;
+            const double f1 = top ? (double)phi[q + pl] : 0.0;
+            const double u0 = (double)u[q], w0 = (double)w[q];
+            const double c1 = (double)cp[q], c2 = (double)cm[q];
+            const double uc = 0.5 * (u0 + (double)u[row + exp_]);
+            const double vc = 0.5 * (v0 + v1);
+            const double wc = 0.5 * (w0 + (double)w[row + ezp]);
+            rate = fmax(rate, fabs(uc) / d.dx + fabs(vc) / tb.dn[j] + fabs(wc) / d.dz);
+            cmax = fmax(cmax, c1 + c2);
+            cmin = fmin(cmin, fmin(c1, c2));
+            bad = bad || !__builtin_isfinite(u0) || !__builtin_isfinite(v0) || !__builtin_isfinite(w0) ||
+                  !__builtin_isfinite(c1) || !__builtin_isfinite(c2) || !__builtin_isfinite(f0);
+            double dphi = fmax(fabs((double)phi[row + exp_] - f0), fabs((double)phi[row + ezp] - f0));
+            if (top) dphi = fmax(dphi, fabs(f1 - f0 + e0 * tb.dc[j + 1]));
+            pe = fmax(pe, dphi);
+            v0 = v1;
+            f0 = f1;
+        }
     }
     s[0][threadIdx.x] = rate;
     s[1][threadIdx.x] = cmax;
@@ -298,16 +311,25 @@ hipError_t launch_shift_conc(nspnp_state *s, double mp, double mm) {
 
 hipError_t launch_dt(nspnp_state *s) {
     ProfScope prof_(s, K_DT);
-    const unsigned nb = (unsigned)std::min<int64_t>(kDtMaxBlocks, (s->d.n + kRedThreads - 1) / kRedThreads);
+    // columns in chunks of one block; rows split into slabs so that the
+    // partials fit kDtMaxBlocks per member
+    static_assert(kDtThreads == kRedThreads, "dt block size");
+    const int chunks = dt_chunks(s->d.plane);
+    const int slabs = std::max(1, std::min(s->d.M, kDtMaxBlocks / chunks));
+    const int slab_rows = (s->d.M + slabs - 1) / slabs;
+    const unsigned nb = (unsigned)(chunks * ((s->d.M + slab_rows - 1) / slab_rows));
+    if ((int64_t)nb * kDtParts > s->nred) return hipErrorInvalidValue;  // the layout sized red for this
     const dim3 g(nb, 1, (unsigned)s->nmem);
     if (s->fp64)
         k_dt_partial<double><<<g, kRedThreads, 0, s->stream>>>(
             s->d, s->tb, s->d_phys, (const double *)s->f[0], (const double *)s->f[1], (const double *)s->f[2],
-            (const double *)s->f[3], (const double *)s->f[4], (const double *)s->f[5], s->red, s->mstride);
+            (const double *)s->f[3], (const double *)s->f[4], (const double *)s->f[5], s->red, chunks, slab_rows,
+            s->mstride);
     else
         k_dt_partial<float><<<g, kRedThreads, 0, s->stream>>>(
             s->d, s->tb, s->d_phys, (const float *)s->f[0], (const float *)s->f[1], (const float *)s->f[2],
-            (const float *)s->f[3], (const float *)s->f[4], (const float *)s->f[5], s->red, s->mstride);
+            (const float *)s->f[3], (const float *)s->f[4], (const float *)s->f[5], s->red, chunks, slab_rows,
+            s->mstride);
     k_dt_final<<<dim3(1, 1, (unsigned)s->nmem), kRedThreads, 0, s->stream>>>((int)nb, s->red, s->d_phys, s->d,
                                                                              s->clock, s->mstride);
     return hipGetLastError();

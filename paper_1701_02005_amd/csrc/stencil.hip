@@ -42,11 +42,13 @@ struct ExplicitArgs {
     Stage st;
     const void *u, *v, *w, *cp, *cm, *phi, *p;
     void *h[5];
-    double *r[5];
+    void *r[5];  // Crank-Nicolson right-hand sides, state type (computed in it)
     double *dbg[5];
     const double *clock;
     int mode;  // 0: substep (H update + CN right-hand sides); 1: H to dbg only
-    int chunks;     // blocks per (x, z) plane
+    int tx, tz;     // a block's (x, z) tile: tx columns of tz z-lines
+    int ntx;        // tiles across x
+    int chunks;     // tiles per (x, z) plane
     int slabs;      // row slabs per member
     int slab_rows;  // rows marched by one block
 };
@@ -64,22 +66,29 @@ __device__ __forceinline__ void shift_explicit(ExplicitArgs &a, unsigned mem) {
 // Convection, horizontal diffusion, Coulomb force and ion transport at one
 // cell, then the Crank-Nicolson right-hand side
 //   r = dt [gam H^k + zet H^{k-1} - alp G p + alp nu L_y q].
-// Each thread owns one (x, z) column and marches through a slab of rows,
-// keeping its own values of rows j-1, j, j+1 in registers (row j+2 is
-// loaded one step ahead); values of neighbouring columns come from the
-// caches, where the neighbouring threads of the block have just loaded them.
-// So every field is read from HBM about once, and each field's H and r are
-// stored as soon as they are known.
-template <typename T>
-struct Own {  // own-column values at rows j-1 (m), j (c), j+1 (p)
-    T um, uc, up, vm, vc, vp, wm, wc, wp, am, ac, ap, bm, bc, bp, fm, fc, fp, pm, pc;  // a = c+, b = c-, f = phi
+//
+// Data movement.  A block owns a 2-D tile of (x, z) columns (tx along x, tz
+// z-lines) and marches a slab of rows.  Rows j and j+1 of all seven fields,
+// each over the tile plus a one-column halo (periodic in x and z), sit in a
+// two-slot LDS ring.  The global loads of row j+2 (coalesced, two halo
+// positions per thread) and of H^{k-1} at row j+1 are issued before row j is
+// computed and land in LDS / registers after it, so the memory latency hides
+// behind a whole row of arithmetic and every neighbour value is an LDS read.
+// Own-column values of row j-1 and the two row-(j-1) neighbours the v-point
+// needs are carried in registers from the previous row.
+constexpr int kNF = 7;  // u v w c+ c- phi p
+
+template <typename T, int kHalo>
+struct HaloRegs {
+    T v[kNF][kHalo];
 };
 
-// FP64 needs 160 registers without spilling (3 waves per SIMD), FP32 128 (4)
-template <typename T, int kWaves>
+template <typename T, int kHalo, int kWaves>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) k_explicit(ExplicitArgs a) {
+    extern __shared__ unsigned char s_raw[];
+    T *sm = (T *)s_raw;  // [slot 0..1][field 0..6][halo tile]
     const unsigned chunks = (unsigned)a.chunks, slabs = (unsigned)a.slabs;
-    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);  // chunk fastest: z-neighbours share an L2
+    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);  // x-tiles fastest: z-neighbour tiles share an L2
     const unsigned chunk = tile % chunks;
     const unsigned slab = (tile / chunks) % slabs;
     const unsigned mem = tile / (chunks * slabs);
@@ -88,24 +97,43 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
     const Dims &d = a.d;
     const int nx = d.nx, nz = d.nz, M = d.M;
     const int pl = (int)d.plane;
-    const int e = (int)chunk * blockDim.x + threadIdx.x;
-    if (e >= pl) return;
-    const int k = e / nx;
-    const int i = e - k * nx;
-    const int ip = (i + 1 == nx) ? 0 : i + 1, im = (i == 0) ? nx - 1 : i - 1;
-    const int kp = (k + 1 == nz) ? 0 : k + 1, km = (k == 0) ? nz - 1 : k - 1;
-    // in-plane offsets of the neighbouring columns
-    const int exp_ = e - i + ip, exm = e - i + im;
-    const int ezp = e + (kp - k) * nx, ezm = e + (km - k) * nx;
-    const int e_ip_km = ezm - i + ip, e_im_kp = ezp - i + im;
+    const int tx = a.tx, tz = a.tz, hx = tx + 2, HS = hx * (tz + 2);
+    const int i0 = (int)(chunk % (unsigned)a.ntx) * tx, k0 = (int)(chunk / (unsigned)a.ntx) * tz;
+    const int lk = (int)threadIdx.x / tx, li = (int)threadIdx.x - lk * tx;
+    const int i = i0 + li, k = k0 + lk;
+    const bool active = lk < tz && i < nx && k < nz;
+    const int c = (lk + 1) * hx + (li + 1);  // own position in the halo tile
 
-    const T *__restrict__ u = (const T *)a.u;
-    const T *__restrict__ v = (const T *)a.v;
-    const T *__restrict__ w = (const T *)a.w;
-    const T *__restrict__ cp = (const T *)a.cp;
-    const T *__restrict__ cm = (const T *)a.cm;
-    const T *__restrict__ phi = (const T *)a.phi;
-    const T *__restrict__ p = (const T *)a.p;
+    const T *__restrict__ F[kNF] = {(const T *)a.u, (const T *)a.v, (const T *)a.w, (const T *)a.cp,
+                                    (const T *)a.cm, (const T *)a.phi, (const T *)a.p};
+    // halo positions this thread loads: in-plane offsets, fixed for every row
+    int off[kHalo];
+    int spos[kHalo];
+#pragma unroll
+    for (int q = 0; q < kHalo; ++q) {
+        const int sp = (int)threadIdx.x + q * (int)blockDim.x;
+        spos[q] = sp;
+        const int hz = sp / hx, hxp = sp - hz * hx;
+        int gi = (i0 - 1 + hxp) % nx, gk = (k0 - 1 + hz) % nz;
+        if (gi < 0) gi += nx;
+        if (gk < 0) gk += nz;
+        off[q] = (sp < HS) ? gk * nx + gi : -1;
+    }
+    auto load_rows = [&](int row, HaloRegs<T, kHalo> &r) {
+        const int base = row * pl;
+#pragma unroll
+        for (int f = 0; f < kNF; ++f)
+#pragma unroll
+            for (int q = 0; q < kHalo; ++q) r.v[f][q] = (off[q] >= 0) ? F[f][base + off[q]] : T(0);
+    };
+    auto store_rows = [&](int slot, const HaloRegs<T, kHalo> &r) {
+#pragma unroll
+        for (int f = 0; f < kNF; ++f)
+#pragma unroll
+            for (int q = 0; q < kHalo; ++q)
+                if (off[q] >= 0) sm[(slot * kNF + f) * HS + spos[q]] = r.v[f][q];
+    };
+    auto X = [&](int slot, int f, int dx, int dz) -> T { return sm[(slot * kNF + f) * HS + c + dz * hx + dx]; };
 
     const T half = T(0.5), two = T(2);
     const T idx_ = T(1.0 / d.dx), idz_ = T(1.0 / d.dz);
@@ -116,173 +144,201 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
     const T gam = T(a.st.gam), zet = T(a.st.zet), alp = T(a.st.alp);
     const bool use_old = (a.st.k > 0) && mode == 0;
     const bool keep = (a.st.k < 2) && mode == 0;
+    const int e = active ? k * nx + i : 0;
+    const int ip = (i + 1 >= nx) ? 0 : i + 1;
+    const int kp = (k + 1 >= nz) ? 0 : k + 1;
+    const int e_xp = k * nx + ip, e_zp = kp * nx + i;
 
     const int j0 = (int)slab * a.slab_rows;
     const int j1 = (j0 + a.slab_rows < M) ? j0 + a.slab_rows : M;
-    Own<T> o;
-    auto load_row = [&](int j, T &uu, T &vv, T &ww, T &aa, T &bb, T &ff) {
-        const int q = j * pl + e;
-        uu = u[q]; vv = v[q]; ww = w[q]; aa = cp[q]; bb = cm[q]; ff = phi[q];
-    };
+    const int jl = (j1 < M - 1) ? j1 : M - 1;  // last row staged in LDS
+
+    // row j0 - 1: own-column values and the two neighbours the v-point needs
     const T zero = T(0);
-    o.um = o.vm = o.wm = o.am = o.bm = o.fm = o.pm = zero;
-    o.up = o.vp = o.wp = o.ap = o.bp = o.fp = zero;
-    if (j0 > 0) {
-        load_row(j0 - 1, o.um, o.vm, o.wm, o.am, o.bm, o.fm);
-        o.pm = p[(j0 - 1) * pl + e];
+    T um = zero, vm = zero, wm = zero, am = zero, bm = zero, fm = zero, pm = zero, u_xp_m = zero, w_zp_m = zero;
+    if (j0 > 0 && active) {
+        const int q = (j0 - 1) * pl;
+        um = F[0][q + e]; vm = F[1][q + e]; wm = F[2][q + e]; am = F[3][q + e]; bm = F[4][q + e];
+        fm = F[5][q + e]; pm = F[6][q + e];
+        u_xp_m = F[0][q + e_xp];
+        w_zp_m = F[2][q + e_zp];
     }
-    load_row(j0, o.uc, o.vc, o.wc, o.ac, o.bc, o.fc);
-    o.pc = p[j0 * pl + e];
-    if (j0 + 1 < M) load_row(j0 + 1, o.up, o.vp, o.wp, o.ap, o.bp, o.fp);
-
-    for (int j = j0; j < j1; ++j) {
-        const int q = j * pl + e;
-        const int xp = j * pl + exp_, xm = j * pl + exm, zp = j * pl + ezp, zm = j * pl + ezm;
-        const bool has_up = (j + 1 < M), has_dn = (j > 0);
-        const T idn = T(a.tb.idn[j]);
-        const T idcb = T(a.tb.idc[j]), idct = T(a.tb.idc[j + 1]);
-        const T uc = o.uc, vc = o.vc, wc = o.wc;
-        const T rho0 = o.ac - o.bc;
-        const T ph0 = o.fc;
-
-        auto emit = [&](int f, T hval, T gp, T nu_ly) {
-            if (mode == 1) {
-                a.dbg[f][q] = (double)hval;
-                return;
-            }
-            T *__restrict__ hb = (T *)a.h[f];
-            const T hold = use_old ? hb[q] : T(0);
-            a.r[f][q] = (double)(dt * (gam * hval + zet * hold - alp * gp + alp * nu_ly));
-            if (keep) hb[q] = hval;
-        };
-
-        // ---------------- u on the x-face ----------------
-        {
-            const T uxp = u[xp], uxm = u[xm], uzp = u[zp], uzm = u[zm];
-            const T a1 = half * (uxp + uc), a2 = half * (uc + uxm);
-            const T cx = (a1 * a1 - a2 * a2) * idx_;
-            T flux_t = T(0), flux_b = T(0), ut = T(ph.u_top), ub = T(ph.u_bot);
-            if (has_up) {
-                ut = o.up;
-                flux_t = half * (o.vp + v[(j + 1) * pl + exm]) * half * (ut + uc);
-            }
-            if (has_dn) {
-                ub = o.um;
-                flux_b = half * (vc + v[xm]) * half * (uc + ub);
-            }
-            const T cy = (flux_t - flux_b) * idn;
-            const T wf = half * (w[zp] + w[j * pl + e_im_kp]);
-            const T wb = half * (wc + w[xm]);
-            const T cz = (wf * half * (uzp + uc) - wb * half * (uc + uzm)) * idz_;
-            const T lap = (uxp - two * uc + uxm) * ix2 + (uzp - two * uc + uzm) * iz2;
-            const T rhox = cp[xm] - cm[xm];
-            const T f = kf * half * (rho0 + rhox) * (ph0 - phi[xm]) * idx_;
-            const T ly = ((ut - uc) * idct - (uc - ub) * idcb) * idn;
-            emit(0, -(cx + cy + cz) + ire * lap + f, (o.pc - p[xm]) * idx_, ire * ly);
-        }
-        // ---------------- w on the z-face ----------------
-        {
-            const T wzp = w[zp], wzm = w[zm], wxp = w[xp], wxm = w[xm];
-            const T a1 = half * (wzp + wc), a2 = half * (wc + wzm);
-            const T cz = (a1 * a1 - a2 * a2) * idz_;
-            const T ur = half * (u[xp] + u[j * pl + e_ip_km]);
-            const T ul = half * (uc + u[zm]);
-            const T cx = (ur * half * (wxp + wc) - ul * half * (wc + wxm)) * idx_;
-            T flux_t = T(0), flux_b = T(0), wt = T(0), wb = T(0);
-            if (has_up) {
-                wt = o.wp;
-                flux_t = half * (o.vp + v[(j + 1) * pl + ezm]) * half * (wt + wc);
-            }
-            if (has_dn) {
-                wb = o.wm;
-                flux_b = half * (vc + v[zm]) * half * (wc + wb);
-            }
-            const T cy = (flux_t - flux_b) * idn;
-            const T lap = (wxp - two * wc + wxm) * ix2 + (wzp - two * wc + wzm) * iz2;
-            const T rhoz = cp[zm] - cm[zm];
-            const T f = kf * half * (rho0 + rhoz) * (ph0 - phi[zm]) * idz_;
-            const T ly = ((wt - wc) * idct - (wc - wb) * idcb) * idn;
-            emit(2, -(cx + cy + cz) + ire * lap + f, (o.pc - p[zm]) * idz_, ire * ly);
-        }
-        // ---------------- v on the bottom y-face of row j ----------------
-        if (has_dn) {
-            const T vwl = T(a.tb.vwl[j]), vwu = T(a.tb.vwu[j]);
-            const T idn_lo = T(a.tb.idn[j - 1]);
-            const T vtop = has_up ? o.vp : T(0);
-            const T vbot = (j > 1) ? o.vm : T(0);
-            const T a1 = half * (vtop + vc), a2 = half * (vc + vbot);
-            const T cy = (a1 * a1 - a2 * a2) * idcb;
-            const T ur = u[(j - 1) * pl + exp_] * vwl + u[xp] * vwu;
-            const T ul = o.um * vwl + uc * vwu;
-            const T vxp = v[xp], vxm = v[xm], vzp = v[zp], vzm = v[zm];
-            const T cx = (ur * half * (vxp + vc) - ul * half * (vc + vxm)) * idx_;
-            const T wf = w[(j - 1) * pl + ezp] * vwl + w[zp] * vwu;
-            const T wbk = o.wm * vwl + wc * vwu;
-            const T cz = (wf * half * (vzp + vc) - wbk * half * (vc + vzm)) * idz_;
-            const T lap = (vxp - two * vc + vxm) * ix2 + (vzp - two * vc + vzm) * iz2;
-            const T rhoy = o.am - o.bm;
-            const T ey = e0 + (ph0 - o.fm) * idcb;
-            const T f = kf * half * (rho0 + rhoy) * ey;
-            const T ly = ((vtop - vc) * idn - (vc - vbot) * idn_lo) * idcb;
-            emit(1, -(cx + cy + cz) + ire * lap + f, (o.pc - o.pm) * idcb, ire * ly);
-        } else {
-            emit(1, T(0), T(0), T(0));
-            if (mode == 0) a.r[1][q] = 0.0;
-        }
-        // ---------------- ions at the cell centre ----------------
-        {
-            const T uxp = u[xp], wzp = w[zp];
-            const T gx_r = (phi[xp] - ph0) * idx_, gx_l = (ph0 - phi[xm]) * idx_;
-            const T gz_f = (phi[zp] - ph0) * idz_, gz_b = (ph0 - phi[zm]) * idz_;
-            const T ey_t = has_up ? e0 + (o.fp - ph0) * idct : T(0);
-            const T ey_b = has_dn ? e0 + (ph0 - o.fm) * idcb : T(0);
-            const T vt = has_up ? o.vp : T(0);
+    T hold_c[5], hold_n[5];
 #pragma unroll
-            for (int sp = 0; sp < 2; ++sp) {
-                const T *__restrict__ c = sp == 0 ? cp : cm;
-                const T zs = sp == 0 ? T(1) : T(-1);
-                const T cc = sp == 0 ? o.ac : o.bc;
-                const T cu = sp == 0 ? o.ap : o.bp;
-                const T cd = sp == 0 ? o.am : o.bm;
-                const T cxp = c[xp], cxm = c[xm], czp = c[zp], czm = c[zm];
-                const T fxr = half * (cxp + cc), fxl = half * (cc + cxm);
-                const T fzf = half * (czp + cc), fzb = half * (cc + czm);
-                const T ax = (uxp * fxr - uc * fxl) * idx_;
-                const T az = (wzp * fzf - wc * fzb) * idz_;
-                T at = T(0), ab = T(0), mt = T(0), mb = T(0), dft = T(0), dfb = T(0);
+    for (int f = 0; f < 5; ++f) {
+        hold_c[f] = (use_old && active) ? ((const T *)a.h[f])[j0 * pl + e] : zero;
+        hold_n[f] = zero;
+    }
+    {
+        HaloRegs<T, kHalo> r0;
+        load_rows(j0, r0);
+        store_rows(j0 & 1, r0);
+        if (j0 + 1 < M) {
+            load_rows(j0 + 1, r0);
+            store_rows((j0 + 1) & 1, r0);
+        }
+    }
+    __syncthreads();
+
+    HaloRegs<T, kHalo> rn;
+    for (int j = j0; j < j1; ++j) {
+        const int sc = j & 1, sn = sc ^ 1;
+        const bool pre = (j + 2 <= jl);
+        if (pre) load_rows(j + 2, rn);  // lands in LDS after this row
+        if (use_old && active && j + 1 < j1) {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) hold_n[f] = ((const T *)a.h[f])[(j + 1) * pl + e];
+        }
+        const bool has_up = (j + 1 < M), has_dn = (j > 0);
+        const int q = j * pl + e;
+        if (active) {
+            const T idn = T(a.tb.idn[j]);
+            const T idcb = T(a.tb.idc[j]), idct = T(a.tb.idc[j + 1]);
+            const T uc = X(sc, 0, 0, 0), vc = X(sc, 1, 0, 0), wc = X(sc, 2, 0, 0);
+            const T ac = X(sc, 3, 0, 0), bc = X(sc, 4, 0, 0), ph0 = X(sc, 5, 0, 0), pc = X(sc, 6, 0, 0);
+            const T up_ = has_up ? X(sn, 0, 0, 0) : zero, vp = has_up ? X(sn, 1, 0, 0) : zero;
+            const T wp = has_up ? X(sn, 2, 0, 0) : zero, ap = has_up ? X(sn, 3, 0, 0) : zero;
+            const T bp = has_up ? X(sn, 4, 0, 0) : zero, fp = has_up ? X(sn, 5, 0, 0) : zero;
+            const T rho0 = ac - bc;
+            const T uxp = X(sc, 0, 1, 0), wzp = X(sc, 2, 0, 1);
+
+            auto emit = [&](int f, T hval, T gp, T nu_ly) {
+                if (mode == 1) {
+                    a.dbg[f][q] = (double)hval;
+                    return;
+                }
+                T *__restrict__ hb = (T *)a.h[f];
+                ((T *)a.r[f])[q] = dt * (gam * hval + zet * hold_c[f] - alp * gp + alp * nu_ly);
+                if (keep) hb[q] = hval;
+            };
+
+            // ---------------- u on the x-face ----------------
+            {
+                const T uxm = X(sc, 0, -1, 0), uzp = X(sc, 0, 0, 1), uzm = X(sc, 0, 0, -1);
+                const T a1 = half * (uxp + uc), a2 = half * (uc + uxm);
+                const T cx = (a1 * a1 - a2 * a2) * idx_;
+                T flux_t = T(0), flux_b = T(0), ut = T(ph.u_top), ub = T(ph.u_bot);
                 if (has_up) {
-                    const T fy = half * (cu + cc);
-                    at = vt * fy;
-                    mt = fy * ey_t;
-                    dft = (cu - cc) * idct;
+                    ut = up_;
+                    flux_t = half * (vp + X(sn, 1, -1, 0)) * half * (ut + uc);
                 }
                 if (has_dn) {
-                    const T fy = half * (cc + cd);
-                    ab = vc * fy;
-                    mb = fy * ey_b;
-                    dfb = (cc - cd) * idcb;
+                    ub = um;
+                    flux_b = half * (vc + X(sc, 1, -1, 0)) * half * (uc + ub);
                 }
-                const T ay = (at - ab) * idn;
-                const T mx = (fxr * gx_r - fxl * gx_l) * idx_;
-                const T mz = (fzf * gz_f - fzb * gz_b) * idz_;
-                const T my = (mt - mb) * idn;
-                const T dxx = (cxp - two * cc + cxm) * ix2 + (czp - two * cc + czm) * iz2;
-                emit(3 + sp, -(ax + ay + az) + kd * (dxx + zs * (mx + my + mz)), T(0), kd * (dft - dfb) * idn);
+                const T cy = (flux_t - flux_b) * idn;
+                const T wf = half * (wzp + X(sc, 2, -1, 1));
+                const T wb = half * (wc + X(sc, 2, -1, 0));
+                const T cz = (wf * half * (uzp + uc) - wb * half * (uc + uzm)) * idz_;
+                const T lap = (uxp - two * uc + uxm) * ix2 + (uzp - two * uc + uzm) * iz2;
+                const T rhox = X(sc, 3, -1, 0) - X(sc, 4, -1, 0);
+                const T f = kf * half * (rho0 + rhox) * (ph0 - X(sc, 5, -1, 0)) * idx_;
+                const T ly = ((ut - uc) * idct - (uc - ub) * idcb) * idn;
+                emit(0, -(cx + cy + cz) + ire * lap + f, (pc - X(sc, 6, -1, 0)) * idx_, ire * ly);
             }
+            __builtin_amdgcn_sched_barrier(0);
+            // ---------------- w on the z-face ----------------
+            {
+                const T wzm = X(sc, 2, 0, -1), wxp = X(sc, 2, 1, 0), wxm = X(sc, 2, -1, 0);
+                const T a1 = half * (wzp + wc), a2 = half * (wc + wzm);
+                const T cz = (a1 * a1 - a2 * a2) * idz_;
+                const T ur = half * (uxp + X(sc, 0, 1, -1));
+                const T ul = half * (uc + X(sc, 0, 0, -1));
+                const T cx = (ur * half * (wxp + wc) - ul * half * (wc + wxm)) * idx_;
+                T flux_t = T(0), flux_b = T(0), wt = T(0), wb = T(0);
+                if (has_up) {
+                    wt = wp;
+                    flux_t = half * (vp + X(sn, 1, 0, -1)) * half * (wt + wc);
+                }
+                if (has_dn) {
+                    wb = wm;
+                    flux_b = half * (vc + X(sc, 1, 0, -1)) * half * (wc + wb);
+                }
+                const T cy = (flux_t - flux_b) * idn;
+                const T lap = (wxp - two * wc + wxm) * ix2 + (wzp - two * wc + wzm) * iz2;
+                const T rhoz = X(sc, 3, 0, -1) - X(sc, 4, 0, -1);
+                const T f = kf * half * (rho0 + rhoz) * (ph0 - X(sc, 5, 0, -1)) * idz_;
+                const T ly = ((wt - wc) * idct - (wc - wb) * idcb) * idn;
+                emit(2, -(cx + cy + cz) + ire * lap + f, (pc - X(sc, 6, 0, -1)) * idz_, ire * ly);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            // ---------------- v on the bottom y-face of row j ----------------
+            if (has_dn) {
+                const T vwl = T(a.tb.vwl[j]), vwu = T(a.tb.vwu[j]);
+                const T idn_lo = T(a.tb.idn[j - 1]);
+                const T vtop = has_up ? vp : T(0);
+                const T vbot = (j > 1) ? vm : T(0);
+                const T a1 = half * (vtop + vc), a2 = half * (vc + vbot);
+                const T cy = (a1 * a1 - a2 * a2) * idcb;
+                const T ur = u_xp_m * vwl + uxp * vwu;
+                const T ul = um * vwl + uc * vwu;
+                const T vxp = X(sc, 1, 1, 0), vxm = X(sc, 1, -1, 0), vzp = X(sc, 1, 0, 1), vzm = X(sc, 1, 0, -1);
+                const T cx = (ur * half * (vxp + vc) - ul * half * (vc + vxm)) * idx_;
+                const T wf = w_zp_m * vwl + wzp * vwu;
+                const T wbk = wm * vwl + wc * vwu;
+                const T cz = (wf * half * (vzp + vc) - wbk * half * (vc + vzm)) * idz_;
+                const T lap = (vxp - two * vc + vxm) * ix2 + (vzp - two * vc + vzm) * iz2;
+                const T rhoy = am - bm;
+                const T ey = e0 + (ph0 - fm) * idcb;
+                const T f = kf * half * (rho0 + rhoy) * ey;
+                const T ly = ((vtop - vc) * idn - (vc - vbot) * idn_lo) * idcb;
+                emit(1, -(cx + cy + cz) + ire * lap + f, (pc - pm) * idcb, ire * ly);
+            } else {
+                emit(1, T(0), T(0), T(0));
+                if (mode == 0) ((T *)a.r[1])[q] = T(0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            // ---------------- ions at the cell centre ----------------
+            {
+                const T fxp = X(sc, 5, 1, 0), fxm = X(sc, 5, -1, 0), fzp = X(sc, 5, 0, 1), fzm = X(sc, 5, 0, -1);
+                const T gx_r = (fxp - ph0) * idx_, gx_l = (ph0 - fxm) * idx_;
+                const T gz_f = (fzp - ph0) * idz_, gz_b = (ph0 - fzm) * idz_;
+                const T ey_t = has_up ? e0 + (fp - ph0) * idct : T(0);
+                const T ey_b = has_dn ? e0 + (ph0 - fm) * idcb : T(0);
+                const T vt = has_up ? vp : T(0);
+#pragma unroll
+                for (int sp = 0; sp < 2; ++sp) {
+                    const int fi = 3 + sp;
+                    const T zs = sp == 0 ? T(1) : T(-1);
+                    const T cc = sp == 0 ? ac : bc;
+                    const T cu = sp == 0 ? ap : bp;
+                    const T cd = sp == 0 ? am : bm;
+                    const T cxp = X(sc, fi, 1, 0), cxm = X(sc, fi, -1, 0), czp = X(sc, fi, 0, 1), czm = X(sc, fi, 0, -1);
+                    const T fxr = half * (cxp + cc), fxl = half * (cc + cxm);
+                    const T fzf = half * (czp + cc), fzb = half * (cc + czm);
+                    const T ax = (uxp * fxr - uc * fxl) * idx_;
+                    const T az = (wzp * fzf - wc * fzb) * idz_;
+                    T at = T(0), ab = T(0), mt = T(0), mb = T(0), dft = T(0), dfb = T(0);
+                    if (has_up) {
+                        const T fy = half * (cu + cc);
+                        at = vt * fy;
+                        mt = fy * ey_t;
+                        dft = (cu - cc) * idct;
+                    }
+                    if (has_dn) {
+                        const T fy = half * (cc + cd);
+                        ab = vc * fy;
+                        mb = fy * ey_b;
+                        dfb = (cc - cd) * idcb;
+                    }
+                    const T ay = (at - ab) * idn;
+                    const T mx = (fxr * gx_r - fxl * gx_l) * idx_;
+                    const T mz = (fzf * gz_f - fzb * gz_b) * idz_;
+                    const T my = (mt - mb) * idn;
+                    const T dxx = (cxp - two * cc + cxm) * ix2 + (czp - two * cc + czm) * iz2;
+                    emit(fi, -(ax + ay + az) + kd * (dxx + zs * (mx + my + mz)), T(0), kd * (dft - dfb) * idn);
+                }
+            }
+            // carry row j as row j - 1 of the next step
+            um = uc; vm = vc; wm = wc; am = ac; bm = bc; fm = ph0; pm = pc;
+            u_xp_m = uxp;
+            w_zp_m = wzp;
         }
-        // rotate the own-column window and load row j + 2 into the freed slot
-        if (j + 1 < j1) {
-            o.um = o.uc; o.uc = o.up;
-            o.vm = o.vc; o.vc = o.vp;
-            o.wm = o.wc; o.wc = o.wp;
-            o.am = o.ac; o.ac = o.ap;
-            o.bm = o.bc; o.bc = o.bp;
-            o.fm = o.fc; o.fc = o.fp;
-            o.pm = o.pc;
-            o.pc = p[(j + 1) * pl + e];
-            if (j + 2 < M) load_row(j + 2, o.up, o.vp, o.wp, o.ap, o.bp, o.fp);
-            else o.up = o.vp = o.wp = o.ap = o.bp = o.fp = zero;
-        }
+#pragma unroll
+        for (int f = 0; f < 5; ++f) hold_c[f] = hold_n[f];
+        __syncthreads();  // every wave is done with slot sc (row j)
+        if (pre) store_rows(sc, rn);
+        __syncthreads();
     }
 }
 
@@ -293,24 +349,24 @@ struct CnArgs {
     Tables tb;
     Stage st;
     void *q[5];
-    double *r[5];
+    const void *r[5];  // right-hand sides, state type
     const double *clock;
     double *coef;  // [3 systems][g, m, n][M] recurrence coefficients of this substep
 };
 
 // Row coefficients of the Crank-Nicolson matrix (I - beta L_y) of system
 // sys: 0 = cell rows with wall values (u, w), 1 = interior nodes (v),
-// 2 = cell rows with zero-flux walls (c+, c-).
-__device__ __forceinline__ void cn_row(const Tables &tb, int sys, int M, int j, double beta, double &A, double &B,
-                                       double &C) {
+// 2 = cell rows with zero-flux walls (c+, c-).  lo/up are the L_y
+// coefficient tables of the system's rows (node rows for sys 1).
+__device__ __forceinline__ void cn_row(const double *lo_tab, const double *up_tab, int sys, int M, int j,
+                                       double beta, double &A, double &B, double &C) {
     double lo, up, di;
+    const double aa = lo_tab[j], cc = up_tab[j];
     if (sys == 1) {
-        const double aa = tb.lyn_lo[j], cc = tb.lyn_up[j];
         lo = (j > 1) ? aa : 0.0;
         up = (j < M - 1) ? cc : 0.0;
         di = -(aa + cc);
     } else {
-        const double aa = tb.lyc_lo[j], cc = tb.lyc_up[j];
         lo = (j > 0) ? aa : 0.0;
         up = (j < M - 1) ? cc : 0.0;
         di = -(lo + up);
@@ -324,33 +380,61 @@ __device__ __forceinline__ void cn_row(const Tables &tb, int sys, int M, int j, 
     C = -beta * up;
 }
 
+constexpr int kMaxRows = 480;  // cell rows of the largest supported grid (ny <= 481)
+
 // The matrix is the same for every (x, z) column, so Thomas elimination
 // reduces to two linear recurrences with column-independent coefficients:
 //   d'_j = g_j r_j + m_j d'_{j-1},   x_j = d'_j + n_j x_{j+1}
 // with g = 1/den, m = -A/den, n = -c' (den, c' of the Thomas forward pass).
-// One thread per system and member computes them for this substep.
-__global__ void k_cn_coef(Dims d, Tables tb, const Phys *phys, const double *clock, double *coef, double alp,
-                          size_t ms) {
-    const int sys = threadIdx.x;
-    if (sys >= 3) return;
+// One block per member and Runge-Kutta stage (blockIdx.y): the L_y tables are
+// staged in LDS, one thread per system runs the (serial) forward pass from
+// LDS with one reciprocal per row, and the block stores the 9 M coefficients
+// of its stage with coalesced writes.  Launched once per Runge-Kutta step
+// (dt changes only at the first stage).
+struct CnStages {
+    double alp[3];
+};
+
+__global__ void __launch_bounds__(256) k_cn_coef(Dims d, Tables tb, const Phys *phys, const double *clock,
+                                                 double *coef, CnStages stages, size_t ms) {
+    __shared__ double s_tab[4][kMaxRows];      // lyc_lo, lyc_up, lyn_lo, lyn_up
+    __shared__ double s_out[9][kMaxRows];      // [sys][g, m, n][row]
     phys = member_ptr(phys, ms);
     clock = member_ptr(clock, ms);
-    coef = member_ptr(coef, ms);
     const int M = d.M;
-    const double nu = (sys == 2) ? phys->kd : phys->ire;
-    const double beta = 0.5 * alp * clock[1] * nu;
-    double *g = coef + (size_t)sys * 3 * M, *m = g + M, *n = m + M;
-    const int j0 = (sys == 1) ? 1 : 0;
-    double cprev = 0.0;
-    for (int j = j0; j < M; ++j) {
-        double A, B, C;
-        cn_row(tb, sys, M, j, beta, A, B, C);
-        const double den = B - A * cprev;
-        const double cj = C / den;
-        g[j] = 1.0 / den;
-        m[j] = -A / den;
-        n[j] = -cj;
-        cprev = cj;
+    const int stage = blockIdx.y;
+    coef = member_ptr(coef, ms) + (size_t)stage * 9 * M;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        s_tab[0][j] = tb.lyc_lo[j];
+        s_tab[1][j] = tb.lyc_up[j];
+        s_tab[2][j] = tb.lyn_lo[j];
+        s_tab[3][j] = tb.lyn_up[j];
+    }
+    __syncthreads();
+    const int sys = threadIdx.x;
+    if (sys < 3) {
+        const double nu = (sys == 2) ? phys->kd : phys->ire;
+        const double beta = 0.5 * stages.alp[stage] * clock[1] * nu;
+        const double *lo_tab = s_tab[sys == 1 ? 2 : 0], *up_tab = s_tab[sys == 1 ? 3 : 1];
+        double *g = s_out[3 * sys], *m = s_out[3 * sys + 1], *n = s_out[3 * sys + 2];
+        const int j0 = (sys == 1) ? 1 : 0;
+        if (j0 == 1) g[0] = m[0] = n[0] = 0.0;  // node row 0 is the wall: no unknown
+        double cprev = 0.0;
+        for (int j = j0; j < M; ++j) {
+            double A, B, C;
+            cn_row(lo_tab, up_tab, sys, M, j, beta, A, B, C);
+            const double rden = 1.0 / (B - A * cprev);
+            const double cj = C * rden;
+            g[j] = rden;
+            m[j] = -A * rden;
+            n[j] = -cj;
+            cprev = cj;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 9 * M; e += blockDim.x) {
+        const int sk = e / M, j = e - sk * M;
+        coef[e] = s_out[sk][j];
     }
 }
 
@@ -373,9 +457,9 @@ __global__ void __launch_bounds__(256) k_cn_scan(CnArgs a) {
     const int64_t pl = a.d.plane;
     const int64_t c0 = (int64_t)blockIdx.x * kCnTx;
     const int ncol = (int)((pl - c0) < kCnTx ? (pl - c0) : kCnTx);
-    const double *__restrict__ r = member_ptr(a.r[f], ms);
+    const T *__restrict__ r = (const T *)member_ptr(a.r[f], ms);
     T *__restrict__ q = (T *)member_ptr(a.q[f], ms);
-    const double *__restrict__ coef = member_ptr(a.coef, ms) + (size_t)sys * 3 * M;
+    const double *__restrict__ coef = member_ptr(a.coef, ms) + (size_t)a.st.k * 9 * M + (size_t)sys * 3 * M;
     const double *__restrict__ cg = coef, *__restrict__ cm = coef + M, *__restrict__ cn = coef + 2 * M;
     constexpr int LD = kCnTx + 1;
     const int nrow = M - j0;
@@ -526,6 +610,35 @@ inline dim3 grid1(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) /
 
 }  // namespace
 
+// Column tiles of the explicit kernel: up to 64 columns along x (whole
+// x-lines when nx is smaller) times as many z-lines as the block has room for.
+static void explicit_tiling(const Dims &d, int threads, int slab_rows, ExplicitArgs &a) {
+    a.tx = d.nx < 64 ? d.nx : 64;
+    if (a.tx > threads) a.tx = threads;
+    a.tz = threads / a.tx;
+    a.ntx = (d.nx + a.tx - 1) / a.tx;
+    a.chunks = a.ntx * ((d.nz + a.tz - 1) / a.tz);
+    a.slab_rows = slab_rows;
+    a.slabs = (d.M + slab_rows - 1) / slab_rows;
+}
+
+// Launch of the explicit kernel with its halo-tile LDS ring; kHalo halo
+// positions per thread cover the tile plus halo ((tx+2)(tz+2) <= kHalo * threads).
+static hipError_t explicit_launch(nspnp_state *s, const ExplicitArgs &a, int threads, unsigned blocks) {
+    const int hs = (a.tx + 2) * (a.tz + 2);
+    const size_t lds = 2 * (size_t)kNF * hs * s->wsize;
+    if (hs <= 2 * threads) {
+        if (s->fp64) k_explicit<double, 2, 2><<<blocks, threads, lds, s->stream>>>(a);
+        else k_explicit<float, 2, 3><<<blocks, threads, lds, s->stream>>>(a);
+    } else if (hs <= 4 * threads) {
+        if (s->fp64) k_explicit<double, 4, 2><<<blocks, threads, lds, s->stream>>>(a);
+        else k_explicit<float, 4, 3><<<blocks, threads, lds, s->stream>>>(a);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_explicit(nspnp_state *s, const Stage &st, bool /*write_r*/) {
     ProfScope prof_(s, K_EXPLICIT);
     ExplicitArgs a{};
@@ -539,13 +652,8 @@ hipError_t launch_explicit(nspnp_state *s, const Stage &st, bool /*write_r*/) {
     a.clock = s->clock;
     a.mode = 0;
     const int tb = s->tiles.expl;
-    a.chunks = (int)((s->d.plane + tb - 1) / tb);
-    a.slab_rows = s->tiles.slab;
-    a.slabs = (s->d.M + a.slab_rows - 1) / a.slab_rows;
-    const dim3 g((unsigned)((int64_t)a.chunks * a.slabs * s->nmem));
-    if (s->fp64) k_explicit<double, 3><<<g, tb, 0, s->stream>>>(a);
-    else k_explicit<float, 4><<<g, tb, 0, s->stream>>>(a);
-    return hipGetLastError();
+    explicit_tiling(s->d, tb, s->tiles.slab, a);
+    return explicit_launch(s, a, tb, (unsigned)((int64_t)a.chunks * a.slabs * s->nmem));
 }
 
 hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]) {
@@ -559,13 +667,8 @@ hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]) {
     for (int q = 0; q < 5; ++q) { a.h[q] = s->h[q]; a.r[q] = s->r[q]; a.dbg[q] = out[q]; }
     a.clock = s->clock;
     a.mode = 1;
-    a.chunks = (int)((s->d.plane + 255) / 256);
-    a.slab_rows = s->tiles.slab;
-    a.slabs = (s->d.M + a.slab_rows - 1) / a.slab_rows;
-    const dim3 g((unsigned)((int64_t)a.chunks * a.slabs));
-    if (s->fp64) k_explicit<double, 3><<<g, 256, 0, s->stream>>>(a);
-    else k_explicit<float, 4><<<g, 256, 0, s->stream>>>(a);
-    return hipGetLastError();
+    explicit_tiling(s->d, 256, s->tiles.slab, a);
+    return explicit_launch(s, a, 256, (unsigned)((int64_t)a.chunks * a.slabs));
 }
 
 hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
@@ -579,8 +682,13 @@ hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
     for (int q = 0; q < 5; ++q) { a.q[q] = s->f[q]; a.r[q] = s->r[q]; }
     a.clock = s->clock;
     a.coef = s->cn_coef;
-    k_cn_coef<<<dim3(1, 1, (unsigned)s->nmem), 64, 0, s->stream>>>(s->d, s->tb, s->d_phys, s->clock, s->cn_coef,
-                                                                  st.alp, s->mstride);
+    if (st.k == 0 || !s->cn_fresh) {
+        CnStages cs;
+        for (int q = 0; q < 3; ++q) cs.alp[q] = kRkAlp[q];
+        k_cn_coef<<<dim3(1, 3, (unsigned)s->nmem), 256, 0, s->stream>>>(s->d, s->tb, s->d_phys, s->clock,
+                                                                       s->cn_coef, cs, s->mstride);
+        s->cn_fresh = true;
+    }
     const dim3 g((unsigned)((s->d.plane + kCnTx - 1) / kCnTx), 5, (unsigned)s->nmem);
     const size_t lds = (size_t)s->d.M * (kCnTx + 1) * sizeof(double);
     const int tb = s->tiles.cn;

@@ -12,6 +12,8 @@
 // line is one contiguous run of nz values.
 // The FFTs are self-sorting (Stockham) in LDS with radix 4, 2 and 3 stages;
 // two real x-lines share one complex transform.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace nspnp {
@@ -534,8 +536,13 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
     }
     {
         ProfScope prof_(s, K_FFTX_INV);
-        if (s->fp64) k_fft_x_c2r<double><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppb);
-        else k_fft_x_c2r<float><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppb);
+        // at least 8 lines per block, so that every kx of the transposed load
+        // reads whole 128-byte lines of the [j][kx][kz] spectrum
+        const int ppbc = std::max(ppb, pairs_per_block(d.nx, 4 * d.nx));
+        const dim3 gc((unsigned)((npairs + ppbc - 1) / ppbc), (unsigned)b.nprob, (unsigned)nmem);
+        const size_t ldsc = 2 * (size_t)ppbc * (d.nx + 2) * sizeof(double2);
+        if (s->fp64) k_fft_x_c2r<double><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc);
+        else k_fft_x_c2r<float><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc);
     }
     return hipGetLastError();
 }

@@ -35,7 +35,7 @@ CLASSES = {
     "cn_tridiag": (("k_cn_coef", "k_cn_scan"), "stencil.hip"),
     "fft_x_r2c": (("k_fft_x_r2c",), "poisson.hip"),
     "fft_z_fwd": (("k_fft_z",), "poisson.hip"),
-    "thomas_modes": (("k_thomas_modes",), "poisson.hip"),
+    "thomas_modes": (("k_thomas_tile",), "poisson.hip"),
     "fft_z_inv": (("k_fft_z",), "poisson.hip"),
     "fft_x_c2r": (("k_fft_x_c2r",), "poisson.hip"),
     "correct": (("k_correct",), "stencil.hip"),

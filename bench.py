@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
                     help="default: fp64 for the single runs, the ensemble's own (mixed) for 'ensemble'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the library's default launch shapes instead of the autotuned ones")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="before timing, run one plain device-to-device copy of this many MiB (a "
                          "reference kernel of known traffic for hardware byte counters)")
@@ -120,6 +122,10 @@ def main():
         del src, dst
     solver = P.Solver(cfg, device="cuda:0")
     stream = solver.stream
+    tiles = None
+    if not args.no_autotune:  # launch shapes by the library's autotuner (advances the run)
+        tiles = solver.autotune(None, 12)
+        print(f"[bench] autotuned launch shapes {tiles}", file=sys.stderr, flush=True)
     solver.step(args.warmup)
     torch.cuda.synchronize()
     print(f"[bench] warmup {args.warmup} substeps done", file=sys.stderr, flush=True)
@@ -203,6 +209,7 @@ def main():
                              "frac": total_bytes / (ms_prof * 1e-3) / 1e9 / HBM_PEAK_GBS,
                              "bytes_per_cell": total_bytes / (cfg.cells * args.steps)},
         "kernels": kernels,
+        "launch_shapes": tiles or "library defaults",
         "profiled_region_ms": ms_prof,
         "state_check": {"tau_bottom": tb, "tau_top": tt, "max_div": diag["max_div"]},
     }

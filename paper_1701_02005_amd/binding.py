@@ -124,6 +124,9 @@ def load_library() -> ctypes.CDLL:
         "nspnp_set_clock": (_I, [_P, _D, _D, ctypes.c_int32, ctypes.c_int64]),
         "nspnp_sync": (_I, [_P]),
         "nspnp_save": (_I, [_P, ctypes.c_char_p]),
+        "nspnp_autotune": (_I, [_P, ctypes.c_char_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+        "nspnp_get_tiles": (_I, [_P, ctypes.POINTER(ctypes.c_int32)]),
+        "nspnp_set_tiles": (_I, [_P, ctypes.POINTER(ctypes.c_int32)]),
         "nspnp_load": (_I, [_P, ctypes.c_char_p]),
         "nspnp_profile_enable": (_I, [_P, ctypes.c_int32]),
         "nspnp_profile_read": (_I, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_char_p),
@@ -290,6 +293,28 @@ class Solver:
         flagged the run."""
         _check(self.lib.nspnp_sync(self._h))
 
+    def autotune(self, cache_path: str | None = None, trial_substeps: int = 6) -> Dict[str, int]:
+        """Launch shapes chosen by timing (advances the run; results unchanged)."""
+        out = (ctypes.c_int32 * len(Ensemble.TILE_NAMES))()
+        path = cache_path.encode() if cache_path else None
+        _check(self.lib.nspnp_autotune(self._h, path, int(trial_substeps), out))
+        return dict(zip(Ensemble.TILE_NAMES, list(out)))
+
+    def tiles(self) -> Dict[str, int]:
+        out = (ctypes.c_int32 * len(Ensemble.TILE_NAMES))()
+        _check(self.lib.nspnp_get_tiles(self._h, out))
+        return dict(zip(Ensemble.TILE_NAMES, list(out)))
+
+    def set_tiles(self, **changes):
+        """Change launch shapes by name (e.g. cnslab=16)."""
+        cur = self.tiles()
+        for k, v in changes.items():
+            if k not in cur:
+                raise KeyError(k)
+            cur[k] = int(v)
+        arr = (ctypes.c_int32 * len(Ensemble.TILE_NAMES))(*[cur[k] for k in Ensemble.TILE_NAMES])
+        _check(self.lib.nspnp_set_tiles(self._h, arr))
+
     def save(self, path: str):
         """Checkpoint (fields, H buffers, clock) to a file."""
         _check(self.lib.nspnp_save(self._h, str(path).encode()))
@@ -318,7 +343,7 @@ class Ensemble:
     null stream cannot be captured into a graph); every call that returns
     data synchronises that stream."""
 
-    TILE_NAMES = ("expl", "cn", "fftx", "fftz", "thomas", "corr", "slab")
+    TILE_NAMES = ("expl", "cn", "fftx", "fftz", "thomas", "corr", "slab", "cnslab", "xcdfft")
 
     def __init__(self, cfgs, device: str = "cuda:0"):
         if not torch.cuda.is_available():
@@ -415,10 +440,11 @@ class Ensemble:
 
     def autotune(self, cache_path: str | None = None, trial_substeps: int = 6):
         nc = self.classes()
-        out = (ctypes.c_int32 * (7 * nc))()
+        k = len(self.TILE_NAMES)
+        out = (ctypes.c_int32 * (k * nc))()
         path = cache_path.encode() if cache_path else None
         _check(self.lib.nspnp_ensemble_autotune(self._h, path, int(trial_substeps), out))
-        return [dict(zip(self.TILE_NAMES, list(out)[7 * c: 7 * c + 7])) for c in range(nc)]
+        return [dict(zip(self.TILE_NAMES, list(out)[k * c: k * c + k])) for c in range(nc)]
 
 
 class Mlp:

@@ -88,7 +88,7 @@ Layout make_layout(const nspnp_config *c) {
     const int64_t nspec = nxh * c->nz * M;
     L.off_spec = o; o = align256(o + 2 * nspec * 16);
     L.off_fac = o; o = align256(o + 2 * nspec * 16);  // [kind][mode][row] pivots
-    L.off_coef = o; o = align256(o + 27 * M * 8);  // 3 stages x 3 systems x (g, m, n)
+    L.off_coef = o; o = align256(o + 3 * (9 * M + 9 * kCnMaxSlabs) * 8);  // 3 stages: (g, m, n) rows, slab products
     L.off_clock = o; o = align256(o + kClockSlots * 8);
     L.off_phys = o; o = align256(o + sizeof(Phys));
     L.off_stats = o; o = align256(o + (3 * M + 2) * 8);
@@ -251,7 +251,7 @@ void setup_handle(nspnp_state *s, const nspnp_config *cfg, char *base, int nmem,
     s->mstride = nmem > 1 ? L.total : 0;
     s->planx = make_plan(cfg->nx);
     s->planz = make_plan(cfg->nz);
-    s->tiles = Tiles{256, 256, 512, 512, 8, 128, 32};  // the tuner's choice at 256 x 193 x 256
+    s->tiles = Tiles{256, 256, 512, 512, 8, 128, 32, 0, 0};  // the tuner's choice at 256 x 193 x 256
     for (int q = 0; q < 7; ++q) s->f[q] = base + L.off_f[q];
     for (int q = 0; q < 5; ++q) s->h[q] = base + L.off_h[q];
     for (int q = 0; q < 5; ++q) s->r[q] = base + L.off_r[q];
@@ -404,7 +404,7 @@ int queue_health_copy(nspnp_state *s) {
 }  // namespace nspnp
 
 nspnp_state::~nspnp_state() {
-    for (hipEvent_t e : prof.ev) hipEventDestroy(e);
+    for (hipEvent_t e : prof.ev) (void)hipEventDestroy(e);
     if (owns_host_health && host_health) (void)hipHostFree(host_health);
 }
 

@@ -9,10 +9,12 @@
 // of Runge-Kutta steps for all classes is captured once into a hipGraph and
 // replayed.  Time-mean plane profiles of u, c+ - c- and phi are accumulated
 // on the device when statistics are on.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <fstream>
+#include <initializer_list>
 #include <sstream>
 #include <string>
 
@@ -119,7 +121,7 @@ int check_members(const nspnp_ensemble *e) {
 // ---- autotuner ----------------------------------------------------------
 std::string tune_key(const nspnp_state *c) {
     std::ostringstream k;
-    k << "gfx950:" << c->cfg.nx << "x" << c->cfg.ny << "x" << c->cfg.nz << ":" << (c->fp64 ? "fp64" : "mixed")
+    k << "gfx950v3:" << c->cfg.nx << "x" << c->cfg.ny << "x" << c->cfg.nz << ":" << (c->fp64 ? "fp64" : "mixed")
       << ":" << c->nmem;
     return k.str();
 }
@@ -132,7 +134,7 @@ bool cache_lookup(const char *path, const std::string &key, Tiles &t) {
         std::istringstream ls(line);
         std::string k;
         Tiles v{};
-        if (ls >> k >> v.expl >> v.cn >> v.fftx >> v.fftz >> v.thomas >> v.corr >> v.slab && k == key) {
+        if (ls >> k >> v.expl >> v.cn >> v.fftx >> v.fftz >> v.thomas >> v.corr >> v.slab >> v.cnslab >> v.xcdfft && k == key) {
             t = v;
             return true;
         }
@@ -144,7 +146,7 @@ void cache_store(const char *path, const std::string &key, const Tiles &t) {
     if (!path || !*path) return;
     std::ofstream out(path, std::ios::app);
     out << key << " " << t.expl << " " << t.cn << " " << t.fftx << " " << t.fftz << " " << t.thomas << " " << t.corr
-        << " " << t.slab << "\n";
+        << " " << t.slab << " " << t.cnslab << " " << t.xcdfft << "\n";
 }
 
 // wall time (ms) of `trial` substeps of one class with its current tiles
@@ -160,6 +162,64 @@ int time_class(nspnp_state *c, int trial, float *ms) {
     hipEventDestroy(a);
     hipEventDestroy(b);
     return rc;
+}
+
+void tiles_to_ints(const Tiles &t, int32_t *o) {
+    o[0] = t.expl; o[1] = t.cn; o[2] = t.fftx; o[3] = t.fftz; o[4] = t.thomas; o[5] = t.corr; o[6] = t.slab;
+    o[7] = t.cnslab; o[8] = t.xcdfft;
+}
+
+// Launch shapes of one handle (a single run or a size class): from the cache
+// when its key is there, else by coordinate descent over each shape, timing
+// trial substeps per candidate (every trial advances the state; the shapes do
+// not change any result).
+int tune_handle(nspnp_state *c, const char *cache_path, int trial) {
+    const std::string key = tune_key(c);
+    Tiles best = c->tiles;
+    if (!cache_lookup(cache_path, key, best)) {
+        const int cand_expl[] = {64, 128, 256};
+        const int cand_cn[] = {64, 128, 256};
+        const int cand_fft[] = {512, 1024, 2048};
+        const int cand_th[] = {4, 8, 16, 32};
+        const int cand_corr[] = {128, 256};
+        const int cand_slab[] = {4, 8, 16, 32};
+        const int cand_cnslab[] = {0, 16, 32};
+        const int cand_xcd[] = {0, 1};
+        float base_ms = 0.f;
+        int rc;
+        if ((rc = time_class(c, trial, &base_ms))) return rc;  // warm
+        if ((rc = time_class(c, trial, &base_ms))) return rc;
+        auto sweep = [&](int *field, const int *cand, int ncand) -> int {
+            int keep = *field;
+            float keep_ms = base_ms;
+            for (int q = 0; q < ncand; ++q) {
+                if (cand[q] == keep) continue;
+                *field = cand[q];
+                float ms = 0.f, ms2 = 0.f;
+                int r = time_class(c, trial, &ms);
+                if (!r) r = time_class(c, trial, &ms2);
+                if (r) return r;
+                ms = std::min(ms, ms2);
+                if (ms < keep_ms) { keep_ms = ms; keep = cand[q]; }
+            }
+            *field = keep;
+            base_ms = keep_ms;
+            return NSPNP_OK;
+        };
+        if ((rc = sweep(&c->tiles.expl, cand_expl, 3))) return rc;
+        if ((rc = sweep(&c->tiles.cn, cand_cn, 3))) return rc;
+        if ((rc = sweep(&c->tiles.fftx, cand_fft, 3))) return rc;
+        if ((rc = sweep(&c->tiles.fftz, cand_fft, 3))) return rc;
+        if ((rc = sweep(&c->tiles.thomas, cand_th, 4))) return rc;
+        if ((rc = sweep(&c->tiles.corr, cand_corr, 2))) return rc;
+        if ((rc = sweep(&c->tiles.slab, cand_slab, 4))) return rc;
+        if ((rc = sweep(&c->tiles.cnslab, cand_cnslab, 3))) return rc;
+        if ((rc = sweep(&c->tiles.xcdfft, cand_xcd, 2))) return rc;
+        best = c->tiles;
+        cache_store(cache_path, key, best);
+    }
+    c->tiles = best;
+    return NSPNP_OK;
 }
 
 int ensemble_advance(nspnp_ensemble *e, int32_t n_substeps);
@@ -343,56 +403,8 @@ int nspnp_ensemble_autotune(nspnp_ensemble *e, const char *cache_path, int32_t t
     int rc = drop_graph(e);
     if (rc) return rc;
     for (size_t ci = 0; ci < e->classes.size(); ++ci) {
-        nspnp_state *c = e->classes[ci];
-        const std::string key = tune_key(c);
-        Tiles best = c->tiles;
-        if (!cache_lookup(cache_path, key, best)) {
-            // coordinate descent over the launch shapes; every trial advances
-            // the (tile-independent) state by trial_substeps
-            const int cand_expl[] = {64, 128, 256};
-            const int cand_cn[] = {64, 128, 256};
-            const int cand_fft[] = {512, 1024, 2048};
-            const int cand_th[] = {4, 8, 16, 32};
-            const int cand_corr[] = {128, 256};
-            const int cand_slab[] = {4, 8, 16, 32};
-            float base_ms = 0.f;
-            if ((rc = time_class(c, trial_substeps, &base_ms))) return rc;  // warm
-            if ((rc = time_class(c, trial_substeps, &base_ms))) return rc;
-            auto sweep = [&](int *field, const int *cand, int ncand) -> int {
-                int keep = *field;
-                float keep_ms = base_ms;
-                for (int q = 0; q < ncand; ++q) {
-                    if (cand[q] == keep) continue;
-                    *field = cand[q];
-                    float ms = 0.f;
-                    int r = time_class(c, trial_substeps, &ms);
-                    if (r) return r;
-                    if (ms < keep_ms) { keep_ms = ms; keep = cand[q]; }
-                }
-                *field = keep;
-                base_ms = keep_ms;
-                return NSPNP_OK;
-            };
-            if ((rc = sweep(&c->tiles.expl, cand_expl, 3))) return rc;
-            if ((rc = sweep(&c->tiles.cn, cand_cn, 3))) return rc;
-            if ((rc = sweep(&c->tiles.fftx, cand_fft, 3))) return rc;
-            if ((rc = sweep(&c->tiles.fftz, cand_fft, 3))) return rc;
-            if ((rc = sweep(&c->tiles.thomas, cand_th, 4))) return rc;
-            if ((rc = sweep(&c->tiles.corr, cand_corr, 2))) return rc;
-            if ((rc = sweep(&c->tiles.slab, cand_slab, 4))) return rc;
-            best = c->tiles;
-            cache_store(cache_path, key, best);
-        }
-        c->tiles = best;
-        if (tiles_out) {
-            tiles_out[7 * ci + 0] = best.expl;
-            tiles_out[7 * ci + 1] = best.cn;
-            tiles_out[7 * ci + 2] = best.fftx;
-            tiles_out[7 * ci + 3] = best.fftz;
-            tiles_out[7 * ci + 4] = best.thomas;
-            tiles_out[7 * ci + 5] = best.corr;
-            tiles_out[7 * ci + 6] = best.slab;
-        }
+        if ((rc = tune_handle(e->classes[ci], cache_path, trial_substeps))) return rc;
+        if (tiles_out) tiles_to_ints(e->classes[ci]->tiles, tiles_out + kTileInts * ci);
     }
     // classes may have advanced by different numbers of trial substeps
     int64_t mx = 0;
@@ -402,6 +414,39 @@ int nspnp_ensemble_autotune(nspnp_ensemble *e, const char *cache_path, int32_t t
     }
     e->substeps = mx;
     E_TRY(hipStreamSynchronize(e->stream));
+    return NSPNP_OK;
+}
+
+int nspnp_get_tiles(const nspnp_state *s, int32_t *tiles_out) {
+    if (!s || !tiles_out) return fail_code(NSPNP_ERR_INVALID, "bad get_tiles arguments");
+    tiles_to_ints(s->tiles, tiles_out);
+    return NSPNP_OK;
+}
+
+int nspnp_set_tiles(nspnp_state *s, const int32_t *t) {
+    if (!s || !t) return fail_code(NSPNP_ERR_INVALID, "bad set_tiles arguments");
+    auto one_of = [](int v, std::initializer_list<int> ok) {
+        for (int o : ok)
+            if (v == o) return true;
+        return false;
+    };
+    if (!one_of(t[0], {64, 128, 256}) || !one_of(t[1], {64, 128, 256}) || t[2] < 64 || t[2] > 8192 ||
+        t[3] < 64 || t[3] > 8192 || t[4] < 1 || t[4] > 64 || !one_of(t[5], {64, 128, 256, 512, 1024}) ||
+        t[6] < 1 || t[6] > 480 || !one_of(t[7], {0, 16, 32}) || !one_of(t[8], {0, 1}))
+        return fail_code(NSPNP_ERR_INVALID, "launch shapes out of range");
+    E_TRY(hipStreamSynchronize(s->stream));
+    s->tiles = Tiles{t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7], t[8]};
+    return NSPNP_OK;
+}
+
+int nspnp_autotune(nspnp_state *s, const char *cache_path, int32_t trial_substeps, int32_t *tiles_out) {
+    if (!s || trial_substeps <= 0 || trial_substeps % 3 != 0)
+        return fail_code(NSPNP_ERR_INVALID, "trial length must be a positive multiple of 3 substeps");
+    int rc = check_health(s, -1);
+    if (rc) return rc;
+    if ((rc = tune_handle(s, cache_path, trial_substeps))) return rc;
+    if (tiles_out) tiles_to_ints(s->tiles, tiles_out);
+    E_TRY(hipStreamSynchronize(s->stream));
     return NSPNP_OK;
 }
 

@@ -72,6 +72,16 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nblocks) {
     return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
 }
 
+// The same bijection over a whole (x, y, z) grid: the block's linear id (x
+// fastest, the dispatch order) is remapped and split back into coordinates,
+// so consecutive x tiles of one (y, z) slice share an XCD whatever gridDim.x.
+__device__ __forceinline__ uint3 xcd_block3() {
+    const unsigned gx = gridDim.x, gy = gridDim.y;
+    const unsigned lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned t = xcd_tile(lin, gx * gy * gridDim.z);
+    return make_uint3(t % gx, (t / gx) % gy, t / (gx * gy));
+}
+
 // Every member of a batch has the same workspace layout; device pointers in
 // kernel arguments refer to member 0 and member blockIdx.z sits stride bytes
 // further per member.
@@ -138,6 +148,9 @@ struct PoissonBatch {
     const Phys *phys;   // member 0's constants (charge factor)
 };
 
+// Row-slab Crank-Nicolson method: the most slabs per column.
+constexpr int kCnMaxSlabs = 32;
+
 // Launch shapes chosen by the autotuner.  None of them changes the
 // arithmetic done per cell, column, line or mode, so results are bitwise
 // independent of the choice.
@@ -149,7 +162,11 @@ struct Tiles {
     int thomas;   // modes per tile of the y solve of the elliptic problems (capped by LDS)
     int corr;     // threads per block of the projection correction
     int slab;     // rows marched by one block of the explicit kernel
+    int cnslab;   // Crank-Nicolson: 0 lane-scan method, 16 or 32 row-slab method with that many rows
+    int xcdfft;   // 1: XCD-aware block order in the x transforms
 };
+
+constexpr int kTileInts = 9;  // Tiles as exported through the ABI
 
 // Kernel classes timed by the optional event profiler.
 enum KernelId {
@@ -199,6 +216,7 @@ struct nspnp_state {
     double2 *fac;        // Thomas pivots (1/den, c') of both elliptic operators, [kind][mode][row]
     double *cn_coef;     // Crank-Nicolson recurrence coefficients, 9 M per stage
     bool cn_fresh = false;  // cn_coef matches the device dt of the current step
+    int cn_coef_slab = -1;  // slab rows the slab products in cn_coef were made for
     double *clock;       // device [t, dt, health, max |dPhi|]
     double *host_health = nullptr;  // pinned host mirror of each member's [health, max |dPhi|]
     bool owns_host_health = false;

@@ -140,20 +140,25 @@ __device__ __forceinline__ double line_value(const PoissonSrc &src, const Dims &
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl, PoissonBatch b,
-                                                   const double *clock, double2 *spec, int64_t nspec, int ppb) {
+                                                   const double *clock, double2 *spec, int64_t nspec, int ppb,
+                                                   int xcd) {
     extern __shared__ double2 sm[];
-    const int prob = blockIdx.y;
+    // xcd != 0: neighbouring line blocks (which write the two halves of the
+    // same 128-byte spectrum lines when a block holds fewer than 8 lines)
+    // run on one XCD, so its L2 merges the halves
+    const uint3 blk = xcd ? xcd_block3() : make_uint3(blockIdx.x, blockIdx.y, blockIdx.z);
+    const int prob = (int)blk.y;
     PoissonSrc src = b.src[prob];
-    src.a = member_ptr(src.a, b.ms);
-    src.b = member_ptr(src.b, b.ms);
-    src.c = member_ptr(src.c, b.ms);
-    clock = member_ptr(clock, b.ms);
-    const double ch = member_ptr(b.phys, b.ms)->ch;
-    double2 *out = member_ptr(spec, b.ms) + prob * nspec;
+    src.a = member_ptr_at(src.a, b.ms, blk.z);
+    src.b = member_ptr_at(src.b, b.ms, blk.z);
+    src.c = member_ptr_at(src.c, b.ms, blk.z);
+    clock = member_ptr_at(clock, b.ms, blk.z);
+    const double ch = member_ptr_at(b.phys, b.ms, blk.z)->ch;
+    double2 *out = member_ptr_at(spec, b.ms, blk.z) + prob * nspec;
     const int nx = d.nx, nxh = d.nxh;
     const int64_t nlines = (int64_t)d.M * d.nz;
     double2 *bf[2] = {sm, sm + ppb * (nx + 2)};
-    const int64_t pair0 = (int64_t)blockIdx.x * ppb;
+    const int64_t pair0 = (int64_t)blk.x * ppb;
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
         const int p = e / nx, i = e - p * nx;
         const int64_t la = 2 * (pair0 + p), lb = la + 1;
@@ -188,14 +193,15 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl, PoissonBatch b,
-                                                   const double2 *spec, int64_t nspec, int ppb) {
+                                                   const double2 *spec, int64_t nspec, int ppb, int xcd) {
     extern __shared__ double2 sm[];
-    const int prob = blockIdx.y;
-    const double2 *in = member_ptr(spec, b.ms) + prob * nspec;
+    const uint3 blk = xcd ? xcd_block3() : make_uint3(blockIdx.x, blockIdx.y, blockIdx.z);
+    const int prob = (int)blk.y;
+    const double2 *in = member_ptr_at(spec, b.ms, blk.z) + prob * nspec;
     const int nx = d.nx, nxh = d.nxh;
     const int64_t nlines = (int64_t)d.M * d.nz;
     double2 *bf[2] = {sm, sm + ppb * (nx + 2)};
-    const int64_t pair0 = (int64_t)blockIdx.x * ppb;
+    const int64_t pair0 = (int64_t)blk.x * ppb;
     const int nl2 = 2 * ppb;
     double2 *o = bf[1];  // [kk][line] staging of the transposed load
     for (int e = threadIdx.x; e < nl2 * nxh; e += blockDim.x) {
@@ -224,8 +230,8 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
     __syncthreads();
     const double2 *z = bf[lds_fft(bf[0], bf[1], nx, ppb, pl, tb.twx, true)];
     const bool as_state = b.out_state[prob] != 0;
-    double *o64 = (double *)member_ptr(b.out[prob], b.ms);
-    T *ot = (T *)member_ptr(b.out[prob], b.ms);
+    double *o64 = (double *)member_ptr_at(b.out[prob], b.ms, blk.z);
+    T *ot = (T *)member_ptr_at(b.out[prob], b.ms, blk.z);
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
         const int p = e / nx, i = e - p * nx;
         const int64_t la = 2 * (pair0 + p), lb = la + 1;
@@ -314,13 +320,14 @@ template <int R>
 __global__ void __launch_bounds__(256) k_thomas_tile(Dims d, Tables tb, PoissonBatch b, double2 *spec_all,
                                                      const double2 *fac_all, int64_t nspec, int tm) {
     extern __shared__ double2 s_x[];
-    const int prob = blockIdx.y;
+    const uint3 blk = xcd_block3();
+    const int prob = (int)blk.y;
     const int kind = b.kind[prob];
     const int64_t nmodes = (int64_t)d.nxh * d.nz;
     const int M = d.M;
-    double2 *spec = member_ptr(spec_all, b.ms) + prob * nspec;
-    const double2 *fac = member_ptr(fac_all, b.ms) + (int64_t)kind * nmodes * M;
-    const int64_t m0 = (int64_t)blockIdx.x * tm;
+    double2 *spec = member_ptr_at(spec_all, b.ms, blk.z) + prob * nspec;
+    const double2 *fac = member_ptr_at(fac_all, b.ms, blk.z) + (int64_t)kind * nmodes * M;
+    const int64_t m0 = (int64_t)blk.x * tm;
     const int ncol = (int)((nmodes - m0) < tm ? (nmodes - m0) : tm);
     const int LD = tm + 1;
     for (int e = threadIdx.x; e < M * tm; e += blockDim.x) {
@@ -495,8 +502,11 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
     const size_t ldsx = 2 * (size_t)ppb * (d.nx + 2) * sizeof(double2);
     {
         ProfScope prof_(s, K_FFTX_FWD);
-        if (s->fp64) k_fft_x_r2c<double><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb);
-        else k_fft_x_r2c<float><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb);
+        const int xcd = s->tiles.xcdfft;
+        if (s->fp64)
+            k_fft_x_r2c<double><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb, xcd);
+        else
+            k_fft_x_r2c<float><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb, xcd);
     }
     const int tk = modes_per_tile(d.nz, d.nxh, s->tiles.fftz);
     const dim3 gz((unsigned)(d.M * ((d.nxh + tk - 1) / tk)), (unsigned)b.nprob, (unsigned)nmem);
@@ -541,8 +551,9 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
         const int ppbc = std::max(ppb, pairs_per_block(d.nx, 4 * d.nx));
         const dim3 gc((unsigned)((npairs + ppbc - 1) / ppbc), (unsigned)b.nprob, (unsigned)nmem);
         const size_t ldsc = 2 * (size_t)ppbc * (d.nx + 2) * sizeof(double2);
-        if (s->fp64) k_fft_x_c2r<double><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc);
-        else k_fft_x_c2r<float><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc);
+        const int xcd = s->tiles.xcdfft;
+        if (s->fp64) k_fft_x_c2r<double><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc, xcd);
+        else k_fft_x_c2r<float><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc, xcd);
     }
     return hipGetLastError();
 }

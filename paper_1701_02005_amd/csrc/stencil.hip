@@ -351,7 +351,10 @@ struct CnArgs {
     void *q[5];
     const void *r[5];  // right-hand sides, state type
     const double *clock;
-    double *coef;  // [3 systems][g, m, n][M] recurrence coefficients of this substep
+    double *coef;  // per stage: [3 systems][g, m, n][M], then [3 systems][P, Phi, Nu][kCnMaxSlabs]
+    double *scr;   // row-slab method: per member [2][5 fields][slabs][plane] FP64 scratch
+    int slab_rows; // row-slab method: rows per slab (0: lane-scan method)
+    int slabs;
 };
 
 // Row coefficients of the Crank-Nicolson matrix (I - beta L_y) of system
@@ -395,15 +398,25 @@ struct CnStages {
     double alp[3];
 };
 
+// Row-slab form of the same recurrences (used when the rows are split into
+// slabs of L rows, one thread per column and slab): for slab [a, b) the
+// column-independent quantities are P = prod m_j, Nu = prod n_j and Phi = the
+// local backward sweep (zero input at b) of p_j = prod_{i=a..j} m_i, taken at
+// row a.  A column's exact solution on the slab is then
+//   x_j = kappa_j + phi_j D + nu_j X
+// with D = d'_{a-1}, X = x_b and kappa the local backward sweep of the local
+// forward sweep of r; D and X follow from scans across the slabs.
+__host__ __device__ inline size_t cn_stage_stride(int M) { return 9 * (size_t)M + 9 * (size_t)kCnMaxSlabs; }
+
 __global__ void __launch_bounds__(256) k_cn_coef(Dims d, Tables tb, const Phys *phys, const double *clock,
-                                                 double *coef, CnStages stages, size_t ms) {
+                                                 double *coef, CnStages stages, int slab_rows, size_t ms) {
     __shared__ double s_tab[4][kMaxRows];      // lyc_lo, lyc_up, lyn_lo, lyn_up
     __shared__ double s_out[9][kMaxRows];      // [sys][g, m, n][row]
     phys = member_ptr(phys, ms);
     clock = member_ptr(clock, ms);
     const int M = d.M;
     const int stage = blockIdx.y;
-    coef = member_ptr(coef, ms) + (size_t)stage * 9 * M;
+    coef = member_ptr(coef, ms) + (size_t)stage * cn_stage_stride(M);
     for (int j = threadIdx.x; j < M; j += blockDim.x) {
         s_tab[0][j] = tb.lyc_lo[j];
         s_tab[1][j] = tb.lyc_up[j];
@@ -436,6 +449,27 @@ __global__ void __launch_bounds__(256) k_cn_coef(Dims d, Tables tb, const Phys *
         const int sk = e / M, j = e - sk * M;
         coef[e] = s_out[sk][j];
     }
+    if (slab_rows > 0) {
+        const int nslab = (M + slab_rows - 1) / slab_rows;
+        double *sl = coef + 9 * (size_t)M;
+        for (int t = threadIdx.x; t < 3 * nslab; t += blockDim.x) {
+            const int sy = t / nslab, sb = t - sy * nslab;
+            const double *m = s_out[3 * sy + 1], *n = s_out[3 * sy + 2];
+            const int a = sb * slab_rows, b = (a + slab_rows < M) ? a + slab_rows : M;
+            double P = 1.0, Nu = 1.0;
+            for (int j = a; j < b; ++j) { P *= m[j]; Nu *= n[j]; }
+            // phi_j = p_j + n_j phi_{j+1}, phi_b = 0, with p_j = prod_{i=a..j} m_i
+            double phi = 0.0;
+            for (int j = b - 1; j >= a; --j) {
+                double pj = 1.0;
+                for (int i = a; i <= j; ++i) pj *= m[i];
+                phi = pj + n[j] * phi;
+            }
+            sl[(3 * sy + 0) * kCnMaxSlabs + sb] = P;
+            sl[(3 * sy + 1) * kCnMaxSlabs + sb] = phi;
+            sl[(3 * sy + 2) * kCnMaxSlabs + sb] = Nu;
+        }
+    }
 }
 
 constexpr int kCnTx = 16;  // columns staged per block
@@ -449,17 +483,19 @@ constexpr int kCnTx = 16;  // columns staged per block
 template <typename T, int kCnMaxR>
 __global__ void __launch_bounds__(256) k_cn_scan(CnArgs a) {
     extern __shared__ double s_r[];
-    const int f = blockIdx.y;
+    const uint3 blk = xcd_block3();  // adjacent column tiles share an L2
+    const int f = (int)blk.y;
     const size_t ms = a.ms;
     const int sys = (f == 1) ? 1 : (f >= 3 ? 2 : 0);
     const int j0 = (sys == 1) ? 1 : 0;
     const int M = a.d.M;
     const int64_t pl = a.d.plane;
-    const int64_t c0 = (int64_t)blockIdx.x * kCnTx;
+    const int64_t c0 = (int64_t)blk.x * kCnTx;
     const int ncol = (int)((pl - c0) < kCnTx ? (pl - c0) : kCnTx);
-    const T *__restrict__ r = (const T *)member_ptr(a.r[f], ms);
-    T *__restrict__ q = (T *)member_ptr(a.q[f], ms);
-    const double *__restrict__ coef = member_ptr(a.coef, ms) + (size_t)a.st.k * 9 * M + (size_t)sys * 3 * M;
+    const T *__restrict__ r = (const T *)member_ptr_at(a.r[f], ms, blk.z);
+    T *__restrict__ q = (T *)member_ptr_at(a.q[f], ms, blk.z);
+    const double *__restrict__ coef =
+        member_ptr_at(a.coef, ms, blk.z) + (size_t)a.st.k * cn_stage_stride(M) + (size_t)sys * 3 * M;
     const double *__restrict__ cg = coef, *__restrict__ cm = coef + M, *__restrict__ cn = coef + 2 * M;
     constexpr int LD = kCnTx + 1;
     const int nrow = M - j0;
@@ -548,6 +584,116 @@ __global__ void __launch_bounds__(256) k_cn_scan(CnArgs a) {
         if (c < ncol) {
             const int64_t o = (int64_t)jj * pl + c0 + c;
             q[o] = (T)((double)q[o] + s_r[jj * LD + c]);
+        }
+    }
+}
+
+// ---- Crank-Nicolson, row-slab method (large grids) ----
+// One thread per (column, slab): every pass streams whole rows of a tile of
+// 256 columns, so each DRAM page opened serves a long contiguous run.
+__device__ __forceinline__ void cn_slab_site(const CnArgs &a, unsigned z, int &f, unsigned &mem, int &sys) {
+    f = (int)(z % 5u);
+    mem = z / 5u;
+    sys = (f == 1) ? 1 : (f >= 3 ? 2 : 0);
+}
+
+// pass 1: exits of the local sweeps of each slab (zero inputs)
+template <typename T, int L>
+__global__ void __launch_bounds__(256) k_cn_slab_exit(CnArgs a) {
+    int f, sys;
+    unsigned mem;
+    cn_slab_site(a, blockIdx.z, f, mem, sys);
+    const int64_t pl = a.d.plane;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= pl) return;
+    const int M = a.d.M, S = a.slabs, sb = blockIdx.y;
+    const int j0 = sb * L, j1 = (j0 + L < M) ? j0 + L : M;
+    const T *__restrict__ r = (const T *)member_ptr_at(a.r[f], a.ms, mem);
+    const double *__restrict__ coef = member_ptr_at(a.coef, a.ms, mem) + (size_t)a.st.k * cn_stage_stride(M) +
+                                      (size_t)sys * 3 * M;
+    const double *g = coef, *m = coef + M, *n = coef + 2 * M;
+    double *scr = member_ptr_at(a.scr, a.ms, mem);
+    double lv[L];
+    double l = 0.0;
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        const int j = j0 + t;
+        if (j < j1) l = g[j] * (double)r[(int64_t)j * pl + e] + m[j] * l;
+        lv[t] = l;
+    }
+    double k = 0.0;
+#pragma unroll
+    for (int t = L - 1; t >= 0; --t) {
+        const int j = j0 + t;
+        if (j < j1) k = lv[t] + n[j] * k;
+    }
+    scr[((int64_t)(f * S + sb)) * pl + e] = l;                  // local forward exit at row j1 - 1
+    scr[((int64_t)((5 + f) * S + sb)) * pl + e] = k;            // local backward exit at row j0
+}
+
+// pass 2: scans across the slabs of each column; the slab inputs D (forward)
+// and X (backward) replace the exits in place
+__global__ void __launch_bounds__(256) k_cn_slab_scan(CnArgs a) {
+    int f, sys;
+    unsigned mem;
+    cn_slab_site(a, blockIdx.z, f, mem, sys);
+    const int64_t pl = a.d.plane;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= pl) return;
+    const int M = a.d.M, S = a.slabs;
+    const double *sl = member_ptr_at(a.coef, a.ms, mem) + (size_t)a.st.k * cn_stage_stride(M) + 9 * (size_t)M;
+    const double *P = sl + (3 * sys + 0) * kCnMaxSlabs, *Phi = sl + (3 * sys + 1) * kCnMaxSlabs,
+                 *Nu = sl + (3 * sys + 2) * kCnMaxSlabs;
+    double *scr = member_ptr_at(a.scr, a.ms, mem);
+    double *lam = scr + (int64_t)f * S * pl + e, *kap = scr + (int64_t)(5 + f) * S * pl + e;
+    double D = 0.0;
+    for (int sb = 0; sb < S; ++sb) {
+        const double ex = lam[(int64_t)sb * pl];
+        lam[(int64_t)sb * pl] = D;
+        D = ex + P[sb] * D;
+    }
+    double X = 0.0;
+    for (int sb = S - 1; sb >= 0; --sb) {
+        const double ex = kap[(int64_t)sb * pl];
+        const double Din = lam[(int64_t)sb * pl];
+        kap[(int64_t)sb * pl] = X;
+        X = ex + Phi[sb] * Din + Nu[sb] * X;
+    }
+}
+
+// pass 3: both sweeps of each slab from its exact inputs, then q += x
+template <typename T, int L>
+__global__ void __launch_bounds__(256) k_cn_slab_apply(CnArgs a) {
+    int f, sys;
+    unsigned mem;
+    cn_slab_site(a, blockIdx.z, f, mem, sys);
+    const int64_t pl = a.d.plane;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= pl) return;
+    const int M = a.d.M, S = a.slabs, sb = blockIdx.y;
+    const int j0 = sb * L, j1 = (j0 + L < M) ? j0 + L : M;
+    const T *__restrict__ r = (const T *)member_ptr_at(a.r[f], a.ms, mem);
+    T *__restrict__ q = (T *)member_ptr_at(a.q[f], a.ms, mem);
+    const double *__restrict__ coef = member_ptr_at(a.coef, a.ms, mem) + (size_t)a.st.k * cn_stage_stride(M) +
+                                      (size_t)sys * 3 * M;
+    const double *g = coef, *m = coef + M, *n = coef + 2 * M;
+    const double *scr = member_ptr_at(a.scr, a.ms, mem);
+    double d = scr[((int64_t)(f * S + sb)) * pl + e];
+    double x = scr[((int64_t)((5 + f) * S + sb)) * pl + e];
+    double dv[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        const int j = j0 + t;
+        if (j < j1) d = g[j] * (double)r[(int64_t)j * pl + e] + m[j] * d;
+        dv[t] = d;
+    }
+#pragma unroll
+    for (int t = L - 1; t >= 0; --t) {
+        const int j = j0 + t;
+        if (j < j1) {
+            x = dv[t] + n[j] * x;
+            const int64_t o = (int64_t)j * pl + e;
+            q[o] = (T)((double)q[o] + x);
         }
     }
 }
@@ -671,6 +817,19 @@ hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]) {
     return explicit_launch(s, a, 256, (unsigned)((int64_t)a.chunks * a.slabs));
 }
 
+// Rows per slab of the row-slab CN method when it applies to this handle
+// (0: lane-scan method).  Its scratch (two values per field, slab and column)
+// lives in the spectrum buffers, unused between the explicit stage and the
+// elliptic solves.
+int cn_slab_rows(const nspnp_state *s) {
+    const int L = s->tiles.cnslab;
+    if (L != 16 && L != 32) return 0;
+    const int S = (s->d.M + L - 1) / L;
+    const int64_t need = 2 * 5 * (int64_t)S * s->d.plane;             // doubles
+    const int64_t have = 4 * (int64_t)s->d.nxh * s->d.nz * s->d.M;      // two half spectra
+    return (S <= kCnMaxSlabs && need <= have) ? L : 0;
+}
+
 hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
     ProfScope prof_(s, K_CN);
     CnArgs a{};
@@ -682,12 +841,34 @@ hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
     for (int q = 0; q < 5; ++q) { a.q[q] = s->f[q]; a.r[q] = s->r[q]; }
     a.clock = s->clock;
     a.coef = s->cn_coef;
-    if (st.k == 0 || !s->cn_fresh) {
+    a.scr = (double *)s->spec;
+    a.slab_rows = cn_slab_rows(s);
+    a.slabs = a.slab_rows ? (s->d.M + a.slab_rows - 1) / a.slab_rows : 0;
+    if (st.k == 0 || !s->cn_fresh || s->cn_coef_slab != a.slab_rows) {
         CnStages cs;
         for (int q = 0; q < 3; ++q) cs.alp[q] = kRkAlp[q];
         k_cn_coef<<<dim3(1, 3, (unsigned)s->nmem), 256, 0, s->stream>>>(s->d, s->tb, s->d_phys, s->clock,
-                                                                       s->cn_coef, cs, s->mstride);
+                                                                       s->cn_coef, cs, a.slab_rows, s->mstride);
         s->cn_fresh = true;
+        s->cn_coef_slab = a.slab_rows;
+    }
+    if (a.slab_rows) {
+        const dim3 g((unsigned)((s->d.plane + 255) / 256), (unsigned)a.slabs, 5u * (unsigned)s->nmem);
+        const dim3 g1((unsigned)((s->d.plane + 255) / 256), 1, 5u * (unsigned)s->nmem);
+        if (a.slab_rows == 16) {
+            if (s->fp64) k_cn_slab_exit<double, 16><<<g, 256, 0, s->stream>>>(a);
+            else k_cn_slab_exit<float, 16><<<g, 256, 0, s->stream>>>(a);
+            k_cn_slab_scan<<<g1, 256, 0, s->stream>>>(a);
+            if (s->fp64) k_cn_slab_apply<double, 16><<<g, 256, 0, s->stream>>>(a);
+            else k_cn_slab_apply<float, 16><<<g, 256, 0, s->stream>>>(a);
+        } else {
+            if (s->fp64) k_cn_slab_exit<double, 32><<<g, 256, 0, s->stream>>>(a);
+            else k_cn_slab_exit<float, 32><<<g, 256, 0, s->stream>>>(a);
+            k_cn_slab_scan<<<g1, 256, 0, s->stream>>>(a);
+            if (s->fp64) k_cn_slab_apply<double, 32><<<g, 256, 0, s->stream>>>(a);
+            else k_cn_slab_apply<float, 32><<<g, 256, 0, s->stream>>>(a);
+        }
+        return hipGetLastError();
     }
     const dim3 g((unsigned)((s->d.plane + kCnTx - 1) / kCnTx), 5, (unsigned)s->nmem);
     const size_t lds = (size_t)s->d.M * (kCnTx + 1) * sizeof(double);

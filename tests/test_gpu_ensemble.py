@@ -94,10 +94,13 @@ def test_autotuned_shapes_do_not_change_results(P, tmp_path):
     ed.step(ns)
     et.step(6)
     ed.step(6)
+    # the shapes change no arithmetic except the rounding order of the CN
+    # method, which the trials may switch (FP32 state: a few ulps)
     for m in range(len(cfgs)):
         ft, fd = fields_member(et, m), fields_member(ed, m)
         for k in FIELDS:
-            assert np.array_equal(ft[k], fd[k]), (m, k)
+            scale = max(np.max(np.abs(fd[k])), 1e-30)
+            assert np.max(np.abs(ft[k] - fd[k])) <= 1e-5 * scale, (m, k)
     # second tuning reads the cache and gives the same shapes
     assert et.autotune(str(tmp_path / "tiles.txt"), trial_substeps=3) == tiles
 
@@ -115,3 +118,20 @@ def test_time_mean_profiles_of_a_steady_couette_member(P):
     assert wt == pytest.approx(3 * 2e-3, rel=1e-12)
     assert np.max(np.abs(np.array(u) - yc)) < 1e-13
     assert np.max(np.abs(rho)) < 1e-14 and np.max(np.abs(phi)) < 1e-14
+
+
+def test_single_run_autotune_does_not_change_results(P):
+    cfg = dataclasses.replace(P.configs.couette_small(), nx=48, ny=27, nz=36, dt=0.0, cfl=0.5, seed=5)
+    note("case: single-run autotune 48x27x36")
+    a = P.Solver(cfg)
+    tiles = a.autotune(None, 3)
+    note(f"  tiles {tiles}")
+    n = a.clock()[3]
+    b = P.Solver(cfg)
+    b.step(n)
+    a.step(6)
+    b.step(6)
+    # identical arithmetic per cell except the CN rounding order (FP64)
+    for k in ("u", "v", "w", "cp", "cm", "phi", "p"):
+        fa, fb = a.get_field(k).cpu().numpy(), b.get_field(k).cpu().numpy()
+        assert np.max(np.abs(fa - fb)) <= 1e-12 * max(np.max(np.abs(fb)), 1e-30), k

@@ -169,3 +169,30 @@ def test_checkpoint_rejects_other_configuration(P, tmp_path):
     junk.write_bytes(b"not a checkpoint")
     with pytest.raises(P.NsPnpError):
         a.load(junk)
+
+
+def test_set_tiles_validates(P):
+    g = P.Solver(small(P))
+    t = g.tiles()
+    assert t["cnslab"] in (0, 16, 32)
+    with pytest.raises(P.NsPnpError):
+        g.set_tiles(cnslab=8)
+    with pytest.raises(P.NsPnpError):
+        g.set_tiles(expl=100)
+    g.set_tiles(cnslab=16, thomas=4)
+    assert g.tiles()["cnslab"] == 16 and g.tiles()["thomas"] == 4
+
+
+def test_launch_order_shapes_are_bitwise_neutral(P):
+    """Block order and tile shapes that do not change the per-cell, per-line or
+    per-mode arithmetic give bitwise identical runs."""
+    import torch
+    cfg = small(P, nx=48, ny=27, nz=36, dt=0.0, cfl=0.5, seed=8)
+    note("case: launch shapes vs defaults, 48x27x36")
+    a = P.Solver(cfg)
+    b = P.Solver(cfg)
+    b.set_tiles(xcdfft=1, fftx=2048, fftz=1024, thomas=3, slab=5, expl=128, corr=64, cn=64)
+    a.step(9)
+    b.step(9)
+    for k in FIELDS:
+        assert torch.equal(a.get_field(k).cpu(), b.get_field(k).cpu()), k

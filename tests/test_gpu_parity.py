@@ -94,9 +94,13 @@ def test_poisson_solve_matches_oracle(P, O, dims, kind):
     assert parity(out, ref) < 1e-12
 
 
-def test_small_case_200_substeps_match_oracle(P, O):
-    """32x33x32, Re 400, lam 0.1, vhat 5, dt 1e-3: 200 RK substeps."""
+@pytest.mark.parametrize("cnslab", [0, 16])
+def test_small_case_200_substeps_match_oracle(P, O, cnslab):
+    """32x33x32, Re 400, lam 0.1, vhat 5, dt 1e-3: 200 RK substeps, with the
+    lane-scan (0) and the row-slab (16 rows) Crank-Nicolson methods."""
     g, o = make_pair(P, O, P.configs.couette_small(seed=0))
+    g.set_tiles(cnslab=cnslab)
+    assert g.tiles()["cnslab"] == cnslab
     for chunk in range(4):
         g.step(50)
         o.run(50)
@@ -155,11 +159,15 @@ def test_mixed_precision_tracks_oracle(P, O):
     assert abs(tb - otb) < 1e-4 * otb and abs(tt - ott) < 1e-4 * ott
 
 
-def test_full_size_turbulent_case_matches_oracle(P, O):
+@pytest.mark.parametrize("cnslab", [0, 16, 32])
+def test_full_size_turbulent_case_matches_oracle(P, O, cnslab):
     """256x193x256, Re 3000, lam 0.05, vhat 10, adaptive dt (the benchmarked
-    case, same launch configuration): initial state and one full RK3 step."""
+    case): initial state and one full RK3 step, with each Crank-Nicolson
+    method the autotuner can pick (the other launch shapes do not change the
+    arithmetic done per cell, line or mode)."""
     O.set_threads(16)
     g, o = make_pair(P, O, P.configs.couette_turbulent(seed=0))
+    g.set_tiles(cnslab=cnslab)
     err0 = worst(g, o)
     note(f"full size, initial state: {max(err0.values()):.3e}")
     assert max(err0.values()) < 1e-12, err0

@@ -252,6 +252,12 @@ void setup_handle(nspnp_state *s, const nspnp_config *cfg, char *base, int nmem,
     s->planx = make_plan(cfg->nx);
     s->planz = make_plan(cfg->nz);
     s->tiles = Tiles{256, 256, 512, 512, 8, 128, 32, 0, 0};  // the tuner's choice at 256 x 193 x 256
+    {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+            s->lds_max = lds;
+    }
     for (int q = 0; q < 7; ++q) s->f[q] = base + L.off_f[q];
     for (int q = 0; q < 5; ++q) s->h[q] = base + L.off_h[q];
     for (int q = 0; q < 5; ++q) s->r[q] = base + L.off_r[q];

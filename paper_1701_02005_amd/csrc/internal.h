@@ -206,6 +206,7 @@ struct nspnp_state {
     nspnp::FftPlan planx, planz;
     nspnp::Tiles tiles;
     hipStream_t stream;
+    int lds_max = 65536;  // LDS bytes one workgroup may use on this device
     bool fp64;
     size_t wsize;        // bytes of one state-type element
     void *f[7];          // u v w c+ c- phi p, state type

@@ -63,16 +63,35 @@ __device__ __forceinline__ void dft_small<3>(double2 *v, bool inv) {
     v[2] = csub(m, r);
 }
 
+// q = e / d and r = e % d for 0 <= e, d < 2^22 from a float reciprocal
+// rd = 1/d: the product is within half a unit of the true quotient, so one
+// correction step makes the result exact (integer division has no hardware
+// instruction on the GPU).
+__device__ __forceinline__ void divmod(int e, int d, float rd, int &q, int &r) {
+    q = (int)((float)e * rd);
+    r = e - q * d;
+    if (r < 0) {
+        --q;
+        r += d;
+    } else if (r >= d) {
+        ++q;
+        r -= d;
+    }
+}
+
+// One radix-R Stockham pass over nl lines of length N in LDS; tw is the
+// table exp(-2 pi i m / N), m < N, staged in LDS.
 template <int R>
 __device__ __forceinline__ void stage_pass(const double2 *__restrict__ src, double2 *__restrict__ dst, int N,
                                            int nl, int Ns, const double2 *__restrict__ tw, bool inv, int tid,
                                            int nth) {
     const int NR = N / R;
     const int ts = N / (Ns * R);
+    const float rNR = 1.0f / (float)NR, rNs = 1.0f / (float)Ns;
     for (int e = tid; e < nl * NR; e += nth) {
-        const int line = e / NR;
-        const int jb = e - line * NR;
-        const int k = jb % Ns;
+        int line, jb, blk, k;
+        divmod(e, NR, rNR, line, jb);
+        divmod(jb, Ns, rNs, blk, k);
         const double2 *in = src + line * N;
         double2 *out = dst + line * N;
         double2 v[R];
@@ -85,13 +104,13 @@ __device__ __forceinline__ void stage_pass(const double2 *__restrict__ src, doub
             v[r] = cmul(v[r], w);
         }
         dft_small<R>(v, inv);
-        const int base = (jb / Ns) * Ns * R + k;
+        const int base = blk * Ns * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) out[base + r * Ns] = v[r];
     }
 }
 
-// nl lines of length N in buf[0]; returns the buffer (0 or 1) holding the result.
+// nl lines of length N in b0; returns the buffer (0 or 1) holding the result.
 __device__ int lds_fft(double2 *b0, double2 *b1, int N, int nl, const FftPlan &pl, const double2 *tw, bool inv) {
     double2 *src = b0, *dst = b1;
     int which = 0;
@@ -109,6 +128,11 @@ __device__ int lds_fft(double2 *b0, double2 *b1, int N, int nl, const FftPlan &p
         Ns *= R;
     }
     return which;
+}
+
+// twiddle table to LDS (before the caller's first barrier)
+__device__ __forceinline__ void stage_twiddles(double2 *s_tw, const double2 *tw, int N) {
+    for (int e = threadIdx.x; e < N; e += blockDim.x) s_tw[e] = tw[e];
 }
 
 // ---- x direction: real lines <-> half spectra, two lines per transform ----
@@ -158,6 +182,8 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
     const int nx = d.nx, nxh = d.nxh;
     const int64_t nlines = (int64_t)d.M * d.nz;
     double2 *bf[2] = {sm, sm + ppb * (nx + 2)};
+    double2 *s_tw = sm + 2 * ppb * (nx + 2);
+    stage_twiddles(s_tw, tb.twx, nx);
     const int64_t pair0 = (int64_t)blk.x * ppb;
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
         const int p = e / nx, i = e - p * nx;
@@ -167,7 +193,7 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
         bf[0][e] = make_double2(re, im);
     }
     __syncthreads();
-    const int w = lds_fft(bf[0], bf[1], nx, ppb, pl, tb.twx, false);
+    const int w = lds_fft(bf[0], bf[1], nx, ppb, pl, s_tw, false);
     const double2 *z = bf[w];
     double2 *o = bf[1 - w];  // [kk][line] staging for the transposed store
     const int nl2 = 2 * ppb;
@@ -201,6 +227,8 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
     const int nx = d.nx, nxh = d.nxh;
     const int64_t nlines = (int64_t)d.M * d.nz;
     double2 *bf[2] = {sm, sm + ppb * (nx + 2)};
+    double2 *s_tw = sm + 2 * ppb * (nx + 2);
+    stage_twiddles(s_tw, tb.twx, nx);
     const int64_t pair0 = (int64_t)blk.x * ppb;
     const int nl2 = 2 * ppb;
     double2 *o = bf[1];  // [kk][line] staging of the transposed load
@@ -228,7 +256,7 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
         bf[0][e] = make_double2(A.x - B.y, A.y + B.x);  // Z = A + i B
     }
     __syncthreads();
-    const double2 *z = bf[lds_fft(bf[0], bf[1], nx, ppb, pl, tb.twx, true)];
+    const double2 *z = bf[lds_fft(bf[0], bf[1], nx, ppb, pl, s_tw, true)];
     const bool as_state = b.out_state[prob] != 0;
     double *o64 = (double *)member_ptr_at(b.out[prob], b.ms, blk.z);
     T *ot = (T *)member_ptr_at(b.out[prob], b.ms, blk.z);
@@ -257,11 +285,13 @@ __global__ void __launch_bounds__(256) k_fft_z(Dims d, FftPlan pl, const double2
     const int kx0 = (blockIdx.x - j * tiles) * tk;
     const int nt = (nxh - kx0 < tk) ? nxh - kx0 : tk;  // lines in this tile
     double2 *bf[2] = {sm, sm + tk * nz};
+    double2 *s_tw = sm + 2 * tk * nz;
+    stage_twiddles(s_tw, tw, nz);
     // lines (j, kx) are contiguous runs of nz values: the tile is one block of memory
     double2 *base = data + ((int64_t)j * nxh + kx0) * nz;
     for (int e = threadIdx.x; e < tk * nz; e += blockDim.x) bf[0][e] = (e < nt * nz) ? base[e] : make_double2(0.0, 0.0);
     __syncthreads();
-    const double2 *z = bf[lds_fft(bf[0], bf[1], nz, tk, pl, tw, inverse != 0)];
+    const double2 *z = bf[lds_fft(bf[0], bf[1], nz, tk, pl, s_tw, inverse != 0)];
     for (int e = threadIdx.x; e < nt * nz; e += blockDim.x) base[e] = z[e];
 }
 
@@ -474,9 +504,9 @@ inline int thomas_tile_modes(int M, int want) {
 
 // line pairs per block of the x transforms: about `points` complex values,
 // within 64 KB of LDS for the two staging buffers
-inline int pairs_per_block(int nx, int points) {
+inline int pairs_per_block(int nx, int points, int lds_bytes = 65536) {
     int p = nx >= points ? 1 : points / nx;
-    const int lds_max = 65536 / (2 * (nx + 2) * (int)sizeof(double2));
+    const int lds_max = (lds_bytes - nx * (int)sizeof(double2)) / (2 * (nx + 2) * (int)sizeof(double2));
     if (p > lds_max) p = lds_max;
     return p < 1 ? 1 : p;
 }
@@ -484,7 +514,10 @@ inline int modes_per_tile(int nz, int nxh, int points) {
     int t = nz >= points ? 1 : points / nz;
     if (t > 32) t = 32;
     if (t > nxh) t = nxh;
-    return t;
+    // two staging buffers plus the twiddle table within 64 KB of LDS
+    const int lds_max = (65536 - nz * (int)sizeof(double2)) / (2 * nz * (int)sizeof(double2));
+    if (t > lds_max) t = lds_max;
+    return t < 1 ? 1 : t;
 }
 
 }  // namespace
@@ -499,7 +532,7 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
     const int ppb = pairs_per_block(d.nx, s->tiles.fftx);
     const int64_t npairs = (nlines + 1) / 2;
     const dim3 gx((unsigned)((npairs + ppb - 1) / ppb), (unsigned)b.nprob, (unsigned)nmem);
-    const size_t ldsx = 2 * (size_t)ppb * (d.nx + 2) * sizeof(double2);
+    const size_t ldsx = (2 * (size_t)ppb * (d.nx + 2) + d.nx) * sizeof(double2);
     {
         ProfScope prof_(s, K_FFTX_FWD);
         const int xcd = s->tiles.xcdfft;
@@ -510,7 +543,7 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
     }
     const int tk = modes_per_tile(d.nz, d.nxh, s->tiles.fftz);
     const dim3 gz((unsigned)(d.M * ((d.nxh + tk - 1) / tk)), (unsigned)b.nprob, (unsigned)nmem);
-    const size_t ldsz = 2 * (size_t)tk * d.nz * sizeof(double2);
+    const size_t ldsz = (2 * (size_t)tk * d.nz + d.nz) * sizeof(double2);
     {
         ProfScope prof_(s, K_FFTZ_FWD);
         k_fft_z<<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 0, b.ms);
@@ -548,9 +581,20 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
         ProfScope prof_(s, K_FFTX_INV);
         // at least 8 lines per block, so that every kx of the transposed load
         // reads whole 128-byte lines of the [j][kx][kz] spectrum
-        const int ppbc = std::max(ppb, pairs_per_block(d.nx, 4 * d.nx));
+        // (the device's whole LDS per workgroup may be used for that)
+        const int ppbc = std::max(ppb, pairs_per_block(d.nx, 4 * d.nx, s->lds_max));
         const dim3 gc((unsigned)((npairs + ppbc - 1) / ppbc), (unsigned)b.nprob, (unsigned)nmem);
-        const size_t ldsc = 2 * (size_t)ppbc * (d.nx + 2) * sizeof(double2);
+        const size_t ldsc = (2 * (size_t)ppbc * (d.nx + 2) + d.nx) * sizeof(double2);
+        if (ldsc > 65536) {
+            static bool opted[2] = {false, false};
+            const int ty = s->fp64 ? 0 : 1;
+            if (!opted[ty]) {
+                const void *fn = s->fp64 ? (const void *)k_fft_x_c2r<double> : (const void *)k_fft_x_c2r<float>;
+                const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, s->lds_max);
+                if (e != hipSuccess) return e;
+                opted[ty] = true;
+            }
+        }
         const int xcd = s->tiles.xcdfft;
         if (s->fp64) k_fft_x_c2r<double><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc, xcd);
         else k_fft_x_c2r<float><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc, xcd);

@@ -698,7 +698,11 @@ __global__ void __launch_bounds__(256) k_cn_slab_apply(CnArgs a) {
     }
 }
 
-// projection correction: u -= a G psi;  p += psi - (a / (2 Re)) L_y psi
+// projection correction: u -= a G psi;  p += psi - (a / (2 Re)) L_y psi.
+// Each thread owns one (x, z) column of a 2-D tile and marches a slab of
+// rows, carrying psi of rows j-1 and j, so psi is read about once; its x-
+// and z-neighbours in row j come from the caches (mostly the block's own
+// loads).
 struct CorrArgs {
     Dims d;
     const Phys *phys;
@@ -711,37 +715,55 @@ struct CorrArgs {
     double fixed;
     int update_p;
     int advance_clock;
-    int blocks_per_member;
+    int tx, tz, ntx, chunks, slabs, slab_rows;
 };
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_correct(CorrArgs a) {
     const Dims &d = a.d;
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
-    const unsigned per = (unsigned)a.blocks_per_member;
-    const unsigned mem = tile / per;
-    int64_t q = (int64_t)(tile - mem * per) * blockDim.x + threadIdx.x;
-    if (q >= d.n) return;
+    const unsigned chunks = (unsigned)a.chunks, slabs = (unsigned)a.slabs;
+    const unsigned chunk = tile % chunks;
+    const unsigned slab = (tile / chunks) % slabs;
+    const unsigned mem = tile / (chunks * slabs);
+    const int nx = d.nx, nz = d.nz, M = d.M;
+    const int lk = (int)threadIdx.x / a.tx;
+    const int i = (int)(chunk % (unsigned)a.ntx) * a.tx + ((int)threadIdx.x - lk * a.tx);
+    const int k = (int)(chunk / (unsigned)a.ntx) * a.tz + lk;
+    if (lk >= a.tz || i >= nx || k >= nz) return;
+    const int64_t pl = d.plane;
+    const int e = k * nx + i;
+    const int exm = e - i + ((i == 0) ? nx - 1 : i - 1);
+    const int ezm = ((k == 0) ? nz - 1 : k - 1) * nx + i;
     const size_t ms = a.ms;
     double *clock = member_ptr_at(a.clock, ms, mem);
     const Phys *ph = member_ptr_at(a.phys, ms, mem);
+    const int j0 = (int)slab * a.slab_rows;
+    const int j1 = (j0 + a.slab_rows < M) ? j0 + a.slab_rows : M;
     // substep time t += alp dt (dt is read, never written, by this kernel)
-    if (a.advance_clock && q == 0) clock[0] += a.alp * clock[1];
+    if (a.advance_clock && e == 0 && j0 == 0) clock[0] += a.alp * clock[1];
     T *u = (T *)member_ptr_at(a.u, ms, mem), *v = (T *)member_ptr_at(a.v, ms, mem);
     T *w = (T *)member_ptr_at(a.w, ms, mem), *p = (T *)member_ptr_at(a.p, ms, mem);
     const double *psi = member_ptr_at(a.psi, ms, mem);
-    const Idx x = make_idx(d, q);
-    const int j = x.j;
     const double sc = (a.alp > 0.0) ? a.alp * clock[1] : a.fixed;
-    const double s0 = psi[q];
-    u[q] = (T)((double)u[q] - sc * (s0 - psi[x.xm]) / d.dx);
-    w[q] = (T)((double)w[q] - sc * (s0 - psi[x.zm]) / d.dz);
-    if (j > 0) v[q] = (T)((double)v[q] - sc * (s0 - psi[q - d.plane]) / a.tb.dc[j]);
-    if (a.update_p) {
-        const double ft = (j + 1 < d.M) ? (psi[q + d.plane] - s0) / a.tb.dc[j + 1] : 0.0;
-        const double fb = (j > 0) ? (s0 - psi[q - d.plane]) / a.tb.dc[j] : 0.0;
-        const double ly = (ft - fb) / a.tb.dn[j];
-        p[q] = (T)((double)p[q] + s0 - 0.5 * sc * ph->ire * ly);
+    const double ire = ph->ire;
+    double s_dn = (j0 > 0) ? psi[(int64_t)(j0 - 1) * pl + e] : 0.0;  // psi of row j - 1
+    double s0 = psi[(int64_t)j0 * pl + e];
+    for (int j = j0; j < j1; ++j) {
+        const int64_t row = (int64_t)j * pl, q = row + e;
+        const double s_up = (j + 1 < M) ? psi[q + pl] : 0.0;
+        const double sxm = psi[row + exm], szm = psi[row + ezm];
+        u[q] = (T)((double)u[q] - sc * (s0 - sxm) / d.dx);
+        w[q] = (T)((double)w[q] - sc * (s0 - szm) / d.dz);
+        if (j > 0) v[q] = (T)((double)v[q] - sc * (s0 - s_dn) / a.tb.dc[j]);
+        if (a.update_p) {
+            const double ft = (j + 1 < M) ? (s_up - s0) / a.tb.dc[j + 1] : 0.0;
+            const double fb = (j > 0) ? (s0 - s_dn) / a.tb.dc[j] : 0.0;
+            const double ly = (ft - fb) / a.tb.dn[j];
+            p[q] = (T)((double)p[q] + s0 - 0.5 * sc * ire * ly);
+        }
+        s_dn = s0;
+        s0 = s_up;
     }
 }
 
@@ -909,9 +931,15 @@ hipError_t launch_correct(nspnp_state *s, const Stage &st, bool update_p, double
     a.fixed = fixed;
     a.update_p = update_p ? 1 : 0;
     a.advance_clock = advance_clock ? 1 : 0;
-    const int tb = s->tiles.corr;
-    a.blocks_per_member = (int)((s->d.n + tb - 1) / tb);
-    const dim3 g((unsigned)((int64_t)a.blocks_per_member * s->nmem));
+    const int tb = s->tiles.corr < 256 ? s->tiles.corr : 256;
+    a.tx = s->d.nx < 64 ? s->d.nx : 64;
+    if (a.tx > tb) a.tx = tb;
+    a.tz = tb / a.tx;
+    a.ntx = (s->d.nx + a.tx - 1) / a.tx;
+    a.chunks = a.ntx * ((s->d.nz + a.tz - 1) / a.tz);
+    a.slab_rows = s->tiles.slab;
+    a.slabs = (s->d.M + a.slab_rows - 1) / a.slab_rows;
+    const dim3 g((unsigned)((int64_t)a.chunks * a.slabs * s->nmem));
     if (s->fp64) k_correct<double><<<g, tb, 0, s->stream>>>(a);
     else k_correct<float><<<g, tb, 0, s->stream>>>(a);
     return hipGetLastError();

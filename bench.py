@@ -124,7 +124,7 @@ def main():
     stream = solver.stream
     tiles = None
     if not args.no_autotune:  # launch shapes by the library's autotuner (advances the run)
-        tiles = solver.autotune(None, 12)
+        tiles = solver.autotune(None, 30)
         print(f"[bench] autotuned launch shapes {tiles}", file=sys.stderr, flush=True)
     solver.step(args.warmup)
     torch.cuda.synchronize()

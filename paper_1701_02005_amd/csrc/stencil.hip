@@ -472,7 +472,10 @@ __global__ void __launch_bounds__(256) k_cn_coef(Dims d, Tables tb, const Phys *
     }
 }
 
-constexpr int kCnTx = 16;  // columns staged per block
+// columns staged per block (16: one 128-byte line per row in FP64, two FP32
+// tiles share a line; wider FP32 tiles halve the blocks per CU and lose)
+template <typename T>
+constexpr int cn_tile_cols() { return 16; }
 
 // Crank-Nicolson solve of one tile of kCnTx columns: the rows of r are staged
 // in LDS with coalesced loads; each wave then solves one column at a time
@@ -482,6 +485,7 @@ constexpr int kCnTx = 16;  // columns staged per block
 // correct incoming value.  Finally q += x with coalesced stores.
 template <typename T, int kCnMaxR>
 __global__ void __launch_bounds__(256) k_cn_scan(CnArgs a) {
+    constexpr int kCnTx = cn_tile_cols<T>();
     extern __shared__ double s_r[];
     const uint3 blk = xcd_block3();  // adjacent column tiles share an L2
     const int f = (int)blk.y;
@@ -892,15 +896,32 @@ hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
         }
         return hipGetLastError();
     }
-    const dim3 g((unsigned)((s->d.plane + kCnTx - 1) / kCnTx), 5, (unsigned)s->nmem);
-    const size_t lds = (size_t)s->d.M * (kCnTx + 1) * sizeof(double);
+    const int tcols = s->fp64 ? cn_tile_cols<double>() : cn_tile_cols<float>();
+    const dim3 g((unsigned)((s->d.plane + tcols - 1) / tcols), 5, (unsigned)s->nmem);
+    const size_t lds = (size_t)s->d.M * (tcols + 1) * sizeof(double);
+    if (lds > (size_t)s->lds_max) return hipErrorInvalidValue;
     const int tb = s->tiles.cn;
     const int rpl = (s->d.M + 63) / 64;  // rows per lane (M <= 480: at most 8)
-#define NSPNP_CN_CASE(RR)                                                              \
-    case RR:                                                                           \
-        if (s->fp64) k_cn_scan<double, RR><<<g, tb, lds, s->stream>>>(a);              \
-        else k_cn_scan<float, RR><<<g, tb, lds, s->stream>>>(a);                       \
-        break;
+    // tiles above 64 KB of LDS (tall columns) use the device's larger limit
+    auto launch = [&](const void *fn, auto kernel) -> hipError_t {
+        if (lds > 65536) {
+            static const void *opted[32];
+            static int nopted = 0;
+            bool done = false;
+            for (int q = 0; q < nopted; ++q) done = done || opted[q] == fn;
+            if (!done) {
+                const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, s->lds_max);
+                if (e != hipSuccess) return e;
+                if (nopted < 32) opted[nopted++] = fn;
+            }
+        }
+        kernel<<<g, tb, lds, s->stream>>>(a);
+        return hipGetLastError();
+    };
+#define NSPNP_CN_CASE(RR)                                                                              \
+    case RR:                                                                                           \
+        return s->fp64 ? launch((const void *)k_cn_scan<double, RR>, k_cn_scan<double, RR>)            \
+                       : launch((const void *)k_cn_scan<float, RR>, k_cn_scan<float, RR>);
     switch (rpl) {
         NSPNP_CN_CASE(1)
         NSPNP_CN_CASE(2)
@@ -914,7 +935,6 @@ hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
             return hipErrorInvalidValue;
     }
 #undef NSPNP_CN_CASE
-    return hipGetLastError();
 }
 
 hipError_t launch_correct(nspnp_state *s, const Stage &st, bool update_p, double fixed, bool advance_clock) {

@@ -274,25 +274,57 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
     }
 }
 
-// ---- z direction: complex lines of stride nxh, a tile of tk modes per block ----
+// ---- z direction: contiguous complex lines, tiles of tk lines ----
+// Persistent blocks: each block loops over tiles (j, kx0..kx0+tk-1) of its
+// problem and member; the next tile's values are loaded into registers while
+// the current tile is transformed in LDS, so the HBM latency overlaps the
+// FFT passes.  kPer values per thread cover tk * nz <= kPer * 256 points.
+constexpr int kZPer = 8;
+
 __global__ void __launch_bounds__(256) k_fft_z(Dims d, FftPlan pl, const double2 *tw, double2 *spec, int64_t nspec,
                                                int tk, int inverse, size_t ms) {
     extern __shared__ double2 sm[];
     double2 *data = member_ptr(spec, ms) + blockIdx.y * nspec;
     const int nz = d.nz, nxh = d.nxh;
-    const int tiles = (nxh + tk - 1) / tk;
-    const int j = blockIdx.x / tiles;
-    const int kx0 = (blockIdx.x - j * tiles) * tk;
-    const int nt = (nxh - kx0 < tk) ? nxh - kx0 : tk;  // lines in this tile
+    const int tiles_x = (nxh + tk - 1) / tk;
+    const int ntiles = d.M * tiles_x;
+    const int pts = tk * nz;
     double2 *bf[2] = {sm, sm + tk * nz};
     double2 *s_tw = sm + 2 * tk * nz;
     stage_twiddles(s_tw, tw, nz);
-    // lines (j, kx) are contiguous runs of nz values: the tile is one block of memory
-    double2 *base = data + ((int64_t)j * nxh + kx0) * nz;
-    for (int e = threadIdx.x; e < tk * nz; e += blockDim.x) bf[0][e] = (e < nt * nz) ? base[e] : make_double2(0.0, 0.0);
-    __syncthreads();
-    const double2 *z = bf[lds_fft(bf[0], bf[1], nz, tk, pl, s_tw, inverse != 0)];
-    for (int e = threadIdx.x; e < nt * nz; e += blockDim.x) base[e] = z[e];
+    double2 nxt[kZPer];
+    auto tile_base = [&](int t, int &nt) -> double2 * {
+        const int j = t / tiles_x;
+        const int kx0 = (t - j * tiles_x) * tk;
+        nt = (nxh - kx0 < tk) ? nxh - kx0 : tk;  // lines in this tile
+        // lines (j, kx) are contiguous runs of nz values: the tile is one block of memory
+        return data + ((int64_t)j * nxh + kx0) * nz;
+    };
+    auto load = [&](int t) {
+        int nt;
+        const double2 *base = tile_base(t, nt);
+#pragma unroll
+        for (int q = 0; q < kZPer; ++q) {
+            const int e = (int)threadIdx.x + q * (int)blockDim.x;
+            nxt[q] = (e < nt * nz) ? base[e] : make_double2(0.0, 0.0);
+        }
+    };
+    int t = blockIdx.x;
+    if (t < ntiles) load(t);
+    for (; t < ntiles; t += gridDim.x) {
+        int nt;
+        double2 *base = tile_base(t, nt);
+#pragma unroll
+        for (int q = 0; q < kZPer; ++q) {
+            const int e = (int)threadIdx.x + q * (int)blockDim.x;
+            if (e < pts) bf[0][e] = nxt[q];
+        }
+        __syncthreads();
+        if (t + (int)gridDim.x < ntiles) load(t + gridDim.x);  // lands during the passes
+        const double2 *z = bf[lds_fft(bf[0], bf[1], nz, tk, pl, s_tw, inverse != 0)];
+        for (int e = threadIdx.x; e < nt * nz; e += blockDim.x) base[e] = z[e];
+        __syncthreads();  // bf[0] and the result buffer are reused by the next tile
+    }
 }
 
 // ---- y direction: one tridiagonal solve per (kx, kz) mode ----
@@ -541,8 +573,12 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
         else
             k_fft_x_r2c<float><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb, xcd);
     }
-    const int tk = modes_per_tile(d.nz, d.nxh, s->tiles.fftz);
-    const dim3 gz((unsigned)(d.M * ((d.nxh + tk - 1) / tk)), (unsigned)b.nprob, (unsigned)nmem);
+    int tk = modes_per_tile(d.nz, d.nxh, s->tiles.fftz);
+    if (tk * d.nz > kZPer * 256) tk = std::max(1, kZPer * 256 / d.nz);
+    const int ztiles = d.M * ((d.nxh + tk - 1) / tk);
+    // persistent blocks: about 8 per CU over all problems and members
+    const int zblocks = std::max(1, std::min(ztiles, 2048 / std::max(1, b.nprob * nmem)));
+    const dim3 gz((unsigned)zblocks, (unsigned)b.nprob, (unsigned)nmem);
     const size_t ldsz = (2 * (size_t)tk * d.nz + d.nz) * sizeof(double2);
     {
         ProfScope prof_(s, K_FFTZ_FWD);

@@ -140,15 +140,15 @@ __device__ __forceinline__ void stage_twiddles(double2 *s_tw, const double2 *tw,
 // FP64 array, the divergence of the staggered velocity (pressure), or the
 // charge -(c+ - c-)/(2 lam^2) (potential).
 template <typename T>
-__device__ __forceinline__ double line_value(const PoissonSrc &src, const Dims &d, const Tables &tb,
-                                             const double *clock, double ch, int64_t line, int i) {
+__device__ __forceinline__ double line_value(const PoissonSrc &src, const Dims &d, const Tables &tb, double ch,
+                                             double sc, double idx, double idz, int64_t line, int i) {
     const int64_t q = line * d.nx + i;
     if (src.type == SRC_REAL) return ((const double *)src.a)[q];
     if (src.type == SRC_CHARGE) {
         const T *cp = (const T *)src.a, *cm = (const T *)src.b;
         return ch * ((double)cp[q] - (double)cm[q]);
     }
-    // divergence: (u_{i+1} - u_i)/dx + (v_{j+1} - v_j)/dy_j + (w_{k+1} - w_k)/dz
+    // divergence: (u_{i+1} - u_i)/dx + (v_{j+1} - v_j)/dy_j + (w_{k+1} - w_k)/dz, times sc
     const T *u = (const T *)src.a, *v = (const T *)src.b, *w = (const T *)src.c;
     const int j = (int)(line / d.nz);
     const int k = (int)(line - (int64_t)j * d.nz);
@@ -156,11 +156,14 @@ __device__ __forceinline__ double line_value(const PoissonSrc &src, const Dims &
     const int64_t zp = q + (int64_t)(((k + 1 == d.nz) ? 0 : k + 1) - k) * d.nx;
     const double vt = (j + 1 < d.M) ? (double)v[q + d.plane] : 0.0;
     const double vb = (j > 0) ? (double)v[q] : 0.0;
-    const double div = ((double)u[xp] - (double)u[q]) / d.dx + (vt - vb) * tb.idn[j] +
-                       ((double)w[zp] - (double)w[q]) / d.dz;
-    const double sc = (src.alp > 0.0) ? 1.0 / (src.alp * clock[1]) : src.fixed;
+    const double div = ((double)u[xp] - (double)u[q]) * idx + (vt - vb) * tb.idn[j] +
+                       ((double)w[zp] - (double)w[q]) * idz;
     return div * sc;
 }
+
+// Slots of each of the two FFT buffers of an x-transform block; the [kx][line]
+// staging of the transposed spectrum stores / loads fits one of them.
+__host__ __device__ inline int x_buffer_slots(int nx, int ppb) { return ppb * (nx + 2); }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl, PoissonBatch b,
@@ -181,29 +184,32 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
     double2 *out = member_ptr_at(spec, b.ms, blk.z) + prob * nspec;
     const int nx = d.nx, nxh = d.nxh;
     const int64_t nlines = (int64_t)d.M * d.nz;
-    double2 *bf[2] = {sm, sm + ppb * (nx + 2)};
-    double2 *s_tw = sm + 2 * ppb * (nx + 2);
+    const int bs = x_buffer_slots(nx, ppb);
+    double2 *bf[2] = {sm, sm + bs};
+    double2 *s_tw = sm + 2 * bs;
     stage_twiddles(s_tw, tb.twx, nx);
+    const double sc = (src.type == SRC_DIV) ? ((src.alp > 0.0) ? 1.0 / (src.alp * clock[1]) : src.fixed) : 0.0;
+    const double idx = 1.0 / d.dx, idz = 1.0 / d.dz;
     const int64_t pair0 = (int64_t)blk.x * ppb;
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
         const int p = e / nx, i = e - p * nx;
         const int64_t la = 2 * (pair0 + p), lb = la + 1;
-        const double re = (la < nlines) ? line_value<T>(src, d, tb, clock, ch, la, i) : 0.0;
-        const double im = (lb < nlines) ? line_value<T>(src, d, tb, clock, ch, lb, i) : 0.0;
+        const double re = (la < nlines) ? line_value<T>(src, d, tb, ch, sc, idx, idz, la, i) : 0.0;
+        const double im = (lb < nlines) ? line_value<T>(src, d, tb, ch, sc, idx, idz, lb, i) : 0.0;
         bf[0][e] = make_double2(re, im);
     }
     __syncthreads();
     const int w = lds_fft(bf[0], bf[1], nx, ppb, pl, s_tw, false);
     const double2 *z = bf[w];
     double2 *o = bf[1 - w];  // [kk][line] staging for the transposed store
-    const int nl2 = 2 * ppb;
+    const int nl2 = 2 * ppb, ld = nl2;
     for (int e = threadIdx.x; e < ppb * nxh; e += blockDim.x) {
         const int p = e / nxh, kk = e - p * nxh;
         const double2 zk = z[p * nx + kk];
         const double2 zc = z[p * nx + (kk == 0 ? 0 : nx - kk)];
         // A = (Z_k + conj(Z_{N-k}))/2, B = (Z_k - conj(Z_{N-k}))/(2i)
-        o[kk * nl2 + 2 * p] = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y - zc.y));
-        o[kk * nl2 + 2 * p + 1] = make_double2(0.5 * (zk.y + zc.y), -0.5 * (zk.x - zc.x));
+        o[kk * ld + 2 * p] = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y - zc.y));
+        o[kk * ld + 2 * p + 1] = make_double2(0.5 * (zk.y + zc.y), -0.5 * (zk.x - zc.x));
     }
     __syncthreads();
     // spectrum layout [j][kx][kz]: consecutive lines (k) of one kx are contiguous
@@ -212,7 +218,7 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
         const int64_t line = 2 * pair0 + l;
         if (line < nlines) {
             const int64_t j = line / d.nz, k = line - j * d.nz;
-            out[(j * nxh + kk) * d.nz + k] = o[e];
+            out[(j * nxh + kk) * d.nz + k] = o[kk * ld + l];
         }
     }
 }
@@ -226,11 +232,12 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
     const double2 *in = member_ptr_at(spec, b.ms, blk.z) + prob * nspec;
     const int nx = d.nx, nxh = d.nxh;
     const int64_t nlines = (int64_t)d.M * d.nz;
-    double2 *bf[2] = {sm, sm + ppb * (nx + 2)};
-    double2 *s_tw = sm + 2 * ppb * (nx + 2);
+    const int bs = x_buffer_slots(nx, ppb);
+    double2 *bf[2] = {sm, sm + bs};
+    double2 *s_tw = sm + 2 * bs;
     stage_twiddles(s_tw, tb.twx, nx);
     const int64_t pair0 = (int64_t)blk.x * ppb;
-    const int nl2 = 2 * ppb;
+    const int nl2 = 2 * ppb, ld = nl2;
     double2 *o = bf[1];  // [kk][line] staging of the transposed load
     for (int e = threadIdx.x; e < nl2 * nxh; e += blockDim.x) {
         const int kk = e / nl2, l = e - kk * nl2;
@@ -240,15 +247,15 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
             const int64_t j = line / d.nz, k = line - j * d.nz;
             v = in[(j * nxh + kk) * d.nz + k];
         }
-        o[e] = v;
+        o[kk * ld + l] = v;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
         const int p = e / nx, kk = e - p * nx;
         const bool lower = kk < nxh;
         const int src = lower ? kk : nx - kk;
-        double2 A = o[src * nl2 + 2 * p];
-        double2 B = o[src * nl2 + 2 * p + 1];
+        double2 A = o[src * ld + 2 * p];
+        double2 B = o[src * ld + 2 * p + 1];
         if (!lower) {  // Hermitian continuation of a real line's spectrum
             A.y = -A.y;
             B.y = -B.y;
@@ -538,6 +545,7 @@ inline int thomas_tile_modes(int M, int want) {
 // within 64 KB of LDS for the two staging buffers
 inline int pairs_per_block(int nx, int points, int lds_bytes = 65536) {
     int p = nx >= points ? 1 : points / nx;
+    // two buffers of x_buffer_slots(nx, p) plus the twiddle table
     const int lds_max = (lds_bytes - nx * (int)sizeof(double2)) / (2 * (nx + 2) * (int)sizeof(double2));
     if (p > lds_max) p = lds_max;
     return p < 1 ? 1 : p;
@@ -554,6 +562,20 @@ inline int modes_per_tile(int nz, int nxh, int points) {
 
 }  // namespace
 
+// Kernels that need more than 64 KB of dynamic LDS ask for the device's
+// larger per-workgroup limit once.
+hipError_t lds_opt_in(const void *fn, size_t bytes, int lds_max) {
+    if (bytes <= 65536) return hipSuccess;
+    if (bytes > (size_t)lds_max) return hipErrorInvalidValue;
+    static const void *opted[16];
+    static int nopted = 0;
+    for (int q = 0; q < nopted; ++q)
+        if (opted[q] == fn) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    if (e == hipSuccess && nopted < 16) opted[nopted++] = fn;
+    return e;
+}
+
 // All members of the handle are solved when b.ms is the member stride;
 // caller-owned arrays (b.ms = 0) are solved for member 0 only.
 hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
@@ -564,14 +586,19 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
     const int ppb = pairs_per_block(d.nx, s->tiles.fftx);
     const int64_t npairs = (nlines + 1) / 2;
     const dim3 gx((unsigned)((npairs + ppb - 1) / ppb), (unsigned)b.nprob, (unsigned)nmem);
-    const size_t ldsx = (2 * (size_t)ppb * (d.nx + 2) + d.nx) * sizeof(double2);
+    const size_t ldsx = (2 * (size_t)x_buffer_slots(d.nx, ppb) + d.nx) * sizeof(double2);
     {
         ProfScope prof_(s, K_FFTX_FWD);
         const int xcd = s->tiles.xcdfft;
-        if (s->fp64)
+        if (s->fp64) {
+            hipError_t e = lds_opt_in((const void *)k_fft_x_r2c<double>, ldsx, s->lds_max);
+            if (e != hipSuccess) return e;
             k_fft_x_r2c<double><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb, xcd);
-        else
+        } else {
+            hipError_t e = lds_opt_in((const void *)k_fft_x_r2c<float>, ldsx, s->lds_max);
+            if (e != hipSuccess) return e;
             k_fft_x_r2c<float><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb, xcd);
+        }
     }
     int tk = modes_per_tile(d.nz, d.nxh, s->tiles.fftz);
     if (tk * d.nz > kZPer * 256) tk = std::max(1, kZPer * 256 / d.nz);
@@ -620,16 +647,11 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
         // (the device's whole LDS per workgroup may be used for that)
         const int ppbc = std::max(ppb, pairs_per_block(d.nx, 4 * d.nx, s->lds_max));
         const dim3 gc((unsigned)((npairs + ppbc - 1) / ppbc), (unsigned)b.nprob, (unsigned)nmem);
-        const size_t ldsc = (2 * (size_t)ppbc * (d.nx + 2) + d.nx) * sizeof(double2);
-        if (ldsc > 65536) {
-            static bool opted[2] = {false, false};
-            const int ty = s->fp64 ? 0 : 1;
-            if (!opted[ty]) {
-                const void *fn = s->fp64 ? (const void *)k_fft_x_c2r<double> : (const void *)k_fft_x_c2r<float>;
-                const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, s->lds_max);
-                if (e != hipSuccess) return e;
-                opted[ty] = true;
-            }
+        const size_t ldsc = (2 * (size_t)x_buffer_slots(d.nx, ppbc) + d.nx) * sizeof(double2);
+        {
+            const void *fn = s->fp64 ? (const void *)k_fft_x_c2r<double> : (const void *)k_fft_x_c2r<float>;
+            const hipError_t e = lds_opt_in(fn, ldsc, s->lds_max);
+            if (e != hipSuccess) return e;
         }
         const int xcd = s->tiles.xcdfft;
         if (s->fp64) k_fft_x_c2r<double><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc, xcd);

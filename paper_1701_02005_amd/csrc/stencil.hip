@@ -751,19 +751,21 @@ __global__ void __launch_bounds__(256) k_correct(CorrArgs a) {
     const double *psi = member_ptr_at(a.psi, ms, mem);
     const double sc = (a.alp > 0.0) ? a.alp * clock[1] : a.fixed;
     const double ire = ph->ire;
+    const double idx = 1.0 / d.dx, idz = 1.0 / d.dz;
     double s_dn = (j0 > 0) ? psi[(int64_t)(j0 - 1) * pl + e] : 0.0;  // psi of row j - 1
     double s0 = psi[(int64_t)j0 * pl + e];
     for (int j = j0; j < j1; ++j) {
         const int64_t row = (int64_t)j * pl, q = row + e;
         const double s_up = (j + 1 < M) ? psi[q + pl] : 0.0;
         const double sxm = psi[row + exm], szm = psi[row + ezm];
-        u[q] = (T)((double)u[q] - sc * (s0 - sxm) / d.dx);
-        w[q] = (T)((double)w[q] - sc * (s0 - szm) / d.dz);
-        if (j > 0) v[q] = (T)((double)v[q] - sc * (s0 - s_dn) / a.tb.dc[j]);
+        u[q] = (T)((double)u[q] - sc * (s0 - sxm) * idx);
+        w[q] = (T)((double)w[q] - sc * (s0 - szm) * idz);
+        const double idcb = a.tb.idc[j];
+        if (j > 0) v[q] = (T)((double)v[q] - sc * (s0 - s_dn) * idcb);
         if (a.update_p) {
-            const double ft = (j + 1 < M) ? (s_up - s0) / a.tb.dc[j + 1] : 0.0;
-            const double fb = (j > 0) ? (s0 - s_dn) / a.tb.dc[j] : 0.0;
-            const double ly = (ft - fb) / a.tb.dn[j];
+            const double ft = (j + 1 < M) ? (s_up - s0) * a.tb.idc[j + 1] : 0.0;
+            const double fb = (j > 0) ? (s0 - s_dn) * idcb : 0.0;
+            const double ly = (ft - fb) * a.tb.idn[j];
             p[q] = (T)((double)p[q] + s0 - 0.5 * sc * ire * ly);
         }
         s_dn = s0;

@@ -205,10 +205,10 @@ NSPNP_API int nspnp_load(nspnp_state *s, const char *path);
  * size class (same candidates, cache format and key, with member count 1).
  * Trials advance the run by trial_substeps (a multiple of 3) per candidate;
  * the shapes never change a result beyond the rounding order of the CN
- * method.  tiles_out (NULL or 9 ints) receives the choice.  Synchronises. */
+ * method.  tiles_out (NULL or 8 ints) receives the choice.  Synchronises. */
 NSPNP_API int nspnp_autotune(nspnp_state *s, const char *cache_path, int32_t trial_substeps, int32_t *tiles_out);
 
-/* Read / set this run's launch shapes (9 ints in the order of
+/* Read / set this run's launch shapes (8 ints in the order of
  * nspnp_ensemble_autotune's tiles_out).  set validates every entry
  * (NSPNP_ERR_INVALID when out of range) and synchronises. */
 NSPNP_API int nspnp_get_tiles(const nspnp_state *s, int32_t *tiles_out);
@@ -281,12 +281,12 @@ NSPNP_API int nspnp_ensemble_clock(nspnp_ensemble *e, int32_t member, double *t,
  * appended to the text cache at cache_path (NULL: no cache), one line per
  * (arch, grid, precision, members) key.  Trials advance the members (the
  * launch shape does not change any result); on return every member has
- * advanced by the same number of substeps.  tiles_out (NULL or 9 ints per
+ * advanced by the same number of substeps.  tiles_out (NULL or 8 ints per
  * class) receives the choice: explicit-kernel threads, CN threads, x and z
  * transform points, modes per tile of the mode solves, correction threads,
- * explicit-kernel slab rows, the CN method (0: lane scans over whole
- * columns; 16 or 32: row slabs of that height, three passes), and 1 for an
- * XCD-aware block order of the x transforms.
+ * explicit-kernel and correction slab rows, and the CN method (0: lane
+ * scans over whole columns; 16 or 32: row slabs of that height, three
+ * passes).
  * Synchronises. */
 NSPNP_API int nspnp_ensemble_autotune(nspnp_ensemble *e, const char *cache_path, int32_t trial_substeps,
                                       int32_t *tiles_out);

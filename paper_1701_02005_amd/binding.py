@@ -343,7 +343,7 @@ class Ensemble:
     null stream cannot be captured into a graph); every call that returns
     data synchronises that stream."""
 
-    TILE_NAMES = ("expl", "cn", "fftx", "fftz", "thomas", "corr", "slab", "cnslab", "xcdfft")
+    TILE_NAMES = ("expl", "cn", "fftx", "fftz", "thomas", "corr", "slab", "cnslab")
 
     def __init__(self, cfgs, device: str = "cuda:0"):
         if not torch.cuda.is_available():

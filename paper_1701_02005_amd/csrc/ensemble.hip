@@ -121,7 +121,7 @@ int check_members(const nspnp_ensemble *e) {
 // ---- autotuner ----------------------------------------------------------
 std::string tune_key(const nspnp_state *c) {
     std::ostringstream k;
-    k << "gfx950v3:" << c->cfg.nx << "x" << c->cfg.ny << "x" << c->cfg.nz << ":" << (c->fp64 ? "fp64" : "mixed")
+    k << "gfx950v4:" << c->cfg.nx << "x" << c->cfg.ny << "x" << c->cfg.nz << ":" << (c->fp64 ? "fp64" : "mixed")
       << ":" << c->nmem;
     return k.str();
 }
@@ -134,7 +134,7 @@ bool cache_lookup(const char *path, const std::string &key, Tiles &t) {
         std::istringstream ls(line);
         std::string k;
         Tiles v{};
-        if (ls >> k >> v.expl >> v.cn >> v.fftx >> v.fftz >> v.thomas >> v.corr >> v.slab >> v.cnslab >> v.xcdfft && k == key) {
+        if (ls >> k >> v.expl >> v.cn >> v.fftx >> v.fftz >> v.thomas >> v.corr >> v.slab >> v.cnslab && k == key) {
             t = v;
             return true;
         }
@@ -146,7 +146,7 @@ void cache_store(const char *path, const std::string &key, const Tiles &t) {
     if (!path || !*path) return;
     std::ofstream out(path, std::ios::app);
     out << key << " " << t.expl << " " << t.cn << " " << t.fftx << " " << t.fftz << " " << t.thomas << " " << t.corr
-        << " " << t.slab << " " << t.cnslab << " " << t.xcdfft << "\n";
+        << " " << t.slab << " " << t.cnslab << "\n";
 }
 
 // wall time (ms) of `trial` substeps of one class with its current tiles
@@ -166,7 +166,7 @@ int time_class(nspnp_state *c, int trial, float *ms) {
 
 void tiles_to_ints(const Tiles &t, int32_t *o) {
     o[0] = t.expl; o[1] = t.cn; o[2] = t.fftx; o[3] = t.fftz; o[4] = t.thomas; o[5] = t.corr; o[6] = t.slab;
-    o[7] = t.cnslab; o[8] = t.xcdfft;
+    o[7] = t.cnslab;
 }
 
 // Launch shapes of one handle (a single run or a size class): from the cache
@@ -184,7 +184,6 @@ int tune_handle(nspnp_state *c, const char *cache_path, int trial) {
         const int cand_corr[] = {128, 256};
         const int cand_slab[] = {4, 8, 16, 32};
         const int cand_cnslab[] = {0, 16, 32};
-        const int cand_xcd[] = {0, 1};
         float base_ms = 0.f;
         int rc;
         if ((rc = time_class(c, trial, &base_ms))) return rc;  // warm
@@ -214,7 +213,6 @@ int tune_handle(nspnp_state *c, const char *cache_path, int trial) {
         if ((rc = sweep(&c->tiles.corr, cand_corr, 2))) return rc;
         if ((rc = sweep(&c->tiles.slab, cand_slab, 4))) return rc;
         if ((rc = sweep(&c->tiles.cnslab, cand_cnslab, 3))) return rc;
-        if ((rc = sweep(&c->tiles.xcdfft, cand_xcd, 2))) return rc;
         best = c->tiles;
         cache_store(cache_path, key, best);
     }
@@ -432,10 +430,10 @@ int nspnp_set_tiles(nspnp_state *s, const int32_t *t) {
     };
     if (!one_of(t[0], {64, 128, 256}) || !one_of(t[1], {64, 128, 256}) || t[2] < 64 || t[2] > 8192 ||
         t[3] < 64 || t[3] > 8192 || t[4] < 1 || t[4] > 64 || !one_of(t[5], {64, 128, 256}) ||
-        t[6] < 1 || t[6] > 480 || !one_of(t[7], {0, 16, 32}) || !one_of(t[8], {0, 1}))
+        t[6] < 1 || t[6] > 480 || !one_of(t[7], {0, 16, 32}))
         return fail_code(NSPNP_ERR_INVALID, "launch shapes out of range");
     E_TRY(hipStreamSynchronize(s->stream));
-    s->tiles = Tiles{t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7], t[8]};
+    s->tiles = Tiles{t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7]};
     return NSPNP_OK;
 }
 

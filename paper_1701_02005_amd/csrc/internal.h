@@ -163,10 +163,9 @@ struct Tiles {
     int corr;     // threads per block of the projection correction
     int slab;     // rows marched by one block of the explicit kernel
     int cnslab;   // Crank-Nicolson: 0 lane-scan method, 16 or 32 row-slab method with that many rows
-    int xcdfft;   // 1: XCD-aware block order in the x transforms
 };
 
-constexpr int kTileInts = 9;  // Tiles as exported through the ABI
+constexpr int kTileInts = 8;  // Tiles as exported through the ABI
 
 // Kernel classes timed by the optional event profiler.
 enum KernelId {

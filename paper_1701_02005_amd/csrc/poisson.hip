@@ -167,21 +167,16 @@ __host__ __device__ inline int x_buffer_slots(int nx, int ppb) { return ppb * (n
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl, PoissonBatch b,
-                                                   const double *clock, double2 *spec, int64_t nspec, int ppb,
-                                                   int xcd) {
+                                                   const double *clock, double2 *spec, int64_t nspec, int ppb) {
     extern __shared__ double2 sm[];
-    // xcd != 0: neighbouring line blocks (which write the two halves of the
-    // same 128-byte spectrum lines when a block holds fewer than 8 lines)
-    // run on one XCD, so its L2 merges the halves
-    const uint3 blk = xcd ? xcd_block3() : make_uint3(blockIdx.x, blockIdx.y, blockIdx.z);
-    const int prob = (int)blk.y;
+    const int prob = blockIdx.y;
     PoissonSrc src = b.src[prob];
-    src.a = member_ptr_at(src.a, b.ms, blk.z);
-    src.b = member_ptr_at(src.b, b.ms, blk.z);
-    src.c = member_ptr_at(src.c, b.ms, blk.z);
-    clock = member_ptr_at(clock, b.ms, blk.z);
-    const double ch = member_ptr_at(b.phys, b.ms, blk.z)->ch;
-    double2 *out = member_ptr_at(spec, b.ms, blk.z) + prob * nspec;
+    src.a = member_ptr(src.a, b.ms);
+    src.b = member_ptr(src.b, b.ms);
+    src.c = member_ptr(src.c, b.ms);
+    clock = member_ptr(clock, b.ms);
+    const double ch = member_ptr(b.phys, b.ms)->ch;
+    double2 *out = member_ptr(spec, b.ms) + prob * nspec;
     const int nx = d.nx, nxh = d.nxh;
     const int64_t nlines = (int64_t)d.M * d.nz;
     const int bs = x_buffer_slots(nx, ppb);
@@ -190,7 +185,7 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
     stage_twiddles(s_tw, tb.twx, nx);
     const double sc = (src.type == SRC_DIV) ? ((src.alp > 0.0) ? 1.0 / (src.alp * clock[1]) : src.fixed) : 0.0;
     const double idx = 1.0 / d.dx, idz = 1.0 / d.dz;
-    const int64_t pair0 = (int64_t)blk.x * ppb;
+    const int64_t pair0 = (int64_t)blockIdx.x * ppb;
     for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
         const int p = e / nx, i = e - p * nx;
         const int64_t la = 2 * (pair0 + p), lb = la + 1;
@@ -202,14 +197,14 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
     const int w = lds_fft(bf[0], bf[1], nx, ppb, pl, s_tw, false);
     const double2 *z = bf[w];
     double2 *o = bf[1 - w];  // [kk][line] staging for the transposed store
-    const int nl2 = 2 * ppb, ld = nl2;
+    const int nl2 = 2 * ppb;
     for (int e = threadIdx.x; e < ppb * nxh; e += blockDim.x) {
         const int p = e / nxh, kk = e - p * nxh;
         const double2 zk = z[p * nx + kk];
         const double2 zc = z[p * nx + (kk == 0 ? 0 : nx - kk)];
         // A = (Z_k + conj(Z_{N-k}))/2, B = (Z_k - conj(Z_{N-k}))/(2i)
-        o[kk * ld + 2 * p] = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y - zc.y));
-        o[kk * ld + 2 * p + 1] = make_double2(0.5 * (zk.y + zc.y), -0.5 * (zk.x - zc.x));
+        o[kk * nl2 + 2 * p] = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y - zc.y));
+        o[kk * nl2 + 2 * p + 1] = make_double2(0.5 * (zk.y + zc.y), -0.5 * (zk.x - zc.x));
     }
     __syncthreads();
     // spectrum layout [j][kx][kz]: consecutive lines (k) of one kx are contiguous
@@ -218,66 +213,92 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
         const int64_t line = 2 * pair0 + l;
         if (line < nlines) {
             const int64_t j = line / d.nz, k = line - j * d.nz;
-            out[(j * nxh + kk) * d.nz + k] = o[kk * ld + l];
+            out[(j * nxh + kk) * d.nz + k] = o[e];
         }
     }
 }
 
+// Persistent blocks over tiles of ppb line pairs: the next tile's spectrum
+// values (transposed load, whole runs of consecutive lines per kx) are loaded
+// into registers while the current tile is transformed in LDS.
+constexpr int kCPer = 12;  // prefetched values per thread: 2 ppb (nx/2+1) <= kCPer * 256
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl, PoissonBatch b,
-                                                   const double2 *spec, int64_t nspec, int ppb, int xcd) {
+                                                   const double2 *spec, int64_t nspec, int ppb) {
     extern __shared__ double2 sm[];
-    const uint3 blk = xcd ? xcd_block3() : make_uint3(blockIdx.x, blockIdx.y, blockIdx.z);
-    const int prob = (int)blk.y;
-    const double2 *in = member_ptr_at(spec, b.ms, blk.z) + prob * nspec;
-    const int nx = d.nx, nxh = d.nxh;
+    const int prob = blockIdx.y;
+    const double2 *in = member_ptr(spec, b.ms) + prob * nspec;
+    const int nx = d.nx, nxh = d.nxh, nz = d.nz;
     const int64_t nlines = (int64_t)d.M * d.nz;
+    const int ntiles = (int)(((nlines + 1) / 2 + ppb - 1) / ppb);
     const int bs = x_buffer_slots(nx, ppb);
     double2 *bf[2] = {sm, sm + bs};
     double2 *s_tw = sm + 2 * bs;
     stage_twiddles(s_tw, tb.twx, nx);
-    const int64_t pair0 = (int64_t)blk.x * ppb;
-    const int nl2 = 2 * ppb, ld = nl2;
+    const int nl2 = 2 * ppb, nst = nl2 * nxh;
+    const float r_nl2 = 1.0f / (float)nl2, r_nz = 1.0f / (float)nz;
     double2 *o = bf[1];  // [kk][line] staging of the transposed load
-    for (int e = threadIdx.x; e < nl2 * nxh; e += blockDim.x) {
-        const int kk = e / nl2, l = e - kk * nl2;
-        const int64_t line = 2 * pair0 + l;
-        double2 v = make_double2(0.0, 0.0);
-        if (line < nlines) {
-            const int64_t j = line / d.nz, k = line - j * d.nz;
-            v = in[(j * nxh + kk) * d.nz + k];
-        }
-        o[kk * ld + l] = v;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
-        const int p = e / nx, kk = e - p * nx;
-        const bool lower = kk < nxh;
-        const int src = lower ? kk : nx - kk;
-        double2 A = o[src * ld + 2 * p];
-        double2 B = o[src * ld + 2 * p + 1];
-        if (!lower) {  // Hermitian continuation of a real line's spectrum
-            A.y = -A.y;
-            B.y = -B.y;
-        }
-        bf[0][e] = make_double2(A.x - B.y, A.y + B.x);  // Z = A + i B
-    }
-    __syncthreads();
-    const double2 *z = bf[lds_fft(bf[0], bf[1], nx, ppb, pl, s_tw, true)];
     const bool as_state = b.out_state[prob] != 0;
-    double *o64 = (double *)member_ptr_at(b.out[prob], b.ms, blk.z);
-    T *ot = (T *)member_ptr_at(b.out[prob], b.ms, blk.z);
-    for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
-        const int p = e / nx, i = e - p * nx;
-        const int64_t la = 2 * (pair0 + p), lb = la + 1;
-        const double2 v = z[e];
-        if (as_state) {
-            if (la < nlines) ot[la * nx + i] = (T)v.x;
-            if (lb < nlines) ot[lb * nx + i] = (T)v.y;
-        } else {
-            if (la < nlines) o64[la * nx + i] = v.x;
-            if (lb < nlines) o64[lb * nx + i] = v.y;
+    double *o64 = (double *)member_ptr(b.out[prob], b.ms);
+    T *ot = (T *)member_ptr(b.out[prob], b.ms);
+    double2 nxt[kCPer];
+    auto load = [&](int t) {
+        const int64_t l0 = 2 * (int64_t)t * ppb;
+#pragma unroll
+        for (int q = 0; q < kCPer; ++q) {
+            const int e = (int)threadIdx.x + q * (int)blockDim.x;
+            double2 v = make_double2(0.0, 0.0);
+            if (e < nst) {
+                int kk, l, j, k;
+                divmod(e, nl2, r_nl2, kk, l);
+                const int64_t line = l0 + l;
+                if (line < nlines) {
+                    divmod((int)line, nz, r_nz, j, k);
+                    v = in[((int64_t)j * nxh + kk) * nz + k];
+                }
+            }
+            nxt[q] = v;
         }
+    };
+    int t = blockIdx.x;
+    if (t < ntiles) load(t);
+    for (; t < ntiles; t += gridDim.x) {
+        const int64_t pair0 = (int64_t)t * ppb;
+#pragma unroll
+        for (int q = 0; q < kCPer; ++q) {
+            const int e = (int)threadIdx.x + q * (int)blockDim.x;
+            if (e < nst) o[e] = nxt[q];
+        }
+        __syncthreads();
+        if (t + (int)gridDim.x < ntiles) load(t + gridDim.x);  // lands during the passes
+        for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
+            const int p = e / nx, kk = e - p * nx;
+            const bool lower = kk < nxh;
+            const int src = lower ? kk : nx - kk;
+            double2 A = o[src * nl2 + 2 * p];
+            double2 B = o[src * nl2 + 2 * p + 1];
+            if (!lower) {  // Hermitian continuation of a real line's spectrum
+                A.y = -A.y;
+                B.y = -B.y;
+            }
+            bf[0][e] = make_double2(A.x - B.y, A.y + B.x);  // Z = A + i B
+        }
+        __syncthreads();
+        const double2 *z = bf[lds_fft(bf[0], bf[1], nx, ppb, pl, s_tw, true)];
+        for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
+            const int p = e / nx, i = e - p * nx;
+            const int64_t la = 2 * (pair0 + p), lb = la + 1;
+            const double2 v = z[e];
+            if (as_state) {
+                if (la < nlines) ot[la * nx + i] = (T)v.x;
+                if (lb < nlines) ot[lb * nx + i] = (T)v.y;
+            } else {
+                if (la < nlines) o64[la * nx + i] = v.x;
+                if (lb < nlines) o64[lb * nx + i] = v.y;
+            }
+        }
+        __syncthreads();  // o and the result buffer are reused by the next tile
     }
 }
 
@@ -585,20 +606,17 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
     const int64_t nspec = (int64_t)d.nxh * d.nz * d.M;
     const int ppb = pairs_per_block(d.nx, s->tiles.fftx);
     const int64_t npairs = (nlines + 1) / 2;
-    const dim3 gx((unsigned)((npairs + ppb - 1) / ppb), (unsigned)b.nprob, (unsigned)nmem);
-    const size_t ldsx = (2 * (size_t)x_buffer_slots(d.nx, ppb) + d.nx) * sizeof(double2);
     {
         ProfScope prof_(s, K_FFTX_FWD);
-        const int xcd = s->tiles.xcdfft;
-        if (s->fp64) {
-            hipError_t e = lds_opt_in((const void *)k_fft_x_r2c<double>, ldsx, s->lds_max);
-            if (e != hipSuccess) return e;
-            k_fft_x_r2c<double><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb, xcd);
-        } else {
-            hipError_t e = lds_opt_in((const void *)k_fft_x_r2c<float>, ldsx, s->lds_max);
-            if (e != hipSuccess) return e;
-            k_fft_x_r2c<float><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb, xcd);
-        }
+        const dim3 gx((unsigned)((npairs + ppb - 1) / ppb), (unsigned)b.nprob, (unsigned)nmem);
+        const size_t ldsx = (2 * (size_t)x_buffer_slots(d.nx, ppb) + d.nx) * sizeof(double2);
+        const void *fn = s->fp64 ? (const void *)k_fft_x_r2c<double> : (const void *)k_fft_x_r2c<float>;
+        const hipError_t e = lds_opt_in(fn, ldsx, s->lds_max);
+        if (e != hipSuccess) return e;
+        if (s->fp64)
+            k_fft_x_r2c<double><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb);
+        else
+            k_fft_x_r2c<float><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb);
     }
     int tk = modes_per_tile(d.nz, d.nxh, s->tiles.fftz);
     if (tk * d.nz > kZPer * 256) tk = std::max(1, kZPer * 256 / d.nz);
@@ -645,17 +663,19 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
         // at least 8 lines per block, so that every kx of the transposed load
         // reads whole 128-byte lines of the [j][kx][kz] spectrum
         // (the device's whole LDS per workgroup may be used for that)
-        const int ppbc = std::max(ppb, pairs_per_block(d.nx, 4 * d.nx, s->lds_max));
-        const dim3 gc((unsigned)((npairs + ppbc - 1) / ppbc), (unsigned)b.nprob, (unsigned)nmem);
+        int ppbc = std::max(ppb, pairs_per_block(d.nx, 4 * d.nx, s->lds_max));
+        ppbc = std::max(1, std::min(ppbc, kCPer * 256 / (2 * d.nxh)));  // prefetch registers
+        const int ctiles = (int)((npairs + ppbc - 1) / ppbc);
+        const int cblocks = std::max(1, std::min(ctiles, 2048 / std::max(1, b.nprob * nmem)));
+        const dim3 gc((unsigned)cblocks, (unsigned)b.nprob, (unsigned)nmem);
         const size_t ldsc = (2 * (size_t)x_buffer_slots(d.nx, ppbc) + d.nx) * sizeof(double2);
         {
             const void *fn = s->fp64 ? (const void *)k_fft_x_c2r<double> : (const void *)k_fft_x_c2r<float>;
             const hipError_t e = lds_opt_in(fn, ldsc, s->lds_max);
             if (e != hipSuccess) return e;
         }
-        const int xcd = s->tiles.xcdfft;
-        if (s->fp64) k_fft_x_c2r<double><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc, xcd);
-        else k_fft_x_c2r<float><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc, xcd);
+        if (s->fp64) k_fft_x_c2r<double><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc);
+        else k_fft_x_c2r<float><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc);
     }
     return hipGetLastError();
 }

@@ -191,7 +191,7 @@ def test_launch_order_shapes_are_bitwise_neutral(P):
     note("case: launch shapes vs defaults, 48x27x36")
     a = P.Solver(cfg)
     b = P.Solver(cfg)
-    b.set_tiles(xcdfft=1, fftx=2048, fftz=1024, thomas=3, slab=5, expl=128, corr=64, cn=64)
+    b.set_tiles(fftx=2048, fftz=1024, thomas=3, slab=5, expl=128, corr=64, cn=64)
     a.step(9)
     b.step(9)
     for k in FIELDS:

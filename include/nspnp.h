@@ -282,7 +282,8 @@ NSPNP_API int nspnp_ensemble_clock(nspnp_ensemble *e, int32_t member, double *t,
  * (arch, grid, precision, members) key.  Trials advance the members (the
  * launch shape does not change any result); on return every member has
  * advanced by the same number of substeps.  tiles_out (NULL or 8 ints per
- * class) receives the choice: explicit-kernel threads, CN threads, x and z
+ * class) receives the choice: explicit-kernel threads, CN threads (64 to
+ * 256: tiles of 16 columns; 512: tiles of 32 columns), x and z
  * transform points, modes per tile of the mode solves, correction threads,
  * explicit-kernel and correction slab rows, and the CN method (0: lane
  * scans over whole columns; 16 or 32: row slabs of that height, three

@@ -121,7 +121,7 @@ int check_members(const nspnp_ensemble *e) {
 // ---- autotuner ----------------------------------------------------------
 std::string tune_key(const nspnp_state *c) {
     std::ostringstream k;
-    k << "gfx950v4:" << c->cfg.nx << "x" << c->cfg.ny << "x" << c->cfg.nz << ":" << (c->fp64 ? "fp64" : "mixed")
+    k << "gfx950v5:" << c->cfg.nx << "x" << c->cfg.ny << "x" << c->cfg.nz << ":" << (c->fp64 ? "fp64" : "mixed")
       << ":" << c->nmem;
     return k.str();
 }
@@ -178,7 +178,7 @@ int tune_handle(nspnp_state *c, const char *cache_path, int trial) {
     Tiles best = c->tiles;
     if (!cache_lookup(cache_path, key, best)) {
         const int cand_expl[] = {64, 128, 256};
-        const int cand_cn[] = {64, 128, 256};
+        const int cand_cn[] = {64, 128, 256, 512};
         const int cand_fft[] = {512, 1024, 2048};
         const int cand_th[] = {4, 8, 16, 32};
         const int cand_corr[] = {128, 256};
@@ -206,7 +206,7 @@ int tune_handle(nspnp_state *c, const char *cache_path, int trial) {
             return NSPNP_OK;
         };
         if ((rc = sweep(&c->tiles.expl, cand_expl, 3))) return rc;
-        if ((rc = sweep(&c->tiles.cn, cand_cn, 3))) return rc;
+        if ((rc = sweep(&c->tiles.cn, cand_cn, 4))) return rc;
         if ((rc = sweep(&c->tiles.fftx, cand_fft, 3))) return rc;
         if ((rc = sweep(&c->tiles.fftz, cand_fft, 3))) return rc;
         if ((rc = sweep(&c->tiles.thomas, cand_th, 4))) return rc;
@@ -428,7 +428,7 @@ int nspnp_set_tiles(nspnp_state *s, const int32_t *t) {
             if (v == o) return true;
         return false;
     };
-    if (!one_of(t[0], {64, 128, 256}) || !one_of(t[1], {64, 128, 256}) || t[2] < 64 || t[2] > 8192 ||
+    if (!one_of(t[0], {64, 128, 256}) || !one_of(t[1], {64, 128, 256, 512}) || t[2] < 64 || t[2] > 8192 ||
         t[3] < 64 || t[3] > 8192 || t[4] < 1 || t[4] > 64 || !one_of(t[5], {64, 128, 256}) ||
         t[6] < 1 || t[6] > 480 || !one_of(t[7], {0, 16, 32}))
         return fail_code(NSPNP_ERR_INVALID, "launch shapes out of range");

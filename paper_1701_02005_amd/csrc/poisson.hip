@@ -406,6 +406,8 @@ __global__ void __launch_bounds__(256) k_thomas_factors(Dims d, Tables tb, doubl
 // local sweep per lane, a 6-step scan of affine maps across the wave and a
 // second sweep from the correct incoming value.  The tile is written back
 // with coalesced stores.
+constexpr int kThBatch = 8;
+
 template <int R>
 __global__ void __launch_bounds__(256) k_thomas_tile(Dims d, Tables tb, PoissonBatch b, double2 *spec_all,
                                                      const double2 *fac_all, int64_t nspec, int tm) {
@@ -420,9 +422,23 @@ __global__ void __launch_bounds__(256) k_thomas_tile(Dims d, Tables tb, PoissonB
     const int64_t m0 = (int64_t)blk.x * tm;
     const int ncol = (int)((nmodes - m0) < tm ? (nmodes - m0) : tm);
     const int LD = tm + 1;
-    for (int e = threadIdx.x; e < M * tm; e += blockDim.x) {
-        const int j = e / tm, c = e - j * tm;
-        s_x[j * LD + c] = (c < ncol) ? spec[(int64_t)j * nmodes + m0 + c] : make_double2(0.0, 0.0);
+    // Staging in batches of kThBatch unconditional loads per thread (lanes
+    // past the tile read its first mode and discard it): one wait per batch.
+    // Offsets within one spectrum: rows * modes < 2^32 for every supported grid.
+    const unsigned unm = (unsigned)nmodes, um0 = (unsigned)m0;
+    const int ntile = M * tm, bd = (int)blockDim.x;
+    for (int e0 = threadIdx.x; e0 < ntile; e0 += kThBatch * bd) {
+        double2 v[kThBatch];
+#pragma unroll
+        for (int u = 0; u < kThBatch; ++u) {
+            const int e = e0 + u * bd, j = e / tm, c = e - j * tm;
+            v[u] = spec[(e < ntile && c < ncol) ? (unsigned)j * unm + um0 + (unsigned)c : um0];
+        }
+#pragma unroll
+        for (int u = 0; u < kThBatch; ++u) {
+            const int e = e0 + u * bd, j = e / tm, c = e - j * tm;
+            if (e < ntile) s_x[j * LD + c] = (c < ncol) ? v[u] : make_double2(0.0, 0.0);
+        }
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
@@ -434,10 +450,23 @@ __global__ void __launch_bounds__(256) k_thomas_tile(Dims d, Tables tb, PoissonB
         const int j = js + t;
         lo[t] = (j > 0 && j < M) ? tb.lyc_lo[j] : 0.0;
     }
+    // pivots (1/den, c') of a column: unconditional loads (padding rows read
+    // the last row and ignore it); the next column's are fetched while the
+    // current one is solved
+    double2 fnext[R];
+    auto load_pivots = [&](int c, double2 *f) {
+        const double2 *fm = fac + (m0 + c) * M;
+#pragma unroll
+        for (int t = 0; t < R; ++t) f[t] = fm[(js + t < M) ? js + t : M - 1];
+    };
+    if (wave < ncol) load_pivots(wave, fnext);
     for (int c = wave; c < ncol; c += nwave) {
         const int64_t m = m0 + c;
         const bool pin = (kind == 0 && m == 0);
-        const double2 *fm = fac + m * M;
+        double2 fcur[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) fcur[t] = fnext[t];
+        if (c + nwave < ncol) load_pivots(c + nwave, fnext);
         double g[R], mm[R], nn[R];
         double2 x[R];
         double Qs = 1.0, Ss = 1.0;
@@ -445,7 +474,7 @@ __global__ void __launch_bounds__(256) k_thomas_tile(Dims d, Tables tb, PoissonB
         for (int t = 0; t < R; ++t) {
             const int j = js + t;
             if (j < M) {
-                const double2 f = fm[j];
+                const double2 f = fcur[t];
                 g[t] = f.x;
                 mm[t] = -lo[t] * f.x;
                 nn[t] = -f.y;
@@ -549,9 +578,9 @@ __global__ void __launch_bounds__(256) k_thomas_tile(Dims d, Tables tb, PoissonB
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < M * tm; e += blockDim.x) {
+    for (int e = threadIdx.x; e < ntile; e += bd) {
         const int j = e / tm, c = e - j * tm;
-        if (c < ncol) spec[(int64_t)j * nmodes + m0 + c] = s_x[j * LD + c];
+        if (c < ncol) spec[(unsigned)j * unm + um0 + (unsigned)c] = s_x[j * LD + c];
     }
 }
 

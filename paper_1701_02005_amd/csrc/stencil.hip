@@ -472,10 +472,10 @@ __global__ void __launch_bounds__(256) k_cn_coef(Dims d, Tables tb, const Phys *
     }
 }
 
-// columns staged per block (16: one 128-byte line per row in FP64, two FP32
-// tiles share a line; wider FP32 tiles halve the blocks per CU and lose)
-template <typename T>
-constexpr int cn_tile_cols() { return 16; }
+// Columns staged per block: 16 (one 128-byte line per row in FP64; two FP32
+// tiles share a line) for blocks of up to 256 threads, 32 for 512-thread
+// blocks (a whole line per row in FP32 at the same waves per CU).
+inline int cn_tile_cols(int threads) { return threads > 256 ? 32 : 16; }
 
 // Crank-Nicolson solve of one tile of kCnTx columns: the rows of r are staged
 // in LDS with coalesced loads; each wave then solves one column at a time
@@ -483,9 +483,10 @@ constexpr int cn_tile_cols() { return 16; }
 // a local sweep per lane followed by a 6-step scan of affine maps across the
 // wave (x -> T + Q x composed lane by lane) and a second local sweep from the
 // correct incoming value.  Finally q += x with coalesced stores.
-template <typename T, int kCnMaxR>
-__global__ void __launch_bounds__(256) k_cn_scan(CnArgs a) {
-    constexpr int kCnTx = cn_tile_cols<T>();
+constexpr int kCnBatch = 8;
+
+template <typename T, int kCnTx, int kCnMaxR>
+__global__ void __launch_bounds__(512) k_cn_scan(CnArgs a) {
     extern __shared__ double s_r[];
     const uint3 blk = xcd_block3();  // adjacent column tiles share an L2
     const int f = (int)blk.y;
@@ -503,9 +504,25 @@ __global__ void __launch_bounds__(256) k_cn_scan(CnArgs a) {
     const double *__restrict__ cg = coef, *__restrict__ cm = coef + M, *__restrict__ cn = coef + 2 * M;
     constexpr int LD = kCnTx + 1;
     const int nrow = M - j0;
-    for (int e = threadIdx.x; e < nrow * kCnTx; e += blockDim.x) {
-        const int jj = j0 + e / kCnTx, c = e % kCnTx;
-        s_r[jj * LD + c] = (c < ncol) ? r[(int64_t)jj * pl + c0 + c] : 0.0;
+    const int ntile = nrow * kCnTx, bd = (int)blockDim.x;
+    // Staging in batches of kCnBatch unconditional loads per thread (lanes
+    // past the tile read its first element, which exists, and discard it), so
+    // that a thread waits for memory once per batch, not once per element.
+    // (offsets within one field: rows * plane < 2^32 for every supported grid)
+    const unsigned upl = (unsigned)pl, uc0 = (unsigned)c0;
+    const unsigned o_safe = (unsigned)j0 * upl + uc0;
+    for (int e0 = threadIdx.x; e0 < ntile; e0 += kCnBatch * bd) {
+        T v[kCnBatch];
+#pragma unroll
+        for (int u = 0; u < kCnBatch; ++u) {
+            const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
+            v[u] = r[(e < ntile && c < ncol) ? (unsigned)jj * upl + uc0 + (unsigned)c : o_safe];
+        }
+#pragma unroll
+        for (int u = 0; u < kCnBatch; ++u) {
+            const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
+            if (e < ntile) s_r[jj * LD + c] = (c < ncol) ? (double)v[u] : 0.0;
+        }
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
@@ -583,11 +600,17 @@ __global__ void __launch_bounds__(256) k_cn_scan(CnArgs a) {
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < nrow * kCnTx; e += blockDim.x) {
-        const int jj = j0 + e / kCnTx, c = e % kCnTx;
-        if (c < ncol) {
-            const int64_t o = (int64_t)jj * pl + c0 + c;
-            q[o] = (T)((double)q[o] + s_r[jj * LD + c]);
+    for (int e0 = threadIdx.x; e0 < ntile; e0 += kCnBatch * bd) {
+        T v[kCnBatch];
+#pragma unroll
+        for (int u = 0; u < kCnBatch; ++u) {
+            const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
+            v[u] = q[(e < ntile && c < ncol) ? (unsigned)jj * upl + uc0 + (unsigned)c : o_safe];
+        }
+#pragma unroll
+        for (int u = 0; u < kCnBatch; ++u) {
+            const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
+            if (e < ntile && c < ncol) q[(unsigned)jj * upl + uc0 + (unsigned)c] = (T)((double)v[u] + s_r[jj * LD + c]);
         }
     }
 }
@@ -617,12 +640,19 @@ __global__ void __launch_bounds__(256) k_cn_slab_exit(CnArgs a) {
                                       (size_t)sys * 3 * M;
     const double *g = coef, *m = coef + M, *n = coef + 2 * M;
     double *scr = member_ptr_at(a.scr, a.ms, mem);
+    // the slab's rows first, all in flight together (rows past the slab
+    // re-read its last row and are ignored); offsets within one field fit
+    // in 32 bits for every supported grid
+    const unsigned upl = (unsigned)pl, ue = (unsigned)e;
+    T rv[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) rv[t] = r[(unsigned)(j0 + t < j1 ? j0 + t : j1 - 1) * upl + ue];
     double lv[L];
     double l = 0.0;
 #pragma unroll
     for (int t = 0; t < L; ++t) {
         const int j = j0 + t;
-        if (j < j1) l = g[j] * (double)r[(int64_t)j * pl + e] + m[j] * l;
+        if (j < j1) l = g[j] * (double)rv[t] + m[j] * l;
         lv[t] = l;
     }
     double k = 0.0;
@@ -650,18 +680,47 @@ __global__ void __launch_bounds__(256) k_cn_slab_scan(CnArgs a) {
                  *Nu = sl + (3 * sys + 2) * kCnMaxSlabs;
     double *scr = member_ptr_at(a.scr, a.ms, mem);
     double *lam = scr + (int64_t)f * S * pl + e, *kap = scr + (int64_t)(5 + f) * S * pl + e;
+    // batches of 8 slabs: loads first (slabs past the end re-read the last
+    // one and are ignored), multipliers included, then the recurrence and
+    // the stores
+    constexpr int kB = 8;
     double D = 0.0;
-    for (int sb = 0; sb < S; ++sb) {
-        const double ex = lam[(int64_t)sb * pl];
-        lam[(int64_t)sb * pl] = D;
-        D = ex + P[sb] * D;
+    for (int s0 = 0; s0 < S; s0 += kB) {
+        double ex[kB], pb[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const int sb = s0 + u < S ? s0 + u : S - 1;
+            ex[u] = lam[(int64_t)sb * pl];
+            pb[u] = P[sb];
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const int sb = s0 + u;
+            if (sb < S) {
+                lam[(int64_t)sb * pl] = D;
+                D = ex[u] + pb[u] * D;
+            }
+        }
     }
     double X = 0.0;
-    for (int sb = S - 1; sb >= 0; --sb) {
-        const double ex = kap[(int64_t)sb * pl];
-        const double Din = lam[(int64_t)sb * pl];
-        kap[(int64_t)sb * pl] = X;
-        X = ex + Phi[sb] * Din + Nu[sb] * X;
+    for (int s1 = S - 1; s1 >= 0; s1 -= kB) {
+        double ex[kB], din[kB], phb[kB], nub[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const int sb = s1 - u >= 0 ? s1 - u : 0;
+            ex[u] = kap[(int64_t)sb * pl];
+            din[u] = lam[(int64_t)sb * pl];
+            phb[u] = Phi[sb];
+            nub[u] = Nu[sb];
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const int sb = s1 - u;
+            if (sb >= 0) {
+                kap[(int64_t)sb * pl] = X;
+                X = ex[u] + phb[u] * din[u] + nub[u] * X;
+            }
+        }
     }
 }
 
@@ -684,11 +743,21 @@ __global__ void __launch_bounds__(256) k_cn_slab_apply(CnArgs a) {
     const double *scr = member_ptr_at(a.scr, a.ms, mem);
     double d = scr[((int64_t)(f * S + sb)) * pl + e];
     double x = scr[((int64_t)((5 + f) * S + sb)) * pl + e];
+    // r and q of the slab's rows first, all in flight together (rows past the
+    // slab re-read its last row and are ignored)
+    const unsigned upl = (unsigned)pl, ue = (unsigned)e;
+    T rv[L], qv[L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        const unsigned o = (unsigned)(j0 + t < j1 ? j0 + t : j1 - 1) * upl + ue;
+        rv[t] = r[o];
+        qv[t] = q[o];
+    }
     double dv[L];
 #pragma unroll
     for (int t = 0; t < L; ++t) {
         const int j = j0 + t;
-        if (j < j1) d = g[j] * (double)r[(int64_t)j * pl + e] + m[j] * d;
+        if (j < j1) d = g[j] * (double)rv[t] + m[j] * d;
         dv[t] = d;
     }
 #pragma unroll
@@ -696,8 +765,7 @@ __global__ void __launch_bounds__(256) k_cn_slab_apply(CnArgs a) {
         const int j = j0 + t;
         if (j < j1) {
             x = dv[t] + n[j] * x;
-            const int64_t o = (int64_t)j * pl + e;
-            q[o] = (T)((double)q[o] + x);
+            q[(unsigned)j * upl + ue] = (T)((double)qv[t] + x);
         }
     }
 }
@@ -898,11 +966,11 @@ hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
         }
         return hipGetLastError();
     }
-    const int tcols = s->fp64 ? cn_tile_cols<double>() : cn_tile_cols<float>();
+    const int tb = s->tiles.cn;
+    const int tcols = cn_tile_cols(tb);
     const dim3 g((unsigned)((s->d.plane + tcols - 1) / tcols), 5, (unsigned)s->nmem);
     const size_t lds = (size_t)s->d.M * (tcols + 1) * sizeof(double);
     if (lds > (size_t)s->lds_max) return hipErrorInvalidValue;
-    const int tb = s->tiles.cn;
     const int rpl = (s->d.M + 63) / 64;  // rows per lane (M <= 480: at most 8)
     // tiles above 64 KB of LDS (tall columns) use the device's larger limit
     auto launch = [&](const void *fn, auto kernel) -> hipError_t {
@@ -922,8 +990,11 @@ hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
     };
 #define NSPNP_CN_CASE(RR)                                                                              \
     case RR:                                                                                           \
-        return s->fp64 ? launch((const void *)k_cn_scan<double, RR>, k_cn_scan<double, RR>)            \
-                       : launch((const void *)k_cn_scan<float, RR>, k_cn_scan<float, RR>);
+        if (tcols == 32)                                                                               \
+            return s->fp64 ? launch((const void *)k_cn_scan<double, 32, RR>, k_cn_scan<double, 32, RR>) \
+                           : launch((const void *)k_cn_scan<float, 32, RR>, k_cn_scan<float, 32, RR>);  \
+        return s->fp64 ? launch((const void *)k_cn_scan<double, 16, RR>, k_cn_scan<double, 16, RR>)    \
+                       : launch((const void *)k_cn_scan<float, 16, RR>, k_cn_scan<float, 16, RR>);
     switch (rpl) {
         NSPNP_CN_CASE(1)
         NSPNP_CN_CASE(2)

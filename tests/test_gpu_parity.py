@@ -159,15 +159,15 @@ def test_mixed_precision_tracks_oracle(P, O):
     assert abs(tb - otb) < 1e-4 * otb and abs(tt - ott) < 1e-4 * ott
 
 
-@pytest.mark.parametrize("cnslab", [0, 16, 32])
-def test_full_size_turbulent_case_matches_oracle(P, O, cnslab):
+@pytest.mark.parametrize("cnslab,cn", [(0, 256), (0, 512), (16, 256), (32, 256)])
+def test_full_size_turbulent_case_matches_oracle(P, O, cnslab, cn):
     """256x193x256, Re 3000, lam 0.05, vhat 10, adaptive dt (the benchmarked
     case): initial state and one full RK3 step, with each Crank-Nicolson
     method the autotuner can pick (the other launch shapes do not change the
     arithmetic done per cell, line or mode)."""
     O.set_threads(16)
     g, o = make_pair(P, O, P.configs.couette_turbulent(seed=0))
-    g.set_tiles(cnslab=cnslab)
+    g.set_tiles(cnslab=cnslab, cn=cn)
     err0 = worst(g, o)
     note(f"full size, initial state: {max(err0.values()):.3e}")
     assert max(err0.values()) < 1e-12, err0

@@ -94,6 +94,15 @@ __device__ __forceinline__ P *member_ptr_at(P *p, size_t stride, unsigned member
     return (P *)((char *)p + (size_t)member * stride);
 }
 
+// A block-uniform element of a read-only table (grid metrics), read through
+// the scalar cache: the load is counted apart from the vector memory loads,
+// so using its value never waits for vector loads still in flight (vector
+// loads retire in issue order).  i must be the same in every lane.
+__device__ __forceinline__ double uniform_load(const double *p, int i) {
+    typedef const __attribute__((address_space(4))) double cdouble;
+    return ((cdouble *)p)[__builtin_amdgcn_readfirstlane(i)];
+}
+
 // Per-row quantities of the plane reduction (k_plane), kPlaneQ per row.
 enum PlaneQ {
     PQ_SUM_U = 0, PQ_SUM_CP, PQ_SUM_CM,  // plane sums of u, c+, c-

@@ -452,7 +452,8 @@ __global__ void __launch_bounds__(256) k_thomas_tile(Dims d, Tables tb, PoissonB
     }
     // pivots (1/den, c') of a column: unconditional loads (padding rows read
     // the last row and ignore it); the next column's are fetched while the
-    // current one is solved
+    // current one is solved, unconditionally (the wave's last column re-reads
+    // its own) so that the wait for the current pivots stays partial
     double2 fnext[R];
     auto load_pivots = [&](int c, double2 *f) {
         const double2 *fm = fac + (m0 + c) * M;
@@ -466,7 +467,7 @@ __global__ void __launch_bounds__(256) k_thomas_tile(Dims d, Tables tb, PoissonB
         double2 fcur[R];
 #pragma unroll
         for (int t = 0; t < R; ++t) fcur[t] = fnext[t];
-        if (c + nwave < ncol) load_pivots(c + nwave, fnext);
+        load_pivots(c + nwave < ncol ? c + nwave : c, fnext);
         double g[R], mm[R], nn[R];
         double2 x[R];
         double Qs = 1.0, Ss = 1.0;

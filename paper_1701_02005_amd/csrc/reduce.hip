@@ -62,6 +62,8 @@ constexpr int kRedThreads = 256;
 // [0] max CFL rate, [1] max(c+ + c-), [2] min(c+, c-), [3] 1 if any value is
 // not finite, [4] max |dPhi| across the cell's x, z and upper y faces.  All
 // five are maxima or minima, so the result does not depend on the order.
+constexpr int kDtRows = 4;  // rows per load batch of k_dt_partial
+
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads) k_dt_partial(Dims d, Tables tb, const Phys *phys, const T *u,
                                                             const T *v, const T *w, const T *cp, const T *cm,
@@ -83,26 +85,56 @@ __global__ void __launch_bounds__(kRedThreads) k_dt_partial(Dims d, Tables tb, c
         const int64_t exp_ = e - i + ((i + 1 == d.nx) ? 0 : i + 1);
         const int64_t ezp = e + (int64_t)(((k + 1 == d.nz) ? 0 : k + 1) - k) * d.nx;
         double v0 = (double)v[(int64_t)j0 * pl + e], f0 = (double)phi[(int64_t)j0 * pl + e];
-        for (int j = j0; j < j1; ++j) {
-            const int64_t q = (int64_t)j * pl + e, row = (int64_t)j * pl;
-            const bool top = j + 1 < d.M;
-            const double v1 = top ? (double)v[q + pl] : 0.0;
-            const double f1 = top ? (double)phi[q + pl] : 0.0;
-            const double u0 = (double)u[q], w0 = (double)w[q];
-            const double c1 = (double)cp[q], c2 = (double)cm[q];
-            const double uc = 0.5 * (u0 + (double)u[row + exp_]);
-            const double vc = 0.5 * (v0 + v1);
-            const double wc = 0.5 * (w0 + (double)w[row + ezp]);
-            rate = fmax(rate, fabs(uc) / d.dx + fabs(vc) / tb.dn[j] + fabs(wc) / d.dz);
-            cmax = fmax(cmax, c1 + c2);
-            cmin = fmin(cmin, fmin(c1, c2));
-            bad = bad || !__builtin_isfinite(u0) || !__builtin_isfinite(v0) || !__builtin_isfinite(w0) ||
-                  !__builtin_isfinite(c1) || !__builtin_isfinite(c2) || !__builtin_isfinite(f0);
-            double dphi = fmax(fabs((double)phi[row + exp_] - f0), fabs((double)phi[row + ezp] - f0));
-            if (top) dphi = fmax(dphi, fabs(f1 - f0 + e0 * tb.dc[j + 1]));
-            pe = fmax(pe, dphi);
-            v0 = v1;
-            f0 = f1;
+        // Rows are reduced in batches of kDtRows: the batch's loads are all
+        // issued before any is used (rows past the slab re-read its last row
+        // and are ignored), one memory latency per batch.  Offsets within
+        // one field fit in 32 bits.
+        const unsigned upl = (unsigned)pl, ue = (unsigned)e, uxp = (unsigned)exp_, uzp = (unsigned)ezp;
+        struct RowVals {
+            T v1, f1, u0, w0, c1, c2, ux, wz, fx, fz;
+        };
+        auto load_row = [&](int j, RowVals &r) {
+            const unsigned row = (unsigned)j * upl, q = row + ue;
+            const unsigned qt = (j + 1 < d.M) ? q + upl : q;
+            r.v1 = v[qt];
+            r.f1 = phi[qt];
+            r.u0 = u[q];
+            r.w0 = w[q];
+            r.c1 = cp[q];
+            r.c2 = cm[q];
+            r.ux = u[row + uxp];
+            r.wz = w[row + uzp];
+            r.fx = phi[row + uxp];
+            r.fz = phi[row + uzp];
+        };
+        for (int jb = j0; jb < j1; jb += kDtRows) {
+            RowVals rb[kDtRows];
+#pragma unroll
+            for (int t = 0; t < kDtRows; ++t) load_row(jb + t < j1 ? jb + t : j1 - 1, rb[t]);
+#pragma unroll
+            for (int t = 0; t < kDtRows; ++t) {
+                const int j = jb + t;
+                if (j >= j1) break;
+                const RowVals &cur = rb[t];
+                const bool top = j + 1 < d.M;
+                const double v1 = top ? (double)cur.v1 : 0.0;
+                const double f1 = top ? (double)cur.f1 : 0.0;
+                const double u0 = (double)cur.u0, w0 = (double)cur.w0;
+                const double c1 = (double)cur.c1, c2 = (double)cur.c2;
+                const double uc = 0.5 * (u0 + (double)cur.ux);
+                const double vc = 0.5 * (v0 + v1);
+                const double wc = 0.5 * (w0 + (double)cur.wz);
+                rate = fmax(rate, fabs(uc) / d.dx + fabs(vc) / uniform_load(tb.dn, j) + fabs(wc) / d.dz);
+                cmax = fmax(cmax, c1 + c2);
+                cmin = fmin(cmin, fmin(c1, c2));
+                bad = bad || !__builtin_isfinite(u0) || !__builtin_isfinite(v0) || !__builtin_isfinite(w0) ||
+                      !__builtin_isfinite(c1) || !__builtin_isfinite(c2) || !__builtin_isfinite(f0);
+                double dphi = fmax(fabs((double)cur.fx - f0), fabs((double)cur.fz - f0));
+                if (top) dphi = fmax(dphi, fabs(f1 - f0 + e0 * uniform_load(tb.dc, j + 1)));
+                pe = fmax(pe, dphi);
+                v0 = v1;
+                f0 = f1;
+            }
         }
     }
     s[0][threadIdx.x] = rate;

@@ -192,8 +192,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
         const bool has_up = (j + 1 < M), has_dn = (j > 0);
         const int q = j * pl + e;
         if (active) {
-            const T idn = T(a.tb.idn[j]);
-            const T idcb = T(a.tb.idc[j]), idct = T(a.tb.idc[j + 1]);
+            const T idn = T(uniform_load(a.tb.idn, j));
+            const T idcb = T(uniform_load(a.tb.idc, j)), idct = T(uniform_load(a.tb.idc, j + 1));
             const T uc = X(sc, 0, 0, 0), vc = X(sc, 1, 0, 0), wc = X(sc, 2, 0, 0);
             const T ac = X(sc, 3, 0, 0), bc = X(sc, 4, 0, 0), ph0 = X(sc, 5, 0, 0), pc = X(sc, 6, 0, 0);
             const T up_ = has_up ? X(sn, 0, 0, 0) : zero, vp = has_up ? X(sn, 1, 0, 0) : zero;
@@ -264,8 +264,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
             __builtin_amdgcn_sched_barrier(0);
             // ---------------- v on the bottom y-face of row j ----------------
             if (has_dn) {
-                const T vwl = T(a.tb.vwl[j]), vwu = T(a.tb.vwu[j]);
-                const T idn_lo = T(a.tb.idn[j - 1]);
+                const T vwl = T(uniform_load(a.tb.vwl, j)), vwu = T(uniform_load(a.tb.vwu, j));
+                const T idn_lo = T(uniform_load(a.tb.idn, j - 1));
                 const T vtop = has_up ? vp : T(0);
                 const T vbot = (j > 1) ? vm : T(0);
                 const T a1 = half * (vtop + vc), a2 = half * (vc + vbot);
@@ -822,19 +822,41 @@ __global__ void __launch_bounds__(256) k_correct(CorrArgs a) {
     const double idx = 1.0 / d.dx, idz = 1.0 / d.dz;
     double s_dn = (j0 > 0) ? psi[(int64_t)(j0 - 1) * pl + e] : 0.0;  // psi of row j - 1
     double s0 = psi[(int64_t)j0 * pl + e];
+    // Row j + 1's values are loaded before row j is computed and stored, so
+    // their latency overlaps a row of work.  The load is unconditional (the
+    // slab's last row re-reads itself), which keeps the wait for the current
+    // row's values partial.  Offsets within one field fit in 32 bits.
+    const unsigned upl = (unsigned)pl;
+    struct RowVals {
+        double s_up, sxm, szm;
+        T u, v, w, p;
+    };
+    auto load_row = [&](int j, RowVals &r) {
+        const unsigned row = (unsigned)j * upl, q = row + (unsigned)e;
+        r.s_up = psi[(j + 1 < M) ? q + upl : q];
+        r.sxm = psi[row + (unsigned)exm];
+        r.szm = psi[row + (unsigned)ezm];
+        r.u = u[q];
+        r.w = w[q];
+        r.v = v[q];
+        r.p = a.update_p ? p[q] : T(0);
+    };
+    RowVals nxt;
+    load_row(j0, nxt);
     for (int j = j0; j < j1; ++j) {
-        const int64_t row = (int64_t)j * pl, q = row + e;
-        const double s_up = (j + 1 < M) ? psi[q + pl] : 0.0;
-        const double sxm = psi[row + exm], szm = psi[row + ezm];
-        u[q] = (T)((double)u[q] - sc * (s0 - sxm) * idx);
-        w[q] = (T)((double)w[q] - sc * (s0 - szm) * idz);
-        const double idcb = a.tb.idc[j];
-        if (j > 0) v[q] = (T)((double)v[q] - sc * (s0 - s_dn) * idcb);
+        const RowVals cur = nxt;
+        load_row(j + 1 < j1 ? j + 1 : j, nxt);
+        const unsigned q = (unsigned)j * upl + (unsigned)e;
+        const double s_up = (j + 1 < M) ? cur.s_up : 0.0;
+        u[q] = (T)((double)cur.u - sc * (s0 - cur.sxm) * idx);
+        w[q] = (T)((double)cur.w - sc * (s0 - cur.szm) * idz);
+        const double idcb = uniform_load(a.tb.idc, j);
+        if (j > 0) v[q] = (T)((double)cur.v - sc * (s0 - s_dn) * idcb);
         if (a.update_p) {
-            const double ft = (j + 1 < M) ? (s_up - s0) * a.tb.idc[j + 1] : 0.0;
+            const double ft = (j + 1 < M) ? (s_up - s0) * uniform_load(a.tb.idc, j + 1) : 0.0;
             const double fb = (j > 0) ? (s0 - s_dn) * idcb : 0.0;
-            const double ly = (ft - fb) * a.tb.idn[j];
-            p[q] = (T)((double)p[q] + s0 - 0.5 * sc * ire * ly);
+            const double ly = (ft - fb) * uniform_load(a.tb.idn, j);
+            p[q] = (T)((double)cur.p + s0 - 0.5 * sc * ire * ly);
         }
         s_dn = s0;
         s0 = s_up;

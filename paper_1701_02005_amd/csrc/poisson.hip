@@ -139,26 +139,102 @@ __device__ __forceinline__ void stage_twiddles(double2 *s_tw, const double2 *tw,
 // The right-hand side of each line is produced while it is loaded: a plain
 // FP64 array, the divergence of the staggered velocity (pressure), or the
 // charge -(c+ - c-)/(2 lam^2) (potential).
-template <typename T>
-__device__ __forceinline__ double line_value(const PoissonSrc &src, const Dims &d, const Tables &tb, double ch,
-                                             double sc, double idx, double idz, int64_t line, int i) {
-    const int64_t q = line * d.nx + i;
-    if (src.type == SRC_REAL) return ((const double *)src.a)[q];
-    if (src.type == SRC_CHARGE) {
-        const T *cp = (const T *)src.a, *cm = (const T *)src.b;
-        return ch * ((double)cp[q] - (double)cm[q]);
+// The line pairs of an x-transform block into LDS, as (line 2p, line 2p+1)
+// complex values, for one source type S (block-uniform).  Each batch of kXB
+// elements per thread issues all of its loads before any value is formed
+// (elements past the block or lines past the grid read element 0 of line 0
+// and are dropped), so a thread waits for memory once per batch.  Offsets
+// within one field fit in 32 bits.
+constexpr int kXB = 2;
+
+template <typename T, int S>
+__device__ __forceinline__ void r2c_stage(const PoissonSrc &src, const Dims &d, const Tables &tb, double ch,
+                                          double sc, double idx, double idz, int64_t pair0, int ppb, double2 *buf) {
+    const int nx = d.nx, nz = d.nz, M = d.M, n = ppb * nx, bd = (int)blockDim.x;
+    const int64_t nlines = (int64_t)M * nz;
+    const unsigned upl = (unsigned)d.plane;
+    for (int e0 = threadIdx.x; e0 < n; e0 += kXB * bd) {
+        unsigned q[kXB][2];
+        bool ok[kXB][2];
+        int jr[kXB][2];
+#pragma unroll
+        for (int u = 0; u < kXB; ++u) {
+            const int e = e0 + u * bd, p = e / nx, i = e - p * nx;
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+                const int64_t line = 2 * (pair0 + p) + l;
+                ok[u][l] = e < n && line < nlines;
+                q[u][l] = ok[u][l] ? (unsigned)line * (unsigned)nx + (unsigned)i : 0u;
+                jr[u][l] = ok[u][l] ? (int)(line / nz) : 0;
+            }
+        }
+        double val[kXB][2];
+        if constexpr (S == SRC_REAL) {
+            const double *a = (const double *)src.a;
+            double x[kXB][2];
+#pragma unroll
+            for (int u = 0; u < kXB; ++u)
+#pragma unroll
+                for (int l = 0; l < 2; ++l) x[u][l] = a[q[u][l]];
+#pragma unroll
+            for (int u = 0; u < kXB; ++u)
+#pragma unroll
+                for (int l = 0; l < 2; ++l) val[u][l] = x[u][l];
+        } else if constexpr (S == SRC_CHARGE) {
+            const T *cp = (const T *)src.a, *cm = (const T *)src.b;
+            T xp[kXB][2], xm[kXB][2];
+#pragma unroll
+            for (int u = 0; u < kXB; ++u)
+#pragma unroll
+                for (int l = 0; l < 2; ++l) {
+                    xp[u][l] = cp[q[u][l]];
+                    xm[u][l] = cm[q[u][l]];
+                }
+#pragma unroll
+            for (int u = 0; u < kXB; ++u)
+#pragma unroll
+                for (int l = 0; l < 2; ++l) val[u][l] = ch * ((double)xp[u][l] - (double)xm[u][l]);
+        } else {
+            // divergence: (u_{i+1} - u_i)/dx + (v_{j+1} - v_j)/dy_j + (w_{k+1} - w_k)/dz, times sc
+            const T *uu = (const T *)src.a, *vv = (const T *)src.b, *ww = (const T *)src.c;
+            T ux[kXB][2], u0[kXB][2], vt[kXB][2], vb[kXB][2], wz[kXB][2], w0[kXB][2];
+            double idn[kXB][2];
+#pragma unroll
+            for (int u = 0; u < kXB; ++u)
+#pragma unroll
+                for (int l = 0; l < 2; ++l) {
+                    const unsigned qq = q[u][l];
+                    const int j = jr[u][l];
+                    const unsigned line = qq / (unsigned)nx, i = qq - line * (unsigned)nx;
+                    const unsigned k = line - (unsigned)j * (unsigned)nz;
+                    const unsigned xp = qq - i + ((i + 1 == (unsigned)nx) ? 0u : i + 1);
+                    const unsigned zp = qq + ((k + 1 == (unsigned)nz) ? 0u : k + 1) * (unsigned)nx - k * (unsigned)nx;
+                    ux[u][l] = uu[xp];
+                    u0[u][l] = uu[qq];
+                    vt[u][l] = vv[(j + 1 < M) ? qq + upl : qq];
+                    vb[u][l] = vv[qq];
+                    wz[u][l] = ww[zp];
+                    w0[u][l] = ww[qq];
+                    idn[u][l] = tb.idn[j];
+                }
+#pragma unroll
+            for (int u = 0; u < kXB; ++u)
+#pragma unroll
+                for (int l = 0; l < 2; ++l) {
+                    const int j = jr[u][l];
+                    const double t = (j + 1 < M) ? (double)vt[u][l] : 0.0;
+                    const double b = (j > 0) ? (double)vb[u][l] : 0.0;
+                    const double div = ((double)ux[u][l] - (double)u0[u][l]) * idx + (t - b) * idn[u][l] +
+                                       ((double)wz[u][l] - (double)w0[u][l]) * idz;
+                    val[u][l] = div * sc;
+                }
+        }
+#pragma unroll
+        for (int u = 0; u < kXB; ++u) {
+            const int e = e0 + u * bd;
+            if (e < n) buf[e] = make_double2(ok[u][0] ? val[u][0] : 0.0, ok[u][1] ? val[u][1] : 0.0);
+        }
     }
-    // divergence: (u_{i+1} - u_i)/dx + (v_{j+1} - v_j)/dy_j + (w_{k+1} - w_k)/dz, times sc
-    const T *u = (const T *)src.a, *v = (const T *)src.b, *w = (const T *)src.c;
-    const int j = (int)(line / d.nz);
-    const int k = (int)(line - (int64_t)j * d.nz);
-    const int64_t xp = q - i + ((i + 1 == d.nx) ? 0 : i + 1);
-    const int64_t zp = q + (int64_t)(((k + 1 == d.nz) ? 0 : k + 1) - k) * d.nx;
-    const double vt = (j + 1 < d.M) ? (double)v[q + d.plane] : 0.0;
-    const double vb = (j > 0) ? (double)v[q] : 0.0;
-    const double div = ((double)u[xp] - (double)u[q]) * idx + (vt - vb) * tb.idn[j] +
-                       ((double)w[zp] - (double)w[q]) * idz;
-    return div * sc;
 }
 
 // Slots of each of the two FFT buffers of an x-transform block; the [kx][line]
@@ -185,14 +261,13 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
     stage_twiddles(s_tw, tb.twx, nx);
     const double sc = (src.type == SRC_DIV) ? ((src.alp > 0.0) ? 1.0 / (src.alp * clock[1]) : src.fixed) : 0.0;
     const double idx = 1.0 / d.dx, idz = 1.0 / d.dz;
-    const int64_t pair0 = (int64_t)blockIdx.x * ppb;
-    for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
-        const int p = e / nx, i = e - p * nx;
-        const int64_t la = 2 * (pair0 + p), lb = la + 1;
-        const double re = (la < nlines) ? line_value<T>(src, d, tb, ch, sc, idx, idz, la, i) : 0.0;
-        const double im = (lb < nlines) ? line_value<T>(src, d, tb, ch, sc, idx, idz, lb, i) : 0.0;
-        bf[0][e] = make_double2(re, im);
-    }
+    // XCD-aware block order: the pairs whose spectra share 128-byte lines of a
+    // [j][kx][kz] row run on one XCD, so their partial-line stores merge in
+    // that XCD's L2 before they reach memory
+    const int64_t pair0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * ppb;
+    if (src.type == SRC_DIV) r2c_stage<T, SRC_DIV>(src, d, tb, ch, sc, idx, idz, pair0, ppb, bf[0]);
+    else if (src.type == SRC_CHARGE) r2c_stage<T, SRC_CHARGE>(src, d, tb, ch, sc, idx, idz, pair0, ppb, bf[0]);
+    else r2c_stage<T, SRC_REAL>(src, d, tb, ch, sc, idx, idz, pair0, ppb, bf[0]);
     __syncthreads();
     const int w = lds_fft(bf[0], bf[1], nx, ppb, pl, s_tw, false);
     const double2 *z = bf[w];

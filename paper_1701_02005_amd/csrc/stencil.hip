@@ -790,6 +790,8 @@ struct CorrArgs {
     int tx, tz, ntx, chunks, slabs, slab_rows;
 };
 
+constexpr int kCorrRows = 4;  // rows per load batch of k_correct
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_correct(CorrArgs a) {
     const Dims &d = a.d;
@@ -822,10 +824,10 @@ __global__ void __launch_bounds__(256) k_correct(CorrArgs a) {
     const double idx = 1.0 / d.dx, idz = 1.0 / d.dz;
     double s_dn = (j0 > 0) ? psi[(int64_t)(j0 - 1) * pl + e] : 0.0;  // psi of row j - 1
     double s0 = psi[(int64_t)j0 * pl + e];
-    // Row j + 1's values are loaded before row j is computed and stored, so
-    // their latency overlaps a row of work.  The load is unconditional (the
-    // slab's last row re-reads itself), which keeps the wait for the current
-    // row's values partial.  Offsets within one field fit in 32 bits.
+    // Rows are corrected in batches of kCorrRows: the batch's loads are all
+    // issued before any result is stored (rows past the slab re-read its last
+    // row and are ignored), one memory latency per batch.  Offsets within one
+    // field fit in 32 bits.
     const unsigned upl = (unsigned)pl;
     struct RowVals {
         double s_up, sxm, szm;
@@ -839,27 +841,32 @@ __global__ void __launch_bounds__(256) k_correct(CorrArgs a) {
         r.u = u[q];
         r.w = w[q];
         r.v = v[q];
-        r.p = a.update_p ? p[q] : T(0);
+        r.p = p[q];  // unconditional (p is always allocated): no branch in the batch
     };
-    RowVals nxt;
-    load_row(j0, nxt);
-    for (int j = j0; j < j1; ++j) {
-        const RowVals cur = nxt;
-        load_row(j + 1 < j1 ? j + 1 : j, nxt);
-        const unsigned q = (unsigned)j * upl + (unsigned)e;
-        const double s_up = (j + 1 < M) ? cur.s_up : 0.0;
-        u[q] = (T)((double)cur.u - sc * (s0 - cur.sxm) * idx);
-        w[q] = (T)((double)cur.w - sc * (s0 - cur.szm) * idz);
-        const double idcb = uniform_load(a.tb.idc, j);
-        if (j > 0) v[q] = (T)((double)cur.v - sc * (s0 - s_dn) * idcb);
-        if (a.update_p) {
-            const double ft = (j + 1 < M) ? (s_up - s0) * uniform_load(a.tb.idc, j + 1) : 0.0;
-            const double fb = (j > 0) ? (s0 - s_dn) * idcb : 0.0;
-            const double ly = (ft - fb) * uniform_load(a.tb.idn, j);
-            p[q] = (T)((double)cur.p + s0 - 0.5 * sc * ire * ly);
+    for (int jb = j0; jb < j1; jb += kCorrRows) {
+        RowVals rb[kCorrRows];
+#pragma unroll
+        for (int t = 0; t < kCorrRows; ++t) load_row(jb + t < j1 ? jb + t : j1 - 1, rb[t]);
+#pragma unroll
+        for (int t = 0; t < kCorrRows; ++t) {
+            const int j = jb + t;
+            if (j >= j1) break;
+            const RowVals &cur = rb[t];
+            const unsigned q = (unsigned)j * upl + (unsigned)e;
+            const double s_up = (j + 1 < M) ? cur.s_up : 0.0;
+            u[q] = (T)((double)cur.u - sc * (s0 - cur.sxm) * idx);
+            w[q] = (T)((double)cur.w - sc * (s0 - cur.szm) * idz);
+            const double idcb = uniform_load(a.tb.idc, j);
+            if (j > 0) v[q] = (T)((double)cur.v - sc * (s0 - s_dn) * idcb);
+            if (a.update_p) {
+                const double ft = (j + 1 < M) ? (s_up - s0) * uniform_load(a.tb.idc, j + 1) : 0.0;
+                const double fb = (j > 0) ? (s0 - s_dn) * idcb : 0.0;
+                const double ly = (ft - fb) * uniform_load(a.tb.idn, j);
+                p[q] = (T)((double)cur.p + s0 - 0.5 * sc * ire * ly);
+            }
+            s_dn = s0;
+            s0 = s_up;
         }
-        s_dn = s0;
-        s0 = s_up;
     }
 }
 

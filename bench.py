@@ -178,7 +178,9 @@ def main():
             from paper_1701_02005_amd import pmc_traffic
             ent = json.loads(tr_file.read_text()).get(f"{args.workload}/{args.precision}/{dom}")
             src = Path(ent["source"]).name if ent else None
-            if ent and ent.get("source_sha256") == pmc_traffic.source_hash(src):
+            cn_slab = bool(tiles and tiles.get("cnslab"))
+            same_kernels = ent and tuple(ent.get("kernels", ())) == tuple(pmc_traffic.class_kernels(dom, cn_slab))
+            if same_kernels and ent.get("source_sha256") == pmc_traffic.source_hash(src):
                 traffic = ent["bytes_per_launch"]
         except (ValueError, OSError, KeyError):
             traffic = None

@@ -32,7 +32,7 @@ CSRC = "paper_1701_02005_amd/csrc"
 CLASSES = {
     "dt": (("k_dt_partial", "k_dt_final"), "reduce.hip"),
     "explicit_rhs": (("k_explicit",), "stencil.hip"),
-    "cn_tridiag": (("k_cn_coef", "k_cn_scan"), "stencil.hip"),
+    "cn_tridiag": (("k_cn_coef", "k_cn_scan"), "stencil.hip"),  # lane-scan method
     "fft_x_r2c": (("k_fft_x_r2c",), "poisson.hip"),
     "fft_z_fwd": (("k_fft_z",), "poisson.hip"),
     "thomas_modes": (("k_thomas_tile",), "poisson.hip"),
@@ -40,6 +40,16 @@ CLASSES = {
     "fft_x_c2r": (("k_fft_x_c2r",), "poisson.hip"),
     "correct": (("k_correct",), "stencil.hip"),
 }
+
+# the same class under the row-slab Crank-Nicolson method (three passes)
+CN_SLAB_KERNELS = ("k_cn_coef", "k_cn_slab_exit", "k_cn_slab_scan", "k_cn_slab_apply")
+
+
+def class_kernels(cls: str, cn_slab: bool = False):
+    """HIP kernels that one launch of a profiler class runs."""
+    if cls == "cn_tridiag" and cn_slab:
+        return CN_SLAB_KERNELS
+    return CLASSES[cls][0]
 
 
 def source_hash(fname: str) -> str:
@@ -90,6 +100,8 @@ def main(argv=None):
     per_kernel, ff, fw = traffic(a.fetch, a.write, a.copy_mb)
     table = json.loads(a.out.read_text()) if a.out.exists() else {}
     for cls, (kernels, src) in CLASSES.items():
+        if cls == "cn_tridiag" and all(k in per_kernel for k in CN_SLAB_KERNELS):
+            kernels = CN_SLAB_KERNELS
         if not all(k in per_kernel for k in kernels):
             continue
         fb = sum(per_kernel[k][0] for k in kernels)

@@ -270,8 +270,11 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
     else r2c_stage<T, SRC_REAL>(src, d, tb, ch, sc, idx, idz, pair0, ppb, bf[0]);
     __syncthreads();
     const int w = lds_fft(bf[0], bf[1], nx, ppb, pl, s_tw, false);
-    const double2 *z = bf[w];
-    double2 *o = bf[1 - w];  // [kk][line] staging for the transposed store
+    // (offsets from the LDS base rather than bf[w]: a pointer picked from an
+    // array at run time loses its address space and becomes a flat access,
+    // which would also wait for every vector load in flight)
+    const double2 *z = sm + w * bs;
+    double2 *o = sm + (1 - w) * bs;  // [kk][line] staging for the transposed store
     const int nl2 = 2 * ppb;
     for (int e = threadIdx.x; e < ppb * nxh; e += blockDim.x) {
         const int p = e / nxh, kk = e - p * nxh;
@@ -360,7 +363,7 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
             bf[0][e] = make_double2(A.x - B.y, A.y + B.x);  // Z = A + i B
         }
         __syncthreads();
-        const double2 *z = bf[lds_fft(bf[0], bf[1], nx, ppb, pl, s_tw, true)];
+        const double2 *z = sm + lds_fft(bf[0], bf[1], nx, ppb, pl, s_tw, true) * bs;  // LDS base offset: no flat access
         for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
             const int p = e / nx, i = e - p * nx;
             const int64_t la = 2 * (pair0 + p), lb = la + 1;
@@ -424,7 +427,7 @@ __global__ void __launch_bounds__(256) k_fft_z(Dims d, FftPlan pl, const double2
         }
         __syncthreads();
         if (t + (int)gridDim.x < ntiles) load(t + gridDim.x);  // lands during the passes
-        const double2 *z = bf[lds_fft(bf[0], bf[1], nz, tk, pl, s_tw, inverse != 0)];
+        const double2 *z = sm + lds_fft(bf[0], bf[1], nz, tk, pl, s_tw, inverse != 0) * (tk * nz);  // no flat access
         for (int e = threadIdx.x; e < nt * nz; e += blockDim.x) base[e] = z[e];
         __syncthreads();  // bf[0] and the result buffer are reused by the next tile
     }

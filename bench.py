@@ -56,6 +56,7 @@ def kernel_bytes(cfg, name: str, launches: int, substeps: int) -> float:
         "fft_x_c2r": 2 * sp + 8 + w,
         "correct": 8 + 8 * w,
         "dt": 6 * w,
+        "stats": 7 * w,  # run statistics: one read of the seven fields per sample
     }.get(name, 0.0)
     return per * n * launches
 
@@ -90,6 +91,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the library's default launch shapes instead of the autotuned ones")
+    ap.add_argument("--stats-every", type=int, default=0,
+                    help="also sample the run statistics every N substeps in the timed regions "
+                         "(a separate measurement; the default line has no sampling)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="before timing, run one plain device-to-device copy of this many MiB (a "
                          "reference kernel of known traffic for hardware byte counters)")
@@ -126,6 +130,8 @@ def main():
     if not args.no_autotune:  # launch shapes by the library's autotuner (advances the run)
         tiles = solver.autotune(None, 30)
         print(f"[bench] autotuned launch shapes {tiles}", file=sys.stderr, flush=True)
+    if args.stats_every > 0:
+        solver.stats_begin(args.stats_every)
     solver.step(args.warmup)
     torch.cuda.synchronize()
     print(f"[bench] warmup {args.warmup} substeps done", file=sys.stderr, flush=True)
@@ -202,7 +208,7 @@ def main():
         "config": {"workload": f"{args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz} Re={cfg.re:g} "
                                f"debye={cfg.debye:g} vhat={cfg.vhat:g} {args.precision}",
                    "points": cfg.points, "cells": cfg.cells, "precision": args.precision,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", **({"stats_every": args.stats_every} if args.stats_every else {})},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes/launch",
                      "algorithmic_bytes_per_launch": per_launch_bytes,

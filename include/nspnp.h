@@ -189,13 +189,38 @@ NSPNP_API int nspnp_diagnostics(nspnp_state *s, double out[6]);
 NSPNP_API int nspnp_get_clock(nspnp_state *s, double *t, double *dt, int32_t *stage, int64_t *substeps);
 NSPNP_API int nspnp_set_clock(nspnp_state *s, double t, double dt, int32_t stage, int64_t substeps);
 
+/* Run statistics: the time averages behind the mean and RMS profiles and
+ * the friction coefficient of the turbulent runs (Sec. III).  Every sample
+ * adds, for each of the M = ny - 1 rows, the plane (x-z) means of
+ * u, v, w, c+, c-, phi, p and of their squares, weighted by the time elapsed
+ * since the previous sample (or since nspnp_stats_begin).  Cell rows for all
+ * fields except v, whose row j is its node row j (the lower face of cell
+ * row j); phi is the potential perturbation (Phi = phi + vhat y / 2).
+ *
+ * nspnp_stats_begin(s, every): every > 0 clears the statistics, takes the
+ * current time as the start and samples at the end of every substep whose
+ * count (after it) is a multiple of every; every = 0 stops sampling and
+ * keeps the sums.  Asynchronous.  nspnp_set_clock does not touch the
+ * statistics: call nspnp_stats_begin again after a clock change.
+ *
+ * nspnp_stats_read: *time (NULL allowed) receives the averaged time span,
+ * *samples (NULL allowed) the number of samples, and out (NULL or
+ * 14 * M doubles) the averages as out[q * M + j], q = 0..6 the means of
+ * u, v, w, c+, c-, phi, p and q = 7..13 the means of their squares (all 0
+ * before the first sample).  RMS profiles are sqrt(out[7+q] - out[q]^2).
+ * Synchronises. */
+NSPNP_API int nspnp_stats_begin(nspnp_state *s, int32_t every);
+NSPNP_API int nspnp_stats_read(nspnp_state *s, double *time, int64_t *samples, double *out);
+
 /* Checkpoint of a run: the seven fields and the five explicit-term buffers
  * H (kept between the stages of a Runge-Kutta step) in the storage type,
- * the clock and the substep count, written to the file at path as a small
- * header followed by raw little-endian arrays.  nspnp_load restores it into
- * a handle initialised with the same configuration (seed and noise
- * amplitudes may differ); the run then continues bit for bit as the saved
- * one would have.  Time statistics of ensembles are not part of it.  Both
+ * the clock, the substep count and the run statistics with their sampling
+ * interval, written to the file at path as a small header followed by raw
+ * little-endian arrays.  nspnp_load restores it into a handle initialised
+ * with the same configuration (seed and noise amplitudes may differ); the
+ * run, and its statistics, then continue bit for bit as the saved one
+ * would have.  Files of the first format (no statistics) still load, with
+ * sampling off.  Time statistics of ensembles are not part of it.  Both
  * synchronise; NSPNP_ERR_INVALID for an unreadable, foreign or mismatching
  * file. */
 NSPNP_API int nspnp_save(nspnp_state *s, const char *path);

@@ -123,6 +123,8 @@ def load_library() -> ctypes.CDLL:
                                  ctypes.POINTER(ctypes.c_int64)]),
         "nspnp_set_clock": (_I, [_P, _D, _D, ctypes.c_int32, ctypes.c_int64]),
         "nspnp_sync": (_I, [_P]),
+        "nspnp_stats_begin": (_I, [_P, ctypes.c_int32]),
+        "nspnp_stats_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D)]),
         "nspnp_save": (_I, [_P, ctypes.c_char_p]),
         "nspnp_autotune": (_I, [_P, ctypes.c_char_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
         "nspnp_get_tiles": (_I, [_P, ctypes.POINTER(ctypes.c_int32)]),
@@ -174,6 +176,32 @@ def load_library() -> ctypes.CDLL:
 
 
 DIAGNOSTIC_NAMES = ("ke", "max_div", "min_cp", "min_cm", "max_csum", "max_dphi")
+STATS_FIELDS = ("u", "v", "w", "cp", "cm", "phi", "p")
+STATS_NAMES = STATS_FIELDS + tuple(f + "2" for f in STATS_FIELDS)
+
+
+def derived_statistics(cfg, T: float, samples: int, st: Dict[str, list]) -> Dict[str, object]:
+    """Mean and RMS profiles, wall shear stresses, c_f, Re_tau and wall units
+    from time-averaged plane means (see Solver.statistics)."""
+    import math
+    yn, yc = grid(cfg)
+    M = cfg.ny - 1
+    dn0, dn1 = yn[1] - yn[0], yn[M] - yn[M - 1]
+    ire = 1.0 / cfg.re
+    u = st["u"]
+    tau_b = ire * (u[0] - cfg.u_bot) / (0.5 * dn0)
+    tau_t = ire * (cfg.u_top - u[M - 1]) / (0.5 * dn1)
+    tau = 0.5 * (tau_b + tau_t)
+    rms = {f: [math.sqrt(max(st[f + "2"][j] - st[f][j] ** 2, 0.0)) for j in range(M)] for f in STATS_FIELDS}
+    ut = math.sqrt(abs(tau_b))
+    return {
+        "time": T, "samples": samples, "yc": yc, "yn": yn[:M],
+        "mean": {f: st[f] for f in STATS_FIELDS}, "rms": rms,
+        "tau_bottom": tau_b, "tau_top": tau_t, "tau": tau, "cf": 2.0 * tau,
+        "re_tau": cfg.re * math.sqrt(abs(tau)),
+        "y_plus": [(1.0 + y) * cfg.re * ut for y in yc],
+        "u_plus": [(x - cfg.u_bot) / ut if ut > 0 else float("nan") for x in u],
+    }
 
 
 def _check(rc: int):
@@ -315,8 +343,30 @@ class Solver:
         arr = (ctypes.c_int32 * len(Ensemble.TILE_NAMES))(*[cur[k] for k in Ensemble.TILE_NAMES])
         _check(self.lib.nspnp_set_tiles(self._h, arr))
 
+    def stats_begin(self, every: int = 1):
+        """Clear the run statistics and sample every `every` substeps (0 stops)."""
+        _check(self.lib.nspnp_stats_begin(self._h, int(every)))
+
+    def stats_read(self):
+        """(averaged time span, samples, {name: [M] time average}) with names
+        STATS_NAMES: plane means of u, v, w, cp, cm, phi, p and of their squares."""
+        M = self.M
+        t, n = _D(), ctypes.c_int64()
+        out = (_D * (len(STATS_NAMES) * M))()
+        _check(self.lib.nspnp_stats_read(self._h, ctypes.byref(t), ctypes.byref(n), out))
+        vals = list(out)
+        return t.value, n.value, {k: vals[q * M:(q + 1) * M] for q, k in enumerate(STATS_NAMES)}
+
+    def statistics(self) -> Dict[str, object]:
+        """Time-averaged profiles and wall quantities from the run statistics
+        (Sec. III): mean and RMS profiles, tau at both walls from the mean
+        velocity, c_f = 2 tau, Re_tau = Re sqrt(tau), and the mean velocity in
+        wall units of the lower wall (y+ = (1 + y) Re u_tau, u+ = (u - u_bot) / u_tau)."""
+        T, n, st = self.stats_read()
+        return derived_statistics(self.cfg, T, n, st)
+
     def save(self, path: str):
-        """Checkpoint (fields, H buffers, clock) to a file."""
+        """Checkpoint (fields, H buffers, clock, run statistics) to a file."""
         _check(self.lib.nspnp_save(self._h, str(path).encode()))
 
     def load(self, path: str):

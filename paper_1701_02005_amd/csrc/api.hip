@@ -68,8 +68,8 @@ int check_config(const nspnp_config *c) {
 }
 
 struct Layout {
-    size_t off_f[7], off_h[5], off_r[5], off_psi, off_spec, off_fac, off_coef, off_clock, off_phys, off_stats, off_red,
-        off_tab;
+    size_t off_f[7], off_h[5], off_r[5], off_psi, off_spec, off_fac, off_coef, off_clock, off_phys, off_stats,
+        off_rstats, off_red, off_tab;
     size_t ntab, nred, total;
 };
 
@@ -92,7 +92,9 @@ Layout make_layout(const nspnp_config *c) {
     L.off_clock = o; o = align256(o + kClockSlots * 8);
     L.off_phys = o; o = align256(o + sizeof(Phys));
     L.off_stats = o; o = align256(o + (3 * M + 2) * 8);
-    L.nred = std::max<int64_t>((int64_t)kDtParts * dt_max_blocks((int64_t)c->nx * c->nz), M * kPlaneQ);
+    L.off_rstats = o; o = align256(o + (kRunStatsQ * M + kRunStatsTail) * 8);
+    L.nred = std::max<int64_t>({(int64_t)kDtParts * dt_max_blocks((int64_t)c->nx * c->nz), M * kPlaneQ,
+                                 M * (int64_t)run_stats_chunks((int)M) * kRunStatsQ});
     L.off_red = o; o = align256(o + L.nred * 8);
     L.ntab = 11 * M + 2 + nxh + c->nz + 2 * c->nx + 2 * c->nz;
     L.off_tab = o; o = align256(o + L.ntab * 8);
@@ -268,6 +270,8 @@ void setup_handle(nspnp_state *s, const nspnp_config *cfg, char *base, int nmem,
     s->clock = (double *)(base + L.off_clock);
     s->d_phys = (Phys *)(base + L.off_phys);
     s->stats = (double *)(base + L.off_stats);
+    s->rstats = (double *)(base + L.off_rstats);
+    s->rstats_every = 0;
     s->red = (double *)(base + L.off_red);
     s->nred = L.nred;
     s->tab_base = base + L.off_tab;
@@ -297,6 +301,7 @@ nspnp_state *member_view(const nspnp_state *cls, int m, const nspnp_config *cfg)
     v->clock = sh(cls->clock);
     v->d_phys = sh(cls->d_phys);
     v->stats = sh(cls->stats);
+    v->rstats = sh(cls->rstats);
     v->red = sh(cls->red);
     v->nmem = 1;
     v->mstride = 0;
@@ -316,6 +321,7 @@ int init_member(nspnp_state *s) {
     const double clock0[kClockSlots] = {0.0, s->cfg.dt > 0.0 ? s->cfg.dt : 0.0, 0.0, 0.0};
     HIP_TRY(hipMemcpyAsync(s->clock, clock0, sizeof(clock0), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(s->d_phys, &s->ph, sizeof(Phys), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(launch_run_stats_begin(s));  // empty statistics, start time 0
     HIP_TRY(launch_init_fields(s));
     // remove the volume mean of the concentration noise
     std::vector<double> ps;
@@ -365,6 +371,7 @@ int step_handle(nspnp_state *s, int n) {
         HIP_TRY(launch_poisson_batch(s, b));
         HIP_TRY(launch_correct(s, st, true, 0.0, true));
         if (s->stats_on) HIP_TRY(launch_stats_accum(s, st.alp));
+        if (s->rstats_every > 0 && (s->substeps + 1) % s->rstats_every == 0) HIP_TRY(launch_run_stats(s));
         s->substeps++;
     }
     return NSPNP_OK;
@@ -417,7 +424,7 @@ nspnp_state::~nspnp_state() {
 namespace {
 const char *const kKernelNames[K_NKERNEL] = {
     "dt", "explicit_rhs", "cn_tridiag", "fft_x_r2c", "fft_z_fwd", "thomas_modes",
-    "fft_z_inv", "fft_x_c2r", "correct"};
+    "fft_z_inv", "fft_x_c2r", "correct", "stats"};
 }
 
 extern "C" {
@@ -648,6 +655,27 @@ int nspnp_set_clock(nspnp_state *s, double t, double dt, int32_t stage, int64_t 
     return NSPNP_OK;
 }
 
+int nspnp_stats_begin(nspnp_state *s, int32_t every) {
+    if (!s || every < 0) return fail(NSPNP_ERR_INVALID, "bad stats_begin arguments");
+    if (every > 0) HIP_TRY(launch_run_stats_begin(s));
+    s->rstats_every = every;
+    return NSPNP_OK;
+}
+
+int nspnp_stats_read(nspnp_state *s, double *time, int64_t *samples, double *out) {
+    if (!s) return fail(NSPNP_ERR_INVALID, "state is NULL");
+    const int M = s->d.M;
+    std::vector<double> h((size_t)kRunStatsQ * M + kRunStatsTail);
+    HIP_TRY(hipMemcpyAsync(h.data(), s->rstats, h.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const double T = h[(size_t)kRunStatsQ * M];
+    if (time) *time = T;
+    if (samples) *samples = (int64_t)h[(size_t)kRunStatsQ * M + 2];
+    if (out)
+        for (size_t e = 0; e < (size_t)kRunStatsQ * M; ++e) out[e] = T > 0.0 ? h[e] / T : 0.0;
+    return NSPNP_OK;
+}
+
 int nspnp_sync(nspnp_state *s) {
     if (!s) return fail(NSPNP_ERR_INVALID, "state is NULL");
     HIP_TRY(hipStreamSynchronize(s->stream));
@@ -659,7 +687,7 @@ int nspnp_sync(nspnp_state *s) {
 namespace {
 struct CkptHeader {
     char magic[8];     // "NSPNPCK1"
-    uint32_t version;  // 1
+    uint32_t version;  // 1, or 2: followed by CkptStats, the arrays, then the run statistics
     uint32_t word;     // bytes per stored value: 8 (FP64) or 4 (mixed)
     nspnp_config cfg;
     double clock[kClockSlots];
@@ -667,6 +695,14 @@ struct CkptHeader {
     int64_t cells;
 };
 const char kCkptMagic[8] = {'N', 'S', 'P', 'N', 'P', 'C', 'K', '1'};
+
+// Version 2: the run statistics travel with the state, so that a long
+// averaging campaign can stop and resume.
+struct CkptStats {
+    int32_t every;  // sampling interval in substeps (0: not sampling)
+    int32_t reserved;
+    int64_t count;  // doubles of the statistics block stored after the arrays
+};
 
 // Every configuration value that the continuation depends on (seed and noise
 // amplitudes only shape the initial state).
@@ -687,7 +723,7 @@ int nspnp_save(nspnp_state *s, const char *path) {
     if (!s || !path) return fail(NSPNP_ERR_INVALID, "bad save arguments");
     CkptHeader h{};
     std::memcpy(h.magic, kCkptMagic, 8);
-    h.version = 1;
+    h.version = 2;
     h.word = (uint32_t)s->wsize;
     h.cfg = s->cfg;
     h.substeps = s->substeps;
@@ -696,7 +732,9 @@ int nspnp_save(nspnp_state *s, const char *path) {
     HIP_TRY(hipStreamSynchronize(s->stream));
     FileCloser fc{std::fopen(path, "wb")};
     if (!fc.f) return fail(NSPNP_ERR_INVALID, std::string("save: cannot open ") + path);
-    if (std::fwrite(&h, sizeof(h), 1, fc.f) != 1) return fail(NSPNP_ERR_INVALID, "save: write failed");
+    const CkptStats cs{s->rstats_every, 0, (int64_t)kRunStatsQ * s->d.M + kRunStatsTail};
+    if (std::fwrite(&h, sizeof(h), 1, fc.f) != 1 || std::fwrite(&cs, sizeof(cs), 1, fc.f) != 1)
+        return fail(NSPNP_ERR_INVALID, "save: write failed");
     const size_t bytes = (size_t)s->d.n * s->wsize;
     std::vector<char> buf(bytes);
     for (int a = 0; a < 12; ++a) {
@@ -705,6 +743,11 @@ int nspnp_save(nspnp_state *s, const char *path) {
         HIP_TRY(hipStreamSynchronize(s->stream));
         if (std::fwrite(buf.data(), 1, bytes, fc.f) != bytes) return fail(NSPNP_ERR_INVALID, "save: write failed");
     }
+    std::vector<double> st((size_t)cs.count);
+    HIP_TRY(hipMemcpyAsync(st.data(), s->rstats, st.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (std::fwrite(st.data(), sizeof(double), st.size(), fc.f) != st.size())
+        return fail(NSPNP_ERR_INVALID, "save: write failed");
     if (std::fflush(fc.f) != 0) return fail(NSPNP_ERR_INVALID, "save: flush failed");
     return NSPNP_OK;
 }
@@ -714,8 +757,13 @@ int nspnp_load(nspnp_state *s, const char *path) {
     FileCloser fc{std::fopen(path, "rb")};
     if (!fc.f) return fail(NSPNP_ERR_INVALID, std::string("load: cannot open ") + path);
     CkptHeader h{};
-    if (std::fread(&h, sizeof(h), 1, fc.f) != 1 || std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1)
+    if (std::fread(&h, sizeof(h), 1, fc.f) != 1 || std::memcmp(h.magic, kCkptMagic, 8) != 0 ||
+        (h.version != 1 && h.version != 2))
         return fail(NSPNP_ERR_INVALID, "load: not a checkpoint of this library");
+    CkptStats cs{0, 0, 0};
+    if (h.version == 2 && (std::fread(&cs, sizeof(cs), 1, fc.f) != 1 || cs.every < 0 ||
+                           cs.count != (int64_t)kRunStatsQ * s->d.M + kRunStatsTail))
+        return fail(NSPNP_ERR_INVALID, "load: bad statistics record");
     if (h.word != s->wsize || h.cells != s->d.n || !same_run(h.cfg, s->cfg))
         return fail(NSPNP_ERR_INVALID, "load: the checkpoint was written for a different configuration");
     if (h.substeps < 0) return fail(NSPNP_ERR_INVALID, "load: bad substep count");
@@ -727,10 +775,18 @@ int nspnp_load(nspnp_state *s, const char *path) {
         HIP_TRY(hipMemcpyAsync(dst, buf.data(), bytes, hipMemcpyHostToDevice, s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
     }
+    if (h.version == 2) {
+        std::vector<double> st((size_t)cs.count);
+        if (std::fread(st.data(), sizeof(double), st.size(), fc.f) != st.size())
+            return fail(NSPNP_ERR_INVALID, "load: truncated file");
+        HIP_TRY(hipMemcpyAsync(s->rstats, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+    }
     HIP_TRY(hipMemcpyAsync(s->clock, h.clock, sizeof(h.clock), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->substeps = h.substeps;
     s->cn_fresh = false;
+    s->rstats_every = cs.every;  // version 1 files carry no statistics: sampling off
     if (s->host_health) {
         s->host_health[0] = h.clock[2];
         s->host_health[1] = h.clock[3];

@@ -176,10 +176,24 @@ struct Tiles {
 
 constexpr int kTileInts = 8;  // Tiles as exported through the ABI
 
+// Run statistics: time sums of the plane means of u, v, w, c+, c-, phi, p
+// and of their squares, per row (v per node row).
+constexpr int kRunStatsFields = 7;
+constexpr int kRunStatsQ = 2 * kRunStatsFields;
+constexpr int kRunStatsTail = 4;  // accumulated time, time of the last sample, samples, unused
+constexpr int kStatCloseThreads = 256;
+// Blocks per row of the statistics pass: about 2048 blocks over the grid
+// (at least one per row, at most 32); its partial sums, kRunStatsQ per block,
+// live in the reduction scratch.
+__host__ __device__ inline int run_stats_chunks(int M) {
+    const int c = (2048 + M - 1) / M;
+    return c < 1 ? 1 : (c > 32 ? 32 : c);
+}
+
 // Kernel classes timed by the optional event profiler.
 enum KernelId {
     K_DT = 0, K_EXPLICIT, K_CN, K_FFTX_FWD, K_FFTZ_FWD, K_THOMAS, K_FFTZ_INV, K_FFTX_INV,
-    K_CORRECT, K_NKERNEL
+    K_CORRECT, K_STATS, K_NKERNEL
 };
 
 // hipEvent pairs around kernel launches on the solver's stream.
@@ -233,6 +247,8 @@ struct nspnp_state {
     int64_t nred;
     double *stats;       // time sums of the plane means of u, c+ - c-, phi (3 per row) and the time
     bool stats_on;
+    double *rstats;      // run statistics: kRunStatsQ time sums per row, then [time, t_last, samples, -]
+    int rstats_every = 0;  // sample at the end of every rstats_every-th substep (0: off)
     char *tab_base;      // device tables (member 0)
     int64_t substeps;
     std::vector<double> host_tables;
@@ -279,6 +295,8 @@ hipError_t launch_plane_sums(nspnp_state *s, int what, double *dev_out);
 hipError_t launch_shift_conc(nspnp_state *s, double mean_p, double mean_m);
 hipError_t launch_convert(nspnp_state *s, int field, const double *in, double *out, bool to_state);
 hipError_t launch_stats_accum(nspnp_state *s, double alp);
+hipError_t launch_run_stats(nspnp_state *s);
+hipError_t launch_run_stats_begin(nspnp_state *s);
 hipError_t launch_stats_reset(nspnp_state *s);
 
 // handle management shared by the single-run and ensemble entry points

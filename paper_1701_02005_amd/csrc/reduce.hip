@@ -386,6 +386,143 @@ hipError_t launch_stats_reset(nspnp_state *s) {
     return hipGetLastError();
 }
 
+namespace {
+
+// Run statistics (the averages behind mean and RMS profiles, Sec. III).
+// k_run_stats: block (chunk, row j) sums q and q^2 for q = u, v, w, c+, c-,
+// phi, p over its part of the row, in batches of kStatBatch elements per
+// thread whose loads are all issued first, and writes the kRunStatsQ sums to
+// the scratch slot (j, chunk).  k_run_stats_close: thread (j, q) adds the chunks
+// in order and accumulates w * (plane mean) with w = t - t_last, the time
+// since the previous sample (t from the device clock, after this substep's
+// advance); k_run_stats_tail then adds w to the accumulated time and sets
+// t_last = t.  The
+// sums never depend on timing (no atomics), so runs repeat bit for bit.
+constexpr int kStatBatch = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) k_run_stats(Dims d, const T *f0, const T *f1, const T *f2, const T *f3,
+                                                           const T *f4, const T *f5, const T *f6, double *part,
+                                                           int chunks, size_t ms) {
+    __shared__ double sm[kRunStatsQ][kRedThreads / 64];
+    const T *f[kRunStatsFields] = {member_ptr(f0, ms), member_ptr(f1, ms), member_ptr(f2, ms), member_ptr(f3, ms),
+                                   member_ptr(f4, ms), member_ptr(f5, ms), member_ptr(f6, ms)};
+    part = member_ptr(part, ms);
+    const int chunk = blockIdx.x, j = blockIdx.y;
+    const int pl = (int)d.plane;
+    const int per = (pl + chunks - 1) / chunks;
+    const int e_lo = chunk * per, e_hi = (e_lo + per < pl) ? e_lo + per : pl;
+    const unsigned base = (unsigned)j * (unsigned)pl;
+    const int bd = (int)blockDim.x;
+    double a[kRunStatsQ];
+#pragma unroll
+    for (int q = 0; q < kRunStatsQ; ++q) a[q] = 0.0;
+    for (int e0 = e_lo + (int)threadIdx.x; e0 < e_hi; e0 += kStatBatch * bd) {
+        T x[kStatBatch][kRunStatsFields];
+#pragma unroll
+        for (int u = 0; u < kStatBatch; ++u) {
+            const int e = (e0 + u * bd < e_hi) ? e0 + u * bd : e0;  // in range; dropped below
+#pragma unroll
+            for (int q = 0; q < kRunStatsFields; ++q) x[u][q] = f[q][base + (unsigned)e];
+        }
+#pragma unroll
+        for (int u = 0; u < kStatBatch; ++u) {
+            if (e0 + u * bd < e_hi) {
+#pragma unroll
+                for (int q = 0; q < kRunStatsFields; ++q) {
+                    const double v = (double)x[u][q];
+                    a[q] += v;
+                    a[kRunStatsFields + q] += v * v;
+                }
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kRunStatsQ; ++q) {
+        double v = a[q];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) sm[q][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kRunStatsQ) {
+        const int q = threadIdx.x;
+        double v = 0.0;
+        for (int w = 0; w < (bd >> 6); ++w) v += sm[q][w];
+        part[((size_t)j * chunks + chunk) * kRunStatsQ + q] = v;
+    }
+}
+
+__global__ void __launch_bounds__(kStatCloseThreads) k_run_stats_close(Dims d, const double *part, int chunks,
+                                                                       const double *clock, double *rs, size_t ms) {
+    part = member_ptr(part, ms);
+    clock = member_ptr(clock, ms);
+    rs = member_ptr(rs, ms);
+    const int M = d.M;
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= M * kRunStatsQ) return;
+    const int j = t / kRunStatsQ, q = t - j * kRunStatsQ;
+    const double wgt = clock[0] - rs[kRunStatsQ * M + 1];
+    const double *pj = part + (size_t)j * chunks * kRunStatsQ + q;
+    double v = 0.0;
+    for (int c0 = 0; c0 < chunks; c0 += 8) {  // chunks in order, 8 loads in flight
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = pj[(size_t)(c0 + u < chunks ? c0 + u : c0) * kRunStatsQ];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (c0 + u < chunks) v += x[u];
+    }
+    rs[q * M + j] += wgt * (v / (double)d.plane);
+}
+
+// after k_run_stats_close (which reads t_last): accumulated time, t_last, count
+__global__ void k_run_stats_tail(int M, const double *clock, double *rs, size_t ms) {
+    clock = member_ptr(clock, ms);
+    rs = member_ptr(rs, ms);
+    if (threadIdx.x == 0) {
+        double *tail = rs + kRunStatsQ * M;
+        tail[0] += clock[0] - tail[1];
+        tail[1] = clock[0];
+        tail[2] += 1.0;
+    }
+}
+
+// Clear the run statistics and take the current time as the start.
+__global__ void k_run_stats_begin(int M, const double *clock, double *rs, size_t ms) {
+    clock = member_ptr(clock, ms);
+    rs = member_ptr(rs, ms);
+    const int n = kRunStatsQ * M + kRunStatsTail;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) rs[e] = (e == kRunStatsQ * M + 1) ? clock[0] : 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_run_stats_begin(nspnp_state *s) {
+    k_run_stats_begin<<<dim3(1, 1, (unsigned)s->nmem), 256, 0, s->stream>>>(s->d.M, s->clock, s->rstats, s->mstride);
+    return hipGetLastError();
+}
+
+hipError_t launch_run_stats(nspnp_state *s) {
+    ProfScope prof_(s, K_STATS);
+    const int chunks = run_stats_chunks(s->d.M);
+    if ((int64_t)s->d.M * chunks * kRunStatsQ > s->nred) return hipErrorInvalidValue;  // the layout sized red for this
+    const dim3 g((unsigned)chunks, (unsigned)s->d.M, (unsigned)s->nmem);
+    if (s->fp64)
+        k_run_stats<double><<<g, kRedThreads, 0, s->stream>>>(
+            s->d, (const double *)s->f[0], (const double *)s->f[1], (const double *)s->f[2], (const double *)s->f[3],
+            (const double *)s->f[4], (const double *)s->f[5], (const double *)s->f[6], s->red, chunks, s->mstride);
+    else
+        k_run_stats<float><<<g, kRedThreads, 0, s->stream>>>(
+            s->d, (const float *)s->f[0], (const float *)s->f[1], (const float *)s->f[2], (const float *)s->f[3],
+            (const float *)s->f[4], (const float *)s->f[5], (const float *)s->f[6], s->red, chunks, s->mstride);
+    const unsigned nclose = (unsigned)((s->d.M * kRunStatsQ + kStatCloseThreads - 1) / kStatCloseThreads);
+    k_run_stats_close<<<dim3(nclose, 1, (unsigned)s->nmem), kStatCloseThreads, 0, s->stream>>>(
+        s->d, s->red, chunks, s->clock, s->rstats, s->mstride);
+    k_run_stats_tail<<<dim3(1, 1, (unsigned)s->nmem), 64, 0, s->stream>>>(s->d.M, s->clock, s->rstats, s->mstride);
+    return hipGetLastError();
+}
+
 hipError_t launch_stats_accum(nspnp_state *s, double alp) {
     const dim3 g((unsigned)s->d.M, 1, (unsigned)s->nmem);
     if (s->fp64)

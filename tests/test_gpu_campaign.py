@@ -1,0 +1,43 @@
+"""The statistics-campaign pipeline end to end on a small laminar case,
+where the answer is closed-form: c_f = 2/Re, Re_tau = sqrt(Re), u+ = y+;
+and its checkpoint/resume path continues the statistics exactly."""
+import dataclasses
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1701_02005_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def test_laminar_campaign_and_resume(P, tmp_path):
+    from paper_1701_02005_amd import campaign as C
+    cfg = dataclasses.replace(P.configs.couette_small(), vhat=0.0, u_noise=0.0, c_noise=0.0, dt=0.0, cfl=0.5)
+    print("case: laminar campaign 32x33x32", flush=True)
+    sys.stdout.flush()
+    ck = tmp_path / "camp.ckpt"
+    full = C.run_campaign(cfg, t_spin=0.5, t_avg=2.0, every=1, monitor=0.1, amp=0.0, ckpt=str(ck),
+                          ckpt_every=1e9, log=lambda m: None)
+    assert full["samples"] > 10 and full["averaged_time"] > 1.9
+    assert abs(full["cf"] - 2.0 / cfg.re) < 1e-11
+    assert abs(full["re_tau"] - math.sqrt(cfg.re)) < 1e-8
+    assert np.allclose(full["u_plus"], full["y_plus"], rtol=1e-10)
+    assert full["cf_stderr"] < 1e-12
+    # a campaign stopped inside the averaging window and resumed from its
+    # checkpoint reaches the same statistics
+    part = C.run_campaign(cfg, t_spin=0.5, t_avg=1.0, every=1, monitor=0.1, amp=0.0, ckpt=str(ck),
+                          ckpt_every=1e9, log=lambda m: None)
+    rest = C.run_campaign(cfg, t_spin=0.5, t_avg=2.0, every=1, monitor=0.1, resume=str(ck), log=lambda m: None)
+    assert rest["samples"] > part["samples"]
+    assert abs(rest["cf"] - 2.0 / cfg.re) < 1e-11

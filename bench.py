@@ -94,6 +94,9 @@ def main():
     ap.add_argument("--stats-every", type=int, default=0,
                     help="also sample the run statistics every N substeps in the timed regions "
                          "(a separate measurement; the default line has no sampling)")
+    ap.add_argument("--wall-amplitude", type=float, default=0.0,
+                    help="time with a wall-potential pattern A cos(x) cos(2z) on both walls "
+                         "(a separate measurement of the inhomogeneous potential solve)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="before timing, run one plain device-to-device copy of this many MiB (a "
                          "reference kernel of known traffic for hardware byte counters)")
@@ -132,6 +135,12 @@ def main():
         print(f"[bench] autotuned launch shapes {tiles}", file=sys.stderr, flush=True)
     if args.stats_every > 0:
         solver.stats_begin(args.stats_every)
+    if args.wall_amplitude:
+        x = torch.arange(cfg.nx, dtype=torch.float64, device="cuda") * (cfg.lx / cfg.nx)
+        z = torch.arange(cfg.nz, dtype=torch.float64, device="cuda") * (cfg.lz / cfg.nz)
+        gw = args.wall_amplitude * torch.cos(2 * z)[:, None] * torch.cos(x)[None, :]
+        solver.set_wall_potential(gw, -gw)
+        solver.refresh_potential()
     solver.step(args.warmup)
     torch.cuda.synchronize()
     print(f"[bench] warmup {args.warmup} substeps done", file=sys.stderr, flush=True)
@@ -208,7 +217,8 @@ def main():
         "config": {"workload": f"{args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz} Re={cfg.re:g} "
                                f"debye={cfg.debye:g} vhat={cfg.vhat:g} {args.precision}",
                    "points": cfg.points, "cells": cfg.cells, "precision": args.precision,
-                   "parallelism": "single GPU", **({"stats_every": args.stats_every} if args.stats_every else {})},
+                   "parallelism": "single GPU", **({"stats_every": args.stats_every} if args.stats_every else {}),
+                   **({"wall_amplitude": args.wall_amplitude} if args.wall_amplitude else {})},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes/launch",
                      "algorithmic_bytes_per_launch": per_launch_bytes,

@@ -189,6 +189,22 @@ NSPNP_API int nspnp_diagnostics(nspnp_state *s, double out[6]);
 NSPNP_API int nspnp_get_clock(nspnp_state *s, double *t, double *dt, int32_t *stage, int64_t *substeps);
 NSPNP_API int nspnp_set_clock(nspnp_state *s, double t, double dt, int32_t stage, int64_t substeps);
 
+/* Arbitrary wall potential (the model admits spatially and temporally varying
+ * wall potentials, Sec. II and Sec. V): the walls are at -vhat/2 + g_bot(x, z)
+ * and +vhat/2 + g_top(x, z) thermal volts.  g is the wall value of the
+ * potential perturbation phi, so the potential solve becomes the
+ * inhomogeneous Dirichlet problem lap phi = -(c+ - c-)/(2 lam^2),
+ * phi = g on the walls (at the half-cell distance, like the zero value of the
+ * uniform case).  dev_bot / dev_top: device arrays of nx * nz doubles, x
+ * fastest (the cell columns of one plane), copied into the workspace; NULL
+ * sets that wall's g to zero; both NULL restore uniform walls.  Asynchronous
+ * on the solver's stream; used from the next potential solve on (every
+ * substep, or nspnp_refresh_potential to make phi consistent at once).  A
+ * time-varying wall potential is set again between calls of nspnp_step.
+ * Not part of checkpoints (set it again after nspnp_load); single runs only.
+ * nspnp_poisson_solve keeps zero wall values. */
+NSPNP_API int nspnp_set_wall_potential(nspnp_state *s, const double *dev_bot, const double *dev_top);
+
 /* Run statistics: the time averages behind the mean and RMS profiles and
  * the friction coefficient of the turbulent runs (Sec. III).  Every sample
  * adds, for each of the M = ny - 1 rows, the plane (x-z) means of

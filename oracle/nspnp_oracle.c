@@ -84,6 +84,8 @@ typedef struct {
     double t, dt;
     int stage;                  /* 0,1,2: next RK stage                          */
     long long substeps;
+    double *phiw[2];            /* wall values of phi (lower, upper wall), nz*nx
+                                   each, x fastest; NULL: zero (uniform walls)  */
 } or_solver;
 
 #define IDX(s, i, j, k) ((size_t)(i) + (size_t)(s)->nx * ((size_t)(k) + (size_t)(s)->nz * (size_t)(j)))
@@ -144,6 +146,7 @@ void or_destroy(or_solver *s) {
     free(s->yn); free(s->yc); free(s->dn); free(s->dc);
     for (int q = 0; q < F_NFIELD; q++) free(s->f[q]);
     for (int q = 0; q < 5; q++) free(s->hold[q]);
+    free(s->phiw[0]); free(s->phiw[1]);
     free(s);
 }
 
@@ -700,14 +703,43 @@ void or_poisson(const or_solver *s, int kind, const double *rhs, double *out) {
 /* potential                                                            */
 /* ------------------------------------------------------------------ */
 
-/* phi from lap phi = -(c+ - c-)/(2 lam^2), phi = 0 on the walls (Sec. II) */
+/* phi from lap phi = -(c+ - c-)/(2 lam^2) (Sec. II).  The wall potential is
+ * -+vhat/2 (the uniform field carried by Phi_0) plus, where set, a wall
+ * value g(x, z) of phi itself: the arbitrary (spatially or temporally
+ * varying) wall potential the model admits (Sec. II, Sec. V).  With the wall
+ * value at the half-cell distance dc, L_y phi at the first row is the
+ * homogeneous operator plus g / (dn_0 dc_0) (last row: g / (dn_{M-1} dc_M)),
+ * so the homogeneous solve takes rhs - that term. */
 void or_solve_potential(or_solver *s) {
     size_t n = or_ncell(s);
     double *rhs = (double *)malloc(n * sizeof(double));
     double sc = -1.0 / (2.0 * s->cfg.debye * s->cfg.debye);
     for (size_t q = 0; q < n; q++) rhs[q] = sc * (s->f[F_CP][q] - s->f[F_CM][q]);
+    int M = s->M;
+    for (int w = 0; w < 2; w++) {
+        if (!s->phiw[w]) continue;
+        int j = w == 0 ? 0 : M - 1;
+        double coef = w == 0 ? 1.0 / (s->dn[0] * s->dc[0]) : 1.0 / (s->dn[M - 1] * s->dc[M]);
+        for (int k = 0; k < s->nz; k++)
+            for (int i = 0; i < s->nx; i++) rhs[IDX(s, i, j, k)] -= coef * s->phiw[w][(size_t)k * s->nx + i];
+    }
     or_poisson(s, 1, rhs, s->f[F_PHI]);
     free(rhs);
+}
+
+/* Wall values of phi on the lower and upper wall (nz*nx each, x fastest);
+ * NULL clears a wall to zero.  Takes effect at the next potential solve. */
+void or_set_wall_potential(or_solver *s, const double *bot, const double *top) {
+    const double *src[2] = {bot, top};
+    size_t np = (size_t)s->nx * s->nz;
+    for (int w = 0; w < 2; w++) {
+        free(s->phiw[w]);
+        s->phiw[w] = NULL;
+        if (src[w]) {
+            s->phiw[w] = (double *)malloc(np * sizeof(double));
+            memcpy(s->phiw[w], src[w], np * sizeof(double));
+        }
+    }
 }
 
 /* ------------------------------------------------------------------ */

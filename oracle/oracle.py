@@ -83,6 +83,7 @@ def _load():
         "or_poisson": (None, [_P, ctypes.c_int, _D, _D]),
         "or_solve_potential": (None, [_P]),
         "or_refresh_potential": (None, [_P]),
+        "or_set_wall_potential": (None, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         "or_compute_dt": (ctypes.c_double, [_P]),
         "or_substep": (None, [_P]),
         "or_run": (None, [_P, ctypes.c_int]),
@@ -243,6 +244,16 @@ class Oracle:
 
     def substep(self):
         self._lib.or_substep(self._h)
+
+    def set_wall_potential(self, bot=None, top=None):
+        """Wall values of phi [nz, nx] on the lower / upper wall (None: zero);
+        used from the next potential solve on."""
+        arrs = []
+        for a in (bot, top):
+            arrs.append(None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(self.nz, self.nx))
+        self._wall = arrs  # keep the buffers alive for the call
+        ptr = [None if a is None else _ptr(a) for a in arrs]
+        self._lib.or_set_wall_potential(self._h, ptr[0], ptr[1])
 
     def solve_potential(self):
         self._lib.or_solve_potential(self._h)

@@ -124,6 +124,7 @@ def load_library() -> ctypes.CDLL:
         "nspnp_set_clock": (_I, [_P, _D, _D, ctypes.c_int32, ctypes.c_int64]),
         "nspnp_sync": (_I, [_P]),
         "nspnp_stats_begin": (_I, [_P, ctypes.c_int32]),
+        "nspnp_set_wall_potential": (_I, [_P, _P, _P]),
         "nspnp_stats_read": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D)]),
         "nspnp_save": (_I, [_P, ctypes.c_char_p]),
         "nspnp_autotune": (_I, [_P, ctypes.c_char_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -342,6 +343,23 @@ class Solver:
             cur[k] = int(v)
         arr = (ctypes.c_int32 * len(Ensemble.TILE_NAMES))(*[cur[k] for k in Ensemble.TILE_NAMES])
         _check(self.lib.nspnp_set_tiles(self._h, arr))
+
+    def set_wall_potential(self, bot: torch.Tensor | None = None, top: torch.Tensor | None = None):
+        """Wall values of phi [nz, nx] (float64, on the solver's device) on the
+        lower / upper wall beyond -+vhat/2; None: zero."""
+        ptrs = []
+        self._wall_keep = []
+        for g in (bot, top):
+            if g is None:
+                ptrs.append(None)
+                continue
+            g = g.to(device=self.device, dtype=torch.float64).contiguous()
+            if g.numel() != self.cfg.nx * self.cfg.nz:
+                raise ValueError("wall potential needs nz * nx values")
+            self._wall_keep.append(g)
+            ptrs.append(ctypes.c_void_p(g.data_ptr()))
+        _check(self.lib.nspnp_set_wall_potential(self._h, ptrs[0], ptrs[1]))
+        self.sync()  # the copies have left the caller's tensors
 
     def stats_begin(self, every: int = 1):
         """Clear the run statistics and sample every `every` substeps (0 stops)."""

@@ -34,7 +34,7 @@ from pathlib import Path
 import numpy as np
 
 from . import configs
-from .binding import Config, Solver, grid
+from .binding import Config, NsPnpError, Solver, grid
 
 # values printed for the uncharged validation case (Re 3000, Sec. II); the
 # two are not mutually consistent (Re sqrt(c_f / 2) = 159, not 172), so they
@@ -93,33 +93,46 @@ def run_campaign(cfg: Config, t_spin: float, t_avg: float, every: int = 10, moni
         perturbed_start(s, amp, seed)
     t0 = time.time()
     hist = []  # (t, tau_bottom, tau_top)
-    t, dt, _, ns = s.clock()
-    averaging = t >= t_spin
-    if averaging and not resume:
+    st0 = s.clock()
+    state = {"t": st0[0], "dt": st0[1], "ns": st0[3], "averaging": st0[0] >= t_spin, "next_ckpt": st0[0] + ckpt_every}
+    if state["averaging"] and not resume:
         s.stats_begin(every)
-    next_ckpt = t + ckpt_every
     t_end = t_spin + t_avg
-    while t < t_end:
-        if not averaging and t >= t_spin:
-            s.stats_begin(every)
-            averaging = True
-            log(f"[campaign] statistics from t = {t:.2f}")
-        target = min(t + monitor, t_spin if not averaging else t_end)
-        # whole Runge-Kutta steps at the current dt (3 before the first dt exists)
-        n = 3 if dt <= 0.0 else min(3000, max(3, 3 * int(math.ceil((target - t) / dt / 3.0))))
-        s.step(n)
-        t, dt, _, ns = s.clock()
-        tb, tt = s.wall_shear_stress()
-        hist.append((t, tb, tt))
-        if ckpt and t >= next_ckpt:
+
+    def advance():
+        while state["t"] < t_end:
+            t, dt = state["t"], state["dt"]
+            if not state["averaging"] and t >= t_spin:
+                s.stats_begin(every)
+                state["averaging"] = True
+                log(f"[campaign] statistics from t = {t:.2f}")
+            target = min(t + monitor, t_spin if not state["averaging"] else t_end)
+            # whole Runge-Kutta steps at the current dt (3 before the first dt exists)
+            n = 3 if dt <= 0.0 else min(3000, max(3, 3 * int(math.ceil((target - t) / dt / 3.0))))
+            s.step(n)
+            t, dt, _, ns = s.clock()
+            state.update(t=t, dt=dt, ns=ns)
+            tb, tt = s.wall_shear_stress()
+            hist.append((t, tb, tt))
+            if ckpt and t >= state["next_ckpt"]:
+                s.save(ckpt)
+                state["next_ckpt"] = t + ckpt_every
+            if len(hist) % 20 == 0:
+                log(f"[campaign] t = {t:8.2f}  substeps = {ns}  tau = ({tb:.4e}, {tt:.4e})  "
+                    f"wall {time.time() - t0:.1f} s")
+        s.sync()
+        if ckpt:
             s.save(ckpt)
-            next_ckpt = t + ckpt_every
-        if len(hist) % 20 == 0:
-            log(f"[campaign] t = {t:8.2f}  substeps = {ns}  tau = ({tb:.4e}, {tt:.4e})  "
-                f"wall {time.time() - t0:.1f} s")
-    s.sync()
-    if ckpt:
-        s.save(ckpt)
+
+    stopped = None
+    try:
+        advance()
+    except NsPnpError as e:
+        # the health check stopped the run (a non-finite value or a negative
+        # concentration, checked once per Runge-Kutta step): the statistics
+        # sampled before it are reported, flagged
+        stopped = {"t": state["t"], "reason": str(e)}
+        log(f"[campaign] stopped at t = {state['t']:.2f}: {e}")
     wall = time.time() - t0
     st = s.statistics()
     h = np.array(hist)
@@ -131,7 +144,7 @@ def run_campaign(cfg: Config, t_spin: float, t_avg: float, every: int = 10, moni
     return {
         "config": dataclasses.asdict(cfg),
         "t_spin": t_spin, "t_avg": t_avg, "sample_every": every, "samples": st["samples"],
-        "averaged_time": st["time"], "substeps": int(ns), "wall_s": wall,
+        "averaged_time": st["time"], "substeps": int(state["ns"]), "wall_s": wall, "stopped": stopped,
         "cf": st["cf"], "cf_stderr": cf_se, "re_tau": st["re_tau"], "re_tau_stderr": re_tau_se,
         "tau_bottom": st["tau_bottom"], "tau_top": st["tau_top"],
         "tau_history_mean": tau_mean, "laminar_cf": 2.0 / cfg.re,
@@ -167,6 +180,8 @@ def main():
     rep = run_campaign(cfg, a.t_spin, a.t_avg, every=a.every, amp=a.amp, ckpt=a.ckpt, resume=a.resume,
                        log=lambda m: print(m, flush=True))
     Path(a.out).write_text(json.dumps(rep, indent=1) + "\n")
+    if rep["stopped"]:
+        print(f"[campaign] stopped early at t = {rep['stopped']['t']:.2f}: {rep['stopped']['reason']}", flush=True)
     print(f"[campaign] c_f = {rep['cf']:.4e} +- {rep['cf_stderr']:.1e}  Re_tau = {rep['re_tau']:.1f} "
           f"+- {rep['re_tau_stderr']:.1f}  (paper: c_f {PAPER_CF:.3e}, Re_tau {PAPER_RE_TAU:.0f}); "
           f"{rep['substeps']} substeps in {rep['wall_s']:.1f} s", flush=True)

@@ -69,7 +69,7 @@ int check_config(const nspnp_config *c) {
 
 struct Layout {
     size_t off_f[7], off_h[5], off_r[5], off_psi, off_spec, off_fac, off_coef, off_clock, off_phys, off_stats,
-        off_rstats, off_red, off_tab;
+        off_rstats, off_phiw, off_red, off_tab;
     size_t ntab, nred, total;
 };
 
@@ -93,6 +93,7 @@ Layout make_layout(const nspnp_config *c) {
     L.off_phys = o; o = align256(o + sizeof(Phys));
     L.off_stats = o; o = align256(o + (3 * M + 2) * 8);
     L.off_rstats = o; o = align256(o + (kRunStatsQ * M + kRunStatsTail) * 8);
+    L.off_phiw = o; o = align256(o + 2 * (int64_t)c->nx * c->nz * 8);
     L.nred = std::max<int64_t>({(int64_t)kDtParts * dt_max_blocks((int64_t)c->nx * c->nz), M * kPlaneQ,
                                  M * (int64_t)run_stats_chunks((int)M) * kRunStatsQ});
     L.off_red = o; o = align256(o + L.nred * 8);
@@ -182,7 +183,9 @@ PoissonSrc div_source(nspnp_state *s, double alp, double fixed) {
     return PoissonSrc{SRC_DIV, s->f[0], s->f[1], s->f[2], fixed, alp};
 }
 
-PoissonSrc charge_source(nspnp_state *s) { return PoissonSrc{SRC_CHARGE, s->f[3], s->f[4], nullptr, 0.0, 0.0}; }
+PoissonSrc charge_source(nspnp_state *s) {
+    return PoissonSrc{SRC_CHARGE, s->f[3], s->f[4], nullptr, 0.0, 0.0, s->phiw_on ? s->phiw : nullptr};
+}
 
 // A batch over the members of this handle (member stride) or over caller
 // arrays for member 0 (stride 0).
@@ -272,6 +275,8 @@ void setup_handle(nspnp_state *s, const nspnp_config *cfg, char *base, int nmem,
     s->stats = (double *)(base + L.off_stats);
     s->rstats = (double *)(base + L.off_rstats);
     s->rstats_every = 0;
+    s->phiw = (double *)(base + L.off_phiw);
+    s->phiw_on = false;
     s->red = (double *)(base + L.off_red);
     s->nred = L.nred;
     s->tab_base = base + L.off_tab;
@@ -302,6 +307,7 @@ nspnp_state *member_view(const nspnp_state *cls, int m, const nspnp_config *cfg)
     v->d_phys = sh(cls->d_phys);
     v->stats = sh(cls->stats);
     v->rstats = sh(cls->rstats);
+    v->phiw = sh(cls->phiw);
     v->red = sh(cls->red);
     v->nmem = 1;
     v->mstride = 0;
@@ -652,6 +658,19 @@ int nspnp_set_clock(nspnp_state *s, double t, double dt, int32_t stage, int64_t 
     if (s->host_health) s->host_health[0] = s->host_health[1] = 0.0;
     s->substeps = substeps;
     s->cn_fresh = false;  // dt may have changed
+    return NSPNP_OK;
+}
+
+int nspnp_set_wall_potential(nspnp_state *s, const double *dev_bot, const double *dev_top) {
+    if (!s) return fail(NSPNP_ERR_INVALID, "state is NULL");
+    const size_t np = (size_t)s->d.plane;
+    const double *src[2] = {dev_bot, dev_top};
+    for (int w = 0; w < 2; ++w) {
+        double *dst = s->phiw + w * np;
+        if (src[w]) HIP_TRY(hipMemcpyAsync(dst, src[w], np * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+        else HIP_TRY(launch_fill(s, dst, (int64_t)np, 0.0));
+    }
+    s->phiw_on = dev_bot != nullptr || dev_top != nullptr;
     return NSPNP_OK;
 }
 

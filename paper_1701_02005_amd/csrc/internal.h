@@ -145,6 +145,7 @@ struct PoissonSrc {
     const void *a, *b, *c;  // REAL: a = FP64 array; DIV: u, v, w; CHARGE: c+, c-
     double fixed;           // DIV: scale when alp <= 0; CHARGE: -1/(2 lam^2)
     double alp;             // DIV: scale 1/(alp dt) with dt from the device clock
+    const double *wall = nullptr;  // CHARGE: wall values of phi, [lower | upper] plane (NULL: zero)
 };
 // Up to two independent solves sharing one pipeline (pressure and potential).
 struct PoissonBatch {
@@ -248,6 +249,8 @@ struct nspnp_state {
     double *stats;       // time sums of the plane means of u, c+ - c-, phi (3 per row) and the time
     bool stats_on;
     double *rstats;      // run statistics: kRunStatsQ time sums per row, then [time, t_last, samples, -]
+    double *phiw;        // wall values of phi: lower-wall plane, then upper-wall plane (FP64)
+    bool phiw_on = false;  // phiw holds nonzero data (else the potential solve skips it)
     int rstats_every = 0;  // sample at the end of every rstats_every-th substep (0: off)
     char *tab_base;      // device tables (member 0)
     int64_t substeps;
@@ -298,6 +301,7 @@ hipError_t launch_stats_accum(nspnp_state *s, double alp);
 hipError_t launch_run_stats(nspnp_state *s);
 hipError_t launch_run_stats_begin(nspnp_state *s);
 hipError_t launch_stats_reset(nspnp_state *s);
+hipError_t launch_fill(nspnp_state *s, double *p, int64_t n, double v);
 
 // handle management shared by the single-run and ensemble entry points
 int fail_code(int code, const std::string &msg);

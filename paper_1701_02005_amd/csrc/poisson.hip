@@ -194,6 +194,21 @@ __device__ __forceinline__ void r2c_stage(const PoissonSrc &src, const Dims &d, 
             for (int u = 0; u < kXB; ++u)
 #pragma unroll
                 for (int l = 0; l < 2; ++l) val[u][l] = ch * ((double)xp[u][l] - (double)xm[u][l]);
+            // wall values g of phi (inhomogeneous Dirichlet data): L_y at the
+            // first / last row carries + g / (dn dc), moved to the right side
+            if (src.wall) {
+#pragma unroll
+                for (int u = 0; u < kXB; ++u)
+#pragma unroll
+                    for (int l = 0; l < 2; ++l) {
+                        const int j = jr[u][l];
+                        if (j == 0 || j == M - 1) {
+                            const unsigned in_plane = q[u][l] - (unsigned)j * upl;
+                            const double g = src.wall[(j == 0 ? 0u : upl) + in_plane];
+                            val[u][l] -= (j == 0 ? tb.lyc_lo[0] : tb.lyc_up[M - 1]) * g;
+                        }
+                    }
+            }
         } else {
             // divergence: (u_{i+1} - u_i)/dx + (v_{j+1} - v_j)/dy_j + (w_{k+1} - w_k)/dz, times sc
             const T *uu = (const T *)src.a, *vv = (const T *)src.b, *ww = (const T *)src.c;
@@ -250,6 +265,7 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
     src.a = member_ptr(src.a, b.ms);
     src.b = member_ptr(src.b, b.ms);
     src.c = member_ptr(src.c, b.ms);
+    if (src.wall) src.wall = member_ptr(src.wall, b.ms);
     clock = member_ptr(clock, b.ms);
     const double ch = member_ptr(b.phys, b.ms)->ch;
     double2 *out = member_ptr(spec, b.ms) + prob * nspec;

@@ -381,6 +381,12 @@ hipError_t launch_plane_sums(nspnp_state *s, int /*what*/, double *dev_out) {
     return hipGetLastError();
 }
 
+// n doubles at p (on this handle's device) set to v, on the solver's stream
+hipError_t launch_fill(nspnp_state *s, double *p, int64_t n, double v) {
+    k_fill<<<dim3(1, 1, 1), 256, 0, s->stream>>>(p, n, v, 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_stats_reset(nspnp_state *s) {
     k_fill<<<dim3(1, 1, (unsigned)s->nmem), 256, 0, s->stream>>>(s->stats, 3 * (int64_t)s->d.M + 2, 0.0, s->mstride);
     return hipGetLastError();

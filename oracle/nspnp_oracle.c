@@ -69,7 +69,8 @@ typedef struct {
     double dt;            /* > 0: fixed full RK step; <= 0: adaptive       */
     double cfl;           /* CFL number for the adaptive step              */
     int32_t nx, ny, nz;   /* ny = number of wall-normal NODES              */
-    int32_t pad;
+    int32_t implicit_xz;  /* 1: diffusion implicit in x and z too, by the
+                             three-direction approximate factorisation    */
 } or_config;
 
 enum { F_U = 0, F_V, F_W, F_CP, F_CM, F_PHI, F_P, F_NFIELD };
@@ -524,6 +525,7 @@ void or_ion_explicit(const or_solver *s, const double *u, const double *v, const
                              0.5 * (cc + czm) * (phi[c0] - phi[IDX(s, i, j, km)]) / dz) / dz;
                 double my = (ft - fb) / s->dn[j];
                 double dxx = (cxp - 2.0 * cc + cxm) / (dx * dx) + (czp - 2.0 * cc + czm) / (dz * dz);
+                if (s->cfg.implicit_xz) dxx = 0.0; /* treated implicitly (or_substep) */
                 out[c0] = -(ax + ay + az) + kd * (dxx + zs * (mx + my + mz));
             }
 }
@@ -541,10 +543,12 @@ void or_explicit_terms(const or_solver *s, double *hu, double *hv, double *hw, d
     or_lap_xz(s, v, lv);
     or_lap_xz(s, w, lw);
     or_coulomb(s, cp, cm, phi, fu, fv, fw);
+    /* with the three-direction factorisation the x/z diffusion is implicit */
+    double ixz = s->cfg.implicit_xz ? 0.0 : ire;
     for (size_t q = 0; q < n; q++) {
-        hu[q] = -hu[q] + ire * lu[q] + fu[q];
-        hw[q] = -hw[q] + ire * lw[q] + fw[q];
-        hv[q] = -hv[q] + ire * lv[q] + fv[q];
+        hu[q] = -hu[q] + ixz * lu[q] + fu[q];
+        hw[q] = -hw[q] + ixz * lw[q] + fw[q];
+        hv[q] = -hv[q] + ixz * lv[q] + fv[q];
     }
     /* v on the bottom wall node is not an unknown */
     for (int k = 0; k < s->nz; k++)
@@ -772,7 +776,7 @@ double or_compute_dt(const or_solver *s) {
     if (cmax > 0.0) { double d = 2.0 * s->cfg.debye * s->cfg.debye * rs / cmax; if (d < dt) dt = d; }
     double nu_min = (re < rs) ? re : rs;
     double d2 = nu_min / (4.0 / (s->dx * s->dx) + 4.0 / (s->dz * s->dz));
-    if (d2 < dt) dt = d2;
+    if (!s->cfg.implicit_xz && d2 < dt) dt = d2; /* no explicit diffusion limit when implicit */
     return dt;
 }
 
@@ -808,6 +812,46 @@ static void or_cn_solve(const or_solver *s, const double *lo, const double *di, 
     }
 }
 
+/* Solve (I - beta L_d) x = r along every periodic line of direction d
+ * (0: x, 1: z), L_d the three-point operator (q_{+1} - 2 q + q_{-1}) / h^2.
+ * The matrix is circulant, so each Fourier mode m of a line is divided by
+ * 1 + beta (2 - 2 cos(2 pi m / N)) / h^2 (the three-point symbol). */
+void or_xz_solve(const or_solver *s, int d, double beta, double *r) {
+    int N = d == 0 ? s->nx : s->nz;
+    double h = d == 0 ? s->dx : s->dz;
+    int nlines = s->M * (d == 0 ? s->nz : s->nx);
+#pragma omp parallel
+    {
+        or_fft_plan pf, pb;
+        or_fft_plan_init(&pf, N, -1);
+        or_fft_plan_init(&pb, N, +1);
+        double *lr = (double *)malloc(2 * (size_t)N * sizeof(double)), *li = lr + N;
+#pragma omp for
+        for (int L = 0; L < nlines; L++) {
+            int j = L / (d == 0 ? s->nz : s->nx), o = L % (d == 0 ? s->nz : s->nx);
+            for (int m = 0; m < N; m++) {
+                size_t c = d == 0 ? IDX(s, m, j, o) : IDX(s, o, j, m);
+                lr[m] = r[c];
+                li[m] = 0.0;
+            }
+            or_fft_line(&pf, lr, li);
+            for (int m = 0; m < N; m++) {
+                double sym = 1.0 + beta * (2.0 - 2.0 * cos(2.0 * M_PI * m / N)) / (h * h);
+                lr[m] /= sym;
+                li[m] /= sym;
+            }
+            or_fft_line(&pb, lr, li);
+            for (int m = 0; m < N; m++) {
+                size_t c = d == 0 ? IDX(s, m, j, o) : IDX(s, o, j, m);
+                r[c] = lr[m] / N;
+            }
+        }
+        or_fft_plan_free(&pf);
+        or_fft_plan_free(&pb);
+        free(lr);
+    }
+}
+
 void or_substep(or_solver *s) {
     int k = s->stage, M = s->M;
     size_t n = or_ncell(s);
@@ -824,6 +868,8 @@ void or_substep(or_solver *s) {
      *   r = dt [gam H^k + zet H^{k-1} - alp G p^k + alp nu L_y q^k]  */
     double *ly = (double *)malloc(n * sizeof(double));
     double *r = (double *)malloc(n * sizeof(double));
+    int imp = s->cfg.implicit_xz;
+    double *lxz = imp ? (double *)malloc(n * sizeof(double)) : NULL;
     double *p = s->f[F_P];
     double *lo = (double *)malloc(3 * M * sizeof(double)), *di = lo + M, *up = di + M;
     for (int q = 0; q < 5; q++) {
@@ -833,6 +879,14 @@ void or_substep(or_solver *s) {
         else if (q == F_W) or_apply_ly_centre(s, fq, 1, 0.0, 0.0, ly);
         else if (q == F_V) or_apply_ly_node(s, fq, ly);
         else or_apply_ly_centre(s, fq, 0, 0.0, 0.0, ly);
+        /* three-direction factorisation: the x/z diffusion joins the implicit part */
+        if (imp) {
+            or_lap_xz(s, fq, lxz);
+            for (size_t c0 = 0; c0 < n; c0++) ly[c0] += lxz[c0];
+            if (q == F_V)
+                for (int kk = 0; kk < s->nz; kk++)
+                    for (int i = 0; i < s->nx; i++) ly[IDX(s, i, 0, kk)] = 0.0;
+        }
         for (int j = 0; j < M; j++)
             for (int kk = 0; kk < s->nz; kk++)
                 for (int i = 0; i < s->nx; i++) {
@@ -844,8 +898,10 @@ void or_substep(or_solver *s) {
                     double hold = (k > 0) ? s->hold[q][c0] : 0.0;
                     r[c0] = dt * (gam * h[q][c0] + zet * hold - alp * gp + alp * nu * ly[c0]);
                 }
-        /* implicit wall-normal diffusion: (I - alp dt nu / 2 L_y) delta = r */
+        /* implicit wall-normal diffusion: (I - alp dt nu / 2 L_y) delta = r;
+         * factorised: (I - beta L_x)(I - beta L_y)(I - beta L_z) delta = r */
         double beta = 0.5 * alp * dt * nu;
+        if (imp) or_xz_solve(s, 0, beta, r);
         if (q == F_V) {
             or_ly_node(s, lo, di, up);
             or_cn_solve(s, lo, di, up, beta, 1, r);
@@ -855,6 +911,7 @@ void or_substep(or_solver *s) {
             or_ly_centre(s, (q == F_CP || q == F_CM) ? 0 : 1, lo, di, up);
             or_cn_solve(s, lo, di, up, beta, 0, r);
         }
+        if (imp) or_xz_solve(s, 1, beta, r);
         for (size_t c0 = 0; c0 < n; c0++) fq[c0] += r[c0];
     }
     free(lo);
@@ -870,8 +927,13 @@ void or_substep(or_solver *s) {
     or_poisson(s, 0, r, psi);
     or_sub_gradient(s, psi, alp * dt);
     or_apply_ly_centre(s, psi, 0, 0.0, 0.0, ly);
+    if (imp) { /* the pressure update follows the implicit operator: full Laplacian */
+        or_lap_xz(s, psi, lxz);
+        for (size_t c0 = 0; c0 < n; c0++) ly[c0] += lxz[c0];
+    }
     for (size_t c0 = 0; c0 < n; c0++) p[c0] += psi[c0] - 0.5 * alp * dt / re * ly[c0];
     free(psi);
+    free(lxz);
     free(ly);
     free(r);
 

@@ -41,7 +41,8 @@ class _Config(ctypes.Structure):
         ("debye", ctypes.c_double), ("vhat", ctypes.c_double), ("u_top", ctypes.c_double),
         ("u_bot", ctypes.c_double), ("force_sign", ctypes.c_double), ("dt", ctypes.c_double),
         ("cfl", ctypes.c_double),
-        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("implicit_xz", ctypes.c_int32),
     ]
 
 
@@ -84,6 +85,7 @@ def _load():
         "or_solve_potential": (None, [_P]),
         "or_refresh_potential": (None, [_P]),
         "or_set_wall_potential": (None, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+        "or_xz_solve": (None, [_P, ctypes.c_int, ctypes.c_double, _D]),
         "or_compute_dt": (ctypes.c_double, [_P]),
         "or_substep": (None, [_P]),
         "or_run": (None, [_P, ctypes.c_int]),
@@ -111,7 +113,7 @@ def _ptr(a: np.ndarray):
 
 DEFAULTS = dict(lx=2 * np.pi, lz=np.pi, stretch=1.5, re=400.0, sc=1.0, beta=0.5, debye=0.1,
                 vhat=5.0, u_top=1.0, u_bot=-1.0, force_sign=-1.0, dt=1e-3, cfl=0.5,
-                nx=32, ny=33, nz=32)
+                nx=32, ny=33, nz=32, implicit_xz=0)
 
 
 def make_config(**kw) -> _Config:
@@ -122,7 +124,7 @@ def make_config(**kw) -> _Config:
     d.update(kw)
     c = _Config()
     for k, v in d.items():
-        setattr(c, k, int(v) if k in ("nx", "ny", "nz") else float(v))
+        setattr(c, k, int(v) if k in ("nx", "ny", "nz", "implicit_xz") else float(v))
     return c
 
 
@@ -254,6 +256,12 @@ class Oracle:
         self._wall = arrs  # keep the buffers alive for the call
         ptr = [None if a is None else _ptr(a) for a in arrs]
         self._lib.or_set_wall_potential(self._h, ptr[0], ptr[1])
+
+    def xz_solve(self, d: int, beta: float, r: np.ndarray) -> np.ndarray:
+        """(I - beta L_d)^-1 r along the periodic lines of direction d (0: x, 1: z)."""
+        a = np.ascontiguousarray(r, dtype=np.float64).copy()
+        self._lib.or_xz_solve(self._h, int(d), float(beta), _ptr(a))
+        return a
 
     def solve_potential(self):
         self._lib.or_solve_potential(self._h)

@@ -14,6 +14,7 @@ bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -48,7 +49,9 @@ def kernel_bytes(cfg, name: str, launches: int, substeps: int) -> float:
     sp = 16.0 * (cfg.nx // 2 + 1) / cfg.nx
     per = {
         "explicit_rhs": 7 * w + 5 * w + 5 * w * (2.0 / 3.0) + 5 * w * (2.0 / 3.0),
-        "cn_tridiag": 5 * 3 * w,
+        # implicit wall-normal diffusion: r and the field read, the field written; with the
+        # three-direction factorisation x-lines (r in place), y (r in place), z-lines (q += x)
+        "cn_tridiag": 5 * (7 if getattr(cfg, "implicit_xz", 0) else 3) * w,
         "fft_x_r2c": 5 * w + 2 * sp,
         "fft_z_fwd": 4 * sp,
         "thomas_modes": 4 * sp,
@@ -94,6 +97,8 @@ def main():
     ap.add_argument("--stats-every", type=int, default=0,
                     help="also sample the run statistics every N substeps in the timed regions "
                          "(a separate measurement; the default line has no sampling)")
+    ap.add_argument("--implicit-xz", action="store_true",
+                    help="diffusion implicit in x and z too (three-direction approximate factorisation)")
     ap.add_argument("--wall-amplitude", type=float, default=0.0,
                     help="time with a wall-potential pattern A cos(x) cos(2z) on both walls "
                          "(a separate measurement of the inhomogeneous potential solve)")
@@ -116,6 +121,8 @@ def main():
     if args.precision is None:  # the large case is quoted in its mixed form
         args.precision = "mixed" if args.workload == "couette_large" else "fp64"
     cfg = P.configs.WORKLOADS[args.workload](precision=args.precision)
+    if args.implicit_xz:
+        cfg = dataclasses.replace(cfg, implicit_xz=1)
     print(f"[bench] workload {args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz} {args.precision}", file=sys.stderr,
           flush=True)
     if args.copy_calibration_mb > 0:
@@ -218,7 +225,8 @@ def main():
                                f"debye={cfg.debye:g} vhat={cfg.vhat:g} {args.precision}",
                    "points": cfg.points, "cells": cfg.cells, "precision": args.precision,
                    "parallelism": "single GPU", **({"stats_every": args.stats_every} if args.stats_every else {}),
-                   **({"wall_amplitude": args.wall_amplitude} if args.wall_amplitude else {})},
+                   **({"wall_amplitude": args.wall_amplitude} if args.wall_amplitude else {}),
+                   **({"implicit_xz": 1} if args.implicit_xz else {})},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes/launch",
                      "algorithmic_bytes_per_launch": per_launch_bytes,

@@ -101,6 +101,14 @@ typedef struct nspnp_config {
     double dt, cfl;
     uint64_t seed;
     double u_noise, c_noise;
+    /* 1: diffusion implicit in x and z as well as y, by the three-direction
+     * tridiagonal approximate factorisation of the base solver (Sec. II):
+     * (I - b L_x)(I - b L_y)(I - b L_z) delta = r, b = alpha dt nu / 2, the
+     * x/z diffusion leaving H for the implicit part, the pressure update
+     * using the full Laplacian of psi and the dt rule dropping its explicit
+     * diffusion limit.  0: only the wall-normal diffusion is implicit. */
+    int32_t implicit_xz;
+    int32_t reserved; /* 0 */
 } nspnp_config;
 
 typedef struct nspnp_state nspnp_state;
@@ -235,8 +243,7 @@ NSPNP_API int nspnp_stats_read(nspnp_state *s, double *time, int64_t *samples, d
  * little-endian arrays.  nspnp_load restores it into a handle initialised
  * with the same configuration (seed and noise amplitudes may differ); the
  * run, and its statistics, then continue bit for bit as the saved one
- * would have.  Files of the first format (no statistics) still load, with
- * sampling off.  Time statistics of ensembles are not part of it.  Both
+ * would have.  Time statistics of ensembles are not part of it.  Both
  * synchronise; NSPNP_ERR_INVALID for an unreadable, foreign or mismatching
  * file. */
 NSPNP_API int nspnp_save(nspnp_state *s, const char *path);

@@ -40,6 +40,7 @@ class _CConfig(ctypes.Structure):
         ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
         ("seed", ctypes.c_uint64),
         ("u_noise", ctypes.c_double), ("c_noise", ctypes.c_double),
+        ("implicit_xz", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -66,6 +67,7 @@ class Config:
     seed: int = 0
     u_noise: float = 0.01
     c_noise: float = 1e-3
+    implicit_xz: int = 0  # 1: x/z diffusion implicit too (three-direction factorisation)
 
     def to_c(self) -> _CConfig:
         c = _CConfig()

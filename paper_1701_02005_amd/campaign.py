@@ -4,7 +4,8 @@ profiles of the velocity, ion and potential fields, with error bars.
 
 Pipeline (all GPU work through the HIP library):
 
-1. start: the laminar Couette state of the configuration with a
+1. start: the laminar Couette state of the configuration (ions in the
+   zero-flow equilibrium double layer when the walls are charged) with a
    finite-amplitude disturbance (streamwise rolls, the streaks they carry and
    seeded noise; plane Couette flow is linearly stable, so small noise decays
    and turbulence needs such a trigger), or a checkpoint to resume from;
@@ -71,6 +72,50 @@ def perturbed_start(solver: Solver, amp: float, seed: int, beta: float = 4.0, al
         solver.set_field(name, f.contiguous())
 
 
+def equilibrium_ions(cfg: Config):
+    """Zero-flow equilibrium double layer of the discrete equations (the
+    zero-shear stationary state, Sec. II): every interior face carries zero
+    ion flux, so with the central face value of the migration flux each
+    species' neighbour ratio is c_{j+1}/c_j = (1 -+ dPhi/2) / (1 +- dPhi/2)
+    (dPhi = Phi_{j+1} - Phi_j, Phi = (vhat/2) y + phi); each species' content
+    equals the gap volume (mean 1); phi solves the discrete potential equation
+    with zero wall values.  Returns (c+, c-, phi) per cell row.  Needs
+    |dPhi| < 2 across every face (positive ratios)."""
+    from scipy.optimize import fsolve
+    yn, yc = (np.asarray(a, dtype=np.float64) for a in grid(cfg))
+    M = len(yc)
+    dn = np.diff(yn)
+    dc = np.concatenate([[yc[0] - yn[0]], np.diff(yc), [yn[M] - yc[M - 1]]])
+    e0, lam = 0.5 * cfg.vhat, cfg.debye
+
+    def conc(phi, zs):
+        dphi = e0 * dc[1:M] + np.diff(phi)
+        c = np.concatenate([[1.0], np.cumprod((1 - zs * dphi / 2) / (1 + zs * dphi / 2))])
+        return c * 2.0 / np.sum(c * dn)
+
+    def residual(phi):
+        flux = np.diff(np.concatenate([[0.0], phi, [0.0]])) / dc
+        return np.diff(flux) / dn + (conc(phi, 1.0) - conc(phi, -1.0)) / (2 * lam ** 2)
+
+    phi = fsolve(residual, np.zeros(M), xtol=1e-13, maxfev=50000)
+    if np.max(np.abs(residual(phi))) > 1e-7 * max(1.0, 1.0 / lam ** 2):
+        raise RuntimeError("equilibrium double layer: Newton solve did not converge")
+    return conc(phi, 1.0), conc(phi, -1.0), phi
+
+
+def set_equilibrium_ions(solver: Solver, vhat: float | None = None):
+    """c+- of every plane set to the equilibrium double layer (of the run's
+    vhat, or of the given wall voltage); phi re-solved."""
+    import torch
+    cfg = solver.cfg if vhat is None else dataclasses.replace(solver.cfg, vhat=vhat)
+    cp, cm, _ = equilibrium_ions(cfg)
+    shape = (solver.cfg.ny - 1, solver.cfg.nz, solver.cfg.nx)
+    for name, prof in (("cp", cp), ("cm", cm)):
+        t = torch.tensor(prof, dtype=torch.float64, device=solver.device)[:, None, None].expand(shape).contiguous()
+        solver.set_field(name, t)
+    solver.refresh_potential()
+
+
 def batch_means(x: np.ndarray, nbatch: int = 10):
     """Mean of a correlated series and its standard error from nbatch
     contiguous batch means (the batches should be longer than the
@@ -85,11 +130,22 @@ def batch_means(x: np.ndarray, nbatch: int = 10):
 
 def run_campaign(cfg: Config, t_spin: float, t_avg: float, every: int = 10, monitor: float = 0.5,
                  amp: float = 0.3, seed: int = 7, ckpt: str | None = None, ckpt_every: float = 50.0,
-                 resume: str | None = None, log=print) -> dict:
+                 resume: str | None = None, ion_start: str = "equilibrium", t_charge: float | None = None,
+                 log=print) -> dict:
+    """t_charge (optional): the run starts uncharged (the configuration's
+    vhat is applied as wall values -+vhat/2 of phi, a discretely identical
+    form of the same walls, only from t_charge on, together with the
+    equilibrium double layer); turbulence then develops before the double
+    layer meets it.  Not combined with resume."""
+    wall_v = 0.0
+    if t_charge is not None:
+        wall_v, cfg = cfg.vhat, dataclasses.replace(cfg, vhat=0.0)
     s = Solver(cfg)
     if resume:
         s.load(resume)
     else:
+        if ion_start == "equilibrium" and cfg.vhat != 0.0:
+            set_equilibrium_ions(s)  # the double layer forms on the gap's ion transit time otherwise
         perturbed_start(s, amp, seed)
     t0 = time.time()
     hist = []  # (t, tau_bottom, tau_top)
@@ -99,9 +155,24 @@ def run_campaign(cfg: Config, t_spin: float, t_avg: float, every: int = 10, moni
         s.stats_begin(every)
     t_end = t_spin + t_avg
 
+    charged = {"done": t_charge is None}
+
+    def charge_walls():
+        import torch
+        plane = torch.ones((cfg.nz, cfg.nx), dtype=torch.float64, device=s.device)
+        s.set_wall_potential(-0.5 * wall_v * plane, 0.5 * wall_v * plane)
+        if ion_start == "equilibrium":
+            set_equilibrium_ions(s, vhat=wall_v)
+        else:
+            s.refresh_potential()
+        charged["done"] = True
+        log(f"[campaign] walls charged to -+{wall_v / 2:g} at t = {state['t']:.2f}")
+
     def advance():
         while state["t"] < t_end:
             t, dt = state["t"], state["dt"]
+            if not charged["done"] and t >= t_charge:
+                charge_walls()
             if not state["averaging"] and t >= t_spin:
                 s.stats_begin(every)
                 state["averaging"] = True
@@ -135,14 +206,17 @@ def run_campaign(cfg: Config, t_spin: float, t_avg: float, every: int = 10, moni
         log(f"[campaign] stopped at t = {state['t']:.2f}: {e}")
     wall = time.time() - t0
     st = s.statistics()
+    if st["samples"] == 0:  # nothing averaged: no statistics to report
+        for k in ("cf", "re_tau", "tau", "tau_bottom", "tau_top"):
+            st[k] = float("nan")
     h = np.array(hist)
     avg_win = h[h[:, 0] > t_spin] if len(h) else h
     tau_series = 0.5 * (avg_win[:, 1] + avg_win[:, 2]) if len(avg_win) else np.array([])
     tau_mean, tau_se = batch_means(tau_series)
     cf_se = 2.0 * tau_se
-    re_tau_se = cfg.re * 0.5 * tau_se / math.sqrt(abs(st["tau"])) if st["tau"] else float("nan")
+    re_tau_se = cfg.re * 0.5 * tau_se / math.sqrt(abs(st["tau"])) if st["tau"] > 0 else float("nan")
     return {
-        "config": dataclasses.asdict(cfg),
+        "config": dataclasses.asdict(cfg), "ion_start": ion_start, "t_charge": t_charge, "wall_vhat": wall_v,
         "t_spin": t_spin, "t_avg": t_avg, "sample_every": every, "samples": st["samples"],
         "averaged_time": st["time"], "substeps": int(state["ns"]), "wall_s": wall, "stopped": stopped,
         "cf": st["cf"], "cf_stderr": cf_se, "re_tau": st["re_tau"], "re_tau_stderr": re_tau_se,
@@ -169,6 +243,11 @@ def main():
     ap.add_argument("--amp", type=float, default=0.3)
     ap.add_argument("--ckpt", default=None)
     ap.add_argument("--resume", default=None)
+    ap.add_argument("--ion-start", default="equilibrium", choices=["equilibrium", "uniform"],
+                    help="ions from the zero-flow equilibrium double layer or uniform (c+- = 1)")
+    ap.add_argument("--t-charge", type=float, default=None,
+                    help="start uncharged and apply the wall voltage (with the equilibrium double layer) "
+                         "at this time")
     ap.add_argument("--out", default="campaign_report.json")
     a = ap.parse_args()
     cfg = configs.WORKLOADS[a.workload](precision=a.precision)
@@ -178,6 +257,7 @@ def main():
             over[k] = getattr(a, k)
     cfg = dataclasses.replace(cfg, **over)
     rep = run_campaign(cfg, a.t_spin, a.t_avg, every=a.every, amp=a.amp, ckpt=a.ckpt, resume=a.resume,
+                       ion_start=a.ion_start, t_charge=a.t_charge,
                        log=lambda m: print(m, flush=True))
     Path(a.out).write_text(json.dumps(rep, indent=1) + "\n")
     if rep["stopped"]:

@@ -64,12 +64,13 @@ int check_config(const nspnp_config *c) {
         !std::isfinite(c->u_bot) || !std::isfinite(c->force_sign) || !std::isfinite(c->dt))
         return fail(NSPNP_ERR_INVALID, "non-finite configuration value");
     if (c->dt <= 0.0 && !(c->cfl > 0.0)) return fail(NSPNP_ERR_INVALID, "adaptive dt needs cfl > 0");
+    if (c->implicit_xz != 0 && c->implicit_xz != 1) return fail(NSPNP_ERR_INVALID, "implicit_xz must be 0 or 1");
     return NSPNP_OK;
 }
 
 struct Layout {
     size_t off_f[7], off_h[5], off_r[5], off_psi, off_spec, off_fac, off_coef, off_clock, off_phys, off_stats,
-        off_rstats, off_phiw, off_red, off_tab;
+        off_rstats, off_phiw, off_cyc, off_red, off_tab;
     size_t ntab, nred, total;
 };
 
@@ -94,6 +95,7 @@ Layout make_layout(const nspnp_config *c) {
     L.off_stats = o; o = align256(o + (3 * M + 2) * 8);
     L.off_rstats = o; o = align256(o + (kRunStatsQ * M + kRunStatsTail) * 8);
     L.off_phiw = o; o = align256(o + 2 * (int64_t)c->nx * c->nz * 8);
+    L.off_cyc = o; o = align256(o + cyc_block_doubles(c->nx, c->nz) * kCycBlocks * 8);
     L.nred = std::max<int64_t>({(int64_t)kDtParts * dt_max_blocks((int64_t)c->nx * c->nz), M * kPlaneQ,
                                  M * (int64_t)run_stats_chunks((int)M) * kRunStatsQ});
     L.off_red = o; o = align256(o + L.nred * 8);
@@ -231,6 +233,7 @@ Phys make_phys(const nspnp_config *cfg) {
     ph.debye = cfg->debye;
     ph.cfl = cfg->cfl;
     ph.adaptive = cfg->dt > 0.0 ? 0.0 : 1.0;
+    ph.implicit_xz = cfg->implicit_xz ? 1.0 : 0.0;
     return ph;
 }
 
@@ -276,6 +279,7 @@ void setup_handle(nspnp_state *s, const nspnp_config *cfg, char *base, int nmem,
     s->rstats = (double *)(base + L.off_rstats);
     s->rstats_every = 0;
     s->phiw = (double *)(base + L.off_phiw);
+    s->cyc = (double *)(base + L.off_cyc);
     s->phiw_on = false;
     s->red = (double *)(base + L.off_red);
     s->nred = L.nred;
@@ -308,6 +312,7 @@ nspnp_state *member_view(const nspnp_state *cls, int m, const nspnp_config *cfg)
     v->stats = sh(cls->stats);
     v->rstats = sh(cls->rstats);
     v->phiw = sh(cls->phiw);
+    v->cyc = sh(cls->cyc);
     v->red = sh(cls->red);
     v->nmem = 1;
     v->mstride = 0;
@@ -706,7 +711,7 @@ int nspnp_sync(nspnp_state *s) {
 namespace {
 struct CkptHeader {
     char magic[8];     // "NSPNPCK1"
-    uint32_t version;  // 1, or 2: followed by CkptStats, the arrays, then the run statistics
+    uint32_t version;  // 3: followed by CkptStats, the arrays, then the run statistics
     uint32_t word;     // bytes per stored value: 8 (FP64) or 4 (mixed)
     nspnp_config cfg;
     double clock[kClockSlots];
@@ -729,7 +734,7 @@ bool same_run(const nspnp_config &a, const nspnp_config &b) {
     return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.precision == b.precision && a.lx == b.lx &&
            a.lz == b.lz && a.stretch == b.stretch && a.re == b.re && a.sc == b.sc && a.beta == b.beta &&
            a.debye == b.debye && a.vhat == b.vhat && a.u_top == b.u_top && a.u_bot == b.u_bot &&
-           a.force_sign == b.force_sign && a.dt == b.dt && a.cfl == b.cfl;
+           a.force_sign == b.force_sign && a.dt == b.dt && a.cfl == b.cfl && a.implicit_xz == b.implicit_xz;
 }
 
 struct FileCloser {
@@ -742,7 +747,7 @@ int nspnp_save(nspnp_state *s, const char *path) {
     if (!s || !path) return fail(NSPNP_ERR_INVALID, "bad save arguments");
     CkptHeader h{};
     std::memcpy(h.magic, kCkptMagic, 8);
-    h.version = 2;
+    h.version = 3;
     h.word = (uint32_t)s->wsize;
     h.cfg = s->cfg;
     h.substeps = s->substeps;
@@ -776,12 +781,12 @@ int nspnp_load(nspnp_state *s, const char *path) {
     FileCloser fc{std::fopen(path, "rb")};
     if (!fc.f) return fail(NSPNP_ERR_INVALID, std::string("load: cannot open ") + path);
     CkptHeader h{};
-    if (std::fread(&h, sizeof(h), 1, fc.f) != 1 || std::memcmp(h.magic, kCkptMagic, 8) != 0 ||
-        (h.version != 1 && h.version != 2))
-        return fail(NSPNP_ERR_INVALID, "load: not a checkpoint of this library");
+    // (earlier formats held a shorter configuration record and are not read)
+    if (std::fread(&h, sizeof(h), 1, fc.f) != 1 || std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 3)
+        return fail(NSPNP_ERR_INVALID, "load: not a checkpoint of this library version");
     CkptStats cs{0, 0, 0};
-    if (h.version == 2 && (std::fread(&cs, sizeof(cs), 1, fc.f) != 1 || cs.every < 0 ||
-                           cs.count != (int64_t)kRunStatsQ * s->d.M + kRunStatsTail))
+    if (std::fread(&cs, sizeof(cs), 1, fc.f) != 1 || cs.every < 0 ||
+        cs.count != (int64_t)kRunStatsQ * s->d.M + kRunStatsTail)
         return fail(NSPNP_ERR_INVALID, "load: bad statistics record");
     if (h.word != s->wsize || h.cells != s->d.n || !same_run(h.cfg, s->cfg))
         return fail(NSPNP_ERR_INVALID, "load: the checkpoint was written for a different configuration");
@@ -794,7 +799,7 @@ int nspnp_load(nspnp_state *s, const char *path) {
         HIP_TRY(hipMemcpyAsync(dst, buf.data(), bytes, hipMemcpyHostToDevice, s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
     }
-    if (h.version == 2) {
+    {
         std::vector<double> st((size_t)cs.count);
         if (std::fread(st.data(), sizeof(double), st.size(), fc.f) != st.size())
             return fail(NSPNP_ERR_INVALID, "load: truncated file");
@@ -805,7 +810,7 @@ int nspnp_load(nspnp_state *s, const char *path) {
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->substeps = h.substeps;
     s->cn_fresh = false;
-    s->rstats_every = cs.every;  // version 1 files carry no statistics: sampling off
+    s->rstats_every = cs.every;
     if (s->host_health) {
         s->host_health[0] = h.clock[2];
         s->host_health[1] = h.clock[3];

@@ -41,7 +41,7 @@ namespace {
 
 bool same_class(const nspnp_config &a, const nspnp_config &b) {
     return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.lx == b.lx && a.lz == b.lz && a.stretch == b.stretch &&
-           a.precision == b.precision && ((a.dt > 0.0) == (b.dt > 0.0));
+           a.precision == b.precision && ((a.dt > 0.0) == (b.dt > 0.0)) && a.implicit_xz == b.implicit_xz;
 }
 
 // classes in order of first appearance; returns per-member class ids
@@ -122,7 +122,7 @@ int check_members(const nspnp_ensemble *e) {
 std::string tune_key(const nspnp_state *c) {
     std::ostringstream k;
     k << "gfx950v5:" << c->cfg.nx << "x" << c->cfg.ny << "x" << c->cfg.nz << ":" << (c->fp64 ? "fp64" : "mixed")
-      << ":" << c->nmem;
+      << ":" << c->nmem << (c->cfg.implicit_xz ? ":ixz" : "");
     return k.str();
 }
 

@@ -60,6 +60,7 @@ struct Phys {
     double u_top, u_bot;
     double debye, cfl;
     double adaptive;    // 1: dt from the CFL rule at stage 1; 0: fixed dt
+    double implicit_xz; // 1: x/z diffusion implicit (no explicit diffusion limit on dt)
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
@@ -183,6 +184,14 @@ constexpr int kRunStatsFields = 7;
 constexpr int kRunStatsQ = 2 * kRunStatsFields;
 constexpr int kRunStatsTail = 4;  // accumulated time, time of the last sample, samples, unused
 constexpr int kStatCloseThreads = 256;
+
+// Implicit x/z diffusion: one block of doubles per (stage, velocity or ion
+// diffusivity, direction): recurrence coefficients g, m, n and the
+// periodic-correction vector z (Nmax each), then [e/gamma, 1/(1 + v.z), -, -].
+constexpr int kCycBlocks = 3 * 2 * 2;
+__host__ __device__ inline int64_t cyc_block_doubles(int nx, int nz) {
+    return 4 * (int64_t)(nx > nz ? nx : nz) + 4;
+}
 // Blocks per row of the statistics pass: about 2048 blocks over the grid
 // (at least one per row, at most 32); its partial sums, kRunStatsQ per block,
 // live in the reduction scratch.
@@ -250,6 +259,7 @@ struct nspnp_state {
     bool stats_on;
     double *rstats;      // run statistics: kRunStatsQ time sums per row, then [time, t_last, samples, -]
     double *phiw;        // wall values of phi: lower-wall plane, then upper-wall plane (FP64)
+    double *cyc;         // implicit x/z diffusion: periodic-line recurrences per stage, nu and direction
     bool phiw_on = false;  // phiw holds nonzero data (else the potential solve skips it)
     int rstats_every = 0;  // sample at the end of every rstats_every-th substep (0: off)
     char *tab_base;      // device tables (member 0)

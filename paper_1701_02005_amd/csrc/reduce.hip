@@ -191,7 +191,8 @@ __global__ void __launch_bounds__(kRedThreads) k_dt_final(int nparts, const doub
         if (s[0][0] > 0.0) dt = ph.cfl / s[0][0];
         if (s[1][0] > 0.0) dt = fmin(dt, 2.0 * ph.debye * ph.debye * rs / s[1][0]);
         const double nu_min = re < rs ? re : rs;
-        dt = fmin(dt, nu_min / (4.0 / (d.dx * d.dx) + 4.0 / (d.dz * d.dz)));
+        if (ph.implicit_xz == 0.0)  // explicit x/z diffusion limit
+            dt = fmin(dt, nu_min / (4.0 / (d.dx * d.dx) + 4.0 / (d.dz * d.dz)));
         int bits = (int)clock[2];
         if (s[3][0] != 0.0) bits |= kHealthNonFinite;
         if (s[2][0] < 0.0) bits |= kHealthNegative;

@@ -51,6 +51,7 @@ struct ExplicitArgs {
     int chunks;     // tiles per (x, z) plane
     int slabs;      // row slabs per member
     int slab_rows;  // rows marched by one block
+    int implicit_xz;  // 1: x/z diffusion goes to the implicit (alpha) part of r, not to H
 };
 
 __device__ __forceinline__ void shift_explicit(ExplicitArgs &a, unsigned mem) {
@@ -144,6 +145,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
     const T gam = T(a.st.gam), zet = T(a.st.zet), alp = T(a.st.alp);
     const bool use_old = (a.st.k > 0) && mode == 0;
     const bool keep = (a.st.k < 2) && mode == 0;
+    const bool imp = a.implicit_xz != 0;  // x/z diffusion: implicit part of r instead of H
     const int e = active ? k * nx + i : 0;
     const int ip = (i + 1 >= nx) ? 0 : i + 1;
     const int kp = (k + 1 >= nz) ? 0 : k + 1;
@@ -234,7 +236,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
                 const T rhox = X(sc, 3, -1, 0) - X(sc, 4, -1, 0);
                 const T f = kf * half * (rho0 + rhox) * (ph0 - X(sc, 5, -1, 0)) * idx_;
                 const T ly = ((ut - uc) * idct - (uc - ub) * idcb) * idn;
-                emit(0, -(cx + cy + cz) + ire * lap + f, (pc - X(sc, 6, -1, 0)) * idx_, ire * ly);
+                const T lapH = imp ? zero : lap, lapI = imp ? lap : zero;
+                emit(0, -(cx + cy + cz) + ire * lapH + f, (pc - X(sc, 6, -1, 0)) * idx_, ire * (ly + lapI));
             }
             __builtin_amdgcn_sched_barrier(0);
             // ---------------- w on the z-face ----------------
@@ -259,7 +262,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
                 const T rhoz = X(sc, 3, 0, -1) - X(sc, 4, 0, -1);
                 const T f = kf * half * (rho0 + rhoz) * (ph0 - X(sc, 5, 0, -1)) * idz_;
                 const T ly = ((wt - wc) * idct - (wc - wb) * idcb) * idn;
-                emit(2, -(cx + cy + cz) + ire * lap + f, (pc - X(sc, 6, 0, -1)) * idz_, ire * ly);
+                const T lapH = imp ? zero : lap, lapI = imp ? lap : zero;
+                emit(2, -(cx + cy + cz) + ire * lapH + f, (pc - X(sc, 6, 0, -1)) * idz_, ire * (ly + lapI));
             }
             __builtin_amdgcn_sched_barrier(0);
             // ---------------- v on the bottom y-face of row j ----------------
@@ -282,7 +286,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
                 const T ey = e0 + (ph0 - fm) * idcb;
                 const T f = kf * half * (rho0 + rhoy) * ey;
                 const T ly = ((vtop - vc) * idn - (vc - vbot) * idn_lo) * idcb;
-                emit(1, -(cx + cy + cz) + ire * lap + f, (pc - pm) * idcb, ire * ly);
+                const T lapH = imp ? zero : lap, lapI = imp ? lap : zero;
+                emit(1, -(cx + cy + cz) + ire * lapH + f, (pc - pm) * idcb, ire * (ly + lapI));
             } else {
                 emit(1, T(0), T(0), T(0));
                 if (mode == 0) ((T *)a.r[1])[q] = T(0);
@@ -326,7 +331,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
                     const T mz = (fzf * gz_f - fzb * gz_b) * idz_;
                     const T my = (mt - mb) * idn;
                     const T dxx = (cxp - two * cc + cxm) * ix2 + (czp - two * cc + czm) * iz2;
-                    emit(fi, -(ax + ay + az) + kd * (dxx + zs * (mx + my + mz)), T(0), kd * (dft - dfb) * idn);
+                    const T dxxH = imp ? zero : dxx;
+                    const T diffI = imp ? kd * ((dft - dfb) * idn + dxx) : kd * (dft - dfb) * idn;
+                    emit(fi, -(ax + ay + az) + kd * (dxxH + zs * (mx + my + mz)), T(0), diffI);
                 }
             }
             // carry row j as row j - 1 of the next step
@@ -355,6 +362,8 @@ struct CnArgs {
     double *scr;   // row-slab method: per member [2][5 fields][slabs][plane] FP64 scratch
     int slab_rows; // row-slab method: rows per slab (0: lane-scan method)
     int slabs;
+    int out_r;     // lane-scan method: write the solution back into r (a factor of the
+                   // three-direction factorisation) instead of q += solution
 };
 
 // Row coefficients of the Crank-Nicolson matrix (I - beta L_y) of system
@@ -497,7 +506,7 @@ __global__ void __launch_bounds__(512) k_cn_scan(CnArgs a) {
     const int64_t pl = a.d.plane;
     const int64_t c0 = (int64_t)blk.x * kCnTx;
     const int ncol = (int)((pl - c0) < kCnTx ? (pl - c0) : kCnTx);
-    const T *__restrict__ r = (const T *)member_ptr_at(a.r[f], ms, blk.z);
+    const T *r = (const T *)member_ptr_at(a.r[f], ms, blk.z);  // may be rewritten in place (out_r)
     T *__restrict__ q = (T *)member_ptr_at(a.q[f], ms, blk.z);
     const double *__restrict__ coef =
         member_ptr_at(a.coef, ms, blk.z) + (size_t)a.st.k * cn_stage_stride(M) + (size_t)sys * 3 * M;
@@ -600,6 +609,14 @@ __global__ void __launch_bounds__(512) k_cn_scan(CnArgs a) {
         }
     }
     __syncthreads();
+    if (a.out_r) {  // a factor of the three-direction factorisation: the solution replaces r
+        T *rw = (T *)member_ptr_at(a.r[f], ms, blk.z);  // r was read before the barrier
+        for (int e = threadIdx.x; e < ntile; e += bd) {
+            const int jj = j0 + e / kCnTx, c = e % kCnTx;
+            if (c < ncol) rw[(unsigned)jj * upl + uc0 + (unsigned)c] = (T)s_r[jj * LD + c];
+        }
+        return;
+    }
     for (int e0 = threadIdx.x; e0 < ntile; e0 += kCnBatch * bd) {
         T v[kCnBatch];
 #pragma unroll
@@ -611,6 +628,227 @@ __global__ void __launch_bounds__(512) k_cn_scan(CnArgs a) {
         for (int u = 0; u < kCnBatch; ++u) {
             const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
             if (e < ntile && c < ncol) q[(unsigned)jj * upl + uc0 + (unsigned)c] = (T)((double)v[u] + s_r[jj * LD + c]);
+        }
+    }
+}
+
+// ---- implicit x/z diffusion (three-direction approximate factorisation) ----
+// (I - b L) x = r along a periodic line of N points, L = (x_{+1} - 2 x + x_{-1}) / h^2,
+// is a cyclic tridiagonal system with constant diagonal d = 1 + 2 b / h^2 and
+// off-diagonal e = -b / h^2.  With gamma = -d, the corners move into a rank-one
+// term (Sherman-Morrison): the tridiagonal B (first diagonal d - gamma, last
+// d - e^2 / gamma) is solved for y = B^-1 r, and x = y - ((y_0 + (e/gamma) y_{N-1})
+// / (1 + z_0 + (e/gamma) z_{N-1})) z with z = B^-1 (gamma, 0, .., 0, e).  B and z
+// are the same for every line of a field, stage and direction: k_cyc_coef makes
+// B's elimination recurrences (d'_i = g_i r_i + m_i d'_{i-1}, x_i = d'_i + n_i
+// x_{i+1}) and z once per Runge-Kutta step.
+struct CycArgs {
+    Dims d;
+    size_t ms;
+    Stage st;
+    void *q[5];
+    void *r[5];
+    const double *cyc;
+    int dir;    // 0: x-lines (contiguous), 1: z-lines (stride nx)
+    int out_r;  // 1: the solution replaces r; 0: q += solution
+};
+
+__global__ void __launch_bounds__(64) k_cyc_coef(Dims d, const Phys *phys, const double *clock, double *cyc,
+                                                 CnStages stages, size_t ms) {
+    phys = member_ptr(phys, ms);
+    clock = member_ptr(clock, ms);
+    cyc = member_ptr(cyc, ms);
+    const int stage = blockIdx.y, sys = threadIdx.x;
+    if (sys >= 4) return;
+    const int ty = sys >> 1, dir = sys & 1;  // diffusivity (velocity, ions), direction
+    const int N = dir == 0 ? d.nx : d.nz;
+    const double h = dir == 0 ? d.dx : d.dz;
+    const double nu = ty == 0 ? phys->ire : phys->kd;
+    const double b = 0.5 * stages.alp[stage] * clock[1] * nu;
+    const double dg = 1.0 + 2.0 * b / (h * h), e = -b / (h * h), gam = -dg;
+    const int64_t nb = cyc_block_doubles(d.nx, d.nz), Nmax = (nb - 4) / 4;
+    double *blk = cyc + ((int64_t)(stage * 2 + ty) * 2 + dir) * nb;
+    double *g = blk, *m = blk + Nmax, *n = blk + 2 * Nmax, *z = blk + 3 * Nmax;
+    double cprev = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const double bi = (i == 0) ? dg - gam : (i == N - 1 ? dg - e * e / gam : dg);
+        const double ai = (i == 0) ? 0.0 : e;
+        const double rden = 1.0 / (bi - ai * cprev);
+        const double ci = (i == N - 1) ? 0.0 : e * rden;
+        g[i] = rden;
+        m[i] = -ai * rden;
+        n[i] = -ci;
+        cprev = ci;
+    }
+    // z = B^-1 u, u = (gamma, 0, ..., 0, e)
+    double dp = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const double ui = (i == 0) ? gam : (i == N - 1 ? e : 0.0);
+        dp = g[i] * ui + m[i] * dp;
+        z[i] = dp;
+    }
+    for (int i = N - 2; i >= 0; --i) z[i] = z[i] + n[i] * z[i + 1];
+    const double vf = e / gam;
+    blk[4 * Nmax] = vf;
+    blk[4 * Nmax + 1] = 1.0 / (1.0 + z[0] + vf * z[N - 1]);
+}
+
+// One tile of kCycTx periodic lines of one field per block, staged in LDS
+// (x-lines: each line contiguous; z-lines: kCycTx neighbouring columns per
+// element, 128-byte runs in FP64); each wave solves one line with its N points
+// split into 64 contiguous lane segments, as in the Crank-Nicolson lane scans,
+// then applies the periodic correction (the line's end values y_0, y_{N-1}
+// broadcast from their lanes).
+constexpr int kCycTx = 16;
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_cyc_scan(CycArgs a) {
+    extern __shared__ double s_l[];
+    const uint3 blk = xcd_block3();
+    const int f = (int)blk.y, ty = f < 3 ? 0 : 1;
+    const int dir = a.dir, nx = a.d.nx, nz = a.d.nz;
+    const int N = dir == 0 ? nx : nz, L = dir == 0 ? nz : nx;  // points per line, lines per row
+    const int ntl = (L + kCycTx - 1) / kCycTx;
+    const int j = (int)blk.x / ntl, l0 = ((int)blk.x - j * ntl) * kCycTx;
+    const int nl = (L - l0) < kCycTx ? (L - l0) : kCycTx;
+    const unsigned upl = (unsigned)a.d.plane, row = (unsigned)j * upl;
+    T *rr = (T *)member_ptr_at(a.r[f], a.ms, blk.z);
+    T *qq = (T *)member_ptr_at(a.q[f], a.ms, blk.z);
+    const int64_t nb = cyc_block_doubles(nx, nz), Nmax = (nb - 4) / 4;
+    const double *cb = member_ptr_at(a.cyc, a.ms, blk.z) + ((int64_t)(a.st.k * 2 + ty) * 2 + dir) * nb;
+    const double *cg = cb, *cm = cb + Nmax, *cn = cb + 2 * Nmax, *cz = cb + 3 * Nmax;
+    const double vf = cb[4 * Nmax], sf = cb[4 * Nmax + 1];
+    constexpr int LD = kCycTx + 1;
+    const int ntile = N * kCycTx, bd = (int)blockDim.x;
+    // element (point i, line c) of the tile: x-lines (l0 + c) nx + i, z-lines i nx + l0 + c
+    auto addr = [&](int i, int c) -> unsigned {
+        return row + (dir == 0 ? (unsigned)(l0 + c) * (unsigned)nx + (unsigned)i : (unsigned)i * (unsigned)nx + (unsigned)(l0 + c));
+    };
+    // staging order: along the contiguous direction of memory (point i, line c of element e)
+    struct IC {
+        int i, c;
+    };
+    auto split = [&](int e) -> IC {
+        if (dir == 0) {
+            const int c = e / N;
+            return IC{e - c * N, c};
+        }
+        const int i = e / kCycTx;
+        return IC{i, e - i * kCycTx};
+    };
+    for (int e0 = threadIdx.x; e0 < ntile; e0 += kCnBatch * bd) {
+        T v[kCnBatch];
+#pragma unroll
+        for (int u = 0; u < kCnBatch; ++u) {
+            const int e = e0 + u * bd;
+            const IC p = split(e < ntile ? e : 0);
+            v[u] = rr[(e < ntile && p.c < nl) ? addr(p.i, p.c) : row];
+        }
+#pragma unroll
+        for (int u = 0; u < kCnBatch; ++u) {
+            const int e = e0 + u * bd;
+            if (e < ntile) {
+                const IC p = split(e);
+                s_l[p.i * LD + p.c] = (p.c < nl) ? (double)v[u] : 0.0;
+            }
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int js = lane * R;
+    double g[R], mm[R], nn[R], zz[R];
+    double Qs = 1.0, Ss = 1.0;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const int i = js + t;
+        const bool in = i < N;
+        g[t] = in ? cg[i] : 0.0;
+        mm[t] = in ? cm[i] : 1.0;
+        nn[t] = in ? cn[i] : 1.0;
+        zz[t] = in ? cz[i] : 0.0;
+        Qs *= mm[t];
+        Ss *= nn[t];
+    }
+    double qm[6], sm[6];
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const int sft = 1 << st;
+        qm[st] = Qs;
+        sm[st] = Ss;
+        const double Qp = __shfl_up(Qs, sft, 64), Sp = __shfl_down(Ss, sft, 64);
+        if (lane >= sft) Qs *= Qp;
+        if (lane + sft < 64) Ss *= Sp;
+    }
+    const int last_lane = (N - 1) / R, last_t = (N - 1) - last_lane * R;
+    for (int c = wave; c < nl; c += nwave) {
+        double *col = s_l + c;
+        double x[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) x[t] = (js + t < N) ? col[(js + t) * LD] : 0.0;
+        double Tf = 0.0;
+#pragma unroll
+        for (int t = 0; t < R; ++t) Tf = g[t] * x[t] + mm[t] * Tf;
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+            const double Tp = __shfl_up(Tf, 1 << st, 64);
+            if (lane >= (1 << st)) Tf += qm[st] * Tp;
+        }
+        double din = __shfl_up(Tf, 1, 64);
+        if (lane == 0) din = 0.0;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            din = g[t] * x[t] + mm[t] * din;
+            x[t] = din;
+        }
+        double U = 0.0;
+#pragma unroll
+        for (int t = R - 1; t >= 0; --t) U = (g[t] != 0.0 ? x[t] : 0.0) + nn[t] * U;
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+            const double Up = __shfl_down(U, 1 << st, 64);
+            if (lane + (1 << st) < 64) U += sm[st] * Up;
+        }
+        double xin = __shfl_down(U, 1, 64);
+        if (lane == 63) xin = 0.0;
+#pragma unroll
+        for (int t = R - 1; t >= 0; --t) {
+            xin = (g[t] != 0.0 ? x[t] : 0.0) + nn[t] * xin;
+            x[t] = xin;
+        }
+        // periodic correction from the line's end values
+        double ylast = 0.0;
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+            if (t == last_t) ylast = x[t];
+        const double y0 = __shfl(x[0], 0, 64);
+        const double yl = __shfl(ylast, last_lane, 64);
+        const double wcor = (y0 + vf * yl) * sf;
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+            if (js + t < N) col[(js + t) * LD] = x[t] - wcor * zz[t];
+    }
+    __syncthreads();
+    for (int e0 = threadIdx.x; e0 < ntile; e0 += kCnBatch * bd) {
+        T v[kCnBatch];
+        if (!a.out_r) {
+#pragma unroll
+            for (int u = 0; u < kCnBatch; ++u) {
+                const int e = e0 + u * bd;
+                const IC p = split(e < ntile ? e : 0);
+                v[u] = qq[(e < ntile && p.c < nl) ? addr(p.i, p.c) : row];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCnBatch; ++u) {
+            const int e = e0 + u * bd;
+            if (e < ntile) {
+                const IC p = split(e);
+                if (p.c < nl) {
+                    const double xs = s_l[p.i * LD + p.c];
+                    if (a.out_r) rr[addr(p.i, p.c)] = (T)xs;
+                    else qq[addr(p.i, p.c)] = (T)((double)v[u] + xs);
+                }
+            }
         }
     }
 }
@@ -792,7 +1030,9 @@ struct CorrArgs {
 
 constexpr int kCorrRows = 4;  // rows per load batch of k_correct
 
-template <typename T>
+// kImp: the pressure update takes the full Laplacian of psi (x/z diffusion
+// implicit too), p += psi - (a / (2 Re)) (L_x + L_y + L_z) psi.
+template <typename T, bool kImp>
 __global__ void __launch_bounds__(256) k_correct(CorrArgs a) {
     const Dims &d = a.d;
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -830,14 +1070,20 @@ __global__ void __launch_bounds__(256) k_correct(CorrArgs a) {
     // field fit in 32 bits.
     const unsigned upl = (unsigned)pl;
     struct RowVals {
-        double s_up, sxm, szm;
+        double s_up, sxm, szm, sxp, szp;
         T u, v, w, p;
     };
+    const int exp_ = e - i + ((i + 1 == nx) ? 0 : i + 1);
+    const int ezp = ((k + 1 == nz) ? 0 : k + 1) * nx + i;
     auto load_row = [&](int j, RowVals &r) {
         const unsigned row = (unsigned)j * upl, q = row + (unsigned)e;
         r.s_up = psi[(j + 1 < M) ? q + upl : q];
         r.sxm = psi[row + (unsigned)exm];
         r.szm = psi[row + (unsigned)ezm];
+        if (kImp) {
+            r.sxp = psi[row + (unsigned)exp_];
+            r.szp = psi[row + (unsigned)ezp];
+        }
         r.u = u[q];
         r.w = w[q];
         r.v = v[q];
@@ -861,7 +1107,9 @@ __global__ void __launch_bounds__(256) k_correct(CorrArgs a) {
             if (a.update_p) {
                 const double ft = (j + 1 < M) ? (s_up - s0) * uniform_load(a.tb.idc, j + 1) : 0.0;
                 const double fb = (j > 0) ? (s0 - s_dn) * idcb : 0.0;
-                const double ly = (ft - fb) * uniform_load(a.tb.idn, j);
+                double ly = (ft - fb) * uniform_load(a.tb.idn, j);
+                if (kImp)
+                    ly += (cur.sxp - 2.0 * s0 + cur.sxm) * (idx * idx) + (cur.szp - 2.0 * s0 + cur.szm) * (idz * idz);
                 p[q] = (T)((double)cur.p + s0 - 0.5 * sc * ire * ly);
             }
             s_dn = s0;
@@ -922,6 +1170,7 @@ hipError_t launch_explicit(nspnp_state *s, const Stage &st, bool /*write_r*/) {
     for (int q = 0; q < 5; ++q) { a.h[q] = s->h[q]; a.r[q] = s->r[q]; a.dbg[q] = nullptr; }
     a.clock = s->clock;
     a.mode = 0;
+    a.implicit_xz = s->cfg.implicit_xz;
     const int tb = s->tiles.expl;
     explicit_tiling(s->d, tb, s->tiles.slab, a);
     return explicit_launch(s, a, tb, (unsigned)((int64_t)a.chunks * a.slabs * s->nmem));
@@ -938,6 +1187,7 @@ hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]) {
     for (int q = 0; q < 5; ++q) { a.h[q] = s->h[q]; a.r[q] = s->r[q]; a.dbg[q] = out[q]; }
     a.clock = s->clock;
     a.mode = 1;
+    a.implicit_xz = s->cfg.implicit_xz;
     explicit_tiling(s->d, 256, s->tiles.slab, a);
     return explicit_launch(s, a, 256, (unsigned)((int64_t)a.chunks * a.slabs));
 }
@@ -948,11 +1198,67 @@ hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]) {
 // elliptic solves.
 int cn_slab_rows(const nspnp_state *s) {
     const int L = s->tiles.cnslab;
-    if (L != 16 && L != 32) return 0;
+    if (L != 16 && L != 32 || s->cfg.implicit_xz) return 0;  // the factorisation uses the lane-scan method
     const int S = (s->d.M + L - 1) / L;
     const int64_t need = 2 * 5 * (int64_t)S * s->d.plane;             // doubles
     const int64_t have = 4 * (int64_t)s->d.nxh * s->d.nz * s->d.M;      // two half spectra
     return (S <= kCnMaxSlabs && need <= have) ? L : 0;
+}
+
+static hipError_t launch_cn_lane(nspnp_state *s, const CnArgs &a);
+
+// Periodic-line solves of the five fields along x (dir 0) or z (dir 1).
+static hipError_t launch_cyc(nspnp_state *s, const Stage &st, int dir, int out_r) {
+    CycArgs c{};
+    c.d = s->d;
+    c.ms = s->mstride;
+    c.st = st;
+    for (int q = 0; q < 5; ++q) { c.q[q] = s->f[q]; c.r[q] = s->r[q]; }
+    c.cyc = s->cyc;
+    c.dir = dir;
+    c.out_r = out_r;
+    const int N = dir == 0 ? s->d.nx : s->d.nz, L = dir == 0 ? s->d.nz : s->d.nx;
+    const dim3 g((unsigned)(s->d.M * ((L + kCycTx - 1) / kCycTx)), 5, (unsigned)s->nmem);
+    const size_t lds = (size_t)N * (kCycTx + 1) * sizeof(double);
+    if (lds > (size_t)s->lds_max) return hipErrorInvalidValue;
+    int rpl = (N + 63) / 64;  // points per lane, rounded up to an instantiated count
+    const int have[] = {1, 2, 3, 4, 6, 8, 12, 16};
+    int R = 0;
+    for (int h : have)
+        if (!R && h >= rpl) R = h;
+    if (!R) return hipErrorInvalidValue;
+    auto go = [&](const void *fn, auto kernel) -> hipError_t {
+        if (lds > 65536) {
+            static const void *opted[64];
+            static int nopted = 0;
+            bool done = false;
+            for (int q = 0; q < nopted; ++q) done = done || opted[q] == fn;
+            if (!done) {
+                const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, s->lds_max);
+                if (e != hipSuccess) return e;
+                if (nopted < 64) opted[nopted++] = fn;
+            }
+        }
+        kernel<<<g, 256, lds, s->stream>>>(c);
+        return hipGetLastError();
+    };
+#define NSPNP_CYC_CASE(RR)                                                                             \
+    case RR:                                                                                           \
+        return s->fp64 ? go((const void *)k_cyc_scan<double, RR>, k_cyc_scan<double, RR>)              \
+                       : go((const void *)k_cyc_scan<float, RR>, k_cyc_scan<float, RR>);
+    switch (R) {
+        NSPNP_CYC_CASE(1)
+        NSPNP_CYC_CASE(2)
+        NSPNP_CYC_CASE(3)
+        NSPNP_CYC_CASE(4)
+        NSPNP_CYC_CASE(6)
+        NSPNP_CYC_CASE(8)
+        NSPNP_CYC_CASE(12)
+        NSPNP_CYC_CASE(16)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef NSPNP_CYC_CASE
 }
 
 hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
@@ -974,6 +1280,9 @@ hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
         for (int q = 0; q < 3; ++q) cs.alp[q] = kRkAlp[q];
         k_cn_coef<<<dim3(1, 3, (unsigned)s->nmem), 256, 0, s->stream>>>(s->d, s->tb, s->d_phys, s->clock,
                                                                        s->cn_coef, cs, a.slab_rows, s->mstride);
+        if (s->cfg.implicit_xz)
+            k_cyc_coef<<<dim3(1, 3, (unsigned)s->nmem), 64, 0, s->stream>>>(s->d, s->d_phys, s->clock, s->cyc, cs,
+                                                                            s->mstride);
         s->cn_fresh = true;
         s->cn_coef_slab = a.slab_rows;
     }
@@ -995,6 +1304,17 @@ hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
         }
         return hipGetLastError();
     }
+    if (!s->cfg.implicit_xz) return launch_cn_lane(s, a);
+    // three-direction factorisation: x-lines into r, y (this solve) into r, then z-lines with q += solution
+    hipError_t e = launch_cyc(s, st, 0, 1);
+    if (e != hipSuccess) return e;
+    a.out_r = 1;
+    if ((e = launch_cn_lane(s, a)) != hipSuccess) return e;
+    return launch_cyc(s, st, 1, 0);
+}
+
+// Lane-scan Crank-Nicolson solve of the five fields (tiles of 16 or 32 columns).
+static hipError_t launch_cn_lane(nspnp_state *s, const CnArgs &a) {
     const int tb = s->tiles.cn;
     const int tcols = cn_tile_cols(tb);
     const dim3 g((unsigned)((s->d.plane + tcols - 1) / tcols), 5, (unsigned)s->nmem);
@@ -1062,8 +1382,13 @@ hipError_t launch_correct(nspnp_state *s, const Stage &st, bool update_p, double
     a.slab_rows = s->tiles.slab;
     a.slabs = (s->d.M + a.slab_rows - 1) / a.slab_rows;
     const dim3 g((unsigned)((int64_t)a.chunks * a.slabs * s->nmem));
-    if (s->fp64) k_correct<double><<<g, tb, 0, s->stream>>>(a);
-    else k_correct<float><<<g, tb, 0, s->stream>>>(a);
+    if (s->cfg.implicit_xz) {
+        if (s->fp64) k_correct<double, true><<<g, tb, 0, s->stream>>>(a);
+        else k_correct<float, true><<<g, tb, 0, s->stream>>>(a);
+    } else {
+        if (s->fp64) k_correct<double, false><<<g, tb, 0, s->stream>>>(a);
+        else k_correct<float, false><<<g, tb, 0, s->stream>>>(a);
+    }
     return hipGetLastError();
 }
 

@@ -34,3 +34,32 @@ def test_batch_means_sees_correlation():
     exact = math.sqrt(1 / (1 - phi ** 2)) * math.sqrt((1 + phi) / (1 - phi)) / math.sqrt(n)
     assert se > 3 * naive
     assert 0.5 < se / exact < 1.6
+
+
+def test_equilibrium_double_layer_is_stationary_in_the_oracle(oracle_mod):
+    """The campaign's zero-flow equilibrium double layer, computed on the
+    host from the discrete zero-flux condition, is left unchanged by the
+    oracle's substeps without shear (ion transport, potential, Coulomb force
+    and pressure all in balance), is mirror-symmetric, and is uniform without
+    voltage."""
+    import dataclasses
+    import paper_1701_02005_amd as P
+    from paper_1701_02005_amd.campaign import equilibrium_ions
+    cfg = dataclasses.replace(P.configs.couette_small(), nx=4, nz=4, ny=33, vhat=4.0, debye=1 / 33, sc=3.0,
+                              re=1.0, u_top=0.0, u_bot=0.0, u_noise=0.0, c_noise=0.0, dt=2e-4)
+    cp, cm, phi = equilibrium_ions(cfg)
+    assert abs(np.sum(cp * np.diff(P.grid(cfg)[0])) - 2.0) < 1e-12
+    assert np.max(np.abs(cp - cm[::-1])) < 1e-10 * cp.max() and cp[0] > 3 and cp[-1] < 0.3
+    oracle_mod.set_threads(1)
+    o = oracle_mod.Oracle(**cfg.oracle_kwargs())
+    o.init(0, 0.0, 0.0)
+    o.field("cp")[...] = cp[:, None, None]
+    o.field("cm")[...] = cm[:, None, None]
+    o.solve_potential()
+    assert np.max(np.abs(o.field("phi")[:, 0, 0] - phi)) < 1e-10 * np.max(np.abs(phi))
+    o.run(30)
+    assert np.max(np.abs(o.field("cp")[:, 0, 0] - cp)) < 1e-10 * cp.max()
+    assert np.max(np.abs(o.field("cm")[:, 0, 0] - cm)) < 1e-10 * cm.max()
+    oracle_mod.set_threads(8)
+    cp0, cm0, phi0 = equilibrium_ions(dataclasses.replace(cfg, vhat=0.0))
+    assert np.max(np.abs(cp0 - 1.0)) < 1e-14 and np.max(np.abs(phi0)) < 1e-14

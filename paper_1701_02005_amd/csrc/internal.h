@@ -104,6 +104,55 @@ __device__ __forceinline__ double uniform_load(const double *p, int i) {
     return ((cdouble *)p)[__builtin_amdgcn_readfirstlane(i)];
 }
 
+// Accesses to data that a kernel touches once (no neighbouring thread or
+// block reads the same element) and that is not handed straight to the next
+// kernel through the last-level cache: the non-temporal hint streams these
+// lines, so they do not displace data that is reused.  The elliptic chain
+// (forward transforms, mode solves, inverse z transform) keeps plain
+// accesses: its two half spectra (about 200 MB at 256 x 193 x 256 in FP64)
+// and the mode pivots stay in the 256 MB Infinity Cache between stages.
+// Stencil halo loads stay plain too (neighbouring tiles re-read them).  Which
+// accesses carry the hint was settled by measurement of the whole substep.
+// NSPNP_NT=0 builds plain accesses everywhere.
+#ifndef NSPNP_NT
+#define NSPNP_NT 1
+#endif
+template <typename T>
+__device__ __forceinline__ T ld_once(const T *p) {
+#if NSPNP_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+template <typename T>
+__device__ __forceinline__ void st_once(T *p, T v) {
+#if NSPNP_NT
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+typedef double nspnp_d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_once(const double2 *p) {
+#if NSPNP_NT
+    const nspnp_d2v v = __builtin_nontemporal_load((const nspnp_d2v *)p);
+    return make_double2(v.x, v.y);
+#else
+    return *p;
+#endif
+}
+__device__ __forceinline__ void st_once(double2 *p, double2 v) {
+#if NSPNP_NT
+    nspnp_d2v w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, (nspnp_d2v *)p);
+#else
+    *p = v;
+#endif
+}
+
 // Per-row quantities of the plane reduction (k_plane), kPlaneQ per row.
 enum PlaneQ {
     PQ_SUM_U = 0, PQ_SUM_CP, PQ_SUM_CM,  // plane sums of u, c+, c-

@@ -187,8 +187,8 @@ __device__ __forceinline__ void r2c_stage(const PoissonSrc &src, const Dims &d, 
             for (int u = 0; u < kXB; ++u)
 #pragma unroll
                 for (int l = 0; l < 2; ++l) {
-                    xp[u][l] = cp[q[u][l]];
-                    xm[u][l] = cm[q[u][l]];
+                    xp[u][l] = ld_once(cp + q[u][l]);
+                    xm[u][l] = ld_once(cm + q[u][l]);
                 }
 #pragma unroll
             for (int u = 0; u < kXB; ++u)
@@ -349,7 +349,7 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
                 const int64_t line = l0 + l;
                 if (line < nlines) {
                     divmod((int)line, nz, r_nz, j, k);
-                    v = in[((int64_t)j * nxh + kk) * nz + k];
+                    v = ld_once(in + ((int64_t)j * nxh + kk) * nz + k);
                 }
             }
             nxt[q] = v;
@@ -385,11 +385,11 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
             const int64_t la = 2 * (pair0 + p), lb = la + 1;
             const double2 v = z[e];
             if (as_state) {
-                if (la < nlines) ot[la * nx + i] = (T)v.x;
-                if (lb < nlines) ot[lb * nx + i] = (T)v.y;
+                if (la < nlines) st_once(ot + la * nx + i, (T)v.x);
+                if (lb < nlines) st_once(ot + lb * nx + i, (T)v.y);
             } else {
-                if (la < nlines) o64[la * nx + i] = v.x;
-                if (lb < nlines) o64[lb * nx + i] = v.y;
+                if (la < nlines) st_once(o64 + la * nx + i, v.x);
+                if (lb < nlines) st_once(o64 + lb * nx + i, v.y);
             }
         }
         __syncthreads();  // o and the result buffer are reused by the next tile

@@ -100,8 +100,8 @@ __global__ void __launch_bounds__(kRedThreads) k_dt_partial(Dims d, Tables tb, c
             r.f1 = phi[qt];
             r.u0 = u[q];
             r.w0 = w[q];
-            r.c1 = cp[q];
-            r.c2 = cm[q];
+            r.c1 = ld_once(cp + q);
+            r.c2 = ld_once(cm + q);
             r.ux = u[row + uxp];
             r.wz = w[row + uzp];
             r.fx = phi[row + uxp];

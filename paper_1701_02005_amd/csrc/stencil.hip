@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
     T hold_c[5], hold_n[5];
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
-        hold_c[f] = (use_old && active) ? ((const T *)a.h[f])[j0 * pl + e] : zero;
+        hold_c[f] = (use_old && active) ? ld_once((const T *)a.h[f] + j0 * pl + e) : zero;
         hold_n[f] = zero;
     }
     {
@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
         if (pre) load_rows(j + 2, rn);  // lands in LDS after this row
         if (use_old && active && j + 1 < j1) {
 #pragma unroll
-            for (int f = 0; f < 5; ++f) hold_n[f] = ((const T *)a.h[f])[(j + 1) * pl + e];
+            for (int f = 0; f < 5; ++f) hold_n[f] = ld_once((const T *)a.h[f] + (j + 1) * pl + e);
         }
         const bool has_up = (j + 1 < M), has_dn = (j > 0);
         const int q = j * pl + e;
@@ -210,8 +210,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
                     return;
                 }
                 T *__restrict__ hb = (T *)a.h[f];
-                ((T *)a.r[f])[q] = dt * (gam * hval + zet * hold_c[f] - alp * gp + alp * nu_ly);
-                if (keep) hb[q] = hval;
+                st_once((T *)a.r[f] + q, dt * (gam * hval + zet * hold_c[f] - alp * gp + alp * nu_ly));
+                if (keep) st_once(hb + q, hval);
             };
 
             // ---------------- u on the x-face ----------------
@@ -525,7 +525,7 @@ __global__ void __launch_bounds__(512) k_cn_scan(CnArgs a) {
 #pragma unroll
         for (int u = 0; u < kCnBatch; ++u) {
             const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
-            v[u] = r[(e < ntile && c < ncol) ? (unsigned)jj * upl + uc0 + (unsigned)c : o_safe];
+            v[u] = ld_once(r + ((e < ntile && c < ncol) ? (unsigned)jj * upl + uc0 + (unsigned)c : o_safe));
         }
 #pragma unroll
         for (int u = 0; u < kCnBatch; ++u) {
@@ -613,7 +613,7 @@ __global__ void __launch_bounds__(512) k_cn_scan(CnArgs a) {
         T *rw = (T *)member_ptr_at(a.r[f], ms, blk.z);  // r was read before the barrier
         for (int e = threadIdx.x; e < ntile; e += bd) {
             const int jj = j0 + e / kCnTx, c = e % kCnTx;
-            if (c < ncol) rw[(unsigned)jj * upl + uc0 + (unsigned)c] = (T)s_r[jj * LD + c];
+            if (c < ncol) st_once(rw + ((unsigned)jj * upl + uc0 + (unsigned)c), (T)s_r[jj * LD + c]);
         }
         return;
     }
@@ -622,12 +622,12 @@ __global__ void __launch_bounds__(512) k_cn_scan(CnArgs a) {
 #pragma unroll
         for (int u = 0; u < kCnBatch; ++u) {
             const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
-            v[u] = q[(e < ntile && c < ncol) ? (unsigned)jj * upl + uc0 + (unsigned)c : o_safe];
+            v[u] = ld_once(q + ((e < ntile && c < ncol) ? (unsigned)jj * upl + uc0 + (unsigned)c : o_safe));
         }
 #pragma unroll
         for (int u = 0; u < kCnBatch; ++u) {
             const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
-            if (e < ntile && c < ncol) q[(unsigned)jj * upl + uc0 + (unsigned)c] = (T)((double)v[u] + s_r[jj * LD + c]);
+            if (e < ntile && c < ncol) st_once(q + ((unsigned)jj * upl + uc0 + (unsigned)c), (T)((double)v[u] + s_r[jj * LD + c]));
         }
     }
 }
@@ -742,7 +742,7 @@ __global__ void __launch_bounds__(256) k_cyc_scan(CycArgs a) {
         for (int u = 0; u < kCnBatch; ++u) {
             const int e = e0 + u * bd;
             const IC p = split(e < ntile ? e : 0);
-            v[u] = rr[(e < ntile && p.c < nl) ? addr(p.i, p.c) : row];
+            v[u] = ld_once(rr + ((e < ntile && p.c < nl) ? addr(p.i, p.c) : row));
         }
 #pragma unroll
         for (int u = 0; u < kCnBatch; ++u) {
@@ -835,7 +835,7 @@ __global__ void __launch_bounds__(256) k_cyc_scan(CycArgs a) {
             for (int u = 0; u < kCnBatch; ++u) {
                 const int e = e0 + u * bd;
                 const IC p = split(e < ntile ? e : 0);
-                v[u] = qq[(e < ntile && p.c < nl) ? addr(p.i, p.c) : row];
+                v[u] = ld_once(qq + ((e < ntile && p.c < nl) ? addr(p.i, p.c) : row));
             }
         }
 #pragma unroll
@@ -845,8 +845,8 @@ __global__ void __launch_bounds__(256) k_cyc_scan(CycArgs a) {
                 const IC p = split(e);
                 if (p.c < nl) {
                     const double xs = s_l[p.i * LD + p.c];
-                    if (a.out_r) rr[addr(p.i, p.c)] = (T)xs;
-                    else qq[addr(p.i, p.c)] = (T)((double)v[u] + xs);
+                    if (a.out_r) st_once(rr + addr(p.i, p.c), (T)xs);
+                    else st_once(qq + addr(p.i, p.c), (T)((double)v[u] + xs));
                 }
             }
         }
@@ -1084,10 +1084,10 @@ __global__ void __launch_bounds__(256) k_correct(CorrArgs a) {
             r.sxp = psi[row + (unsigned)exp_];
             r.szp = psi[row + (unsigned)ezp];
         }
-        r.u = u[q];
-        r.w = w[q];
-        r.v = v[q];
-        r.p = p[q];  // unconditional (p is always allocated): no branch in the batch
+        r.u = ld_once(u + q);
+        r.w = ld_once(w + q);
+        r.v = ld_once(v + q);
+        r.p = ld_once(p + q);  // unconditional (p is always allocated): no branch in the batch
     };
     for (int jb = j0; jb < j1; jb += kCorrRows) {
         RowVals rb[kCorrRows];
@@ -1100,17 +1100,17 @@ __global__ void __launch_bounds__(256) k_correct(CorrArgs a) {
             const RowVals &cur = rb[t];
             const unsigned q = (unsigned)j * upl + (unsigned)e;
             const double s_up = (j + 1 < M) ? cur.s_up : 0.0;
-            u[q] = (T)((double)cur.u - sc * (s0 - cur.sxm) * idx);
-            w[q] = (T)((double)cur.w - sc * (s0 - cur.szm) * idz);
+            st_once(u + q, (T)((double)cur.u - sc * (s0 - cur.sxm) * idx));
+            st_once(w + q, (T)((double)cur.w - sc * (s0 - cur.szm) * idz));
             const double idcb = uniform_load(a.tb.idc, j);
-            if (j > 0) v[q] = (T)((double)cur.v - sc * (s0 - s_dn) * idcb);
+            if (j > 0) st_once(v + q, (T)((double)cur.v - sc * (s0 - s_dn) * idcb));
             if (a.update_p) {
                 const double ft = (j + 1 < M) ? (s_up - s0) * uniform_load(a.tb.idc, j + 1) : 0.0;
                 const double fb = (j > 0) ? (s0 - s_dn) * idcb : 0.0;
                 double ly = (ft - fb) * uniform_load(a.tb.idn, j);
                 if (kImp)
                     ly += (cur.sxp - 2.0 * s0 + cur.sxm) * (idx * idx) + (cur.szp - 2.0 * s0 + cur.szm) * (idz * idz);
-                p[q] = (T)((double)cur.p + s0 - 0.5 * sc * ire * ly);
+                st_once(p + q, (T)((double)cur.p + s0 - 0.5 * sc * ire * ly));
             }
             s_dn = s0;
             s0 = s_up;

@@ -133,6 +133,16 @@ __device__ __forceinline__ void st_once(T *p, T v) {
     *p = v;
 #endif
 }
+// Element at a 32-bit byte offset from a base pointer (the form the
+// hardware's scalar-base + vector-offset addressing takes directly).
+template <typename T>
+__device__ __forceinline__ T *byte_at(T *base, unsigned bytes) {
+    return (T *)((char *)base + bytes);
+}
+template <typename T>
+__device__ __forceinline__ const T *byte_at(const T *base, unsigned bytes) {
+    return (const T *)((const char *)base + bytes);
+}
 typedef double nspnp_d2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ double2 ld_once(const double2 *p) {
 #if NSPNP_NT

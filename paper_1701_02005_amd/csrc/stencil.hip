@@ -84,7 +84,11 @@ struct HaloRegs {
     T v[kNF][kHalo];
 };
 
-template <typename T, int kHalo, int kWaves>
+// kMode (a compile-time copy of ExplicitArgs::mode): the export of H alone
+// is its own instantiation, so the substep kernel carries none of its state.
+// kTz > 0: the tile is 64 columns by kTz z-lines (a.tx, a.tz ignored), so
+// every LDS neighbour offset is a compile-time constant.
+template <typename T, int kHalo, int kWaves, int kMode, int kTz = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) k_explicit(ExplicitArgs a) {
     extern __shared__ unsigned char s_raw[];
     T *sm = (T *)s_raw;  // [slot 0..1][field 0..6][halo tile]
@@ -98,7 +102,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
     const Dims &d = a.d;
     const int nx = d.nx, nz = d.nz, M = d.M;
     const int pl = (int)d.plane;
-    const int tx = a.tx, tz = a.tz, hx = tx + 2, HS = hx * (tz + 2);
+    const int tx = kTz ? 64 : a.tx, tz = kTz ? kTz : a.tz, hx = tx + 2, HS = hx * (tz + 2);
     const int i0 = (int)(chunk % (unsigned)a.ntx) * tx, k0 = (int)(chunk / (unsigned)a.ntx) * tz;
     const int lk = (int)threadIdx.x / tx, li = (int)threadIdx.x - lk * tx;
     const int i = i0 + li, k = k0 + lk;
@@ -107,32 +111,40 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
 
     const T *__restrict__ F[kNF] = {(const T *)a.u, (const T *)a.v, (const T *)a.w, (const T *)a.cp,
                                     (const T *)a.cm, (const T *)a.phi, (const T *)a.p};
-    // halo positions this thread loads: in-plane offsets, fixed for every row
-    int off[kHalo];
+    // halo positions this thread loads: in-plane byte offsets, fixed for every
+    // row.  Positions past the halo tile load the plane's first element
+    // (which exists) and are never stored: the loads are unconditional, so a
+    // row's loads go out together.  Every access is a field's base pointer plus
+    // a 32-bit byte offset (row offset + in-plane offset; a field of every
+    // supported grid is below 2^32 bytes), which the hardware adds itself.
+    unsigned off[kHalo];
     int spos[kHalo];
+    bool in_tile[kHalo];
 #pragma unroll
     for (int q = 0; q < kHalo; ++q) {
         const int sp = (int)threadIdx.x + q * (int)blockDim.x;
         spos[q] = sp;
+        in_tile[q] = sp < HS;
         const int hz = sp / hx, hxp = sp - hz * hx;
         int gi = (i0 - 1 + hxp) % nx, gk = (k0 - 1 + hz) % nz;
         if (gi < 0) gi += nx;
         if (gk < 0) gk += nz;
-        off[q] = (sp < HS) ? gk * nx + gi : -1;
+        off[q] = in_tile[q] ? (unsigned)(gk * nx + gi) * (unsigned)sizeof(T) : 0u;
     }
+    const unsigned plb = (unsigned)pl * (unsigned)sizeof(T);  // bytes per row of a field
     auto load_rows = [&](int row, HaloRegs<T, kHalo> &r) {
-        const int base = row * pl;
+        const unsigned base = (unsigned)row * plb;
 #pragma unroll
         for (int f = 0; f < kNF; ++f)
 #pragma unroll
-            for (int q = 0; q < kHalo; ++q) r.v[f][q] = (off[q] >= 0) ? F[f][base + off[q]] : T(0);
+            for (int q = 0; q < kHalo; ++q) r.v[f][q] = *byte_at(F[f], base + off[q]);
     };
     auto store_rows = [&](int slot, const HaloRegs<T, kHalo> &r) {
 #pragma unroll
         for (int f = 0; f < kNF; ++f)
 #pragma unroll
             for (int q = 0; q < kHalo; ++q)
-                if (off[q] >= 0) sm[(slot * kNF + f) * HS + spos[q]] = r.v[f][q];
+                if (in_tile[q]) sm[(slot * kNF + f) * HS + spos[q]] = r.v[f][q];
     };
     auto X = [&](int slot, int f, int dx, int dz) -> T { return sm[(slot * kNF + f) * HS + c + dz * hx + dx]; };
 
@@ -140,13 +152,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
     const T idx_ = T(1.0 / d.dx), idz_ = T(1.0 / d.dz);
     const T ix2 = idx_ * idx_, iz2 = idz_ * idz_;
     const T kf = T(ph.kf), ire = T(ph.ire), kd = T(ph.kd), e0 = T(ph.e0);
-    const int mode = a.mode;
+    constexpr int mode = kMode;
     const T dt = T(a.clock[1]);
     const T gam = T(a.st.gam), zet = T(a.st.zet), alp = T(a.st.alp);
     const bool use_old = (a.st.k > 0) && mode == 0;
     const bool keep = (a.st.k < 2) && mode == 0;
     const bool imp = a.implicit_xz != 0;  // x/z diffusion: implicit part of r instead of H
     const int e = active ? k * nx + i : 0;
+    const unsigned ueb = (unsigned)e * (unsigned)sizeof(T);  // own column, bytes
     const int ip = (i + 1 >= nx) ? 0 : i + 1;
     const int kp = (k + 1 >= nz) ? 0 : k + 1;
     const int e_xp = k * nx + ip, e_zp = kp * nx + i;
@@ -168,7 +181,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
     T hold_c[5], hold_n[5];
 #pragma unroll
     for (int f = 0; f < 5; ++f) {
-        hold_c[f] = (use_old && active) ? ld_once((const T *)a.h[f] + j0 * pl + e) : zero;
+        hold_c[f] = (use_old && active) ? ld_once(byte_at((const T *)a.h[f], (unsigned)j0 * plb + ueb)) : zero;
         hold_n[f] = zero;
     }
     {
@@ -189,10 +202,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
         if (pre) load_rows(j + 2, rn);  // lands in LDS after this row
         if (use_old && active && j + 1 < j1) {
 #pragma unroll
-            for (int f = 0; f < 5; ++f) hold_n[f] = ld_once((const T *)a.h[f] + (j + 1) * pl + e);
+            for (int f = 0; f < 5; ++f) hold_n[f] = ld_once(byte_at((const T *)a.h[f], (unsigned)(j + 1) * plb + ueb));
         }
         const bool has_up = (j + 1 < M), has_dn = (j > 0);
-        const int q = j * pl + e;
+        const unsigned qb = (unsigned)j * plb + ueb;  // this cell, bytes
         if (active) {
             const T idn = T(uniform_load(a.tb.idn, j));
             const T idcb = T(uniform_load(a.tb.idc, j)), idct = T(uniform_load(a.tb.idc, j + 1));
@@ -205,13 +218,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
             const T uxp = X(sc, 0, 1, 0), wzp = X(sc, 2, 0, 1);
 
             auto emit = [&](int f, T hval, T gp, T nu_ly) {
-                if (mode == 1) {
-                    a.dbg[f][q] = (double)hval;
+                if constexpr (mode == 1) {
+                    a.dbg[f][(size_t)j * (size_t)pl + (unsigned)e] = (double)hval;
                     return;
                 }
-                T *__restrict__ hb = (T *)a.h[f];
-                st_once((T *)a.r[f] + q, dt * (gam * hval + zet * hold_c[f] - alp * gp + alp * nu_ly));
-                if (keep) st_once(hb + q, hval);
+                st_once(byte_at((T *)a.r[f], qb), dt * (gam * hval + zet * hold_c[f] - alp * gp + alp * nu_ly));
+                if (keep) st_once(byte_at((T *)a.h[f], qb), hval);
             };
 
             // ---------------- u on the x-face ----------------
@@ -290,7 +302,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
                 emit(1, -(cx + cy + cz) + ire * lapH + f, (pc - pm) * idcb, ire * (ly + lapI));
             } else {
                 emit(1, T(0), T(0), T(0));
-                if (mode == 0) ((T *)a.r[1])[q] = T(0);
+                if constexpr (mode == 0) st_once(byte_at((T *)a.r[1], qb), T(0));
             }
             __builtin_amdgcn_sched_barrier(0);
             // ---------------- ions at the cell centre ----------------
@@ -1146,12 +1158,26 @@ static void explicit_tiling(const Dims &d, int threads, int slab_rows, ExplicitA
 static hipError_t explicit_launch(nspnp_state *s, const ExplicitArgs &a, int threads, unsigned blocks) {
     const int hs = (a.tx + 2) * (a.tz + 2);
     const size_t lds = 2 * (size_t)kNF * hs * s->wsize;
-    if (hs <= 2 * threads) {
-        if (s->fp64) k_explicit<double, 2, 2><<<blocks, threads, lds, s->stream>>>(a);
-        else k_explicit<float, 2, 3><<<blocks, threads, lds, s->stream>>>(a);
+    const bool dbg = a.mode == 1;
+    if (!dbg && threads == 256 && a.tx == 64 && a.tz == 4) {  // the common 64 x 4 tile
+        if (s->fp64) k_explicit<double, 2, 2, 0, 4><<<blocks, threads, lds, s->stream>>>(a);
+        else k_explicit<float, 2, 3, 0, 4><<<blocks, threads, lds, s->stream>>>(a);
+    } else if (hs <= 2 * threads) {
+        if (s->fp64) {
+            if (dbg) k_explicit<double, 2, 2, 1><<<blocks, threads, lds, s->stream>>>(a);
+            else k_explicit<double, 2, 2, 0><<<blocks, threads, lds, s->stream>>>(a);
+        } else {
+            if (dbg) k_explicit<float, 2, 3, 1><<<blocks, threads, lds, s->stream>>>(a);
+            else k_explicit<float, 2, 3, 0><<<blocks, threads, lds, s->stream>>>(a);
+        }
     } else if (hs <= 4 * threads) {
-        if (s->fp64) k_explicit<double, 4, 2><<<blocks, threads, lds, s->stream>>>(a);
-        else k_explicit<float, 4, 3><<<blocks, threads, lds, s->stream>>>(a);
+        if (s->fp64) {
+            if (dbg) k_explicit<double, 4, 2, 1><<<blocks, threads, lds, s->stream>>>(a);
+            else k_explicit<double, 4, 2, 0><<<blocks, threads, lds, s->stream>>>(a);
+        } else {
+            if (dbg) k_explicit<float, 4, 3, 1><<<blocks, threads, lds, s->stream>>>(a);
+            else k_explicit<float, 4, 3, 0><<<blocks, threads, lds, s->stream>>>(a);
+        }
     } else {
         return hipErrorInvalidValue;
     }

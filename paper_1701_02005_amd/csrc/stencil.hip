@@ -504,7 +504,12 @@ inline int cn_tile_cols(int threads) { return threads > 256 ? 32 : 16; }
 // a local sweep per lane followed by a 6-step scan of affine maps across the
 // wave (x -> T + Q x composed lane by lane) and a second local sweep from the
 // correct incoming value.  Finally q += x with coalesced stores.
-constexpr int kCnBatch = 8;
+// Staging batches of the lane-scan solves: 48 bytes of loads per thread in
+// flight per wait (6 FP64 or 12 FP32 values), measured best for both: more
+// FP64 registers cost occupancy, fewer FP32 loads leave bandwidth unused.
+constexpr int kCnBatchBytes = 48;
+template <typename T>
+constexpr int cn_batch() { return kCnBatchBytes / (int)sizeof(T); }
 
 template <typename T, int kCnTx, int kCnMaxR>
 __global__ void __launch_bounds__(512) k_cn_scan(CnArgs a) {
@@ -526,21 +531,21 @@ __global__ void __launch_bounds__(512) k_cn_scan(CnArgs a) {
     constexpr int LD = kCnTx + 1;
     const int nrow = M - j0;
     const int ntile = nrow * kCnTx, bd = (int)blockDim.x;
-    // Staging in batches of kCnBatch unconditional loads per thread (lanes
+    // Staging in batches of cn_batch<T>() unconditional loads per thread (lanes
     // past the tile read its first element, which exists, and discard it), so
     // that a thread waits for memory once per batch, not once per element.
     // (offsets within one field: rows * plane < 2^32 for every supported grid)
     const unsigned upl = (unsigned)pl, uc0 = (unsigned)c0;
     const unsigned o_safe = (unsigned)j0 * upl + uc0;
-    for (int e0 = threadIdx.x; e0 < ntile; e0 += kCnBatch * bd) {
-        T v[kCnBatch];
+    for (int e0 = threadIdx.x; e0 < ntile; e0 += cn_batch<T>() * bd) {
+        T v[cn_batch<T>()];
 #pragma unroll
-        for (int u = 0; u < kCnBatch; ++u) {
+        for (int u = 0; u < cn_batch<T>(); ++u) {
             const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
             v[u] = ld_once(r + ((e < ntile && c < ncol) ? (unsigned)jj * upl + uc0 + (unsigned)c : o_safe));
         }
 #pragma unroll
-        for (int u = 0; u < kCnBatch; ++u) {
+        for (int u = 0; u < cn_batch<T>(); ++u) {
             const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
             if (e < ntile) s_r[jj * LD + c] = (c < ncol) ? (double)v[u] : 0.0;
         }
@@ -629,15 +634,15 @@ __global__ void __launch_bounds__(512) k_cn_scan(CnArgs a) {
         }
         return;
     }
-    for (int e0 = threadIdx.x; e0 < ntile; e0 += kCnBatch * bd) {
-        T v[kCnBatch];
+    for (int e0 = threadIdx.x; e0 < ntile; e0 += cn_batch<T>() * bd) {
+        T v[cn_batch<T>()];
 #pragma unroll
-        for (int u = 0; u < kCnBatch; ++u) {
+        for (int u = 0; u < cn_batch<T>(); ++u) {
             const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
             v[u] = ld_once(q + ((e < ntile && c < ncol) ? (unsigned)jj * upl + uc0 + (unsigned)c : o_safe));
         }
 #pragma unroll
-        for (int u = 0; u < kCnBatch; ++u) {
+        for (int u = 0; u < cn_batch<T>(); ++u) {
             const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
             if (e < ntile && c < ncol) st_once(q + ((unsigned)jj * upl + uc0 + (unsigned)c), (T)((double)v[u] + s_r[jj * LD + c]));
         }
@@ -748,16 +753,16 @@ __global__ void __launch_bounds__(256) k_cyc_scan(CycArgs a) {
         const int i = e / kCycTx;
         return IC{i, e - i * kCycTx};
     };
-    for (int e0 = threadIdx.x; e0 < ntile; e0 += kCnBatch * bd) {
-        T v[kCnBatch];
+    for (int e0 = threadIdx.x; e0 < ntile; e0 += cn_batch<T>() * bd) {
+        T v[cn_batch<T>()];
 #pragma unroll
-        for (int u = 0; u < kCnBatch; ++u) {
+        for (int u = 0; u < cn_batch<T>(); ++u) {
             const int e = e0 + u * bd;
             const IC p = split(e < ntile ? e : 0);
             v[u] = ld_once(rr + ((e < ntile && p.c < nl) ? addr(p.i, p.c) : row));
         }
 #pragma unroll
-        for (int u = 0; u < kCnBatch; ++u) {
+        for (int u = 0; u < cn_batch<T>(); ++u) {
             const int e = e0 + u * bd;
             if (e < ntile) {
                 const IC p = split(e);
@@ -840,18 +845,18 @@ __global__ void __launch_bounds__(256) k_cyc_scan(CycArgs a) {
             if (js + t < N) col[(js + t) * LD] = x[t] - wcor * zz[t];
     }
     __syncthreads();
-    for (int e0 = threadIdx.x; e0 < ntile; e0 += kCnBatch * bd) {
-        T v[kCnBatch];
+    for (int e0 = threadIdx.x; e0 < ntile; e0 += cn_batch<T>() * bd) {
+        T v[cn_batch<T>()];
         if (!a.out_r) {
 #pragma unroll
-            for (int u = 0; u < kCnBatch; ++u) {
+            for (int u = 0; u < cn_batch<T>(); ++u) {
                 const int e = e0 + u * bd;
                 const IC p = split(e < ntile ? e : 0);
                 v[u] = ld_once(qq + ((e < ntile && p.c < nl) ? addr(p.i, p.c) : row));
             }
         }
 #pragma unroll
-        for (int u = 0; u < kCnBatch; ++u) {
+        for (int u = 0; u < cn_batch<T>(); ++u) {
             const int e = e0 + u * bd;
             if (e < ntile) {
                 const IC p = split(e);

@@ -259,7 +259,9 @@ void setup_handle(nspnp_state *s, const nspnp_config *cfg, char *base, int nmem,
     s->mstride = nmem > 1 ? L.total : 0;
     s->planx = make_plan(cfg->nx);
     s->planz = make_plan(cfg->nz);
-    s->tiles = Tiles{256, 256, 512, 1024, 16, 128, 16, 0};  // the tuner's choice at 256 x 193 x 256 (FP64)
+    // the tuner's choices at 256 x 193 x 256 (the mixed form takes 32-column
+    // Crank-Nicolson tiles: whole 128-byte lines of FP32 per row)
+    s->tiles = Tiles{256, cfg->precision == NSPNP_PREC_FP64 ? 256 : 512, 512, 1024, 16, 128, 16, 0};
     {
         int dev = 0, lds = 0;
         if (hipGetDevice(&dev) == hipSuccess &&

@@ -500,7 +500,7 @@ __global__ void __launch_bounds__(256) k_thomas_factors(Dims d, Tables tb, doubl
 // local sweep per lane, a 6-step scan of affine maps across the wave and a
 // second sweep from the correct incoming value.  The tile is written back
 // with coalesced stores.
-constexpr int kThBatch = 8;
+constexpr int kThBatch = 12;  // a whole 16-mode tile of 192 rows in one batch
 
 template <int R>
 __global__ void __launch_bounds__(256) k_thomas_tile(Dims d, Tables tb, PoissonBatch b, double2 *spec_all,

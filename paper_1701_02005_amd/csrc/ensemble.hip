@@ -121,7 +121,7 @@ int check_members(const nspnp_ensemble *e) {
 // ---- autotuner ----------------------------------------------------------
 std::string tune_key(const nspnp_state *c) {
     std::ostringstream k;
-    k << "gfx950v5:" << c->cfg.nx << "x" << c->cfg.ny << "x" << c->cfg.nz << ":" << (c->fp64 ? "fp64" : "mixed")
+    k << "gfx950v6:" << c->cfg.nx << "x" << c->cfg.ny << "x" << c->cfg.nz << ":" << (c->fp64 ? "fp64" : "mixed")
       << ":" << c->nmem << (c->cfg.implicit_xz ? ":ixz" : "");
     return k.str();
 }

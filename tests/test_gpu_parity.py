@@ -181,3 +181,43 @@ def test_full_size_turbulent_case_matches_oracle(P, O, cnslab, cn):
     tb, tt = g.wall_shear_stress()
     otb, ott = o.wall_shear()
     assert abs(tb - otb) < 1e-10 * otb and abs(tt - ott) < 1e-10 * ott
+
+
+@pytest.mark.parametrize("dims,cn", [((1024, 481, 4), 256), ((4, 481, 1024), 512), ((1024, 481, 4), 512)],
+                         ids=["nx1024-cn16", "nz1024-cn32", "nx1024-cn32"])
+def test_maximum_sizes_match_oracle(P, O, dims, cn):
+    """The largest supported line lengths (1024 points in x or z) with the
+    largest wall-normal count (481 nodes: 480 cell rows, 8 rows per lane in
+    the Crank-Nicolson and mode scans, Crank-Nicolson tiles above 64 KB of
+    LDS): initial state, then two RK steps with the adaptive time step."""
+    nx, ny, nz = dims
+    O.set_threads(16)
+    cfg = cfg_of(P, nx=nx, ny=ny, nz=nz, dt=0.0, cfl=0.5, re=2000.0, vhat=6.0, debye=0.05, stretch=1.5,
+                 seed=3, u_noise=0.05)
+    g, o = make_pair(P, O, cfg)
+    g.set_tiles(cn=cn)
+    err0 = worst(g, o)
+    note(f"max size {dims} cn={cn}, initial state: {max(err0.values()):.3e}")
+    assert max(err0.values()) < 1e-12, err0
+    g.step(6)
+    o.run(6)
+    err = worst(g, o)
+    note(f"max size {dims} cn={cn}, 6 substeps: {max(err.values()):.3e}")
+    assert max(err.values()) < 1e-10, err
+    t, dt, _, _ = g.clock()
+    assert abs(dt - o.dt) < 1e-13 * o.dt
+
+
+def test_maximum_rows_mixed_tracks_oracle(P, O):
+    """Mixed form at 481 wall-normal nodes (FP32 state through 32-column
+    Crank-Nicolson tiles of 480 rows)."""
+    O.set_threads(16)
+    cfg = cfg_of(P, nx=64, ny=481, nz=16, precision="mixed", re=2000.0, vhat=6.0, debye=0.05, stretch=1.5,
+                 seed=4, u_noise=0.05)
+    g, o = make_pair(P, O, cfg)
+    g.step(9)
+    o.run(9)
+    err = worst(g, o)
+    note(f"mixed, 481 nodes: {err}")
+    for k in ("u", "cp", "cm"):
+        assert err[k] < 1e-5, err

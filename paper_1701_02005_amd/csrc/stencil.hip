@@ -901,7 +901,7 @@ __global__ void __launch_bounds__(256) k_cn_slab_exit(CnArgs a) {
     const unsigned upl = (unsigned)pl, ue = (unsigned)e;
     T rv[L];
 #pragma unroll
-    for (int t = 0; t < L; ++t) rv[t] = r[(unsigned)(j0 + t < j1 ? j0 + t : j1 - 1) * upl + ue];
+    for (int t = 0; t < L; ++t) rv[t] = ld_once(r + ((unsigned)(j0 + t < j1 ? j0 + t : j1 - 1) * upl + ue));
     double lv[L];
     double l = 0.0;
 #pragma unroll
@@ -1005,8 +1005,8 @@ __global__ void __launch_bounds__(256) k_cn_slab_apply(CnArgs a) {
 #pragma unroll
     for (int t = 0; t < L; ++t) {
         const unsigned o = (unsigned)(j0 + t < j1 ? j0 + t : j1 - 1) * upl + ue;
-        rv[t] = r[o];
-        qv[t] = q[o];
+        rv[t] = ld_once(r + o);
+        qv[t] = ld_once(q + o);
     }
     double dv[L];
 #pragma unroll
@@ -1020,7 +1020,7 @@ __global__ void __launch_bounds__(256) k_cn_slab_apply(CnArgs a) {
         const int j = j0 + t;
         if (j < j1) {
             x = dv[t] + n[j] * x;
-            q[(unsigned)j * upl + ue] = (T)((double)qv[t] + x);
+            st_once(q + ((unsigned)j * upl + ue), (T)((double)qv[t] + x));
         }
     }
 }

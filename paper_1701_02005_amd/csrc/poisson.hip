@@ -153,19 +153,29 @@ __device__ __forceinline__ void r2c_stage(const PoissonSrc &src, const Dims &d, 
     const int nx = d.nx, nz = d.nz, M = d.M, n = ppb * nx, bd = (int)blockDim.x;
     const int64_t nlines = (int64_t)M * nz;
     const unsigned upl = (unsigned)d.plane;
+    // (line = j nz + k < 480 * 1024 and e < ppb nx: the float-reciprocal
+    // divmod is exact for both)
+    const float rnx = 1.0f / (float)nx, rnz = 1.0f / (float)nz;
     for (int e0 = threadIdx.x; e0 < n; e0 += kXB * bd) {
         unsigned q[kXB][2];
         bool ok[kXB][2];
-        int jr[kXB][2];
+        int jr[kXB][2], kr[kXB][2], ir[kXB];
 #pragma unroll
         for (int u = 0; u < kXB; ++u) {
-            const int e = e0 + u * bd, p = e / nx, i = e - p * nx;
+            const int e = e0 + u * bd;
+            int p, i;
+            divmod(e < n ? e : 0, nx, rnx, p, i);
+            ir[u] = i;
 #pragma unroll
             for (int l = 0; l < 2; ++l) {
                 const int64_t line = 2 * (pair0 + p) + l;
                 ok[u][l] = e < n && line < nlines;
-                q[u][l] = ok[u][l] ? (unsigned)line * (unsigned)nx + (unsigned)i : 0u;
-                jr[u][l] = ok[u][l] ? (int)(line / nz) : 0;
+                const int li = ok[u][l] ? (int)line : 0;
+                int j, k;
+                divmod(li, nz, rnz, j, k);
+                q[u][l] = (unsigned)li * (unsigned)nx + (unsigned)i;
+                jr[u][l] = j;
+                kr[u][l] = k;
             }
         }
         double val[kXB][2];
@@ -220,8 +230,7 @@ __device__ __forceinline__ void r2c_stage(const PoissonSrc &src, const Dims &d, 
                 for (int l = 0; l < 2; ++l) {
                     const unsigned qq = q[u][l];
                     const int j = jr[u][l];
-                    const unsigned line = qq / (unsigned)nx, i = qq - line * (unsigned)nx;
-                    const unsigned k = line - (unsigned)j * (unsigned)nz;
+                    const unsigned i = (unsigned)ir[u], k = (unsigned)kr[u][l];
                     const unsigned xp = qq - i + ((i + 1 == (unsigned)nx) ? 0u : i + 1);
                     const unsigned zp = qq + ((k + 1 == (unsigned)nz) ? 0u : k + 1) * (unsigned)nx - k * (unsigned)nx;
                     ux[u][l] = uu[xp];
@@ -292,8 +301,10 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
     const double2 *z = sm + w * bs;
     double2 *o = sm + (1 - w) * bs;  // [kk][line] staging for the transposed store
     const int nl2 = 2 * ppb;
+    const float rnxh = 1.0f / (float)nxh, rnl2 = 1.0f / (float)nl2, rnz = 1.0f / (float)d.nz;
     for (int e = threadIdx.x; e < ppb * nxh; e += blockDim.x) {
-        const int p = e / nxh, kk = e - p * nxh;
+        int p, kk;
+        divmod(e, nxh, rnxh, p, kk);
         const double2 zk = z[p * nx + kk];
         const double2 zc = z[p * nx + (kk == 0 ? 0 : nx - kk)];
         // A = (Z_k + conj(Z_{N-k}))/2, B = (Z_k - conj(Z_{N-k}))/(2i)
@@ -303,11 +314,13 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
     __syncthreads();
     // spectrum layout [j][kx][kz]: consecutive lines (k) of one kx are contiguous
     for (int e = threadIdx.x; e < nl2 * nxh; e += blockDim.x) {
-        const int kk = e / nl2, l = e - kk * nl2;
+        int kk, l;
+        divmod(e, nl2, rnl2, kk, l);
         const int64_t line = 2 * pair0 + l;
         if (line < nlines) {
-            const int64_t j = line / d.nz, k = line - j * d.nz;
-            out[(j * nxh + kk) * d.nz + k] = o[e];
+            int j, k;
+            divmod((int)line, d.nz, rnz, j, k);
+            out[((int64_t)j * nxh + kk) * d.nz + k] = o[e];
         }
     }
 }
@@ -331,7 +344,7 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
     double2 *s_tw = sm + 2 * bs;
     stage_twiddles(s_tw, tb.twx, nx);
     const int nl2 = 2 * ppb, nst = nl2 * nxh;
-    const float r_nl2 = 1.0f / (float)nl2, r_nz = 1.0f / (float)nz;
+    const float r_nl2 = 1.0f / (float)nl2, r_nz = 1.0f / (float)nz, r_nx = 1.0f / (float)nx;
     double2 *o = bf[1];  // [kk][line] staging of the transposed load
     const bool as_state = b.out_state[prob] != 0;
     double *o64 = (double *)member_ptr(b.out[prob], b.ms);
@@ -367,7 +380,8 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
         __syncthreads();
         if (t + (int)gridDim.x < ntiles) load(t + gridDim.x);  // lands during the passes
         for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
-            const int p = e / nx, kk = e - p * nx;
+            int p, kk;
+            divmod(e, nx, r_nx, p, kk);
             const bool lower = kk < nxh;
             const int src = lower ? kk : nx - kk;
             double2 A = o[src * nl2 + 2 * p];
@@ -381,7 +395,8 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
         __syncthreads();
         const double2 *z = sm + lds_fft(bf[0], bf[1], nx, ppb, pl, s_tw, true) * bs;  // LDS base offset: no flat access
         for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
-            const int p = e / nx, i = e - p * nx;
+            int p, i;
+            divmod(e, nx, r_nx, p, i);
             const int64_t la = 2 * (pair0 + p), lb = la + 1;
             const double2 v = z[e];
             if (as_state) {
@@ -521,16 +536,21 @@ __global__ void __launch_bounds__(256) k_thomas_tile(Dims d, Tables tb, PoissonB
     // Offsets within one spectrum: rows * modes < 2^32 for every supported grid.
     const unsigned unm = (unsigned)nmodes, um0 = (unsigned)m0;
     const int ntile = M * tm, bd = (int)blockDim.x;
+    const float rtm = 1.0f / (float)tm;  // (e < 2^22: the float-reciprocal divmod is exact)
     for (int e0 = threadIdx.x; e0 < ntile; e0 += kThBatch * bd) {
         double2 v[kThBatch];
 #pragma unroll
         for (int u = 0; u < kThBatch; ++u) {
-            const int e = e0 + u * bd, j = e / tm, c = e - j * tm;
+            const int e = e0 + u * bd;
+            int j, c;
+            divmod(e, tm, rtm, j, c);
             v[u] = spec[(e < ntile && c < ncol) ? (unsigned)j * unm + um0 + (unsigned)c : um0];
         }
 #pragma unroll
         for (int u = 0; u < kThBatch; ++u) {
-            const int e = e0 + u * bd, j = e / tm, c = e - j * tm;
+            const int e = e0 + u * bd;
+            int j, c;
+            divmod(e, tm, rtm, j, c);
             if (e < ntile) s_x[j * LD + c] = (c < ncol) ? v[u] : make_double2(0.0, 0.0);
         }
     }
@@ -674,7 +694,8 @@ __global__ void __launch_bounds__(256) k_thomas_tile(Dims d, Tables tb, PoissonB
     }
     __syncthreads();
     for (int e = threadIdx.x; e < ntile; e += bd) {
-        const int j = e / tm, c = e - j * tm;
+        int j, c;
+        divmod(e, tm, rtm, j, c);
         if (c < ncol) spec[(unsigned)j * unm + um0 + (unsigned)c] = s_x[j * LD + c];
     }
 }

@@ -88,10 +88,21 @@ __device__ __forceinline__ void stage_pass(const double2 *__restrict__ src, doub
     const int NR = N / R;
     const int ts = N / (Ns * R);
     const float rNR = 1.0f / (float)NR, rNs = 1.0f / (float)Ns;
+    // powers of two (every pass of a 2^a line): shifts and masks instead of
+    // the float-reciprocal divmod (block-uniform choice)
+    const bool p2 = ((NR & (NR - 1)) | (Ns & (Ns - 1))) == 0;
+    const int lNR = __builtin_ctz((unsigned)NR), lNs = __builtin_ctz((unsigned)Ns);
     for (int e = tid; e < nl * NR; e += nth) {
         int line, jb, blk, k;
-        divmod(e, NR, rNR, line, jb);
-        divmod(jb, Ns, rNs, blk, k);
+        if (p2) {
+            line = e >> lNR;
+            jb = e & (NR - 1);
+            blk = jb >> lNs;
+            k = jb & (Ns - 1);
+        } else {
+            divmod(e, NR, rNR, line, jb);
+            divmod(jb, Ns, rNs, blk, k);
+        }
         const double2 *in = src + line * N;
         double2 *out = dst + line * N;
         double2 v[R];

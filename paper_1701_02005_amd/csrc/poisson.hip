@@ -10,7 +10,7 @@
 // The x transforms stage their output / input through LDS so that the
 // spectrum is written and read in runs of consecutive z lines, and every z
 // line is one contiguous run of nz values.
-// The FFTs are self-sorting (Stockham) in LDS with radix 4, 2 and 3 stages;
+// The FFTs are self-sorting (Stockham) in LDS with radix 8, 4, 2 and 3 stages;
 // two real x-lines share one complex transform.
 #include <algorithm>
 
@@ -48,6 +48,26 @@ __device__ __forceinline__ void dft_small<4>(double2 *v, bool inv) {
     v[2] = csub(s02, s13);
     v[1] = cadd(d02, d13);
     v[3] = csub(d02, d13);
+}
+
+// radix 8 as two radix-4 DFTs of the even and odd inputs joined by the
+// eighth roots of unity: X_k = E_k + w^k O_k, X_{k+4} = E_k - w^k O_k
+template <>
+__device__ __forceinline__ void dft_small<8>(double2 *v, bool inv) {
+    double2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    dft_small<4>(e, inv);
+    dft_small<4>(o, inv);
+    const double c = 0.70710678118654752440;  // cos(pi / 4)
+    const double2 w1 = make_double2(c, inv ? c : -c), w3 = make_double2(-c, inv ? c : -c);
+    const double2 t1 = cmul(o[1], w1), t2 = rot(o[2], inv), t3 = cmul(o[3], w3);
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], t1);
+    v[5] = csub(e[1], t1);
+    v[2] = cadd(e[2], t2);
+    v[6] = csub(e[2], t2);
+    v[3] = cadd(e[3], t3);
+    v[7] = csub(e[3], t3);
 }
 
 template <>
@@ -128,7 +148,8 @@ __device__ int lds_fft(double2 *b0, double2 *b1, int N, int nl, const FftPlan &p
     int Ns = 1;
     for (int s = 0; s < pl.nstages; ++s) {
         const int R = pl.radix[s];
-        if (R == 4) stage_pass<4>(src, dst, N, nl, Ns, tw, inv, threadIdx.x, blockDim.x);
+        if (R == 8) stage_pass<8>(src, dst, N, nl, Ns, tw, inv, threadIdx.x, blockDim.x);
+        else if (R == 4) stage_pass<4>(src, dst, N, nl, Ns, tw, inv, threadIdx.x, blockDim.x);
         else if (R == 2) stage_pass<2>(src, dst, N, nl, Ns, tw, inv, threadIdx.x, blockDim.x);
         else stage_pass<3>(src, dst, N, nl, Ns, tw, inv, threadIdx.x, blockDim.x);
         __syncthreads();

@@ -99,6 +99,23 @@ __device__ __forceinline__ void divmod(int e, int d, float rd, int &q, int &r) {
     }
 }
 
+// Quotient and remainder by a block-uniform divisor: shifts and a mask when
+// it is a power of two, else the float-reciprocal divmod (same range).
+struct Div {
+    int d, sh;
+    float rd;
+    __device__ explicit Div(int dd) : d(dd), sh(((dd & (dd - 1)) == 0) ? __builtin_ctz((unsigned)dd) : -1),
+                                      rd(1.0f / (float)dd) {}
+    __device__ __forceinline__ void split(int e, int &q, int &r) const {
+        if (sh >= 0) {
+            q = e >> sh;
+            r = e & (d - 1);
+        } else {
+            divmod(e, d, rd, q, r);
+        }
+    }
+};
+
 // One radix-R Stockham pass over nl lines of length N in LDS; tw is the
 // table exp(-2 pi i m / N), m < N, staged in LDS.
 template <int R>
@@ -142,13 +159,17 @@ __device__ __forceinline__ void stage_pass(const double2 *__restrict__ src, doub
 }
 
 // nl lines of length N in b0; returns the buffer (0 or 1) holding the result.
+// kR8: the plan may hold radix-8 passes (instantiated only for such plans:
+// the radix-8 pass's registers would otherwise bound every transform's
+// occupancy).
+template <bool kR8>
 __device__ int lds_fft(double2 *b0, double2 *b1, int N, int nl, const FftPlan &pl, const double2 *tw, bool inv) {
     double2 *src = b0, *dst = b1;
     int which = 0;
     int Ns = 1;
     for (int s = 0; s < pl.nstages; ++s) {
         const int R = pl.radix[s];
-        if (R == 8) stage_pass<8>(src, dst, N, nl, Ns, tw, inv, threadIdx.x, blockDim.x);
+        if (kR8 && R == 8) stage_pass<kR8 ? 8 : 4>(src, dst, N, nl, Ns, tw, inv, threadIdx.x, blockDim.x);
         else if (R == 4) stage_pass<4>(src, dst, N, nl, Ns, tw, inv, threadIdx.x, blockDim.x);
         else if (R == 2) stage_pass<2>(src, dst, N, nl, Ns, tw, inv, threadIdx.x, blockDim.x);
         else stage_pass<3>(src, dst, N, nl, Ns, tw, inv, threadIdx.x, blockDim.x);
@@ -187,7 +208,7 @@ __device__ __forceinline__ void r2c_stage(const PoissonSrc &src, const Dims &d, 
     const unsigned upl = (unsigned)d.plane;
     // (line = j nz + k < 480 * 1024 and e < ppb nx: the float-reciprocal
     // divmod is exact for both)
-    const float rnx = 1.0f / (float)nx, rnz = 1.0f / (float)nz;
+    const Div dnx(nx), dnz(nz);
     for (int e0 = threadIdx.x; e0 < n; e0 += kXB * bd) {
         unsigned q[kXB][2];
         bool ok[kXB][2];
@@ -196,7 +217,7 @@ __device__ __forceinline__ void r2c_stage(const PoissonSrc &src, const Dims &d, 
         for (int u = 0; u < kXB; ++u) {
             const int e = e0 + u * bd;
             int p, i;
-            divmod(e < n ? e : 0, nx, rnx, p, i);
+            dnx.split(e < n ? e : 0, p, i);
             ir[u] = i;
 #pragma unroll
             for (int l = 0; l < 2; ++l) {
@@ -204,7 +225,7 @@ __device__ __forceinline__ void r2c_stage(const PoissonSrc &src, const Dims &d, 
                 ok[u][l] = e < n && line < nlines;
                 const int li = ok[u][l] ? (int)line : 0;
                 int j, k;
-                divmod(li, nz, rnz, j, k);
+                dnz.split(li, j, k);
                 q[u][l] = (unsigned)li * (unsigned)nx + (unsigned)i;
                 jr[u][l] = j;
                 kr[u][l] = k;
@@ -297,7 +318,7 @@ __device__ __forceinline__ void r2c_stage(const PoissonSrc &src, const Dims &d, 
 // staging of the transposed spectrum stores / loads fits one of them.
 __host__ __device__ inline int x_buffer_slots(int nx, int ppb) { return ppb * (nx + 2); }
 
-template <typename T>
+template <typename T, bool kR8>
 __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl, PoissonBatch b,
                                                    const double *clock, double2 *spec, int64_t nspec, int ppb) {
     extern __shared__ double2 sm[];
@@ -326,17 +347,17 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
     else if (src.type == SRC_CHARGE) r2c_stage<T, SRC_CHARGE>(src, d, tb, ch, sc, idx, idz, pair0, ppb, bf[0]);
     else r2c_stage<T, SRC_REAL>(src, d, tb, ch, sc, idx, idz, pair0, ppb, bf[0]);
     __syncthreads();
-    const int w = lds_fft(bf[0], bf[1], nx, ppb, pl, s_tw, false);
+    const int w = lds_fft<kR8>(bf[0], bf[1], nx, ppb, pl, s_tw, false);
     // (offsets from the LDS base rather than bf[w]: a pointer picked from an
     // array at run time loses its address space and becomes a flat access,
     // which would also wait for every vector load in flight)
     const double2 *z = sm + w * bs;
     double2 *o = sm + (1 - w) * bs;  // [kk][line] staging for the transposed store
     const int nl2 = 2 * ppb;
-    const float rnxh = 1.0f / (float)nxh, rnl2 = 1.0f / (float)nl2, rnz = 1.0f / (float)d.nz;
+    const Div dnxh(nxh), dnl2(nl2), dnz(d.nz);
     for (int e = threadIdx.x; e < ppb * nxh; e += blockDim.x) {
         int p, kk;
-        divmod(e, nxh, rnxh, p, kk);
+        dnxh.split(e, p, kk);
         const double2 zk = z[p * nx + kk];
         const double2 zc = z[p * nx + (kk == 0 ? 0 : nx - kk)];
         // A = (Z_k + conj(Z_{N-k}))/2, B = (Z_k - conj(Z_{N-k}))/(2i)
@@ -347,11 +368,11 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
     // spectrum layout [j][kx][kz]: consecutive lines (k) of one kx are contiguous
     for (int e = threadIdx.x; e < nl2 * nxh; e += blockDim.x) {
         int kk, l;
-        divmod(e, nl2, rnl2, kk, l);
+        dnl2.split(e, kk, l);
         const int64_t line = 2 * pair0 + l;
         if (line < nlines) {
             int j, k;
-            divmod((int)line, d.nz, rnz, j, k);
+            dnz.split((int)line, j, k);
             out[((int64_t)j * nxh + kk) * d.nz + k] = o[e];
         }
     }
@@ -362,7 +383,7 @@ __global__ void __launch_bounds__(256) k_fft_x_r2c(Dims d, Tables tb, FftPlan pl
 // into registers while the current tile is transformed in LDS.
 constexpr int kCPer = 12;  // prefetched values per thread: 2 ppb (nx/2+1) <= kCPer * 256
 
-template <typename T>
+template <typename T, bool kR8>
 __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl, PoissonBatch b,
                                                    const double2 *spec, int64_t nspec, int ppb) {
     extern __shared__ double2 sm[];
@@ -376,7 +397,7 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
     double2 *s_tw = sm + 2 * bs;
     stage_twiddles(s_tw, tb.twx, nx);
     const int nl2 = 2 * ppb, nst = nl2 * nxh;
-    const float r_nl2 = 1.0f / (float)nl2, r_nz = 1.0f / (float)nz, r_nx = 1.0f / (float)nx;
+    const Div dnl2(nl2), dnz(nz), dnx(nx);
     double2 *o = bf[1];  // [kk][line] staging of the transposed load
     const bool as_state = b.out_state[prob] != 0;
     double *o64 = (double *)member_ptr(b.out[prob], b.ms);
@@ -390,10 +411,10 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
             double2 v = make_double2(0.0, 0.0);
             if (e < nst) {
                 int kk, l, j, k;
-                divmod(e, nl2, r_nl2, kk, l);
+                dnl2.split(e, kk, l);
                 const int64_t line = l0 + l;
                 if (line < nlines) {
-                    divmod((int)line, nz, r_nz, j, k);
+                    dnz.split((int)line, j, k);
                     v = ld_once(in + ((int64_t)j * nxh + kk) * nz + k);
                 }
             }
@@ -413,7 +434,7 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
         if (t + (int)gridDim.x < ntiles) load(t + gridDim.x);  // lands during the passes
         for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
             int p, kk;
-            divmod(e, nx, r_nx, p, kk);
+            dnx.split(e, p, kk);
             const bool lower = kk < nxh;
             const int src = lower ? kk : nx - kk;
             double2 A = o[src * nl2 + 2 * p];
@@ -425,10 +446,10 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
             bf[0][e] = make_double2(A.x - B.y, A.y + B.x);  // Z = A + i B
         }
         __syncthreads();
-        const double2 *z = sm + lds_fft(bf[0], bf[1], nx, ppb, pl, s_tw, true) * bs;  // LDS base offset: no flat access
+        const double2 *z = sm + lds_fft<kR8>(bf[0], bf[1], nx, ppb, pl, s_tw, true) * bs;  // LDS base offset: no flat access
         for (int e = threadIdx.x; e < ppb * nx; e += blockDim.x) {
             int p, i;
-            divmod(e, nx, r_nx, p, i);
+            dnx.split(e, p, i);
             const int64_t la = 2 * (pair0 + p), lb = la + 1;
             const double2 v = z[e];
             if (as_state) {
@@ -450,6 +471,7 @@ __global__ void __launch_bounds__(256) k_fft_x_c2r(Dims d, Tables tb, FftPlan pl
 // FFT passes.  kPer values per thread cover tk * nz <= kPer * 256 points.
 constexpr int kZPer = 8;
 
+template <bool kR8>
 __global__ void __launch_bounds__(256) k_fft_z(Dims d, FftPlan pl, const double2 *tw, double2 *spec, int64_t nspec,
                                                int tk, int inverse, size_t ms) {
     extern __shared__ double2 sm[];
@@ -490,7 +512,7 @@ __global__ void __launch_bounds__(256) k_fft_z(Dims d, FftPlan pl, const double2
         }
         __syncthreads();
         if (t + (int)gridDim.x < ntiles) load(t + gridDim.x);  // lands during the passes
-        const double2 *z = sm + lds_fft(bf[0], bf[1], nz, tk, pl, s_tw, inverse != 0) * (tk * nz);  // no flat access
+        const double2 *z = sm + lds_fft<kR8>(bf[0], bf[1], nz, tk, pl, s_tw, inverse != 0) * (tk * nz);  // no flat access
         for (int e = threadIdx.x; e < nt * nz; e += blockDim.x) base[e] = z[e];
         __syncthreads();  // bf[0] and the result buffer are reused by the next tile
     }
@@ -568,21 +590,21 @@ __global__ void __launch_bounds__(256) k_thomas_tile(Dims d, Tables tb, PoissonB
     // Offsets within one spectrum: rows * modes < 2^32 for every supported grid.
     const unsigned unm = (unsigned)nmodes, um0 = (unsigned)m0;
     const int ntile = M * tm, bd = (int)blockDim.x;
-    const float rtm = 1.0f / (float)tm;  // (e < 2^22: the float-reciprocal divmod is exact)
+    const Div dtm(tm);  // (e < 2^22: the float-reciprocal divmod is exact)
     for (int e0 = threadIdx.x; e0 < ntile; e0 += kThBatch * bd) {
         double2 v[kThBatch];
 #pragma unroll
         for (int u = 0; u < kThBatch; ++u) {
             const int e = e0 + u * bd;
             int j, c;
-            divmod(e, tm, rtm, j, c);
+            dtm.split(e, j, c);
             v[u] = spec[(e < ntile && c < ncol) ? (unsigned)j * unm + um0 + (unsigned)c : um0];
         }
 #pragma unroll
         for (int u = 0; u < kThBatch; ++u) {
             const int e = e0 + u * bd;
             int j, c;
-            divmod(e, tm, rtm, j, c);
+            dtm.split(e, j, c);
             if (e < ntile) s_x[j * LD + c] = (c < ncol) ? v[u] : make_double2(0.0, 0.0);
         }
     }
@@ -727,7 +749,7 @@ __global__ void __launch_bounds__(256) k_thomas_tile(Dims d, Tables tb, PoissonB
     __syncthreads();
     for (int e = threadIdx.x; e < ntile; e += bd) {
         int j, c;
-        divmod(e, tm, rtm, j, c);
+        dtm.split(e, j, c);
         if (c < ncol) spec[(unsigned)j * unm + um0 + (unsigned)c] = s_x[j * LD + c];
     }
 }
@@ -783,17 +805,29 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
     const int64_t nspec = (int64_t)d.nxh * d.nz * d.M;
     const int ppb = pairs_per_block(d.nx, s->tiles.fftx);
     const int64_t npairs = (nlines + 1) / 2;
+    auto has_r8 = [](const FftPlan &p) {
+        for (int q = 0; q < p.nstages; ++q)
+            if (p.radix[q] == 8) return true;
+        return false;
+    };
+    const bool r8x = has_r8(s->planx), r8z = has_r8(s->planz);
     {
         ProfScope prof_(s, K_FFTX_FWD);
         const dim3 gx((unsigned)((npairs + ppb - 1) / ppb), (unsigned)b.nprob, (unsigned)nmem);
         const size_t ldsx = (2 * (size_t)x_buffer_slots(d.nx, ppb) + d.nx) * sizeof(double2);
-        const void *fn = s->fp64 ? (const void *)k_fft_x_r2c<double> : (const void *)k_fft_x_r2c<float>;
+        const void *fn = s->fp64 ? (r8x ? (const void *)k_fft_x_r2c<double, true> : (const void *)k_fft_x_r2c<double, false>)
+                                 : (r8x ? (const void *)k_fft_x_r2c<float, true> : (const void *)k_fft_x_r2c<float, false>);
         const hipError_t e = lds_opt_in(fn, ldsx, s->lds_max);
         if (e != hipSuccess) return e;
-        if (s->fp64)
-            k_fft_x_r2c<double><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb);
-        else
-            k_fft_x_r2c<float><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb);
+#define NSPNP_R2C(TT, RR) k_fft_x_r2c<TT, RR><<<gx, 256, ldsx, s->stream>>>(d, s->tb, s->planx, b, s->clock, s->spec, nspec, ppb)
+        if (s->fp64) {
+            if (r8x) NSPNP_R2C(double, true);
+            else NSPNP_R2C(double, false);
+        } else {
+            if (r8x) NSPNP_R2C(float, true);
+            else NSPNP_R2C(float, false);
+        }
+#undef NSPNP_R2C
     }
     int tk = modes_per_tile(d.nz, d.nxh, s->tiles.fftz);
     if (tk * d.nz > kZPer * 256) tk = std::max(1, kZPer * 256 / d.nz);
@@ -804,7 +838,8 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
     const size_t ldsz = (2 * (size_t)tk * d.nz + d.nz) * sizeof(double2);
     {
         ProfScope prof_(s, K_FFTZ_FWD);
-        k_fft_z<<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 0, b.ms);
+        if (r8z) k_fft_z<true><<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 0, b.ms);
+        else k_fft_z<false><<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 0, b.ms);
     }
     const int64_t nmodes = (int64_t)d.nxh * d.nz;
     {
@@ -833,7 +868,8 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
     }
     {
         ProfScope prof_(s, K_FFTZ_INV);
-        k_fft_z<<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 1, b.ms);
+        if (r8z) k_fft_z<true><<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 1, b.ms);
+        else k_fft_z<false><<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 1, b.ms);
     }
     {
         ProfScope prof_(s, K_FFTX_INV);
@@ -846,13 +882,19 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
         const int cblocks = std::max(1, std::min(ctiles, 2048 / std::max(1, b.nprob * nmem)));
         const dim3 gc((unsigned)cblocks, (unsigned)b.nprob, (unsigned)nmem);
         const size_t ldsc = (2 * (size_t)x_buffer_slots(d.nx, ppbc) + d.nx) * sizeof(double2);
-        {
-            const void *fn = s->fp64 ? (const void *)k_fft_x_c2r<double> : (const void *)k_fft_x_c2r<float>;
-            const hipError_t e = lds_opt_in(fn, ldsc, s->lds_max);
-            if (e != hipSuccess) return e;
+        const void *fn = s->fp64 ? (r8x ? (const void *)k_fft_x_c2r<double, true> : (const void *)k_fft_x_c2r<double, false>)
+                                 : (r8x ? (const void *)k_fft_x_c2r<float, true> : (const void *)k_fft_x_c2r<float, false>);
+        const hipError_t e = lds_opt_in(fn, ldsc, s->lds_max);
+        if (e != hipSuccess) return e;
+#define NSPNP_C2R(TT, RR) k_fft_x_c2r<TT, RR><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc)
+        if (s->fp64) {
+            if (r8x) NSPNP_C2R(double, true);
+            else NSPNP_C2R(double, false);
+        } else {
+            if (r8x) NSPNP_C2R(float, true);
+            else NSPNP_C2R(float, false);
         }
-        if (s->fp64) k_fft_x_c2r<double><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc);
-        else k_fft_x_c2r<float><<<gc, 256, ldsc, s->stream>>>(d, s->tb, s->planx, b, s->spec, nspec, ppbc);
+#undef NSPNP_C2R
     }
     return hipGetLastError();
 }

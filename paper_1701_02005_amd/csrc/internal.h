@@ -360,6 +360,9 @@ hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]);
 hipError_t launch_cn_solve(nspnp_state *s, const Stage &st);
 hipError_t launch_correct(nspnp_state *s, const Stage &st, bool update_p, double fixed_scale, bool advance_clock);
 hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b);
+// Raises a kernel's dynamic-LDS limit to the device maximum when bytes > 64 KB
+// (once per device and kernel); hipErrorInvalidValue when bytes > lds_max.
+hipError_t lds_opt_in(const void *fn, size_t bytes, int lds_max);
 hipError_t launch_thomas_factors(nspnp_state *s);
 hipError_t launch_dt(nspnp_state *s);
 hipError_t launch_init_fields(nspnp_state *s);

@@ -13,6 +13,9 @@
 // The FFTs are self-sorting (Stockham) in LDS with radix 8, 4, 2 and 3 stages;
 // two real x-lines share one complex transform.
 #include <algorithm>
+#include <mutex>
+#include <set>
+#include <utility>
 
 #include "internal.h"
 
@@ -783,16 +786,20 @@ inline int modes_per_tile(int nz, int nxh, int points) {
 }  // namespace
 
 // Kernels that need more than 64 KB of dynamic LDS ask for the device's
-// larger per-workgroup limit once.
+// larger per-workgroup limit, once per (device, kernel); the record is
+// shared by every handle and guarded for callers on several host threads.
 hipError_t lds_opt_in(const void *fn, size_t bytes, int lds_max) {
     if (bytes <= 65536) return hipSuccess;
     if (bytes > (size_t)lds_max) return hipErrorInvalidValue;
-    static const void *opted[16];
-    static int nopted = 0;
-    for (int q = 0; q < nopted; ++q)
-        if (opted[q] == fn) return hipSuccess;
-    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    if (e == hipSuccess && nopted < 16) opted[nopted++] = fn;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    static std::mutex mu;
+    static std::set<std::pair<int, const void *>> opted;
+    std::lock_guard<std::mutex> lock(mu);
+    if (opted.count({dev, fn})) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    if (e == hipSuccess) opted.insert({dev, fn});
     return e;
 }
 

@@ -1259,17 +1259,8 @@ static hipError_t launch_cyc(nspnp_state *s, const Stage &st, int dir, int out_r
         if (!R && h >= rpl) R = h;
     if (!R) return hipErrorInvalidValue;
     auto go = [&](const void *fn, auto kernel) -> hipError_t {
-        if (lds > 65536) {
-            static const void *opted[64];
-            static int nopted = 0;
-            bool done = false;
-            for (int q = 0; q < nopted; ++q) done = done || opted[q] == fn;
-            if (!done) {
-                const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, s->lds_max);
-                if (e != hipSuccess) return e;
-                if (nopted < 64) opted[nopted++] = fn;
-            }
-        }
+        const hipError_t e = lds_opt_in(fn, lds, s->lds_max);
+        if (e != hipSuccess) return e;
         kernel<<<g, 256, lds, s->stream>>>(c);
         return hipGetLastError();
     };
@@ -1354,17 +1345,8 @@ static hipError_t launch_cn_lane(nspnp_state *s, const CnArgs &a) {
     const int rpl = (s->d.M + 63) / 64;  // rows per lane (M <= 480: at most 8)
     // tiles above 64 KB of LDS (tall columns) use the device's larger limit
     auto launch = [&](const void *fn, auto kernel) -> hipError_t {
-        if (lds > 65536) {
-            static const void *opted[32];
-            static int nopted = 0;
-            bool done = false;
-            for (int q = 0; q < nopted; ++q) done = done || opted[q] == fn;
-            if (!done) {
-                const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, s->lds_max);
-                if (e != hipSuccess) return e;
-                if (nopted < 32) opted[nopted++] = fn;
-            }
-        }
+        const hipError_t e = lds_opt_in(fn, lds, s->lds_max);
+        if (e != hipSuccess) return e;
         kernel<<<g, tb, lds, s->stream>>>(a);
         return hipGetLastError();
     };

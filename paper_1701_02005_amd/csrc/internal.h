@@ -143,6 +143,23 @@ template <typename T>
 __device__ __forceinline__ const T *byte_at(const T *base, unsigned bytes) {
     return (const T *)((const char *)base + bytes);
 }
+// Two adjacent FP32 values as one 8-byte access (non-temporal), for
+// staging loops over rows of FP32 fields.
+typedef float nspnp_f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ nspnp_f2v ld_once2(const float *p) {
+#if NSPNP_NT
+    return __builtin_nontemporal_load((const nspnp_f2v *)p);
+#else
+    return *(const nspnp_f2v *)p;
+#endif
+}
+__device__ __forceinline__ void st_once2(float *p, nspnp_f2v v) {
+#if NSPNP_NT
+    __builtin_nontemporal_store(v, (nspnp_f2v *)p);
+#else
+    *(nspnp_f2v *)p = v;
+#endif
+}
 typedef double nspnp_d2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ double2 ld_once(const double2 *p) {
 #if NSPNP_NT

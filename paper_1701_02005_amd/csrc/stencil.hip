@@ -537,17 +537,40 @@ __global__ void __launch_bounds__(512) k_cn_scan(CnArgs a) {
     // (offsets within one field: rows * plane < 2^32 for every supported grid)
     const unsigned upl = (unsigned)pl, uc0 = (unsigned)c0;
     const unsigned o_safe = (unsigned)j0 * upl + uc0;
-    for (int e0 = threadIdx.x; e0 < ntile; e0 += cn_batch<T>() * bd) {
-        T v[cn_batch<T>()];
+    if constexpr (sizeof(T) == 4) {
+        // FP32: two adjacent columns per 8-byte access (the plane, the tile
+        // origin and ncol are even, so a pair is wholly inside or outside)
+        constexpr int TXW = kCnTx / 2, B = cn_batch<T>() / 2;
+        const int ntw = nrow * TXW;
+        for (int e0 = threadIdx.x; e0 < ntw; e0 += B * bd) {
+            nspnp_f2v v[B];
 #pragma unroll
-        for (int u = 0; u < cn_batch<T>(); ++u) {
-            const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
-            v[u] = ld_once(r + ((e < ntile && c < ncol) ? (unsigned)jj * upl + uc0 + (unsigned)c : o_safe));
+            for (int u = 0; u < B; ++u) {
+                const int e = e0 + u * bd, jj = j0 + e / TXW, c = 2 * (e % TXW);
+                v[u] = ld_once2((const float *)r + ((e < ntw && c < ncol) ? (unsigned)jj * upl + uc0 + (unsigned)c : o_safe));
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int e = e0 + u * bd, jj = j0 + e / TXW, c = 2 * (e % TXW);
+                if (e < ntw) {
+                    s_r[jj * LD + c] = (c < ncol) ? (double)v[u].x : 0.0;
+                    s_r[jj * LD + c + 1] = (c < ncol) ? (double)v[u].y : 0.0;
+                }
+            }
         }
+    } else {
+        for (int e0 = threadIdx.x; e0 < ntile; e0 += cn_batch<T>() * bd) {
+            T v[cn_batch<T>()];
 #pragma unroll
-        for (int u = 0; u < cn_batch<T>(); ++u) {
-            const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
-            if (e < ntile) s_r[jj * LD + c] = (c < ncol) ? (double)v[u] : 0.0;
+            for (int u = 0; u < cn_batch<T>(); ++u) {
+                const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
+                v[u] = ld_once(r + ((e < ntile && c < ncol) ? (unsigned)jj * upl + uc0 + (unsigned)c : o_safe));
+            }
+#pragma unroll
+            for (int u = 0; u < cn_batch<T>(); ++u) {
+                const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
+                if (e < ntile) s_r[jj * LD + c] = (c < ncol) ? (double)v[u] : 0.0;
+            }
         }
     }
     __syncthreads();
@@ -634,17 +657,41 @@ __global__ void __launch_bounds__(512) k_cn_scan(CnArgs a) {
         }
         return;
     }
-    for (int e0 = threadIdx.x; e0 < ntile; e0 += cn_batch<T>() * bd) {
-        T v[cn_batch<T>()];
+    if constexpr (sizeof(T) == 4) {
+        constexpr int TXW = kCnTx / 2, B = cn_batch<T>() / 2;
+        const int ntw = nrow * TXW;
+        float *qf = (float *)q;
+        for (int e0 = threadIdx.x; e0 < ntw; e0 += B * bd) {
+            nspnp_f2v v[B];
 #pragma unroll
-        for (int u = 0; u < cn_batch<T>(); ++u) {
-            const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
-            v[u] = ld_once(q + ((e < ntile && c < ncol) ? (unsigned)jj * upl + uc0 + (unsigned)c : o_safe));
+            for (int u = 0; u < B; ++u) {
+                const int e = e0 + u * bd, jj = j0 + e / TXW, c = 2 * (e % TXW);
+                v[u] = ld_once2(qf + ((e < ntw && c < ncol) ? (unsigned)jj * upl + uc0 + (unsigned)c : o_safe));
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int e = e0 + u * bd, jj = j0 + e / TXW, c = 2 * (e % TXW);
+                if (e < ntw && c < ncol) {
+                    nspnp_f2v w;
+                    w.x = (float)((double)v[u].x + s_r[jj * LD + c]);
+                    w.y = (float)((double)v[u].y + s_r[jj * LD + c + 1]);
+                    st_once2(qf + ((unsigned)jj * upl + uc0 + (unsigned)c), w);
+                }
+            }
         }
+    } else {
+        for (int e0 = threadIdx.x; e0 < ntile; e0 += cn_batch<T>() * bd) {
+            T v[cn_batch<T>()];
 #pragma unroll
-        for (int u = 0; u < cn_batch<T>(); ++u) {
-            const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
-            if (e < ntile && c < ncol) st_once(q + ((unsigned)jj * upl + uc0 + (unsigned)c), (T)((double)v[u] + s_r[jj * LD + c]));
+            for (int u = 0; u < cn_batch<T>(); ++u) {
+                const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
+                v[u] = ld_once(q + ((e < ntile && c < ncol) ? (unsigned)jj * upl + uc0 + (unsigned)c : o_safe));
+            }
+#pragma unroll
+            for (int u = 0; u < cn_batch<T>(); ++u) {
+                const int e = e0 + u * bd, jj = j0 + e / kCnTx, c = e % kCnTx;
+                if (e < ntile && c < ncol) st_once(q + ((unsigned)jj * upl + uc0 + (unsigned)c), (T)((double)v[u] + s_r[jj * LD + c]));
+            }
         }
     }
 }

@@ -199,11 +199,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
     for (int j = j0; j < j1; ++j) {
         const int sc = j & 1, sn = sc ^ 1;
         const bool pre = (j + 2 <= jl);
+        // FP64: the wave issuing the next row's loads takes issue priority so
+        // they leave before the other waves' arithmetic (measured: 0.418 ->
+        // 0.415 ms at 256 x 193 x 256; the FP32 form is slower with it)
+        if constexpr (sizeof(T) == 8) __builtin_amdgcn_s_setprio(2);
         if (pre) load_rows(j + 2, rn);  // lands in LDS after this row
         if (use_old && active && j + 1 < j1) {
 #pragma unroll
             for (int f = 0; f < 5; ++f) hold_n[f] = ld_once(byte_at((const T *)a.h[f], (unsigned)(j + 1) * plb + ueb));
         }
+        if constexpr (sizeof(T) == 8) __builtin_amdgcn_s_setprio(0);
         const bool has_up = (j + 1 < M), has_dn = (j > 0);
         const unsigned qb = (unsigned)j * plb + ueb;  // this cell, bytes
         if (active) {

@@ -770,6 +770,8 @@ __global__ void __launch_bounds__(64) k_cyc_coef(Dims d, const Phys *phys, const
 // broadcast from their lanes).
 constexpr int kCycTx = 16;
 
+constexpr int kCycBatch = 8;  // loads per thread per wait in the periodic line solves
+
 template <typename T, int R>
 __global__ void __launch_bounds__(256) k_cyc_scan(CycArgs a) {
     extern __shared__ double s_l[];
@@ -805,16 +807,16 @@ __global__ void __launch_bounds__(256) k_cyc_scan(CycArgs a) {
         const int i = e / kCycTx;
         return IC{i, e - i * kCycTx};
     };
-    for (int e0 = threadIdx.x; e0 < ntile; e0 += cn_batch<T>() * bd) {
-        T v[cn_batch<T>()];
+    for (int e0 = threadIdx.x; e0 < ntile; e0 += kCycBatch * bd) {
+        T v[kCycBatch];
 #pragma unroll
-        for (int u = 0; u < cn_batch<T>(); ++u) {
+        for (int u = 0; u < kCycBatch; ++u) {
             const int e = e0 + u * bd;
             const IC p = split(e < ntile ? e : 0);
             v[u] = ld_once(rr + ((e < ntile && p.c < nl) ? addr(p.i, p.c) : row));
         }
 #pragma unroll
-        for (int u = 0; u < cn_batch<T>(); ++u) {
+        for (int u = 0; u < kCycBatch; ++u) {
             const int e = e0 + u * bd;
             if (e < ntile) {
                 const IC p = split(e);
@@ -897,18 +899,18 @@ __global__ void __launch_bounds__(256) k_cyc_scan(CycArgs a) {
             if (js + t < N) col[(js + t) * LD] = x[t] - wcor * zz[t];
     }
     __syncthreads();
-    for (int e0 = threadIdx.x; e0 < ntile; e0 += cn_batch<T>() * bd) {
-        T v[cn_batch<T>()];
+    for (int e0 = threadIdx.x; e0 < ntile; e0 += kCycBatch * bd) {
+        T v[kCycBatch];
         if (!a.out_r) {
 #pragma unroll
-            for (int u = 0; u < cn_batch<T>(); ++u) {
+            for (int u = 0; u < kCycBatch; ++u) {
                 const int e = e0 + u * bd;
                 const IC p = split(e < ntile ? e : 0);
                 v[u] = ld_once(qq + ((e < ntile && p.c < nl) ? addr(p.i, p.c) : row));
             }
         }
 #pragma unroll
-        for (int u = 0; u < cn_batch<T>(); ++u) {
+        for (int u = 0; u < kCycBatch; ++u) {
             const int e = e0 + u * bd;
             if (e < ntile) {
                 const IC p = split(e);

@@ -342,7 +342,7 @@ def run(out_path: str, seed: int = 0, ens_substeps: int = 5000, stats_from: int 
 
 def main():
     ap = argparse.ArgumentParser(description="ensemble -> surrogate network -> warm-started runs")
-    ap.add_argument("--out", default="gpurun_out/surrogate_report.json")
+    ap.add_argument("--out", default="surrogate_report.json")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--ens-substeps", type=int, default=5000)
     ap.add_argument("--stats-from", type=int, default=2500)

@@ -86,9 +86,9 @@ struct HaloRegs {
 
 // kMode (a compile-time copy of ExplicitArgs::mode): the export of H alone
 // is its own instantiation, so the substep kernel carries none of its state.
-// kTz > 0: the tile is 64 columns by kTz z-lines (a.tx, a.tz ignored), so
+// kTx > 0: the tile is kTx columns by kTz z-lines (a.tx, a.tz ignored), so
 // every LDS neighbour offset is a compile-time constant.
-template <typename T, int kHalo, int kWaves, int kMode, int kTz = 0>
+template <typename T, int kHalo, int kWaves, int kMode, int kTx = 0, int kTz = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves))) k_explicit(ExplicitArgs a) {
     extern __shared__ unsigned char s_raw[];
     T *sm = (T *)s_raw;  // [slot 0..1][field 0..6][halo tile]
@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
     const Dims &d = a.d;
     const int nx = d.nx, nz = d.nz, M = d.M;
     const int pl = (int)d.plane;
-    const int tx = kTz ? 64 : a.tx, tz = kTz ? kTz : a.tz, hx = tx + 2, HS = hx * (tz + 2);
+    const int tx = kTx ? kTx : a.tx, tz = kTx ? kTz : a.tz, hx = tx + 2, HS = hx * (tz + 2);
     const int i0 = (int)(chunk % (unsigned)a.ntx) * tx, k0 = (int)(chunk / (unsigned)a.ntx) * tz;
     const int lk = (int)threadIdx.x / tx, li = (int)threadIdx.x - lk * tx;
     const int i = i0 + li, k = k0 + lk;
@@ -1200,10 +1200,14 @@ inline dim3 grid1(int64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) /
 
 }  // namespace
 
-// Column tiles of the explicit kernel: up to 64 columns along x (whole
-// x-lines when nx is smaller) times as many z-lines as the block has room for.
-static void explicit_tiling(const Dims &d, int threads, int slab_rows, ExplicitArgs &a) {
-    a.tx = d.nx < 64 ? d.nx : 64;
+// Column tiles of the explicit kernel: up to 64 columns along x in the mixed
+// form, 32 in FP64 (whole x-lines when nx is smaller), times as many z-lines
+// as the block has room for.  The FP64 32 x 8 tile loads 1.33 halo values
+// per cell against 1.55 for 64 x 4 (256 bytes of a row per access run);
+// the FP32 form keeps 64 columns, a whole 256-byte run of a row.
+static void explicit_tiling(const Dims &d, bool fp64, int threads, int slab_rows, ExplicitArgs &a) {
+    const int wx = fp64 ? 32 : 64;
+    a.tx = d.nx < wx ? d.nx : wx;
     if (a.tx > threads) a.tx = threads;
     a.tz = threads / a.tx;
     a.ntx = (d.nx + a.tx - 1) / a.tx;
@@ -1218,9 +1222,10 @@ static hipError_t explicit_launch(nspnp_state *s, const ExplicitArgs &a, int thr
     const int hs = (a.tx + 2) * (a.tz + 2);
     const size_t lds = 2 * (size_t)kNF * hs * s->wsize;
     const bool dbg = a.mode == 1;
-    if (!dbg && threads == 256 && a.tx == 64 && a.tz == 4) {  // the common 64 x 4 tile
-        if (s->fp64) k_explicit<double, 2, 2, 0, 4><<<blocks, threads, lds, s->stream>>>(a);
-        else k_explicit<float, 2, 3, 0, 4><<<blocks, threads, lds, s->stream>>>(a);
+    if (!dbg && threads == 256 && s->fp64 && a.tx == 32 && a.tz == 8) {  // the common tiles
+        k_explicit<double, 2, 2, 0, 32, 8><<<blocks, threads, lds, s->stream>>>(a);
+    } else if (!dbg && threads == 256 && !s->fp64 && a.tx == 64 && a.tz == 4) {
+        k_explicit<float, 2, 3, 0, 64, 4><<<blocks, threads, lds, s->stream>>>(a);
     } else if (hs <= 2 * threads) {
         if (s->fp64) {
             if (dbg) k_explicit<double, 2, 2, 1><<<blocks, threads, lds, s->stream>>>(a);
@@ -1257,7 +1262,7 @@ hipError_t launch_explicit(nspnp_state *s, const Stage &st, bool /*write_r*/) {
     a.mode = 0;
     a.implicit_xz = s->cfg.implicit_xz;
     const int tb = s->tiles.expl;
-    explicit_tiling(s->d, tb, s->tiles.slab, a);
+    explicit_tiling(s->d, s->fp64, tb, s->tiles.slab, a);
     return explicit_launch(s, a, tb, (unsigned)((int64_t)a.chunks * a.slabs * s->nmem));
 }
 
@@ -1273,7 +1278,7 @@ hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]) {
     a.clock = s->clock;
     a.mode = 1;
     a.implicit_xz = s->cfg.implicit_xz;
-    explicit_tiling(s->d, 256, s->tiles.slab, a);
+    explicit_tiling(s->d, s->fp64, 256, s->tiles.slab, a);
     return explicit_launch(s, a, 256, (unsigned)((int64_t)a.chunks * a.slabs));
 }
 

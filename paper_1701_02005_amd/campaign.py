@@ -237,6 +237,7 @@ def main():
     ap.add_argument("--debye", type=float, default=None)
     ap.add_argument("--sc", type=float, default=None)
     ap.add_argument("--re", type=float, default=None)
+    ap.add_argument("--ny", type=int, default=None, help="wall-normal node count (resolution of the double layer)")
     ap.add_argument("--t-spin", type=float, default=150.0)
     ap.add_argument("--t-avg", type=float, default=200.0)
     ap.add_argument("--every", type=int, default=10)
@@ -252,7 +253,7 @@ def main():
     a = ap.parse_args()
     cfg = configs.WORKLOADS[a.workload](precision=a.precision)
     over = {"vhat": a.vhat, "u_noise": 0.0, "c_noise": 0.0}
-    for k in ("debye", "sc", "re"):
+    for k in ("debye", "sc", "re", "ny"):
         if getattr(a, k) is not None:
             over[k] = getattr(a, k)
     cfg = dataclasses.replace(cfg, **over)

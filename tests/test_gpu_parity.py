@@ -79,7 +79,12 @@ def test_explicit_terms_match_oracle(P, O, dims):
     assert max(err.values()) < 1e-12, err
 
 
-@pytest.mark.parametrize("dims", [SMALL, RAGGED, TINY], ids=["small", "ragged", "tiny"])
+# lines of 512 points and more take radix-8 passes: 768 = 8 8 4 3, 512 = 8 8 8
+LONG_X = dict(nx=768, ny=9, nz=512)
+LONG_Z = dict(nx=512, ny=9, nz=768)
+
+
+@pytest.mark.parametrize("dims", [SMALL, RAGGED, TINY, LONG_X, LONG_Z], ids=["small", "ragged", "tiny", "long-x", "long-z"])
 @pytest.mark.parametrize("kind", [0, 1])
 def test_poisson_solve_matches_oracle(P, O, dims, kind):
     import torch
@@ -91,7 +96,12 @@ def test_poisson_solve_matches_oracle(P, O, dims, kind):
     t = torch.tensor(rhs, dtype=torch.float64, device="cuda")
     out = g.poisson_solve(kind, t).cpu().numpy()
     ref = o.poisson(kind, rhs)
-    assert parity(out, ref) < 1e-12
+    # two FFT implementations of different rounding order: their difference
+    # grows with the plane size (393 216 points on the long grids, where the
+    # zero-flux pressure operator's low modes amplify it to ~1.6e-12); the
+    # bar stays well below the 1e-10 of whole-step parity
+    bar = 1e-11 if dims in (LONG_X, LONG_Z) else 1e-12
+    assert parity(out, ref) < bar
 
 
 @pytest.mark.parametrize("cnslab", [0, 16])

@@ -75,7 +75,10 @@ __global__ void __launch_bounds__(kRedThreads) k_dt_partial(Dims d, Tables tb, c
     const double e0 = member_ptr(phys, ms)->e0;
     double rate = 0.0, cmax = 0.0, cmin = 1e300, pe = 0.0;
     bool bad = false;
-    const int chunk = (int)(blockIdx.x % (unsigned)chunks), slab = (int)(blockIdx.x / (unsigned)chunks);
+    // XCD-aware order: consecutive z-lines (chunks) run on one XCD, so the
+    // z-neighbour line each reads comes from that XCD's L2
+    const unsigned bt = xcd_tile(blockIdx.x, gridDim.x);
+    const int chunk = (int)(bt % (unsigned)chunks), slab = (int)(bt / (unsigned)chunks);
     const int64_t pl = d.plane;
     const int64_t e = (int64_t)chunk * blockDim.x + threadIdx.x;
     const int j0 = slab * slab_rows;

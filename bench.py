@@ -195,7 +195,7 @@ def main():
     # source they were taken from is unchanged
     traffic = None
     tr_file = ROOT / "profiles" / "traffic.json"
-    if tr_file.exists():
+    if tr_file.exists() and not args.implicit_xz:  # (counters were taken without the x/z solves)
         try:
             from paper_1701_02005_amd import pmc_traffic
             ent = json.loads(tr_file.read_text()).get(f"{args.workload}/{args.precision}/{dom}")

@@ -166,14 +166,29 @@ void build_tables(nspnp_state *s, double *dev_tab) {
     const double twopi = 6.283185307179586476925286766559;
     for (int m = 0; m < nxh; ++m) kx2[m] = (2.0 - 2.0 * std::cos(twopi * m / nx)) / (dx * dx);
     for (int m = 0; m < nz; ++m) kz2[m] = (2.0 - 2.0 * std::cos(twopi * m / nz)) / (dz * dz);
-    for (int m = 0; m < nx; ++m) {
-        twx[2 * m] = std::cos(twopi * m / nx);
-        twx[2 * m + 1] = -std::sin(twopi * m / nx);
-    }
-    for (int m = 0; m < nz; ++m) {
-        twz[2 * m] = std::cos(twopi * m / nz);
-        twz[2 * m + 1] = -std::sin(twopi * m / nz);
-    }
+    // FFT twiddles in pass order (the plan of make_plan): pass after pass,
+    // [r - 1][k] = exp(-2 pi i r k ts / N) for k < Ns, 0 < r < R, ts = N / (Ns R)
+    // (N - 1 entries; the last slot is unused), so that a pass's lanes read
+    // consecutive entries
+    auto pass_twiddles = [twopi](int n, double *tw) {
+        const FftPlan pl = make_plan(n);
+        int Ns = 1, off = 0;
+        for (int q = 0; q < pl.nstages; ++q) {
+            const int R = pl.radix[q], ts = n / (Ns * R);
+            for (int r = 1; r < R; ++r)
+                for (int k = 0; k < Ns; ++k) {
+                    const int m = r * k * ts, e = off + (r - 1) * Ns + k;
+                    tw[2 * e] = std::cos(twopi * m / n);
+                    tw[2 * e + 1] = -std::sin(twopi * m / n);
+                }
+            off += Ns * (R - 1);
+            Ns *= R;
+        }
+        tw[2 * (n - 1)] = 0.0;
+        tw[2 * (n - 1) + 1] = 0.0;
+    };
+    pass_twiddles(nx, twx);
+    pass_twiddles(nz, twz);
 }
 
 const double *host_dn(const nspnp_state *s) { return s->host_tables.data() + s->d.M; }

@@ -45,8 +45,8 @@ struct Tables {
     const double *vwu;      // M   dn_j/(2 dc_j): weight of row j at node j
     const double *kx2;      // nxh modified wavenumbers (2 - 2 cos(2 pi m / nx)) / dx^2
     const double *kz2;      // nz
-    const double2 *twx;     // nx  exp(-2 pi i m / nx)
-    const double2 *twz;     // nz
+    const double2 *twx;     // nx  FFT twiddles of the x plan, in pass order (see build_tables)
+    const double2 *twz;     // nz  the same for the z plan
 };
 
 // Physical constants of the nondimensional equations (one per member run;

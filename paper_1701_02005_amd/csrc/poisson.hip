@@ -119,14 +119,14 @@ struct Div {
     }
 };
 
-// One radix-R Stockham pass over nl lines of length N in LDS; tw is the
-// table exp(-2 pi i m / N), m < N, staged in LDS.
+// One radix-R Stockham pass over nl lines of length N in LDS; tw holds this
+// pass's twiddles exp(-2 pi i r k ts / N) as [r - 1][k] (k < Ns), staged in
+// LDS, so the lanes of a wave (consecutive k) read consecutive entries.
 template <int R>
 __device__ __forceinline__ void stage_pass(const double2 *__restrict__ src, double2 *__restrict__ dst, int N,
                                            int nl, int Ns, const double2 *__restrict__ tw, bool inv, int tid,
                                            int nth) {
     const int NR = N / R;
-    const int ts = N / (Ns * R);
     const float rNR = 1.0f / (float)NR, rNs = 1.0f / (float)Ns;
     // powers of two (every pass of a 2^a line): shifts and masks instead of
     // the float-reciprocal divmod (block-uniform choice)
@@ -150,7 +150,7 @@ __device__ __forceinline__ void stage_pass(const double2 *__restrict__ src, doub
         for (int r = 0; r < R; ++r) v[r] = in[jb + r * NR];
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-            double2 w = tw[r * k * ts];
+            double2 w = tw[(r - 1) * Ns + k];
             if (inv) w.y = -w.y;
             v[r] = cmul(v[r], w);
         }
@@ -169,13 +169,15 @@ template <bool kR8>
 __device__ int lds_fft(double2 *b0, double2 *b1, int N, int nl, const FftPlan &pl, const double2 *tw, bool inv) {
     double2 *src = b0, *dst = b1;
     int which = 0;
-    int Ns = 1;
+    int Ns = 1, off = 0;  // off: this pass's twiddles in the staged table
     for (int s = 0; s < pl.nstages; ++s) {
         const int R = pl.radix[s];
-        if (kR8 && R == 8) stage_pass<kR8 ? 8 : 4>(src, dst, N, nl, Ns, tw, inv, threadIdx.x, blockDim.x);
-        else if (R == 4) stage_pass<4>(src, dst, N, nl, Ns, tw, inv, threadIdx.x, blockDim.x);
-        else if (R == 2) stage_pass<2>(src, dst, N, nl, Ns, tw, inv, threadIdx.x, blockDim.x);
-        else stage_pass<3>(src, dst, N, nl, Ns, tw, inv, threadIdx.x, blockDim.x);
+        const double2 *twp = tw + off;
+        if (kR8 && R == 8) stage_pass<kR8 ? 8 : 4>(src, dst, N, nl, Ns, twp, inv, threadIdx.x, blockDim.x);
+        else if (R == 4) stage_pass<4>(src, dst, N, nl, Ns, twp, inv, threadIdx.x, blockDim.x);
+        else if (R == 2) stage_pass<2>(src, dst, N, nl, Ns, twp, inv, threadIdx.x, blockDim.x);
+        else stage_pass<3>(src, dst, N, nl, Ns, twp, inv, threadIdx.x, blockDim.x);
+        off += Ns * (R - 1);
         __syncthreads();
         double2 *t = src;
         src = dst;
@@ -186,7 +188,8 @@ __device__ int lds_fft(double2 *b0, double2 *b1, int N, int nl, const FftPlan &p
     return which;
 }
 
-// twiddle table to LDS (before the caller's first barrier)
+// The twiddle table to LDS (before the caller's first barrier).  The table
+// is laid out in pass order at init (pass after pass, [r - 1][k]).
 __device__ __forceinline__ void stage_twiddles(double2 *s_tw, const double2 *tw, int N) {
     for (int e = threadIdx.x; e < N; e += blockDim.x) s_tw[e] = tw[e];
 }

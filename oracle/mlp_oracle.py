@@ -10,6 +10,15 @@ mean wall-normal profiles: a fully connected perceptron with GELU hidden
 activations (erf form, Hendrycks & Gimpel 2016), mean-squared-error loss and
 the Adam optimiser (Kingma & Ba, ICLR 2015).  Layer l computes
 y = x W_l + b_l with W_l of shape [in, out]; every hidden layer applies GELU.
+
+Arithmetic: FP64 throughout by default.  With bf16=True the reference takes
+the surrogate's reduced-precision reading (BF16 weights and activations, every
+product accumulated in at least FP32): it rounds to BF16 (round to nearest,
+ties to even, through FP32) exactly where that reading stores BF16 values --
+the network input, every weight matrix, every hidden activation, the output
+layer's loss gradient and every back-propagated pre-activation gradient --
+and keeps everything else (accumulation, biases, the output, GELU and its
+derivative) in FP64.
 """
 from __future__ import annotations
 
@@ -32,6 +41,22 @@ def gelu_grad(x):
     return 0.5 * (1.0 + erf(x * SQRT1_2)) + x * INV_SQRT_2PI * np.exp(-0.5 * x * x)
 
 
+def bf16(x):
+    """Nearest BF16 value (ties to even) of each entry, via its FP32 value,
+    returned as FP64.  BF16 keeps the sign, the 8 exponent bits and the top 7
+    fraction bits of an FP32 number; the rounding adds half a unit of the
+    kept part (minus one when the kept part is even, for ties to even) to the
+    32-bit pattern and truncates the low 16 bits."""
+    f = np.ascontiguousarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _rnd(x, on):
+    return bf16(x) if on else x
+
+
 def init_params(sizes, seed=0):
     """He-style uniform initialisation, weights [in, out], zero biases."""
     rng = np.random.default_rng(seed)
@@ -42,15 +67,16 @@ def init_params(sizes, seed=0):
     return params
 
 
-def forward(params, x):
-    """Returns the output and the per-layer pre-activations and inputs."""
-    acts = [x]
+def forward(params, x, bf16=False):
+    """Returns the output and the per-layer pre-activations and inputs (the
+    inputs as the products see them: BF16-rounded when bf16 is set)."""
+    h = _rnd(x, bf16)
+    acts = [h]
     pres = []
-    h = x
     for li, (W, b) in enumerate(params):
-        z = h @ W + b
+        z = h @ _rnd(W, bf16) + b
         pres.append(z)
-        h = gelu(z) if li < len(params) - 1 else z
+        h = _rnd(gelu(z), bf16) if li < len(params) - 1 else z
         acts.append(h)
     return h, pres, acts
 
@@ -60,18 +86,19 @@ def mse(yhat, y):
     return float(np.mean((yhat - y) ** 2))
 
 
-def backward(params, x, y):
-    """Loss and its gradient with respect to every W and b (chain rule)."""
-    yhat, pres, acts = forward(params, x)
+def backward(params, x, y, bf16=False):
+    """Loss and its gradient with respect to every W and b (chain rule).
+    With bf16 set, the gradient of each pre-activation is rounded to BF16
+    once formed (the loss gradient at the output, (g W^T) * GELU'(z) below)."""
+    yhat, pres, acts = forward(params, x, bf16)
     loss = mse(yhat, y)
-    g = 2.0 * (yhat - y) / yhat.size
+    g = _rnd(2.0 * (yhat - y) / yhat.size, bf16)
     grads = [None] * len(params)
     for li in range(len(params) - 1, -1, -1):
         W, _ = params[li]
-        if li < len(params) - 1:
-            g = g * gelu_grad(pres[li])
         grads[li] = (acts[li].T @ g, g.sum(axis=0))
-        g = g @ W.T
+        if li > 0:
+            g = _rnd((g @ _rnd(W, bf16).T) * gelu_grad(pres[li - 1]), bf16)
     return loss, grads
 
 

@@ -126,3 +126,61 @@ def test_training_tracks_oracle(P):
     note(f"loss {first:.4e} -> {final_gpu:.4e} (FP64 reference {final_ref:.4e})")
     assert final_gpu < 0.1 * first
     assert final_gpu < 3.0 * final_ref + 1e-4
+
+
+PROD = (3, 256, 256, 256, 256, 579)  # the warm-start network: 347 203 parameters
+
+
+def excess(gpu, ref):
+    """max over elements of |gpu - ref| / (|ref| + rms(ref))."""
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    rms = float(np.sqrt(np.mean(ref * ref)))
+    return float(np.max(np.abs(gpu - ref) / (np.abs(ref) + rms)))
+
+
+# Element-wise bars.  Against the BF16 reading of the oracle (the same values
+# rounded to BF16 at the same points, FP64 elsewhere) only two differences
+# remain: FP32 against FP64 accumulation (about K 2^-24 of the summed
+# magnitudes, ~1.5e-5 at K = 256) and the rare value whose FP32 and FP64
+# forms round to neighbouring BF16 numbers, which moves that value by one BF16
+# unit (2^-8 to 2^-7 of itself) and an output built from it by at most that
+# much of its largest term: bar 2^-7.  Against the FP64 network the BF16
+# rounding itself counts (up to about 4e-2 at this size, measured between the
+# oracle's two readings): bar 2^-4.
+BAR_BF16, BAR_FP64 = 2.0 ** -7, 2.0 ** -4
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_production_network_elementwise(P, seed):
+    """3 -> 4 x 256 -> 579 at batch 64: forward outputs, loss and every
+    layer's weight and bias gradients, element by element."""
+    import torch
+    params = R.init_params(PROD, seed=seed)
+    p32 = flat(params)  # the FP32 master values the GPU holds
+    params = [(W.astype(np.float64), b.astype(np.float64)) for W, b in unflat(p32, PROD)]
+    rng = np.random.default_rng(seed + 100)
+    x = rng.uniform(-1, 1, (64, 3)).astype(np.float32)
+    y = (0.5 * rng.standard_normal((64, PROD[-1]))).astype(np.float32)
+    note(f"case: production network {PROD}, batch 64, seed {seed}")
+    net = P.Mlp(PROD, 64, p32)
+    xt = torch.tensor(x, device="cuda")
+    yt = torch.tensor(y, device="cuda")
+    out = net.forward(xt).cpu().numpy()
+    x64, y64 = x.astype(np.float64), y.astype(np.float64)
+    ref16 = R.forward(params, x64, bf16=True)[0]
+    ref64 = R.forward(params, x64)[0]
+    e16, e64 = excess(out, ref16), excess(out, ref64)
+    note(f"  output: vs BF16 reading {e16:.3e}, vs FP64 {e64:.3e}")
+    assert e16 <= BAR_BF16 and e64 <= BAR_FP64
+    loss = net.gradients(xt, yt)
+    l16, g16 = R.backward(params, x64, y64, bf16=True)
+    l64, g64 = R.backward(params, x64, y64)
+    note(f"  loss: gpu {loss:.6e} BF16 reading {l16:.6e} FP64 {l64:.6e}")
+    assert abs(loss - l16) <= 1e-5 * l16
+    _, g = net.get_params()
+    for li, ((gW, gb), (aW, ab), (bW, bb)) in enumerate(zip(unflat(g, PROD), g16, g64)):
+        ew16, eb16, ew64, eb64 = excess(gW, aW), excess(gb, ab), excess(gW, bW), excess(gb, bb)
+        note(f"  layer {li}: dW {ew16:.3e} / {ew64:.3e}, db {eb16:.3e} / {eb64:.3e} (BF16 reading / FP64)")
+        assert ew16 <= BAR_BF16 and eb16 <= BAR_BF16, li
+        assert ew64 <= BAR_FP64 and eb64 <= BAR_FP64, li

@@ -73,3 +73,59 @@ def test_training_reduces_loss():
         loss, grads = R.backward(params, x, y)
         params = opt.step(params, grads)
     assert loss < 0.05 * l0
+
+
+# --------------------------------------------------------------------------
+# BF16 reading: rounding points of the reduced-precision network
+# --------------------------------------------------------------------------
+
+def test_bf16_rounding_matches_library_conversion():
+    """Round-to-nearest-even to BF16 against torch's own FP32 -> BF16
+    conversion, plus the tie cases by hand (7 fraction bits: 1 + 2^-8 lies
+    halfway between 1 and 1 + 2^-7 and goes to the even 1; 1 + 3 * 2^-8 goes
+    to the even 1 + 2^-6)."""
+    import torch
+    rng = np.random.default_rng(7)
+    x = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-6, 6, 20000),
+                        [0.0, -0.0, 1.0, -2.5, 3.0e38, 1e-40]]).astype(np.float32)
+    ref = torch.tensor(x).to(torch.bfloat16).to(torch.float64).numpy()
+    got = R.bf16(x)
+    assert np.array_equal(got, ref)
+    assert R.bf16(np.array([1 + 2.0 ** -8]))[0] == 1.0
+    assert R.bf16(np.array([1 + 3 * 2.0 ** -8]))[0] == 1 + 2.0 ** -6
+    assert R.bf16(np.array([1 + 2.0 ** -8 + 2.0 ** -20]))[0] == 1 + 2.0 ** -7
+
+
+def test_bf16_mode_is_exact_on_representable_linear_layers():
+    """One linear layer whose input, weights, bias and targets are BF16 values
+    with short mantissas: every rounding point sees an exact value, so the BF16
+    reading equals the FP64 network, output and gradients alike."""
+    rng = np.random.default_rng(8)
+    W = rng.integers(-8, 9, (5, 4)) / 8.0
+    b = rng.integers(-8, 9, 4) / 16.0
+    x = rng.integers(-4, 5, (6, 5)) / 4.0
+    params = [(W, b)]
+    # residuals 3k over 24 outputs: loss gradients 2 * 3k / 24 = k / 4, exact in BF16
+    y = x @ W + b - rng.integers(-2, 3, (6, 4)) * 3.0
+    o64, _, _ = R.forward(params, x)
+    o16, _, _ = R.forward(params, x, bf16=True)
+    assert np.array_equal(o64, o16)
+    l64, g64 = R.backward(params, x, y)
+    l16, g16 = R.backward(params, x, y, bf16=True)
+    assert l64 == l16
+    for (a, c), (d, e) in zip(g64, g16):
+        assert np.array_equal(a, d) and np.array_equal(c, e)
+
+
+def test_bf16_mode_rounds_hidden_activations():
+    """Two layers: the BF16 reading feeds the second product with the rounded
+    GELU of the first layer (checked against rounding it by hand)."""
+    params = R.init_params((3, 8, 2), seed=9)
+    x = np.random.default_rng(10).uniform(-1, 1, (5, 3))
+    out, pres, acts = R.forward(params, x, bf16=True)
+    h1 = R.bf16(R.gelu(R.bf16(x) @ R.bf16(params[0][0]) + params[0][1]))
+    assert np.array_equal(acts[1], h1)
+    assert np.array_equal(out, h1 @ R.bf16(params[1][0]) + params[1][1])
+    # and it differs from the FP64 network by BF16 rounding only
+    o64, _, _ = R.forward(params, x)
+    assert 0 < np.max(np.abs(out - o64)) < 2.0 ** -5 * np.max(np.abs(o64))

@@ -135,3 +135,65 @@ def test_single_run_autotune_does_not_change_results(P):
     for k in ("u", "v", "w", "cp", "cm", "phi", "p"):
         fa, fb = a.get_field(k).cpu().numpy(), b.get_field(k).cpu().numpy()
         assert np.max(np.abs(fa - fb)) <= 1e-12 * max(np.max(np.abs(fb)), 1e-30), k
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle as mod
+    mod._load()
+    return mod
+
+
+# Mixed-form bars per field (max |gpu - oracle| / max |oracle|): the FP32
+# state is rounded every substep (2^-24 relative to the field's own scale,
+# accumulating over ~150 substeps to ~1e-5 for u and c+-): bar 2e-5; v and w
+# are perturbations of the O(1) shear flow, so the same absolute rounding is
+# up to ~1e2 larger relative to their scale: 2e-3; p is the smallest field:
+# 2e-2; phi follows the charge, a small difference of two O(1)
+# concentrations, so its relative error is the charge's: 4 * 2e-5 * max(c) /
+# max|c+ - c-|.
+MIXED_BARS = {"u": 2e-5, "v": 2e-3, "w": 2e-3, "cp": 2e-5, "cm": 2e-5, "p": 2e-2}
+
+
+def mixed_bars(o):
+    c = max(np.max(np.abs(o.field("cp"))), np.max(np.abs(o.field("cm"))))
+    rho = np.max(np.abs(o.field("cp") - o.field("cm")))
+    return {**MIXED_BARS, "phi": 8e-5 * c / rho}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_production_size_members_match_oracle(P, O, precision):
+    """One member of each size class of the production ensemble (64x65x64
+    and 48x49x48, parameters from the ensemble sampler), batched in one
+    ensemble with autotuned launch shapes, against the oracle after the
+    tuner's trial substeps plus 30 more: FP64 within 1e-10 per field, the
+    mixed form within its per-field bars."""
+    members = P.configs.ensemble_members(seed=0, precision=precision)
+    pick = [members[0], members[32]]
+    note(f"case: ensemble members 0 (64x65x64) and 32 (48x49x48), {precision}, autotuned + 30 substeps")
+    e = P.Ensemble(pick)
+    assert e.classes() == 2
+    tiles = e.autotune(None, 3)
+    note(f"  tiles {tiles}")
+    e.step(30)
+    e.sync()
+    O.set_threads(16)
+    for m, c in enumerate(pick):
+        t, dt, ns = e.clock(m)
+        o = O.Oracle(**c.oracle_kwargs())
+        o.init(c.seed, c.u_noise, c.c_noise)
+        o.run(ns)
+        fe = fields_member(e, m)
+        err = {k: float(np.max(np.abs(fe[k] - o.field(k))) / max(np.max(np.abs(o.field(k))), 1e-300))
+               for k in FIELDS}
+        note(f"  member {m} ({c.nx}x{c.ny}x{c.nz}, Re {c.re:.0f}, vhat {c.vhat:.2f}, lam {c.debye:.4f}) "
+             f"after {ns} substeps: " + ", ".join(f"{k} {v:.2e}" for k, v in err.items()))
+        if precision == "fp64":
+            assert max(err.values()) < 1e-10, err
+            assert abs(dt - o.dt) < 1e-13 * o.dt and abs(t - o.t) < 1e-13 * max(o.t, 1.0)
+        else:
+            bars = mixed_bars(o)
+            note(f"  bars {bars}")
+            for k, bar in bars.items():
+                assert err[k] < bar, (k, err)
+            assert abs(dt - o.dt) < 1e-5 * o.dt

@@ -104,11 +104,13 @@ def test_poisson_solve_matches_oracle(P, O, dims, kind):
     assert parity(out, ref) < bar
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("cnslab", [0, 16])
-def test_small_case_200_substeps_match_oracle(P, O, cnslab):
+def test_small_case_200_substeps_match_oracle(P, O, cnslab, seed):
     """32x33x32, Re 400, lam 0.1, vhat 5, dt 1e-3: 200 RK substeps, with the
-    lane-scan (0) and the row-slab (16 rows) Crank-Nicolson methods."""
-    g, o = make_pair(P, O, P.configs.couette_small(seed=0))
+    lane-scan (0) and the row-slab (16 rows) Crank-Nicolson methods, for
+    seeds 0, 1 and 2."""
+    g, o = make_pair(P, O, P.configs.couette_small(seed=seed))
     g.set_tiles(cnslab=cnslab)
     assert g.tiles()["cnslab"] == cnslab
     for chunk in range(4):
@@ -155,41 +157,79 @@ def test_printed_force_sign_matches_oracle(P, O):
     assert max(err.values()) < 1e-10, err
 
 
+# Mixed-form bars per field (max |gpu - oracle| / max |oracle|).  The FP32
+# state is rounded every substep, 2^-24 of each value: over n substeps the
+# O(1) fields u, c+, c- drift by about n 2^-24 (~4e-6 at n = 60): bar 1e-5.
+# v and w are perturbations about 1e-2 of the shear flow, so the same
+# absolute rounding is up to ~1e2 times larger relative to their own scale:
+# bar 1e-4.  p is the smallest field (pressure increments of the projection):
+# bar 1e-2.  phi is solved from the charge c+ - c-, a small difference of two
+# O(1) concentrations: through the same linear solve its relative error is at
+# most the charge's, i.e. about 2 * 1e-5 * max(c) / max|c+ - c-|, taken with
+# a factor 2.
+MIXED_BARS = {"u": 1e-5, "v": 1e-4, "w": 1e-4, "cp": 1e-5, "cm": 1e-5, "p": 1e-2}
+
+
+def mixed_bars(o):
+    c = max(np.max(np.abs(o.field("cp"))), np.max(np.abs(o.field("cm"))))
+    rho = np.max(np.abs(o.field("cp") - o.field("cm")))
+    return {**MIXED_BARS, "phi": 4e-5 * c / rho}
+
+
 def test_mixed_precision_tracks_oracle(P, O):
-    """FP32 state and stencils, FP64 solves: errors at FP32 rounding level."""
+    """FP32 state and stencils, FP64 solves: errors at FP32 rounding level,
+    every field within its bar."""
     g, o = make_pair(P, O, P.configs.couette_small(precision="mixed", seed=0))
     g.step(60)
     o.run(60)
     err = worst(g, o)
-    note(f"mixed errors: {err}")
-    for k in ("u", "cp", "cm"):
-        assert err[k] < 1e-5, err
+    bars = mixed_bars(o)
+    note(f"mixed errors: {err}; bars {bars}")
+    for k, bar in bars.items():
+        assert err[k] < bar, (k, err)
     tb, tt = g.wall_shear_stress()
     otb, ott = o.wall_shear()
     assert abs(tb - otb) < 1e-4 * otb and abs(tt - ott) < 1e-4 * ott
 
 
-@pytest.mark.parametrize("cnslab,cn", [(0, 256), (0, 512), (16, 256), (32, 256)])
-def test_full_size_turbulent_case_matches_oracle(P, O, cnslab, cn):
-    """256x193x256, Re 3000, lam 0.05, vhat 10, adaptive dt (the benchmarked
-    case): initial state and one full RK3 step, with each Crank-Nicolson
-    method the autotuner can pick (the other launch shapes do not change the
-    arithmetic done per cell, line or mode)."""
+@pytest.fixture(scope="module")
+def turbulent_oracle(P, O):
+    """The oracle's 256x193x256 run (Re 3000, lam 0.05, vhat 10, adaptive
+    dt): initial state and the state after 30 substeps (ten RK steps)."""
     O.set_threads(16)
-    g, o = make_pair(P, O, P.configs.couette_turbulent(seed=0))
+    cfg = P.configs.couette_turbulent(seed=0)
+    note("oracle: 256x193x256, initial state and 30 substeps")
+    o = O.Oracle(**cfg.oracle_kwargs())
+    o.init(cfg.seed, cfg.u_noise, cfg.c_noise)
+    init = o.state()
+    o.run(30)
+    return dict(init=init, final=o.state(), dt=o.dt, t=o.t, tau=o.wall_shear())
+
+
+@pytest.mark.parametrize("cnslab,cn", [(0, 256), (0, 512), (16, 256), (32, 256)])
+def test_full_size_turbulent_case_matches_oracle(P, turbulent_oracle, cnslab, cn):
+    """256x193x256, Re 3000, lam 0.05, vhat 10, adaptive dt: initial state
+    and 30 substeps (ten RK steps), with each Crank-Nicolson method the
+    autotuner can pick (the other launch shapes do not change the arithmetic
+    done per cell, line or mode)."""
+    ref = turbulent_oracle
+    cfg = P.configs.couette_turbulent(seed=0)
+    note(f"case: 256x193x256 fp64 cnslab={cnslab} cn={cn}, 30 substeps")
+    g = P.Solver(cfg)
     g.set_tiles(cnslab=cnslab, cn=cn)
-    err0 = worst(g, o)
+    gf = gpu_fields(g)
+    err0 = {k: parity(gf[k], ref["init"][k]) for k in FIELDS}
     note(f"full size, initial state: {max(err0.values()):.3e}")
     assert max(err0.values()) < 1e-12, err0
-    g.step(3)
-    o.run(3)
-    err = worst(g, o)
-    note(f"full size, 3 substeps: {max(err.values()):.3e}")
+    g.step(30)
+    gf = gpu_fields(g)
+    err = {k: parity(gf[k], ref["final"][k]) for k in FIELDS}
+    note(f"full size, 30 substeps: {max(err.values()):.3e}")
     assert max(err.values()) < 1e-10, err
     t, dt, _, _ = g.clock()
-    assert abs(dt - o.dt) < 1e-13 * o.dt
+    assert abs(dt - ref["dt"]) < 1e-13 * ref["dt"] and abs(t - ref["t"]) < 1e-13 * ref["t"]
     tb, tt = g.wall_shear_stress()
-    otb, ott = o.wall_shear()
+    otb, ott = ref["tau"]
     assert abs(tb - otb) < 1e-10 * otb and abs(tt - ott) < 1e-10 * ott
 
 
@@ -228,6 +268,7 @@ def test_maximum_rows_mixed_tracks_oracle(P, O):
     g.step(9)
     o.run(9)
     err = worst(g, o)
-    note(f"mixed, 481 nodes: {err}")
-    for k in ("u", "cp", "cm"):
-        assert err[k] < 1e-5, err
+    bars = mixed_bars(o)
+    note(f"mixed, 481 nodes: {err}; bars {bars}")
+    for k, bar in bars.items():
+        assert err[k] < bar, (k, err)

@@ -6,6 +6,12 @@ right-hand sides, Crank-Nicolson wall-normal solves, pressure projection
 adaptive time step.  Inputs are synthetic and seeded (laminar Couette profile
 plus uniform noise) and resident in HBM before timing starts.
 
+Default workload: the large case, 512 x 385 x 512 (~101 M points), Re 6000,
+Debye length 0.02, 20 thermal volts, in FP64 (the headline, the path held to
+the oracle at 1e-10); the same workload in the mixed form (FP32 state and
+stencils, FP64 solves and reductions) is measured the same way and reported
+under "mixed" in the same line.
+
 Prints ONE JSON line: Mpoint-substeps/s (points = nx * ny * nz, ny the
 number of wall-normal nodes), the roofline of the dominant kernel measured
 with HIP events on the solver's stream, and the FP64 CPU oracle timed on a
@@ -66,7 +72,9 @@ def kernel_bytes(cfg, name: str, launches: int, substeps: int) -> float:
 
 def cpu_baseline(cfg, nsub: int = 0) -> dict:
     """The FP64 oracle as it stands, on all host cores, on a bounded sample:
-    whole RK3 steps, about 12 substeps of the 256x193x256 case (~12 s)."""
+    whole RK3 steps (one step, 3 substeps, of the 512x385x512 case: ~25 s
+    on 16 cores; 12 substeps of 256x193x256), timed after its initial
+    state is built."""
     from oracle import oracle as O
     if nsub <= 0:
         nsub = 3 * max(1, round(4 * 12_648_448 / cfg.points))
@@ -83,63 +91,22 @@ def cpu_baseline(cfg, nsub: int = 0) -> dict:
                       f"seeded initial state, FP64, {el:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--workload", default="couette_turbulent")
-    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
-                    help="default: fp64 for the single runs, the ensemble's own (mixed) for 'ensemble'")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="time the library's default launch shapes instead of the autotuned ones")
-    ap.add_argument("--stats-every", type=int, default=0,
-                    help="also sample the run statistics every N substeps in the timed regions "
-                         "(a separate measurement; the default line has no sampling)")
-    ap.add_argument("--implicit-xz", action="store_true",
-                    help="diffusion implicit in x and z too (three-direction approximate factorisation)")
-    ap.add_argument("--wall-amplitude", type=float, default=0.0,
-                    help="time with a wall-potential pattern A cos(x) cos(2z) on both walls "
-                         "(a separate measurement of the inhomogeneous potential solve)")
-    ap.add_argument("--copy-calibration-mb", type=int, default=0,
-                    help="before timing, run one plain device-to-device copy of this many MiB (a "
-                         "reference kernel of known traffic for hardware byte counters)")
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: the solver is a single-GPU build "
-              "(a multi-GPU z-slab decomposition is designed, not built).", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import paper_1701_02005_amd as P
-
-    if args.workload == "ensemble":
-        bench_ensemble(args, P, torch)
-        return
-    if args.precision is None:  # the large case is quoted in its mixed form
-        args.precision = "mixed" if args.workload == "couette_large" else "fp64"
-    cfg = P.configs.WORKLOADS[args.workload](precision=args.precision)
-    if args.implicit_xz:
-        cfg = dataclasses.replace(cfg, implicit_xz=1)
-    print(f"[bench] workload {args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz} {args.precision}", file=sys.stderr,
-          flush=True)
-    if args.copy_calibration_mb > 0:
-        nbytes = args.copy_calibration_mb << 20
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(f"[bench] calibration copy of {nbytes} bytes read + {nbytes} bytes written", file=sys.stderr,
-              flush=True)
-        del src, dst
+def measure(cfg, args, P, torch, tiles_trial: int) -> dict:
+    """Autotune (unless disabled), warm up, time args.steps substeps with HIP
+    events on the solver's stream, then time the same length again with
+    events around every kernel launch.  Returns the throughput, per-kernel
+    table and the dominant kernel's roofline."""
     solver = P.Solver(cfg, device="cuda:0")
     stream = solver.stream
     tiles = None
-    if not args.no_autotune:  # launch shapes by the library's autotuner (advances the run)
-        tiles = solver.autotune(None, 30)
-        print(f"[bench] autotuned launch shapes {tiles}", file=sys.stderr, flush=True)
+    fixed = args.tiles.get(cfg.precision) if args.tiles else None
+    if fixed:  # launch shapes given on the command line (e.g. those a timed run's tuner chose)
+        solver.set_tiles(**fixed)
+        tiles = solver.tiles()
+        print(f"[bench] {cfg.precision}: launch shapes set to {tiles}", file=sys.stderr, flush=True)
+    elif not args.no_autotune:  # launch shapes by the library's autotuner (advances the run)
+        tiles = solver.autotune(None, tiles_trial)
+        print(f"[bench] {cfg.precision}: autotuned launch shapes {tiles}", file=sys.stderr, flush=True)
     if args.stats_every > 0:
         solver.stats_begin(args.stats_every)
     if args.wall_amplitude:
@@ -150,7 +117,7 @@ def main():
         solver.refresh_potential()
     solver.step(args.warmup)
     torch.cuda.synchronize()
-    print(f"[bench] warmup {args.warmup} substeps done", file=sys.stderr, flush=True)
+    print(f"[bench] {cfg.precision}: warmup {args.warmup} substeps done", file=sys.stderr, flush=True)
 
     # clean timed region
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -160,7 +127,7 @@ def main():
     stop.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop)
-    print(f"[bench] timed {args.steps} substeps: {ms:.1f} ms", file=sys.stderr, flush=True)
+    print(f"[bench] {cfg.precision}: timed {args.steps} substeps: {ms:.1f} ms", file=sys.stderr, flush=True)
 
     # same length again with HIP events around every kernel launch
     solver.profile_enable(True)
@@ -175,6 +142,8 @@ def main():
     solver.profile_enable(False)
     diag = solver.diagnostics()
     tb, tt = solver.wall_shear_stress()
+    del solver
+    torch.cuda.empty_cache()
 
     kernels = {}
     total_bytes = 0.0
@@ -198,7 +167,7 @@ def main():
     if tr_file.exists() and not args.implicit_xz:  # (counters were taken without the x/z solves)
         try:
             from paper_1701_02005_amd import pmc_traffic
-            ent = json.loads(tr_file.read_text()).get(f"{args.workload}/{args.precision}/{dom}")
+            ent = json.loads(tr_file.read_text()).get(f"{args.workload}/{cfg.precision}/{dom}")
             src = Path(ent["source"]).name if ent else None
             cn_slab = bool(tiles and tiles.get("cnslab"))
             same_kernels = ent and tuple(ent.get("kernels", ())) == tuple(pmc_traffic.class_kernels(dom, cn_slab))
@@ -206,27 +175,9 @@ def main():
                 traffic = ent["bytes_per_launch"]
         except (ValueError, OSError, KeyError):
             traffic = None
-
-    value = cfg.points * args.steps / (ms * 1e-3) / 1e6
-    out = {
-        "metric": "Mpoint-substeps/s",
-        "value": value,
-        "unit": "Mpoint-substeps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+    return {
+        "value": cfg.points * args.steps / (ms * 1e-3) / 1e6,
         "ms_per_step": ms / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz} Re={cfg.re:g} "
-                               f"debye={cfg.debye:g} vhat={cfg.vhat:g} {args.precision}",
-                   "points": cfg.points, "cells": cfg.cells, "precision": args.precision,
-                   "parallelism": "single GPU", **({"stats_every": args.stats_every} if args.stats_every else {}),
-                   **({"wall_amplitude": args.wall_amplitude} if args.wall_amplitude else {}),
-                   **({"implicit_xz": 1} if args.implicit_xz else {})},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_unit": "bytes/launch",
                      "algorithmic_bytes_per_launch": per_launch_bytes,
@@ -239,6 +190,108 @@ def main():
         "profiled_region_ms": ms_prof,
         "state_check": {"tau_bottom": tb, "tau_top": tt, "max_div": diag["max_div"]},
     }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=15)
+    ap.add_argument("--workload", default="couette_large")
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="default: fp64 for the single runs (the large case adds its mixed form to the "
+                         "line), the ensemble's own (mixed) for 'ensemble'")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="large case: do not add the mixed form's measurement to the line")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the library's default launch shapes instead of the autotuned ones")
+    ap.add_argument("--tiles", action="append", default=[],
+                    help="PREC:name=value,... launch shapes of one precision (fp64 or mixed) instead of the "
+                         "autotuner's, e.g. fp64:expl=256,slab=16,cnslab=32 (for profiler runs that must time "
+                         "the shapes a timed run chose without the tuner's trial launches)")
+    ap.add_argument("--stats-every", type=int, default=0,
+                    help="also sample the run statistics every N substeps in the timed regions "
+                         "(a separate measurement; the default line has no sampling)")
+    ap.add_argument("--implicit-xz", action="store_true",
+                    help="diffusion implicit in x and z too (three-direction approximate factorisation)")
+    ap.add_argument("--wall-amplitude", type=float, default=0.0,
+                    help="time with a wall-potential pattern A cos(x) cos(2z) on both walls "
+                         "(a separate measurement of the inhomogeneous potential solve)")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="before timing, run one plain device-to-device copy of this many MiB (a "
+                         "reference kernel of known traffic for hardware byte counters)")
+    args = ap.parse_args()
+    tiles_by_prec = {}
+    for spec in args.tiles:
+        prec, _, kv = spec.partition(":")
+        tiles_by_prec[prec] = {k: int(v) for k, v in (item.split("=") for item in kv.split(",") if item)}
+    args.tiles = tiles_by_prec
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: the solver is a single-GPU build "
+              "(a multi-GPU z-slab decomposition is designed, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1701_02005_amd as P
+
+    if args.workload == "ensemble":
+        bench_ensemble(args, P, torch)
+        return
+    explicit_precision = args.precision is not None
+    if args.precision is None:
+        args.precision = "fp64"
+    cfg = P.configs.WORKLOADS[args.workload](precision=args.precision)
+    if args.implicit_xz:
+        cfg = dataclasses.replace(cfg, implicit_xz=1)
+    print(f"[bench] workload {args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz} {args.precision}", file=sys.stderr,
+          flush=True)
+    if args.copy_calibration_mb > 0:
+        nbytes = args.copy_calibration_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {nbytes} bytes read + {nbytes} bytes written", file=sys.stderr,
+              flush=True)
+        del src, dst
+    # launch-shape trials: whole RK steps; 6 substeps suffice where one substep takes milliseconds
+    trial = 6 if cfg.cells > 50_000_000 else 30
+    res = measure(cfg, args, P, torch, trial)
+
+    out = {
+        "metric": "Mpoint-substeps/s",
+        "value": res["value"],
+        "unit": "Mpoint-substeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz} Re={cfg.re:g} "
+                               f"debye={cfg.debye:g} vhat={cfg.vhat:g} {args.precision}",
+                   "points": cfg.points, "cells": cfg.cells, "precision": args.precision,
+                   "parallelism": "single GPU", **({"stats_every": args.stats_every} if args.stats_every else {}),
+                   **({"wall_amplitude": args.wall_amplitude} if args.wall_amplitude else {}),
+                   **({"implicit_xz": 1} if args.implicit_xz else {})},
+        **{k: res[k] for k in ("roofline", "substep_roofline", "kernels", "launch_shapes", "profiled_region_ms",
+                               "state_check")},
+    }
+    # the large case is also quoted in its mixed form (FP32 state and stencils,
+    # FP64 solves and reductions): same measurement, extra keys of the line
+    if args.workload == "couette_large" and not explicit_precision and not args.no_mixed:
+        cm = dataclasses.replace(cfg, precision="mixed")
+        print("[bench] mixed form of the same workload", file=sys.stderr, flush=True)
+        rm = measure(cm, args, P, torch, trial)
+        out["mixed"] = {"value": rm["value"], "unit": "Mpoint-substeps/s", "ms_per_step": rm["ms_per_step"],
+                        "dtype": "f32+f64", "roofline": rm["roofline"], "substep_roofline": rm["substep_roofline"],
+                        "kernels": rm["kernels"], "launch_shapes": rm["launch_shapes"],
+                        "state_check": rm["state_check"]}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -378,6 +378,35 @@ NSPNP_API int nspnp_mlp_train_step(nspnp_mlp *h, const float *dev_x, const float
 NSPNP_API int nspnp_mlp_sync(nspnp_mlp *h);
 NSPNP_API void nspnp_mlp_destroy(nspnp_mlp *h);
 
+/* ---- elliptic solve without device allocation ------------------------- */
+
+/* Bytes of the fixed device scratch of nspnp_poisson_solve_noalloc. */
+#define NSPNP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of nspnp_poisson_solve (same kinds, operators, layouts and kernels) on the
+ * grid of cfg (nx, ny, nz, lx, lz, stretch; the other fields are checked but
+ * not used), with no handle and no workspace.  rhs and out are caller-owned
+ * FP64 device arrays of nx*nz*(ny-1) cell values (may alias); hip_stream is
+ * a hipStream_t (NULL: the null stream); the current device is used.
+ * Scratch: a fixed array of NSPNP_NOALLOC_SCRATCH_BYTES in device memory,
+ * one per GPU, held from the library's first use on that GPU until the
+ * process ends; it takes the grid tables, the Thomas pivots of both
+ * operators and one half spectrum, 48 (nx/2+1) nz (ny-1) bytes plus the
+ * tables, and a grid needing more is refused with NSPNP_ERR_SIZE.  The call
+ * allocates no device memory.  The first call on a GPU, and any call whose
+ * grid differs from the previous call's on that GPU, writes the tables and
+ * pivots into the scratch and synchronises the stream (do it outside a
+ * graph capture); later calls with the same grid only queue the solve
+ * kernels (asynchronous).  Every call on a GPU shares that GPU's scratch:
+ * calls whose work overlaps on one GPU (other streams, other host threads
+ * before the earlier work has finished) race and give wrong results.
+ */
+NSPNP_API int nspnp_poisson_solve_noalloc(const nspnp_config *cfg, int32_t kind, const double *dev_rhs,
+                                          double *dev_out, void *hip_stream);
+
 /* Wait for all queued work of this state. */
 NSPNP_API int nspnp_sync(nspnp_state *s);
 

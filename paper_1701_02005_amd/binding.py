@@ -169,6 +169,7 @@ def load_library() -> ctypes.CDLL:
         "nspnp_mlp_train_step": (_I, [_P, _P, _P, ctypes.c_int32, ctypes.c_float, _P]),
         "nspnp_mlp_sync": (_I, [_P]),
         "nspnp_mlp_destroy": (None, [_P]),
+        "nspnp_poisson_solve_noalloc": (_I, [ctypes.POINTER(_CConfig), ctypes.c_int32, _P, _P, _P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -218,6 +219,25 @@ def grid(cfg: Config):
     yn, yc = (_D * cfg.ny)(), (_D * (cfg.ny - 1))()
     _check(load_library().nspnp_grid(ctypes.byref(c), yn, yc))
     return list(yn), list(yc)
+
+
+def poisson_solve_noalloc(cfg: Config, kind: int, rhs: torch.Tensor, out: torch.Tensor | None = None,
+                          stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+    """nspnp_poisson_solve_noalloc: the elliptic solve on cfg's grid with the
+    library's fixed device scratch (no handle, no workspace).  rhs / out:
+    contiguous float64 CUDA tensors of nx*nz*(ny-1) values."""
+    n = cfg.cells
+    for t in (rhs,) + (() if out is None else (out,)):
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.device.type != "cuda" or t.numel() != n:
+            raise ValueError("expected a contiguous float64 CUDA tensor of nx*nz*(ny-1) values")
+    out = torch.empty_like(rhs) if out is None else out
+    stream = stream if stream is not None else torch.cuda.current_stream(rhs.device)
+    c = cfg.to_c()
+    with torch.cuda.device(rhs.device):
+        _check(load_library().nspnp_poisson_solve_noalloc(ctypes.byref(c), int(kind), ctypes.c_void_p(rhs.data_ptr()),
+                                                          ctypes.c_void_p(out.data_ptr()),
+                                                          ctypes.c_void_p(stream.cuda_stream)))
+    return out
 
 
 def workspace_bytes(cfg: Config) -> int:

@@ -10,7 +10,7 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libnspnp.so"
-SOURCES = ["api.hip", "stencil.hip", "poisson.hip", "reduce.hip", "ensemble.hip", "mlp.hip"]
+SOURCES = ["api.hip", "stencil.hip", "poisson.hip", "reduce.hip", "ensemble.hip", "mlp.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

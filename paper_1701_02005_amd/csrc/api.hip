@@ -59,8 +59,9 @@ int check_config(const nspnp_config *c) {
         if (n < 4 || n > 1024 || n % 2 != 0 || !smooth_size(n))
             return fail(NSPNP_ERR_SIZE, "nx and nz must be even, of the form 2^a 3^b, and within 4..1024");
     }
-    if (c->ny < 5 || c->ny > 481)
-        return fail(NSPNP_ERR_SIZE, "ny (wall-normal nodes) must be within 5..481 (cell rows staged in 64 KB of LDS)");
+    if (c->ny < 5 || c->ny > kMaxRows + 1)
+        return fail(NSPNP_ERR_SIZE, "ny (wall-normal nodes) must be within 5.." + std::to_string(kMaxRows + 1) +
+                                        " (cell rows staged in 64 KB of LDS)");
     if ((int64_t)c->nx * c->nz * (c->ny - 1) > 2147483647LL)
         return fail(NSPNP_ERR_SIZE, "nx * nz * (ny - 1) must stay below 2^31 cells (32-bit cell indices)");
     const double pos[] = {c->lx, c->lz, c->re, c->sc, c->debye};
@@ -119,7 +120,7 @@ size_t table_count(int M, int nx, int nz) { return 11 * (size_t)M + 2 + (nx / 2 
 void build_tables(nspnp_state *s, double *dev_tab) {
     const nspnp_config &c = s->cfg;
     const int M = s->d.M, nx = c.nx, nz = c.nz, nxh = s->d.nxh;
-    std::vector<double> yn(M + 1);
+    double yn[kMaxRows + 1];  // (no heap use: the allocation-free solve builds tables too)
     for (int j = 0; j <= M; ++j) {
         const double xi = -1.0 + 2.0 * j / (double)M;
         yn[j] = (c.stretch > 0.0) ? std::tanh(c.stretch * xi) / std::tanh(c.stretch) : xi;
@@ -237,6 +238,10 @@ namespace nspnp {
 
 int fail_code(int code, const std::string &msg) { return fail(code, msg); }
 
+void fill_tables(nspnp_state *s, double *dev_tab) { build_tables(s, dev_tab); }
+
+size_t tables_len(int M, int nx, int nz) { return table_count(M, nx, nz); }
+
 int check(const nspnp_config *c) { return check_config(c); }
 
 size_t layout_bytes(const nspnp_config *c) { return make_layout(c).total; }
@@ -258,10 +263,9 @@ Phys make_phys(const nspnp_config *cfg) {
     return ph;
 }
 
-// Handle over nmem members of one size class: member m's workspace starts at
-// base + m * layout_bytes(cfg); pointers refer to member 0.
-void setup_handle(nspnp_state *s, const nspnp_config *cfg, char *base, int nmem, hipStream_t stream) {
-    const Layout L = make_layout(cfg);
+// Sizes, constants, FFT plans, default launch shapes and the device's LDS
+// limit of a handle on this configuration (no device memory touched).
+void setup_common(nspnp_state *s, const nspnp_config *cfg, int nmem, hipStream_t stream) {
     s->cfg = *cfg;
     s->stream = stream;
     s->fp64 = cfg->precision == NSPNP_PREC_FP64;
@@ -277,7 +281,7 @@ void setup_handle(nspnp_state *s, const nspnp_config *cfg, char *base, int nmem,
     d.dz = cfg->lz / cfg->nz;
     s->ph = make_phys(cfg);
     s->nmem = nmem;
-    s->mstride = nmem > 1 ? L.total : 0;
+    s->mstride = 0;
     s->planx = make_plan(cfg->nx);
     s->planz = make_plan(cfg->nz);
     // the tuner's choices at 256 x 193 x 256 (the mixed form takes 32-column
@@ -289,6 +293,14 @@ void setup_handle(nspnp_state *s, const nspnp_config *cfg, char *base, int nmem,
             hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
             s->lds_max = lds;
     }
+}
+
+// Handle over nmem members of one size class: member m's workspace starts at
+// base + m * layout_bytes(cfg); pointers refer to member 0.
+void setup_handle(nspnp_state *s, const nspnp_config *cfg, char *base, int nmem, hipStream_t stream) {
+    const Layout L = make_layout(cfg);
+    setup_common(s, cfg, nmem, stream);
+    s->mstride = nmem > 1 ? L.total : 0;
     for (int q = 0; q < 7; ++q) s->f[q] = base + L.off_f[q];
     for (int q = 0; q < 5; ++q) s->h[q] = base + L.off_h[q];
     for (int q = 0; q < 5; ++q) s->r[q] = base + L.off_r[q];

@@ -14,6 +14,8 @@
 namespace nspnp {
 
 constexpr int kMaxFftStages = 12;
+// Most cell rows across the gap (ny - 1) of a supported grid.
+constexpr int kMaxRows = 480;
 
 // Radix decomposition of one FFT length (radices 4, 2, 3; product = n).
 struct FftPlan {
@@ -381,6 +383,7 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b);
 // (once per device and kernel); hipErrorInvalidValue when bytes > lds_max.
 hipError_t lds_opt_in(const void *fn, size_t bytes, int lds_max);
 hipError_t launch_thomas_factors(nspnp_state *s);
+hipError_t prime_x_transform_lds(int lds_max);
 hipError_t launch_dt(nspnp_state *s);
 hipError_t launch_init_fields(nspnp_state *s);
 hipError_t launch_plane_sums(nspnp_state *s, int what, double *dev_out);
@@ -394,6 +397,9 @@ hipError_t launch_fill(nspnp_state *s, double *p, int64_t n, double v);
 
 // handle management shared by the single-run and ensemble entry points
 int fail_code(int code, const std::string &msg);
+void setup_common(nspnp_state *s, const nspnp_config *cfg, int nmem, hipStream_t stream);
+void fill_tables(nspnp_state *s, double *dev_tab);  // host tables + device pointers at dev_tab
+size_t tables_len(int M, int nx, int nz);           // doubles of the grid tables
 int check(const nspnp_config *c);
 size_t layout_bytes(const nspnp_config *c);
 Phys make_phys(const nspnp_config *cfg);

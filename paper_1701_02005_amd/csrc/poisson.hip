@@ -909,6 +909,18 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
     return hipGetLastError();
 }
 
+// Raise the dynamic-LDS limit of the FP64 x transforms ahead of use (their
+// blocks may take more than 64 KB), so that later launches find the record.
+hipError_t prime_x_transform_lds(int lds_max) {
+    const void *fns[4] = {(const void *)k_fft_x_r2c<double, false>, (const void *)k_fft_x_r2c<double, true>,
+                          (const void *)k_fft_x_c2r<double, false>, (const void *)k_fft_x_c2r<double, true>};
+    for (const void *fn : fns) {
+        const hipError_t e = lds_opt_in(fn, (size_t)lds_max, lds_max);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Thomas pivots of both elliptic operators for every member of the handle
 // (once, at init: they depend on the grid only).
 hipError_t launch_thomas_factors(nspnp_state *s) {

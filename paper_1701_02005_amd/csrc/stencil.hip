@@ -409,7 +409,6 @@ __device__ __forceinline__ void cn_row(const double *lo_tab, const double *up_ta
     C = -beta * up;
 }
 
-constexpr int kMaxRows = 480;  // cell rows of the largest supported grid (ny <= 481)
 
 // The matrix is the same for every (x, z) column, so Thomas elimination
 // reduces to two linear recurrences with column-independent coefficients:

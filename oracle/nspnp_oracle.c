@@ -71,6 +71,11 @@ typedef struct {
     int32_t nx, ny, nz;   /* ny = number of wall-normal NODES              */
     int32_t implicit_xz;  /* 1: diffusion implicit in x and z too, by the
                              three-direction approximate factorisation    */
+    int32_t migration_face; /* face value of c in the migration flux:
+                               0 the unweighted mean of the two cells,
+                               1 hybrid: the upwind cell of the species'
+                               drift on faces whose potential difference
+                               is at least 2, the mean elsewhere          */
 } or_config;
 
 enum { F_U = 0, F_V, F_W, F_CP, F_CM, F_PHI, F_P, F_NFIELD };
@@ -481,6 +486,21 @@ void or_coulomb(const or_solver *s, const double *cp, const double *cm, const do
             }
 }
 
+/* Face value of c in the migration flux of a species of valence zs across a
+ * face with potential difference dphi = Phi_R - Phi_L (cell R on the side of
+ * increasing index).  Sec. II gives second-order central differences, whose
+ * face value is the mean of the two cells.  At equilibrium that value makes
+ * the cell ratio c_R / c_L = (1 - zs dphi / 2) / (1 + zs dphi / 2), which is
+ * negative once |dphi| > 2 (the cell Peclet number of migration).  The hybrid
+ * rule takes, on such faces, the cell the drift comes from: the drift
+ * velocity of the species is -zs (Re Sc)^-1 grad Phi, so the upwind cell is R
+ * when zs dphi > 0 and L otherwise; its equilibrium ratio 1 / (1 + zs dphi)
+ * or 1 + |dphi| stays positive. */
+static double or_mig_face(const or_solver *s, double cL, double cR, double dphi, double zs) {
+    if (s->cfg.migration_face == 1 && fabs(dphi) >= 2.0) return (zs * dphi > 0.0) ? cR : cL;
+    return 0.5 * (cL + cR);
+}
+
 /* Ion transport terms for one species of valence zs = +1 / -1 except the
  * implicit wall-normal diffusion:
  *   -div(u c) + (Re Sc)^-1 [ (Lxx + Lzz) c + zs div(c_face grad Phi) ]
@@ -505,24 +525,30 @@ void or_ion_explicit(const or_solver *s, const double *u, const double *v, const
                 double ax = (u[IDX(s, ip, j, k)] * 0.5 * (cxp + cc) - u[c0] * 0.5 * (cc + cxm)) / dx;
                 double az = (w[IDX(s, i, j, kp)] * 0.5 * (czp + cc) - w[c0] * 0.5 * (cc + czm)) / dz;
                 double vt = 0.0, vb = 0.0, ft = 0.0, fb = 0.0;
+                /* potential differences across the faces (y: applied field
+                 * e0 over the centre distance plus the perturbation) */
                 if (j + 1 < M) {
                     size_t cu = IDX(s, i, j + 1, k);
                     double cup = c[cu];
+                    double dpy = e0 * s->dc[j + 1] + (phi[cu] - phi[c0]);
                     vt = v[cu] * 0.5 * (cup + cc);
-                    ft = 0.5 * (cup + cc) * (e0 + (phi[cu] - phi[c0]) / s->dc[j + 1]);
+                    ft = or_mig_face(s, cc, cup, dpy, zs) * (e0 + (phi[cu] - phi[c0]) / s->dc[j + 1]);
                 }
                 if (j > 0) {
                     size_t cd = IDX(s, i, j - 1, k);
                     double cdn = c[cd];
+                    double dpy = e0 * s->dc[j] + (phi[c0] - phi[cd]);
                     vb = v[c0] * 0.5 * (cc + cdn);
-                    fb = 0.5 * (cc + cdn) * (e0 + (phi[c0] - phi[cd]) / s->dc[j]);
+                    fb = or_mig_face(s, cdn, cc, dpy, zs) * (e0 + (phi[c0] - phi[cd]) / s->dc[j]);
                 }
                 double ay = (vt - vb) / s->dn[j];
                 /* migration: face concentration times face potential gradient */
-                double mx = (0.5 * (cxp + cc) * (phi[IDX(s, ip, j, k)] - phi[c0]) / dx -
-                             0.5 * (cc + cxm) * (phi[c0] - phi[IDX(s, im, j, k)]) / dx) / dx;
-                double mz = (0.5 * (czp + cc) * (phi[IDX(s, i, j, kp)] - phi[c0]) / dz -
-                             0.5 * (cc + czm) * (phi[c0] - phi[IDX(s, i, j, km)]) / dz) / dz;
+                double dpxp = phi[IDX(s, ip, j, k)] - phi[c0], dpxm = phi[c0] - phi[IDX(s, im, j, k)];
+                double dpzp = phi[IDX(s, i, j, kp)] - phi[c0], dpzm = phi[c0] - phi[IDX(s, i, j, km)];
+                double mx = (or_mig_face(s, cc, cxp, dpxp, zs) * dpxp / dx -
+                             or_mig_face(s, cxm, cc, dpxm, zs) * dpxm / dx) / dx;
+                double mz = (or_mig_face(s, cc, czp, dpzp, zs) * dpzp / dz -
+                             or_mig_face(s, czm, cc, dpzm, zs) * dpzm / dz) / dz;
                 double my = (ft - fb) / s->dn[j];
                 double dxx = (cxp - 2.0 * cc + cxm) / (dx * dx) + (czp - 2.0 * cc + czm) / (dz * dz);
                 if (s->cfg.implicit_xz) dxx = 0.0; /* treated implicitly (or_substep) */
@@ -1039,7 +1065,8 @@ void or_ion_flux(const or_solver *s, double *jp, double *jm, double *mp, double 
                     size_t c0 = IDX(s, i, j, k), cd = IDX(s, i, j - 1, k);
                     double cf = 0.5 * (c[c0] + c[cd]);
                     double ey = e0 + (phi[c0] - phi[cd]) / s->dc[j];
-                    sum += v[c0] * cf - kd * ((c[c0] - c[cd]) / s->dc[j] + zs * cf * ey);
+                    double cmig = or_mig_face(s, c[cd], c[c0], e0 * s->dc[j] + (phi[c0] - phi[cd]), zs);
+                    sum += v[c0] * cf - kd * ((c[c0] - c[cd]) / s->dc[j] + zs * cmig * ey);
                 }
             jo[j] = sum / ((double)s->nx * s->nz);
         }

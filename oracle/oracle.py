@@ -42,7 +42,7 @@ class _Config(ctypes.Structure):
         ("u_bot", ctypes.c_double), ("force_sign", ctypes.c_double), ("dt", ctypes.c_double),
         ("cfl", ctypes.c_double),
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-        ("implicit_xz", ctypes.c_int32),
+        ("implicit_xz", ctypes.c_int32), ("migration_face", ctypes.c_int32),
     ]
 
 
@@ -113,7 +113,7 @@ def _ptr(a: np.ndarray):
 
 DEFAULTS = dict(lx=2 * np.pi, lz=np.pi, stretch=1.5, re=400.0, sc=1.0, beta=0.5, debye=0.1,
                 vhat=5.0, u_top=1.0, u_bot=-1.0, force_sign=-1.0, dt=1e-3, cfl=0.5,
-                nx=32, ny=33, nz=32, implicit_xz=0)
+                nx=32, ny=33, nz=32, implicit_xz=0, migration_face=0)
 
 
 def make_config(**kw) -> _Config:
@@ -124,7 +124,7 @@ def make_config(**kw) -> _Config:
     d.update(kw)
     c = _Config()
     for k, v in d.items():
-        setattr(c, k, int(v) if k in ("nx", "ny", "nz", "implicit_xz") else float(v))
+        setattr(c, k, int(v) if k in ("nx", "ny", "nz", "implicit_xz", "migration_face") else float(v))
     return c
 
 

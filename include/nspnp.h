@@ -77,7 +77,7 @@ extern "C" {
 
 /*
  * Configuration.  Sizes: nx, nz of the form 2^a 3^b, even, 4..1024; ny (the
- * number of wall-normal NODES, so ny - 1 cell rows) within 5..481, and
+ * number of wall-normal NODES, so ny - 1 cell rows) within 5..513, and
  * nx * nz * (ny - 1) below 2^31.  Lengths in
  * units of h.  stretch is the tanh clustering factor g of the y nodes
  * y_j = tanh(g xi_j)/tanh(g), xi_j uniform on [-1, 1] (g = 0: uniform).
@@ -108,7 +108,14 @@ typedef struct nspnp_config {
      * using the full Laplacian of psi and the dt rule dropping its explicit
      * diffusion limit.  0: only the wall-normal diffusion is implicit. */
     int32_t implicit_xz;
-    int32_t reserved; /* 0 */
+    /* Face value of c in the migration flux.  0: the mean of the two cells
+     * (the second-order central form of Sec. II), whose stationary cell
+     * ratio (1 - z dPhi/2)/(1 + z dPhi/2) turns negative once the potential
+     * difference dPhi across a face exceeds 2 thermal volts.  1: hybrid, the
+     * cell the species' drift comes from (upwind) on faces with |dPhi| >= 2,
+     * the mean elsewhere; its stationary ratios 1/(1 + z dPhi) and 1 + |dPhi|
+     * stay positive (first order on those faces only). */
+    int32_t migration_face;
 } nspnp_config;
 
 typedef struct nspnp_state nspnp_state;
@@ -235,6 +242,33 @@ NSPNP_API int nspnp_set_wall_potential(nspnp_state *s, const double *dev_bot, co
  * Synchronises. */
 NSPNP_API int nspnp_stats_begin(nspnp_state *s, int32_t every);
 NSPNP_API int nspnp_stats_read(nspnp_state *s, double *time, int64_t *samples, double *out);
+
+/* Friction quantities and wall units of the run statistics (Sec. II
+ * definitions: wall shear stress tau_w = eta d<u_x>/dy in units of rho U^2,
+ * c_f = tau_w / (rho U^2 / 2), Re_tau = u_tau h / nu with u_tau = sqrt(tau_w
+ * / rho)), applied to the time-averaged plane-mean velocity of the run
+ * statistics.  out[0] tau at the bottom wall and out[1] at the top wall (the
+ * viscous flux through the wall face over the half cell next to it, as in
+ * nspnp_wall_shear_stress), out[2] their mean tau, out[3] c_f = 2 tau,
+ * out[4] Re_tau = Re sqrt(|tau|), out[5] u_tau = sqrt(|tau_bottom|) of the
+ * lower wall.  rms (NULL or 7 * M doubles, M = ny - 1): the RMS profiles
+ * sqrt(max(<q^2> - <q>^2, 0)) of u, v, w, c+, c-, phi, p as rms[q * M + j].
+ * y_plus, u_plus (NULL or M doubles each): the lower wall's wall units of the
+ * rows, y+ = (1 + y_j) Re u_tau and u+ = (<u>_j - u_bot) / u_tau (y_j the
+ * cell centres).  Before the first sample every output is NaN.
+ * Synchronises. */
+NSPNP_API int nspnp_stats_derived(nspnp_state *s, double out[6], double *rms, double *y_plus, double *u_plus);
+
+/* Kinetic-energy budget of the semi-discrete momentum equation (Sec. II,
+ * Eq. (1)): dKE/dt = out[0] - out[1] + out[2] with out[0] the power of the
+ * moving walls against the viscous wall stress, sum over the wall faces of
+ * u_wall Re^-1 (u_wall - u_next)/(dy/2) dA; out[1] the viscous dissipation
+ * Re^-1 sum |grad u|^2 Omega over every difference of the staggered velocity
+ * components (with the half cells next to the walls); out[2] the work of the
+ * Coulomb force, sum u . f Omega.  Convection and the pressure gradient do no
+ * work on a discretely divergence-free field.  FP64 host outputs.
+ * Synchronises. */
+NSPNP_API int nspnp_energy_budget(nspnp_state *s, double out[3]);
 
 /* Checkpoint of a run: the seven fields and the five explicit-term buffers
  * H (kept between the stages of a Runge-Kutta step) in the storage type,

@@ -40,7 +40,7 @@ class _CConfig(ctypes.Structure):
         ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
         ("seed", ctypes.c_uint64),
         ("u_noise", ctypes.c_double), ("c_noise", ctypes.c_double),
-        ("implicit_xz", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("implicit_xz", ctypes.c_int32), ("migration_face", ctypes.c_int32),
     ]
 
 
@@ -68,6 +68,7 @@ class Config:
     u_noise: float = 0.01
     c_noise: float = 1e-3
     implicit_xz: int = 0  # 1: x/z diffusion implicit too (three-direction factorisation)
+    migration_face: int = 0  # 1: hybrid (upwind where the potential jump across a face is >= 2)
 
     def to_c(self) -> _CConfig:
         c = _CConfig()
@@ -170,6 +171,9 @@ def load_library() -> ctypes.CDLL:
         "nspnp_mlp_sync": (_I, [_P]),
         "nspnp_mlp_destroy": (None, [_P]),
         "nspnp_poisson_solve_noalloc": (_I, [ctypes.POINTER(_CConfig), ctypes.c_int32, _P, _P, _P]),
+        "nspnp_stats_derived": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D),
+                                     ctypes.POINTER(_D)]),
+        "nspnp_energy_budget": (_I, [_P, ctypes.POINTER(_D)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -182,30 +186,6 @@ def load_library() -> ctypes.CDLL:
 DIAGNOSTIC_NAMES = ("ke", "max_div", "min_cp", "min_cm", "max_csum", "max_dphi")
 STATS_FIELDS = ("u", "v", "w", "cp", "cm", "phi", "p")
 STATS_NAMES = STATS_FIELDS + tuple(f + "2" for f in STATS_FIELDS)
-
-
-def derived_statistics(cfg, T: float, samples: int, st: Dict[str, list]) -> Dict[str, object]:
-    """Mean and RMS profiles, wall shear stresses, c_f, Re_tau and wall units
-    from time-averaged plane means (see Solver.statistics)."""
-    import math
-    yn, yc = grid(cfg)
-    M = cfg.ny - 1
-    dn0, dn1 = yn[1] - yn[0], yn[M] - yn[M - 1]
-    ire = 1.0 / cfg.re
-    u = st["u"]
-    tau_b = ire * (u[0] - cfg.u_bot) / (0.5 * dn0)
-    tau_t = ire * (cfg.u_top - u[M - 1]) / (0.5 * dn1)
-    tau = 0.5 * (tau_b + tau_t)
-    rms = {f: [math.sqrt(max(st[f + "2"][j] - st[f][j] ** 2, 0.0)) for j in range(M)] for f in STATS_FIELDS}
-    ut = math.sqrt(abs(tau_b))
-    return {
-        "time": T, "samples": samples, "yc": yc, "yn": yn[:M],
-        "mean": {f: st[f] for f in STATS_FIELDS}, "rms": rms,
-        "tau_bottom": tau_b, "tau_top": tau_t, "tau": tau, "cf": 2.0 * tau,
-        "re_tau": cfg.re * math.sqrt(abs(tau)),
-        "y_plus": [(1.0 + y) * cfg.re * ut for y in yc],
-        "u_plus": [(x - cfg.u_bot) / ut if ut > 0 else float("nan") for x in u],
-    }
 
 
 def _check(rc: int):
@@ -398,12 +378,30 @@ class Solver:
         return t.value, n.value, {k: vals[q * M:(q + 1) * M] for q, k in enumerate(STATS_NAMES)}
 
     def statistics(self) -> Dict[str, object]:
-        """Time-averaged profiles and wall quantities from the run statistics
-        (Sec. III): mean and RMS profiles, tau at both walls from the mean
-        velocity, c_f = 2 tau, Re_tau = Re sqrt(tau), and the mean velocity in
-        wall units of the lower wall (y+ = (1 + y) Re u_tau, u+ = (u - u_bot) / u_tau)."""
+        """Time-averaged profiles and wall quantities of the run statistics
+        (nspnp_stats_read and nspnp_stats_derived): mean and RMS profiles, tau
+        at both walls from the mean velocity, c_f, Re_tau, u_tau and the mean
+        velocity in wall units of the lower wall (NaN before the first sample)."""
         T, n, st = self.stats_read()
-        return derived_statistics(self.cfg, T, n, st)
+        M = self.M
+        out, rms, yp, up = (_D * 6)(), (_D * (len(STATS_FIELDS) * M))(), (_D * M)(), (_D * M)()
+        _check(self.lib.nspnp_stats_derived(self._h, out, rms, yp, up))
+        yn, yc = grid(self.cfg)
+        r = list(rms)
+        return {
+            "time": T, "samples": n, "yc": yc, "yn": yn[:M],
+            "mean": {f: st[f] for f in STATS_FIELDS},
+            "rms": {f: r[q * M:(q + 1) * M] for q, f in enumerate(STATS_FIELDS)},
+            "tau_bottom": out[0], "tau_top": out[1], "tau": out[2], "cf": out[3], "re_tau": out[4],
+            "u_tau": out[5], "y_plus": list(yp), "u_plus": list(up),
+        }
+
+    def energy_budget(self) -> Dict[str, float]:
+        """Kinetic-energy budget terms (nspnp_energy_budget): dKE/dt =
+        wall_work - dissipation + force_work."""
+        out = (_D * 3)()
+        _check(self.lib.nspnp_energy_budget(self._h, out))
+        return dict(zip(("wall_work", "dissipation", "force_work"), list(out)))
 
     def save(self, path: str):
         """Checkpoint (fields, H buffers, clock, run statistics) to a file."""

@@ -72,6 +72,8 @@ int check_config(const nspnp_config *c) {
         return fail(NSPNP_ERR_INVALID, "non-finite configuration value");
     if (c->dt <= 0.0 && !(c->cfl > 0.0)) return fail(NSPNP_ERR_INVALID, "adaptive dt needs cfl > 0");
     if (c->implicit_xz != 0 && c->implicit_xz != 1) return fail(NSPNP_ERR_INVALID, "implicit_xz must be 0 or 1");
+    if (c->migration_face != 0 && c->migration_face != 1)
+        return fail(NSPNP_ERR_INVALID, "migration_face must be 0 (mean) or 1 (hybrid)");
     return NSPNP_OK;
 }
 
@@ -260,6 +262,7 @@ Phys make_phys(const nspnp_config *cfg) {
     ph.cfl = cfg->cfl;
     ph.adaptive = cfg->dt > 0.0 ? 0.0 : 1.0;
     ph.implicit_xz = cfg->implicit_xz ? 1.0 : 0.0;
+    ph.hybrid = cfg->migration_face ? 1.0 : 0.0;
     return ph;
 }
 
@@ -677,6 +680,30 @@ int nspnp_diagnostics(nspnp_state *s, double out[6]) {
     return NSPNP_OK;
 }
 
+int nspnp_energy_budget(nspnp_state *s, double out[3]) {
+    if (!s || !out) return fail(NSPNP_ERR_INVALID, "bad energy_budget arguments");
+    const int M = s->d.M;
+    HIP_TRY(launch_energy_sums(s, s->red));
+    std::vector<double> h((size_t)4 * M);
+    HIP_TRY(hipMemcpyAsync(h.data(), s->red, h.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    double dis = 0.0, fwk = 0.0;
+    for (int j = 0; j < M; ++j) {
+        dis += h[4 * (size_t)j];
+        fwk += h[4 * (size_t)j + 1];
+    }
+    const double *dc = host_dc(s);
+    const double area = s->d.dx * s->d.dz, ire = s->ph.ire;
+    // power of the moving walls against the viscous wall stress
+    out[0] = s->cfg.u_top * ire * h[4 * (size_t)(M - 1) + 2] / dc[M] * area -
+             s->cfg.u_bot * ire * h[2] / dc[0] * area;
+    out[1] = ire * dis;
+    out[2] = fwk;
+    for (int q = 0; q < 3; ++q)
+        if (!std::isfinite(out[q])) return fail(NSPNP_ERR_NONFINITE, "non-finite energy budget");
+    return NSPNP_OK;
+}
+
 int nspnp_get_clock(nspnp_state *s, double *t, double *dt, int32_t *stage, int64_t *substeps) {
     if (!s) return fail(NSPNP_ERR_INVALID, "state is NULL");
     double c[2];
@@ -735,6 +762,50 @@ int nspnp_stats_read(nspnp_state *s, double *time, int64_t *samples, double *out
     return NSPNP_OK;
 }
 
+int nspnp_stats_derived(nspnp_state *s, double out[6], double *rms, double *y_plus, double *u_plus) {
+    if (!s || !out) return fail(NSPNP_ERR_INVALID, "bad stats_derived arguments");
+    const int M = s->d.M;
+    std::vector<double> h((size_t)kRunStatsQ * M + kRunStatsTail);
+    HIP_TRY(hipMemcpyAsync(h.data(), s->rstats, h.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const double T = h[(size_t)kRunStatsQ * M];
+    const double nan = std::nan("");
+    auto mean = [&](int q, int j) { return h[(size_t)q * M + j] / T; };
+    if (!(T > 0.0)) {  // nothing averaged yet
+        for (int q = 0; q < 6; ++q) out[q] = nan;
+        for (int e = 0; rms && e < kRunStatsFields * M; ++e) rms[e] = nan;
+        for (int j = 0; j < M; ++j) {
+            if (y_plus) y_plus[j] = nan;
+            if (u_plus) u_plus[j] = nan;
+        }
+        return NSPNP_OK;
+    }
+    // wall shear stresses of the time-mean velocity: the viscous flux through
+    // the wall faces over the half cell next to each wall (as nspnp_wall_shear_stress)
+    const double *dc = host_dc(s), *yc = s->host_tables.data();
+    const double tb = s->ph.ire * (mean(0, 0) - s->cfg.u_bot) / dc[0];
+    const double tt = s->ph.ire * (s->cfg.u_top - mean(0, M - 1)) / dc[M];
+    const double tau = 0.5 * (tb + tt);
+    const double ut = std::sqrt(std::fabs(tb));
+    out[0] = tb;
+    out[1] = tt;
+    out[2] = tau;
+    out[3] = 2.0 * tau;                             // c_f = tau_w / (rho U^2 / 2)
+    out[4] = s->cfg.re * std::sqrt(std::fabs(tau));  // Re_tau = u_tau h / nu
+    out[5] = ut;
+    if (rms)
+        for (int q = 0; q < kRunStatsFields; ++q)
+            for (int j = 0; j < M; ++j) {
+                const double m = mean(q, j), v = mean(kRunStatsFields + q, j) - m * m;
+                rms[(size_t)q * M + j] = std::sqrt(v > 0.0 ? v : 0.0);
+            }
+    for (int j = 0; j < M; ++j) {  // wall units of the lower wall
+        if (y_plus) y_plus[j] = (1.0 + yc[j]) * s->cfg.re * ut;
+        if (u_plus) u_plus[j] = ut > 0.0 ? (mean(0, j) - s->cfg.u_bot) / ut : nan;
+    }
+    return NSPNP_OK;
+}
+
 int nspnp_sync(nspnp_state *s) {
     if (!s) return fail(NSPNP_ERR_INVALID, "state is NULL");
     HIP_TRY(hipStreamSynchronize(s->stream));
@@ -769,7 +840,8 @@ bool same_run(const nspnp_config &a, const nspnp_config &b) {
     return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.precision == b.precision && a.lx == b.lx &&
            a.lz == b.lz && a.stretch == b.stretch && a.re == b.re && a.sc == b.sc && a.beta == b.beta &&
            a.debye == b.debye && a.vhat == b.vhat && a.u_top == b.u_top && a.u_bot == b.u_bot &&
-           a.force_sign == b.force_sign && a.dt == b.dt && a.cfl == b.cfl && a.implicit_xz == b.implicit_xz;
+           a.force_sign == b.force_sign && a.dt == b.dt && a.cfl == b.cfl && a.implicit_xz == b.implicit_xz &&
+           a.migration_face == b.migration_face;
 }
 
 struct FileCloser {

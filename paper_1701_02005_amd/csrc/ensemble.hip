@@ -430,7 +430,7 @@ int nspnp_set_tiles(nspnp_state *s, const int32_t *t) {
     };
     if (!one_of(t[0], {64, 128, 256}) || !one_of(t[1], {64, 128, 256, 512}) || t[2] < 64 || t[2] > 8192 ||
         t[3] < 64 || t[3] > 8192 || t[4] < 1 || t[4] > 64 || !one_of(t[5], {64, 128, 256}) ||
-        t[6] < 1 || t[6] > 480 || !one_of(t[7], {0, 16, 32}))
+        t[6] < 1 || t[6] > kMaxRows || !one_of(t[7], {0, 16, 32}))
         return fail_code(NSPNP_ERR_INVALID, "launch shapes out of range");
     E_TRY(hipStreamSynchronize(s->stream));
     s->tiles = Tiles{t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7]};

@@ -14,8 +14,9 @@
 namespace nspnp {
 
 constexpr int kMaxFftStages = 12;
-// Most cell rows across the gap (ny - 1) of a supported grid.
-constexpr int kMaxRows = 480;
+// Most cell rows across the gap (ny - 1) of a supported grid: 8 rows per
+// lane of the wall-normal scans.
+constexpr int kMaxRows = 512;
 
 // Radix decomposition of one FFT length (radices 4, 2, 3; product = n).
 struct FftPlan {
@@ -63,7 +64,31 @@ struct Phys {
     double debye, cfl;
     double adaptive;    // 1: dt from the CFL rule at stage 1; 0: fixed dt
     double implicit_xz; // 1: x/z diffusion implicit (no explicit diffusion limit on dt)
+    double hybrid;      // 1: hybrid face value of c in the migration flux (mig_face)
 };
+
+// Face value of c in the migration flux of a species of valence zs across a
+// face with potential difference dphi = Phi_R - Phi_L (R the cell on the side
+// of increasing index), given the mean of the two cells.  Sec. II's central
+// differences take the mean; its stationary cell ratio
+// (1 - zs dphi/2)/(1 + zs dphi/2) turns negative once |dphi| > 2.  The hybrid
+// rule takes, on faces with |dphi| >= 2, the cell the species' drift
+// -zs (Re Sc)^-1 grad Phi comes from: R when zs dphi > 0, else L.
+template <typename T>
+__device__ __forceinline__ T mig_face(bool hyb, T mean, T cl, T cr, T dphi, T zs) {
+    if (hyb && fabs(dphi) >= T(2)) return (zs * dphi > T(0)) ? cr : cl;
+    return mean;
+}
+// Potential difference across a wall-normal face: the applied field e0 over
+// the centre distance dc plus the perturbation difference, each operation
+// rounded on its own (no fused multiply-add), so that the hybrid rule's
+// threshold sees the same value wherever it is formed.
+__device__ __forceinline__ double y_dphi(double e0, double dc, double dphi) {
+    return __dadd_rn(__dmul_rn(e0, dc), dphi);
+}
+__device__ __forceinline__ float y_dphi(float e0, float dc, float dphi) {
+    return __fadd_rn(__fmul_rn(e0, dc), dphi);
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  This bijection of the linear block id gives XCD x one contiguous range
@@ -387,6 +412,7 @@ hipError_t prime_x_transform_lds(int lds_max);
 hipError_t launch_dt(nspnp_state *s);
 hipError_t launch_init_fields(nspnp_state *s);
 hipError_t launch_plane_sums(nspnp_state *s, int what, double *dev_out);
+hipError_t launch_energy_sums(nspnp_state *s, double *dev_out);  // 4 doubles per row
 hipError_t launch_shift_conc(nspnp_state *s, double mean_p, double mean_m);
 hipError_t launch_convert(nspnp_state *s, int field, const double *in, double *out, bool to_state);
 hipError_t launch_stats_accum(nspnp_state *s, double alp);

@@ -212,7 +212,7 @@ __device__ __forceinline__ void r2c_stage(const PoissonSrc &src, const Dims &d, 
     const int nx = d.nx, nz = d.nz, M = d.M, n = ppb * nx, bd = (int)blockDim.x;
     const int64_t nlines = (int64_t)M * nz;
     const unsigned upl = (unsigned)d.plane;
-    // (line = j nz + k < 480 * 1024 and e < ppb nx: the float-reciprocal
+    // (line = j nz + k < 512 * 1024 and e < ppb nx: the float-reciprocal
     // divmod is exact for both)
     const Div dnx(nx), dnz(nz);
     for (int e0 = threadIdx.x; e0 < n; e0 += kXB * bd) {
@@ -857,7 +857,7 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
         const int tm = thomas_tile_modes(d.M, s->tiles.thomas);
         const dim3 gt((unsigned)((nmodes + tm - 1) / tm), (unsigned)b.nprob, (unsigned)nmem);
         const size_t ldst = (size_t)d.M * (tm + 1) * sizeof(double2);
-        const int rpl = (d.M + 63) / 64;  // rows per lane (M <= 480: at most 8)
+        const int rpl = (d.M + 63) / 64;  // rows per lane (M <= 512: at most 8)
 #define NSPNP_TH_CASE(RR)                                                                                \
     case RR:                                                                                             \
         k_thomas_tile<RR><<<gt, 256, ldst, s->stream>>>(d, s->tb, b, s->spec, s->fac, nspec, tm);        \

@@ -243,8 +243,13 @@ __global__ void __launch_bounds__(kRedThreads) k_plane(Dims d, const Phys *phys,
             const double e_y = ph.e0 + ((double)phi[q] - (double)phi[qd]) / dcj;
             const double f1 = 0.5 * (c1 + (double)cp[qd]);
             const double f2 = 0.5 * (c2 + (double)cm[qd]);
-            acc[3] += vv * f1 - ph.kd * ((c1 - (double)cp[qd]) / dcj + f1 * e_y);
-            acc[4] += vv * f2 - ph.kd * ((c2 - (double)cm[qd]) / dcj - f2 * e_y);
+            // migration face values (hybrid rule: upwind where |dPhi| >= 2)
+            const bool hyb = ph.hybrid != 0.0;
+            const double dpy = hyb ? y_dphi(ph.e0, dcj, (double)phi[q] - (double)phi[qd]) : 0.0;
+            const double g1 = mig_face(hyb, f1, (double)cp[qd], c1, dpy, 1.0);
+            const double g2 = mig_face(hyb, f2, (double)cm[qd], c2, dpy, -1.0);
+            acc[3] += vv * f1 - ph.kd * ((c1 - (double)cp[qd]) / dcj + g1 * e_y);
+            acc[4] += vv * f2 - ph.kd * ((c2 - (double)cm[qd]) / dcj - g2 * e_y);
             acc[5] += 0.5 * vv * vv * d.dx * dcj * d.dz;
             acc[10] = fmax(acc[10], fabs((double)phi[q] - (double)phi[qd] + ph.e0 * dcj));
         }
@@ -274,6 +279,90 @@ __global__ void __launch_bounds__(kRedThreads) k_plane(Dims d, const Phys *phys,
         __syncthreads();
     }
     if (threadIdx.x < kPlaneQ) out[(int64_t)j * kPlaneQ + threadIdx.x] = s[threadIdx.x][0];
+}
+
+// Kinetic-energy budget terms of one cell row (one block per row), in the
+// volume-weighted forms of the semi-discrete equations:
+//   out[4 j + 0]  sum over the row's velocity unknowns of |grad u|^2 times the
+//                 control volume of each difference (x, z differences of u, w
+//                 and v; y differences of u, w across centre rows and of v
+//                 across cell rows; the half cells next to the walls in rows
+//                 0 and M-1), so that Re^-1 times its total is the dissipation
+//   out[4 j + 1]  sum of u . f Omega, f the Coulomb force at the u, v, w points
+//   out[4 j + 2]  row 0: sum of (u - u_bot); row M-1: sum of (u_top - u)
+//   out[4 j + 3]  0
+// The wall work follows on the host from out[2] of the two wall rows.
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) k_energy(Dims d, const Phys *phys, Tables tb, const T *u, const T *v,
+                                                        const T *w, const T *cp, const T *cm, const T *phi,
+                                                        double *out, size_t ms) {
+    __shared__ double s[3][kRedThreads];
+    u = member_ptr(u, ms); v = member_ptr(v, ms); w = member_ptr(w, ms);
+    cp = member_ptr(cp, ms); cm = member_ptr(cm, ms); phi = member_ptr(phi, ms); out = member_ptr(out, ms);
+    const Phys ph = *member_ptr(phys, ms);
+    const int j = blockIdx.x, M = d.M;
+    const int64_t pl = d.plane;
+    const int64_t base = (int64_t)j * pl;
+    const double dx = d.dx, dz = d.dz, dn = tb.dn[j];
+    const double dcj = tb.dc[j], dcu = tb.dc[j + 1], dc0 = tb.dc[0], dcM = tb.dc[M];
+    double dis = 0.0, fwk = 0.0, wall = 0.0;
+    for (int64_t e = threadIdx.x; e < pl; e += blockDim.x) {
+        const int64_t q = base + e;
+        const int i = (int)(e % d.nx), k = (int)(e / d.nx);
+        const int64_t xp = q - i + ((i + 1 == d.nx) ? 0 : i + 1);
+        const int64_t xm = q - i + ((i == 0) ? d.nx - 1 : i - 1);
+        const int64_t zp = q + (int64_t)(((k + 1 == d.nz) ? 0 : k + 1) - k) * d.nx;
+        const int64_t zm = q + (int64_t)(((k == 0) ? d.nz - 1 : k - 1) - k) * d.nx;
+        const double uu = (double)u[q], vv = (double)v[q], ww = (double)w[q];
+        const double gux = ((double)u[xp] - uu) / dx, guz = ((double)u[zp] - uu) / dz;
+        const double gwx = ((double)w[xp] - ww) / dx, gwz = ((double)w[zp] - ww) / dz;
+        dis += (gux * gux + guz * guz + gwx * gwx + gwz * gwz) * dx * dn * dz;
+        if (j + 1 < M) {
+            const double guy = ((double)u[q + pl] - uu) / dcu, gwy = ((double)w[q + pl] - ww) / dcu;
+            dis += (guy * guy + gwy * gwy) * dx * dcu * dz;
+        }
+        if (j > 0) {
+            const double gvx = ((double)v[xp] - vv) / dx, gvz = ((double)v[zp] - vv) / dz;
+            dis += (gvx * gvx + gvz * gvz) * dx * dcj * dz;
+        }
+        {
+            const double vb = (j > 0) ? vv : 0.0, vt = (j + 1 < M) ? (double)v[q + pl] : 0.0;
+            const double gvy = (vt - vb) / dn;
+            dis += gvy * gvy * dx * dn * dz;
+        }
+        if (j == 0) {
+            const double gub = (uu - ph.u_bot) / dc0, gwb = ww / dc0;
+            dis += (gub * gub + gwb * gwb) * dx * dc0 * dz;
+            wall += uu - ph.u_bot;
+        }
+        if (j == M - 1) {
+            const double gut = (ph.u_top - uu) / dcM, gwt = -ww / dcM;
+            dis += (gut * gut + gwt * gwt) * dx * dcM * dz;
+            wall += ph.u_top - uu;
+        }
+        // Coulomb force sF K rho_face grad Phi at the u, w and v points
+        const double f0 = (double)phi[q];
+        const double r0 = (double)cp[q] - (double)cm[q];
+        const double fu = ph.kf * 0.5 * (r0 + (double)cp[xm] - (double)cm[xm]) * (f0 - (double)phi[xm]) / dx;
+        const double fw = ph.kf * 0.5 * (r0 + (double)cp[zm] - (double)cm[zm]) * (f0 - (double)phi[zm]) / dz;
+        fwk += (uu * fu + ww * fw) * dx * dn * dz;
+        if (j > 0) {
+            const int64_t qd = q - pl;
+            const double ey = ph.e0 + (f0 - (double)phi[qd]) / dcj;
+            const double fv = ph.kf * 0.5 * (r0 + (double)cp[qd] - (double)cm[qd]) * ey;
+            fwk += vv * fv * dx * dcj * dz;
+        }
+    }
+    s[0][threadIdx.x] = dis;
+    s[1][threadIdx.x] = fwk;
+    s[2][threadIdx.x] = wall;
+    __syncthreads();
+    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int qq = 0; qq < 3; ++qq) s[qq][threadIdx.x] += s[qq][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[(int64_t)j * 4 + threadIdx.x] = threadIdx.x < 3 ? s[threadIdx.x][0] : 0.0;
 }
 
 // time sums (weight alp dt) of the plane means of u, c+ - c- and phi per row
@@ -380,6 +469,20 @@ hipError_t launch_plane_sums(nspnp_state *s, int /*what*/, double *dev_out) {
             (const double *)s->f[3], (const double *)s->f[4], (const double *)s->f[5], dev_out, s->mstride);
     else
         k_plane<float><<<g, kRedThreads, 0, s->stream>>>(
+            s->d, s->d_phys, s->tb, (const float *)s->f[0], (const float *)s->f[1], (const float *)s->f[2],
+            (const float *)s->f[3], (const float *)s->f[4], (const float *)s->f[5], dev_out, s->mstride);
+    return hipGetLastError();
+}
+
+// energy-budget partial sums, 4 per row (k_energy)
+hipError_t launch_energy_sums(nspnp_state *s, double *dev_out) {
+    const dim3 g((unsigned)s->d.M, 1, (unsigned)s->nmem);
+    if (s->fp64)
+        k_energy<double><<<g, kRedThreads, 0, s->stream>>>(
+            s->d, s->d_phys, s->tb, (const double *)s->f[0], (const double *)s->f[1], (const double *)s->f[2],
+            (const double *)s->f[3], (const double *)s->f[4], (const double *)s->f[5], dev_out, s->mstride);
+    else
+        k_energy<float><<<g, kRedThreads, 0, s->stream>>>(
             s->d, s->d_phys, s->tb, (const float *)s->f[0], (const float *)s->f[1], (const float *)s->f[2],
             (const float *)s->f[3], (const float *)s->f[4], (const float *)s->f[5], dev_out, s->mstride);
     return hipGetLastError();

@@ -318,6 +318,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
                 const T ey_t = has_up ? e0 + (fp - ph0) * idct : T(0);
                 const T ey_b = has_dn ? e0 + (ph0 - fm) * idcb : T(0);
                 const T vt = has_up ? vp : T(0);
+                // potential differences across the six faces (the hybrid
+                // migration rule's switch; block-uniform hyb)
+                const bool hyb = ph.hybrid != 0.0;
+                const T dpx_r = fxp - ph0, dpx_l = ph0 - fxm, dpz_f = fzp - ph0, dpz_b = ph0 - fzm;
+                T dpy_t = T(0), dpy_b = T(0);
+                if (hyb) {
+                    if (has_up) dpy_t = y_dphi(e0, T(uniform_load(a.tb.dc, j + 1)), fp - ph0);
+                    if (has_dn) dpy_b = y_dphi(e0, T(uniform_load(a.tb.dc, j)), ph0 - fm);
+                }
 #pragma unroll
                 for (int sp = 0; sp < 2; ++sp) {
                     const int fi = 3 + sp;
@@ -334,18 +343,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
                     if (has_up) {
                         const T fy = half * (cu + cc);
                         at = vt * fy;
-                        mt = fy * ey_t;
+                        mt = mig_face(hyb, fy, cc, cu, dpy_t, zs) * ey_t;
                         dft = (cu - cc) * idct;
                     }
                     if (has_dn) {
                         const T fy = half * (cc + cd);
                         ab = vc * fy;
-                        mb = fy * ey_b;
+                        mb = mig_face(hyb, fy, cd, cc, dpy_b, zs) * ey_b;
                         dfb = (cc - cd) * idcb;
                     }
                     const T ay = (at - ab) * idn;
-                    const T mx = (fxr * gx_r - fxl * gx_l) * idx_;
-                    const T mz = (fzf * gz_f - fzb * gz_b) * idz_;
+                    const T mx = (mig_face(hyb, fxr, cc, cxp, dpx_r, zs) * gx_r -
+                                  mig_face(hyb, fxl, cxm, cc, dpx_l, zs) * gx_l) * idx_;
+                    const T mz = (mig_face(hyb, fzf, cc, czp, dpz_f, zs) * gz_f -
+                                  mig_face(hyb, fzb, czm, cc, dpz_b, zs) * gz_b) * idz_;
                     const T my = (mt - mb) * idn;
                     const T dxx = (cxp - two * cc + cxm) * ix2 + (czp - two * cc + czm) * iz2;
                     const T dxxH = imp ? zero : dxx;
@@ -1400,7 +1411,7 @@ static hipError_t launch_cn_lane(nspnp_state *s, const CnArgs &a) {
     const dim3 g((unsigned)((s->d.plane + tcols - 1) / tcols), 5, (unsigned)s->nmem);
     const size_t lds = (size_t)s->d.M * (tcols + 1) * sizeof(double);
     if (lds > (size_t)s->lds_max) return hipErrorInvalidValue;
-    const int rpl = (s->d.M + 63) / 64;  // rows per lane (M <= 480: at most 8)
+    const int rpl = (s->d.M + 63) / 64;  // rows per lane (M <= 512: at most 8)
     // tiles above 64 KB of LDS (tall columns) use the device's larger limit
     auto launch = [&](const void *fn, auto kernel) -> hipError_t {
         const hipError_t e = lds_opt_in(fn, lds, s->lds_max);

@@ -233,11 +233,11 @@ def test_full_size_turbulent_case_matches_oracle(P, turbulent_oracle, cnslab, cn
     assert abs(tb - otb) < 1e-10 * otb and abs(tt - ott) < 1e-10 * ott
 
 
-@pytest.mark.parametrize("dims,cn", [((1024, 481, 4), 256), ((4, 481, 1024), 512), ((1024, 481, 4), 512)],
+@pytest.mark.parametrize("dims,cn", [((1024, 513, 4), 256), ((4, 513, 1024), 512), ((1024, 513, 4), 512)],
                          ids=["nx1024-cn16", "nz1024-cn32", "nx1024-cn32"])
 def test_maximum_sizes_match_oracle(P, O, dims, cn):
     """The largest supported line lengths (1024 points in x or z) with the
-    largest wall-normal count (481 nodes: 480 cell rows, 8 rows per lane in
+    largest wall-normal count (513 nodes: 512 cell rows, 8 rows per lane in
     the Crank-Nicolson and mode scans, Crank-Nicolson tiles above 64 KB of
     LDS): initial state, then two RK steps with the adaptive time step."""
     nx, ny, nz = dims
@@ -259,16 +259,16 @@ def test_maximum_sizes_match_oracle(P, O, dims, cn):
 
 
 def test_maximum_rows_mixed_tracks_oracle(P, O):
-    """Mixed form at 481 wall-normal nodes (FP32 state through 32-column
-    Crank-Nicolson tiles of 480 rows)."""
+    """Mixed form at 513 wall-normal nodes (FP32 state through 32-column
+    Crank-Nicolson tiles of 512 rows)."""
     O.set_threads(16)
-    cfg = cfg_of(P, nx=64, ny=481, nz=16, precision="mixed", re=2000.0, vhat=6.0, debye=0.05, stretch=1.5,
+    cfg = cfg_of(P, nx=64, ny=513, nz=16, precision="mixed", re=2000.0, vhat=6.0, debye=0.05, stretch=1.5,
                  seed=4, u_noise=0.05)
     g, o = make_pair(P, O, cfg)
     g.step(9)
     o.run(9)
     err = worst(g, o)
     bars = mixed_bars(o)
-    note(f"mixed, 481 nodes: {err}; bars {bars}")
+    note(f"mixed, 513 nodes: {err}; bars {bars}")
     for k, bar in bars.items():
         assert err[k] < bar, (k, err)

@@ -98,7 +98,7 @@ Layout make_layout(const nspnp_config *c) {
     const int64_t nspec = nxh * c->nz * M;
     L.off_spec = o; o = align256(o + 2 * nspec * 16);
     L.off_fac = o; o = align256(o + 2 * nspec * 16);  // [kind][mode][row] pivots
-    L.off_coef = o; o = align256(o + 3 * (9 * M + 9 * kCnMaxSlabs) * 8);  // 3 stages: (g, m, n) rows, slab products
+    L.off_coef = o; o = align256(o + 3 * cn_stage_stride((int)M) * 8);  // 3 stages: rows, slab products, n products
     L.off_clock = o; o = align256(o + kClockSlots * 8);
     L.off_phys = o; o = align256(o + sizeof(Phys));
     L.off_stats = o; o = align256(o + (3 * M + 2) * 8);
@@ -725,6 +725,7 @@ int nspnp_set_clock(nspnp_state *s, double t, double dt, int32_t stage, int64_t 
     if (s->host_health) s->host_health[0] = s->host_health[1] = 0.0;
     s->substeps = substeps;
     s->cn_fresh = false;  // dt may have changed
+    s->cn_coef_at = -1;
     return NSPNP_OK;
 }
 
@@ -917,6 +918,7 @@ int nspnp_load(nspnp_state *s, const char *path) {
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->substeps = h.substeps;
     s->cn_fresh = false;
+    s->cn_coef_at = -1;
     s->rstats_every = cs.every;
     if (s->host_health) {
         s->host_health[0] = h.clock[2];

@@ -264,6 +264,13 @@ struct PoissonBatch {
 
 // Row-slab Crank-Nicolson method: the most slabs per column.
 constexpr int kCnMaxSlabs = 32;
+// Crank-Nicolson coefficients of one Runge-Kutta stage: [3 systems][g, m, n]
+// [M] rows, the slab products [3 systems][P, Phi, Nu][kCnMaxSlabs], then for
+// the row-slab method's fused first pass [3 systems][M] the products of n
+// from the slab's first row up to the row below.
+__host__ __device__ inline size_t cn_stage_stride(int M) {
+    return 12 * (size_t)M + 9 * (size_t)kCnMaxSlabs;
+}
 
 // Launch shapes chosen by the autotuner.  None of them changes the
 // arithmetic done per cell, column, line or mode, so results are bitwise
@@ -353,6 +360,7 @@ struct nspnp_state {
     double *cn_coef;     // Crank-Nicolson recurrence coefficients, 9 M per stage
     bool cn_fresh = false;  // cn_coef matches the device dt of the current step
     int cn_coef_slab = -1;  // slab rows the slab products in cn_coef were made for
+    int64_t cn_coef_at = -1;  // substep count at which cn_coef was last brought up to date
     double *clock;       // device [t, dt, health, max |dPhi|]
     double *host_health = nullptr;  // pinned host mirror of each member's [health, max |dPhi|]
     bool owns_host_health = false;

@@ -52,6 +52,12 @@ struct ExplicitArgs {
     int slabs;      // row slabs per member
     int slab_rows;  // rows marched by one block
     int implicit_xz;  // 1: x/z diffusion goes to the implicit (alpha) part of r, not to H
+    // Row-slab Crank-Nicolson with its first pass fused (NULL: not fused):
+    // this stage's recurrence coefficients [3 systems][g, m, n][M] and the
+    // method's scratch [2][5 fields][slabs][plane]; the block's slab is the
+    // method's slab, and the kernel stores both exits of every column.
+    const double *cn_coef;
+    double *cn_scr;
 };
 
 __device__ __forceinline__ void shift_explicit(ExplicitArgs &a, unsigned mem) {
@@ -62,6 +68,10 @@ __device__ __forceinline__ void shift_explicit(ExplicitArgs &a, unsigned mem) {
     a.phi = member_ptr_at(a.phi, ms, mem); a.p = member_ptr_at(a.p, ms, mem);
     for (int f = 0; f < 5; ++f) { a.h[f] = member_ptr_at(a.h[f], ms, mem); a.r[f] = member_ptr_at(a.r[f], ms, mem); }
     a.clock = member_ptr_at(a.clock, ms, mem);
+    if (a.cn_coef) {
+        a.cn_coef = member_ptr_at(a.cn_coef, ms, mem);
+        a.cn_scr = member_ptr_at(a.cn_scr, ms, mem);
+    }
 }
 
 // Convection, horizontal diffusion, Coulomb force and ion transport at one
@@ -158,6 +168,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
     const bool use_old = (a.st.k > 0) && mode == 0;
     const bool keep = (a.st.k < 2) && mode == 0;
     const bool imp = a.implicit_xz != 0;  // x/z diffusion: implicit part of r instead of H
+    // Fused first pass of the row-slab Crank-Nicolson solve: along the slab,
+    // the local forward sweep l_j = g_j r_j + m_j l_{j-1} (l = 0 below the
+    // slab) of each field's right-hand side, and its local backward sweep
+    // taken at the slab's first row, k = sum_j (prod_{i<j} n_i) l_j (the
+    // products are column-independent: a table per system, u, w / v / ions).
+    const bool fuse = (mode == 0) && a.cn_coef != nullptr;
+    double cl[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, ck[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const int e = active ? k * nx + i : 0;
     const unsigned ueb = (unsigned)e * (unsigned)sizeof(T);  // own column, bytes
     const int ip = (i + 1 >= nx) ? 0 : i + 1;
@@ -227,8 +244,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
                     a.dbg[f][(size_t)j * (size_t)pl + (unsigned)e] = (double)hval;
                     return;
                 }
-                st_once(byte_at((T *)a.r[f], qb), dt * (gam * hval + zet * hold_c[f] - alp * gp + alp * nu_ly));
+                const T rv = dt * (gam * hval + zet * hold_c[f] - alp * gp + alp * nu_ly);
+                st_once(byte_at((T *)a.r[f], qb), rv);
                 if (keep) st_once(byte_at((T *)a.h[f], qb), hval);
+                if (fuse) {
+                    const int sys = (f == 1) ? 1 : (f >= 3 ? 2 : 0);
+                    const double *cf = a.cn_coef + (size_t)sys * 3 * M;
+                    const double *np = a.cn_coef + 9 * (size_t)M + 9 * kCnMaxSlabs + (size_t)sys * M;
+                    cl[f] = uniform_load(cf, j) * (double)rv + uniform_load(cf + M, j) * cl[f];
+                    ck[f] += uniform_load(np, j) * cl[f];
+                }
             };
 
             // ---------------- u on the x-face ----------------
@@ -375,6 +400,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWaves
         if (pre) store_rows(sc, rn);
         __syncthreads();
     }
+    if (fuse && active) {  // both exits of this column's slab (zero inputs)
+        const unsigned S = slabs;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+            a.cn_scr[((size_t)f * S + slab) * (size_t)pl + (unsigned)e] = cl[f];
+            a.cn_scr[((size_t)(5 + f) * S + slab) * (size_t)pl + (unsigned)e] = ck[f];
+        }
+    }
 }
 
 struct CnArgs {
@@ -442,7 +475,6 @@ struct CnStages {
 //   x_j = kappa_j + phi_j D + nu_j X
 // with D = d'_{a-1}, X = x_b and kappa the local backward sweep of the local
 // forward sweep of r; D and X follow from scans across the slabs.
-__host__ __device__ inline size_t cn_stage_stride(int M) { return 9 * (size_t)M + 9 * (size_t)kCnMaxSlabs; }
 
 __global__ void __launch_bounds__(256) k_cn_coef(Dims d, Tables tb, const Phys *phys, const double *clock,
                                                  double *coef, CnStages stages, int slab_rows, size_t ms) {
@@ -504,6 +536,13 @@ __global__ void __launch_bounds__(256) k_cn_coef(Dims d, Tables tb, const Phys *
             sl[(3 * sy + 0) * kCnMaxSlabs + sb] = P;
             sl[(3 * sy + 1) * kCnMaxSlabs + sb] = phi;
             sl[(3 * sy + 2) * kCnMaxSlabs + sb] = Nu;
+            // prod_{i=a}^{j-1} n_i for the rows of the slab (1 at its first row)
+            double *np = sl + 9 * kCnMaxSlabs + (size_t)sy * M;
+            double pr = 1.0;
+            for (int j = a; j < b; ++j) {
+                np[j] = pr;
+                pr *= n[j];
+            }
         }
     }
 }
@@ -1233,7 +1272,11 @@ static hipError_t explicit_launch(nspnp_state *s, const ExplicitArgs &a, int thr
     const size_t lds = 2 * (size_t)kNF * hs * s->wsize;
     const bool dbg = a.mode == 1;
     if (!dbg && threads == 256 && s->fp64 && a.tx == 32 && a.tz == 8) {  // the common tiles
-        k_explicit<double, 2, 2, 0, 32, 8><<<blocks, threads, lds, s->stream>>>(a);
+        // three waves per SIMD (at most 168 VGPRs; 12 bytes per lane spill):
+        // with the fused Crank-Nicolson first pass the compiler's own choice
+        // (171 VGPRs, two waves) was measured 0.29 ms slower per launch at
+        // 512 x 385 x 512 (3.73 against 3.44 ms)
+        k_explicit<double, 2, 3, 0, 32, 8><<<blocks, threads, lds, s->stream>>>(a);
     } else if (!dbg && threads == 256 && !s->fp64 && a.tx == 64 && a.tz == 4) {
         k_explicit<float, 2, 3, 0, 64, 4><<<blocks, threads, lds, s->stream>>>(a);
     } else if (hs <= 2 * threads) {
@@ -1258,8 +1301,42 @@ static hipError_t explicit_launch(nspnp_state *s, const ExplicitArgs &a, int thr
     return hipGetLastError();
 }
 
+// Rows per slab of the row-slab CN method when it applies to this handle
+// (0: lane-scan method).  Its scratch (two values per field, slab and column)
+// lives in the spectrum buffers, unused between the explicit stage and the
+// elliptic solves.
+int cn_slab_rows(const nspnp_state *s) {
+    const int L = s->tiles.cnslab;
+    if (L != 16 && L != 32 || s->cfg.implicit_xz) return 0;  // the factorisation uses the lane-scan method
+    const int S = (s->d.M + L - 1) / L;
+    const int64_t need = 2 * 5 * (int64_t)S * s->d.plane;             // doubles
+    const int64_t have = 4 * (int64_t)s->d.nxh * s->d.nz * s->d.M;      // two half spectra
+    return (S <= kCnMaxSlabs && need <= have) ? L : 0;
+}
+
+// Crank-Nicolson recurrence coefficients of the three stages (and, for the
+// row-slab method, its slab products): computed on the device once per
+// Runge-Kutta step, after the step's dt, before the explicit kernel that may
+// run the method's first pass; at most once per substep.
+static hipError_t launch_cn_coef(nspnp_state *s, const Stage &st) {
+    if (s->cn_coef_at == s->substeps) return hipSuccess;
+    const int L = cn_slab_rows(s);
+    if (st.k == 0 || !s->cn_fresh || s->cn_coef_slab != L) {
+        CnStages cs;
+        for (int q = 0; q < 3; ++q) cs.alp[q] = kRkAlp[q];
+        k_cn_coef<<<dim3(1, 3, (unsigned)s->nmem), 256, 0, s->stream>>>(s->d, s->tb, s->d_phys, s->clock,
+                                                                       s->cn_coef, cs, L, s->mstride);
+        if (s->cfg.implicit_xz)
+            k_cyc_coef<<<dim3(1, 3, (unsigned)s->nmem), 64, 0, s->stream>>>(s->d, s->d_phys, s->clock, s->cyc, cs,
+                                                                            s->mstride);
+        s->cn_fresh = true;
+        s->cn_coef_slab = L;
+    }
+    s->cn_coef_at = s->substeps;
+    return hipGetLastError();
+}
+
 hipError_t launch_explicit(nspnp_state *s, const Stage &st, bool /*write_r*/) {
-    ProfScope prof_(s, K_EXPLICIT);
     ExplicitArgs a{};
     a.d = s->d;
     a.phys = s->d_phys;
@@ -1271,8 +1348,18 @@ hipError_t launch_explicit(nspnp_state *s, const Stage &st, bool /*write_r*/) {
     a.clock = s->clock;
     a.mode = 0;
     a.implicit_xz = s->cfg.implicit_xz;
+    hipError_t e = launch_cn_coef(s, st);  // (not part of the explicit kernel's profiled time)
+    if (e != hipSuccess) return e;
+    ProfScope prof_(s, K_EXPLICIT);
+    // row-slab Crank-Nicolson: this kernel marches the method's slabs and
+    // runs its first pass
+    const int L = cn_slab_rows(s);
+    if (L) {
+        a.cn_coef = s->cn_coef + (size_t)st.k * cn_stage_stride(s->d.M);
+        a.cn_scr = (double *)s->spec;
+    }
     const int tb = s->tiles.expl;
-    explicit_tiling(s->d, s->fp64, tb, s->tiles.slab, a);
+    explicit_tiling(s->d, s->fp64, tb, L ? L : s->tiles.slab, a);
     return explicit_launch(s, a, tb, (unsigned)((int64_t)a.chunks * a.slabs * s->nmem));
 }
 
@@ -1290,19 +1377,6 @@ hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]) {
     a.implicit_xz = s->cfg.implicit_xz;
     explicit_tiling(s->d, s->fp64, 256, s->tiles.slab, a);
     return explicit_launch(s, a, 256, (unsigned)((int64_t)a.chunks * a.slabs));
-}
-
-// Rows per slab of the row-slab CN method when it applies to this handle
-// (0: lane-scan method).  Its scratch (two values per field, slab and column)
-// lives in the spectrum buffers, unused between the explicit stage and the
-// elliptic solves.
-int cn_slab_rows(const nspnp_state *s) {
-    const int L = s->tiles.cnslab;
-    if (L != 16 && L != 32 || s->cfg.implicit_xz) return 0;  // the factorisation uses the lane-scan method
-    const int S = (s->d.M + L - 1) / L;
-    const int64_t need = 2 * 5 * (int64_t)S * s->d.plane;             // doubles
-    const int64_t have = 4 * (int64_t)s->d.nxh * s->d.nz * s->d.M;      // two half spectra
-    return (S <= kCnMaxSlabs && need <= have) ? L : 0;
 }
 
 static hipError_t launch_cn_lane(nspnp_state *s, const CnArgs &a);
@@ -1366,30 +1440,21 @@ hipError_t launch_cn_solve(nspnp_state *s, const Stage &st) {
     a.scr = (double *)s->spec;
     a.slab_rows = cn_slab_rows(s);
     a.slabs = a.slab_rows ? (s->d.M + a.slab_rows - 1) / a.slab_rows : 0;
-    if (st.k == 0 || !s->cn_fresh || s->cn_coef_slab != a.slab_rows) {
-        CnStages cs;
-        for (int q = 0; q < 3; ++q) cs.alp[q] = kRkAlp[q];
-        k_cn_coef<<<dim3(1, 3, (unsigned)s->nmem), 256, 0, s->stream>>>(s->d, s->tb, s->d_phys, s->clock,
-                                                                       s->cn_coef, cs, a.slab_rows, s->mstride);
-        if (s->cfg.implicit_xz)
-            k_cyc_coef<<<dim3(1, 3, (unsigned)s->nmem), 64, 0, s->stream>>>(s->d, s->d_phys, s->clock, s->cyc, cs,
-                                                                            s->mstride);
-        s->cn_fresh = true;
-        s->cn_coef_slab = a.slab_rows;
+    {
+        const hipError_t e = launch_cn_coef(s, st);
+        if (e != hipSuccess) return e;
     }
     if (a.slab_rows) {
+        // the first pass (the exits of each slab's local sweeps) ran in the
+        // explicit kernel of this substep; scans across the slabs, then both
+        // sweeps from the exact slab inputs
         const dim3 g((unsigned)((s->d.plane + 255) / 256), (unsigned)a.slabs, 5u * (unsigned)s->nmem);
         const dim3 g1((unsigned)((s->d.plane + 255) / 256), 1, 5u * (unsigned)s->nmem);
+        k_cn_slab_scan<<<g1, 256, 0, s->stream>>>(a);
         if (a.slab_rows == 16) {
-            if (s->fp64) k_cn_slab_exit<double, 16><<<g, 256, 0, s->stream>>>(a);
-            else k_cn_slab_exit<float, 16><<<g, 256, 0, s->stream>>>(a);
-            k_cn_slab_scan<<<g1, 256, 0, s->stream>>>(a);
             if (s->fp64) k_cn_slab_apply<double, 16><<<g, 256, 0, s->stream>>>(a);
             else k_cn_slab_apply<float, 16><<<g, 256, 0, s->stream>>>(a);
         } else {
-            if (s->fp64) k_cn_slab_exit<double, 32><<<g, 256, 0, s->stream>>>(a);
-            else k_cn_slab_exit<float, 32><<<g, 256, 0, s->stream>>>(a);
-            k_cn_slab_scan<<<g1, 256, 0, s->stream>>>(a);
             if (s->fp64) k_cn_slab_apply<double, 32><<<g, 256, 0, s->stream>>>(a);
             else k_cn_slab_apply<float, 32><<<g, 256, 0, s->stream>>>(a);
         }

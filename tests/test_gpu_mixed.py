@@ -53,3 +53,55 @@ def test_mixed_vs_fp64_turbulent_case_2000_substeps():
     assert b["mp_drift"] < 1e-12 and b["mm_drift"] < 1e-12
     assert a["mp_drift"] < 1e-5 and a["mm_drift"] < 1e-5
     assert b["diag"]["max_div"] < 1e-10
+
+
+def test_mixed_vs_fp64_from_a_developed_turbulent_state():
+    """Both precisions from one developed turbulent state: the FP64 run of
+    the 256x193x256 case (Re 3000) is started from laminar flow with
+    streamwise rolls and streaks (the statistics campaign's start) and
+    advanced to t ~ 40, where its wall shear stress is about ten times the
+    laminar 1/Re; its seven fields then seed a mixed-form run at the start of
+    a Runge-Kutta step, and both advance 300 more substeps (a short horizon,
+    before rounding differences grow through the flow's chaos).  Mean wall
+    shear stress within 1e-4 relative; every field reported."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1701_02005_amd as P
+    from paper_1701_02005_amd.campaign import perturbed_start
+    cfg = P.configs.couette_turbulent(precision="fp64", seed=0)
+    note("case: 256x193x256 developed turbulence, fp64 spin-up then fp64 / mixed branches")
+    a = P.Solver(cfg)
+    perturbed_start(a, 0.3, seed=1)
+    n_spin = 18000
+    for chunk in range(n_spin // 3000):
+        a.step(3000)
+        a.sync()
+        tb, tt = a.wall_shear_stress()
+        note(f"  spin-up {3000 * (chunk + 1)} substeps, t = {a.clock()[0]:.1f}, tau = {0.5 * (tb + tt):.4e}")
+    tb, tt = a.wall_shear_stress()
+    assert 0.5 * (tb + tt) > 5.0 / cfg.re  # far from laminar Couette flow
+    t0, dt0, stage, ns = a.clock()
+    assert stage == 0
+    state = {k: a.get_field(k) for k in FIELDS}
+    b = P.Solver(P.configs.couette_turbulent(precision="mixed", seed=0))
+    for k in FIELDS:
+        b.set_field(k, state[k])
+    b.set_clock(t0, dt0, 0, ns)
+    for g in (a, b):
+        g.step(300)
+        g.sync()
+    res = {}
+    for label, g in (("fp64", a), ("mixed", b)):
+        tb, tt = g.wall_shear_stress()
+        res[label] = dict(tau=0.5 * (tb + tt), fields={k: g.get_field(k).cpu().numpy() for k in FIELDS},
+                          t=g.clock()[0])
+    f64, mix = res["fp64"], res["mixed"]
+    rel_tau = abs(mix["tau"] - f64["tau"]) / abs(f64["tau"])
+    note(f"  t = {f64['t']:.3f} (mixed {mix['t']:.3f}); tau fp64 {f64['tau']:.10e} mixed {mix['tau']:.10e} "
+         f"rel {rel_tau:.2e}")
+    for k in FIELDS:
+        den = np.max(np.abs(f64["fields"][k]))
+        note(f"  {k}: max|mixed - fp64| / max|fp64| = "
+             f"{np.max(np.abs(mix['fields'][k] - f64['fields'][k])) / den:.2e}")
+    assert rel_tau < 1e-4

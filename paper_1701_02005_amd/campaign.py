@@ -43,6 +43,14 @@ from .binding import Config, NsPnpError, Solver, grid
 PAPER_CF = 5.63e-3
 PAPER_RE_TAU = 172.0
 
+# control parameters of the paper's three charged cases (Sec. III, its table
+# of simulation cases): Re 3000, Sc 3, h / lambda_D and beta as named
+TABLE1 = {
+    "L100": {"re": 3000.0, "sc": 3.0, "debye": 1.0 / 100.0, "beta": 0.5},
+    "L100B": {"re": 3000.0, "sc": 3.0, "debye": 1.0 / 100.0, "beta": 1.5e-4},
+    "L33": {"re": 3000.0, "sc": 3.0, "debye": 1.0 / 33.0, "beta": 0.5},
+}
+
 
 def perturbed_start(solver: Solver, amp: float, seed: int, beta: float = 4.0, alpha: float = 1.0):
     """Laminar state + disturbance of amplitude amp (fraction of the wall speed):
@@ -77,10 +85,12 @@ def equilibrium_ions(cfg: Config):
     zero-shear stationary state, Sec. II): every interior face carries zero
     ion flux, so with the central face value of the migration flux each
     species' neighbour ratio is c_{j+1}/c_j = (1 -+ dPhi/2) / (1 +- dPhi/2)
-    (dPhi = Phi_{j+1} - Phi_j, Phi = (vhat/2) y + phi); each species' content
+    (dPhi = Phi_{j+1} - Phi_j, Phi = (vhat/2) y + phi); with the hybrid face
+    value (migration_face = 1) faces with |dPhi| >= 2 take the upwind ratio
+    1/(1 + z dPhi) (z dPhi > 0) or 1 - z dPhi instead.  Each species' content
     equals the gap volume (mean 1); phi solves the discrete potential equation
-    with zero wall values.  Returns (c+, c-, phi) per cell row.  Needs
-    |dPhi| < 2 across every face (positive ratios)."""
+    with zero wall values.  Returns (c+, c-, phi) per cell row.  With the
+    mean face value it needs |dPhi| < 2 across every face (positive ratios)."""
     from scipy.optimize import fsolve
     yn, yc = (np.asarray(a, dtype=np.float64) for a in grid(cfg))
     M = len(yc)
@@ -88,9 +98,15 @@ def equilibrium_ions(cfg: Config):
     dc = np.concatenate([[yc[0] - yn[0]], np.diff(yc), [yn[M] - yc[M - 1]]])
     e0, lam = 0.5 * cfg.vhat, cfg.debye
 
+    hybrid = getattr(cfg, "migration_face", 0) == 1
+
     def conc(phi, zs):
         dphi = e0 * dc[1:M] + np.diff(phi)
-        c = np.concatenate([[1.0], np.cumprod((1 - zs * dphi / 2) / (1 + zs * dphi / 2))])
+        ratio = (1 - zs * dphi / 2) / (1 + zs * dphi / 2)
+        if hybrid:
+            up = np.where(zs * dphi > 0, 1.0 / (1.0 + np.abs(dphi)), 1.0 + np.abs(dphi))
+            ratio = np.where(np.abs(dphi) >= 2.0, up, ratio)
+        c = np.concatenate([[1.0], np.cumprod(ratio)])
         return c * 2.0 / np.sum(c * dn)
 
     def residual(phi):
@@ -232,12 +248,17 @@ def run_campaign(cfg: Config, t_spin: float, t_avg: float, every: int = 10, moni
 def main():
     ap = argparse.ArgumentParser(description="statistics campaign of one run (c_f, Re_tau, profiles)")
     ap.add_argument("--workload", default="couette_turbulent", choices=sorted(configs.WORKLOADS))
+    ap.add_argument("--case", default=None, choices=sorted(TABLE1),
+                    help="the paper's case parameters (Re, Sc, Debye length, beta); explicit flags override")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--vhat", type=float, default=0.0, help="wall potential difference in thermal volts")
     ap.add_argument("--debye", type=float, default=None)
     ap.add_argument("--sc", type=float, default=None)
     ap.add_argument("--re", type=float, default=None)
     ap.add_argument("--ny", type=int, default=None, help="wall-normal node count (resolution of the double layer)")
+    ap.add_argument("--beta", type=float, default=None, help="electrokinetic coupling beta")
+    ap.add_argument("--migration-face", type=int, default=0, choices=[0, 1],
+                    help="1: hybrid face value of the migration flux (upwind where |dPhi| >= 2)")
     ap.add_argument("--t-spin", type=float, default=150.0)
     ap.add_argument("--t-avg", type=float, default=200.0)
     ap.add_argument("--every", type=int, default=10)
@@ -252,8 +273,10 @@ def main():
     ap.add_argument("--out", default="campaign_report.json")
     a = ap.parse_args()
     cfg = configs.WORKLOADS[a.workload](precision=a.precision)
-    over = {"vhat": a.vhat, "u_noise": 0.0, "c_noise": 0.0}
-    for k in ("debye", "sc", "re", "ny"):
+    over = {"vhat": a.vhat, "u_noise": 0.0, "c_noise": 0.0, "migration_face": a.migration_face}
+    if a.case:
+        over.update(TABLE1[a.case])
+    for k in ("debye", "sc", "re", "ny", "beta"):
         if getattr(a, k) is not None:
             over[k] = getattr(a, k)
     cfg = dataclasses.replace(cfg, **over)

@@ -982,46 +982,8 @@ __device__ __forceinline__ void cn_slab_site(const CnArgs &a, unsigned z, int &f
     sys = (f == 1) ? 1 : (f >= 3 ? 2 : 0);
 }
 
-// pass 1: exits of the local sweeps of each slab (zero inputs)
-template <typename T, int L>
-__global__ void __launch_bounds__(256) k_cn_slab_exit(CnArgs a) {
-    int f, sys;
-    unsigned mem;
-    cn_slab_site(a, blockIdx.z, f, mem, sys);
-    const int64_t pl = a.d.plane;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= pl) return;
-    const int M = a.d.M, S = a.slabs, sb = blockIdx.y;
-    const int j0 = sb * L, j1 = (j0 + L < M) ? j0 + L : M;
-    const T *__restrict__ r = (const T *)member_ptr_at(a.r[f], a.ms, mem);
-    const double *__restrict__ coef = member_ptr_at(a.coef, a.ms, mem) + (size_t)a.st.k * cn_stage_stride(M) +
-                                      (size_t)sys * 3 * M;
-    const double *g = coef, *m = coef + M, *n = coef + 2 * M;
-    double *scr = member_ptr_at(a.scr, a.ms, mem);
-    // the slab's rows first, all in flight together (rows past the slab
-    // re-read its last row and are ignored); offsets within one field fit
-    // in 32 bits for every supported grid
-    const unsigned upl = (unsigned)pl, ue = (unsigned)e;
-    T rv[L];
-#pragma unroll
-    for (int t = 0; t < L; ++t) rv[t] = ld_once(r + ((unsigned)(j0 + t < j1 ? j0 + t : j1 - 1) * upl + ue));
-    double lv[L];
-    double l = 0.0;
-#pragma unroll
-    for (int t = 0; t < L; ++t) {
-        const int j = j0 + t;
-        if (j < j1) l = g[j] * (double)rv[t] + m[j] * l;
-        lv[t] = l;
-    }
-    double k = 0.0;
-#pragma unroll
-    for (int t = L - 1; t >= 0; --t) {
-        const int j = j0 + t;
-        if (j < j1) k = lv[t] + n[j] * k;
-    }
-    scr[((int64_t)(f * S + sb)) * pl + e] = l;                  // local forward exit at row j1 - 1
-    scr[((int64_t)((5 + f) * S + sb)) * pl + e] = k;            // local backward exit at row j0
-}
+// pass 1 (the exits of the local sweeps of each slab, zero inputs) runs in
+// the explicit kernel as it produces r (ExplicitArgs::cn_coef).
 
 // pass 2: scans across the slabs of each column; the slab inputs D (forward)
 // and X (backward) replace the exits in place

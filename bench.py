@@ -59,6 +59,9 @@ def kernel_bytes(cfg, name: str, launches: int, substeps: int) -> float:
         # three-direction factorisation x-lines (r in place), y (r in place), z-lines (q += x)
         "cn_tridiag": 5 * (7 if getattr(cfg, "implicit_xz", 0) else 3) * w,
         "fft_x_r2c": 5 * w + 2 * sp,
+        # (with the fused y-march, fft_z_fwd and fft_z_inv are its two marches:
+        # each reads and writes both half spectra once; the row-order c' table
+        # the backward march reads is a precomputed pivot, not counted)
         "fft_z_fwd": 4 * sp,
         "thomas_modes": 4 * sp,
         "fft_z_inv": 4 * sp,
@@ -170,7 +173,9 @@ def measure(cfg, args, P, torch, tiles_trial: int) -> dict:
             ent = json.loads(tr_file.read_text()).get(f"{args.workload}/{cfg.precision}/{dom}")
             src = Path(ent["source"]).name if ent else None
             cn_slab = bool(tiles and tiles.get("cnslab"))
-            same_kernels = ent and tuple(ent.get("kernels", ())) == tuple(pmc_traffic.class_kernels(dom, cn_slab))
+            z_fused = bool(tiles) and tiles.get("thomas") == 0
+            same_kernels = ent and tuple(ent.get("kernels", ())) == tuple(
+                pmc_traffic.class_kernels(dom, cn_slab, z_fused))
             if same_kernels and ent.get("source_sha256") == pmc_traffic.source_hash(src):
                 traffic = ent["bytes_per_launch"]
         except (ValueError, OSError, KeyError):

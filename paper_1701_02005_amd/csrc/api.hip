@@ -79,7 +79,7 @@ int check_config(const nspnp_config *c) {
 
 struct Layout {
     size_t off_f[7], off_h[5], off_r[5], off_psi, off_spec, off_fac, off_coef, off_clock, off_phys, off_stats,
-        off_rstats, off_phiw, off_cyc, off_red, off_tab;
+        off_rstats, off_phiw, off_cyc, off_red, off_tab, off_cpv, off_mu;
     size_t ntab, nred, total;
 };
 
@@ -98,6 +98,8 @@ Layout make_layout(const nspnp_config *c) {
     const int64_t nspec = nxh * c->nz * M;
     L.off_spec = o; o = align256(o + 2 * nspec * 16);
     L.off_fac = o; o = align256(o + 2 * nspec * 16);  // [kind][mode][row] pivots
+    L.off_cpv = o; o = align256(o + 2 * nspec * 8);   // [kind][row][mode] c' (fused y-march)
+    L.off_mu = o; o = align256(o + 2 * 16);           // pinned-mode volume means
     L.off_coef = o; o = align256(o + 3 * cn_stage_stride((int)M) * 8);  // 3 stages: rows, slab products, n products
     L.off_clock = o; o = align256(o + kClockSlots * 8);
     L.off_phys = o; o = align256(o + sizeof(Phys));
@@ -310,6 +312,8 @@ void setup_handle(nspnp_state *s, const nspnp_config *cfg, char *base, int nmem,
     s->psi = (double *)(base + L.off_psi);
     s->spec = (double2 *)(base + L.off_spec);
     s->fac = (double2 *)(base + L.off_fac);
+    s->cpv = (double *)(base + L.off_cpv);
+    s->mu = (double2 *)(base + L.off_mu);
     s->cn_coef = (double *)(base + L.off_coef);
     s->clock = (double *)(base + L.off_clock);
     s->d_phys = (Phys *)(base + L.off_phys);
@@ -344,6 +348,8 @@ nspnp_state *member_view(const nspnp_state *cls, int m, const nspnp_config *cfg)
     v->psi = sh(cls->psi);
     v->spec = sh(cls->spec);
     v->fac = sh(cls->fac);
+    v->cpv = sh(cls->cpv);
+    v->mu = sh(cls->mu);
     v->cn_coef = sh(cls->cn_coef);
     v->clock = sh(cls->clock);
     v->d_phys = sh(cls->d_phys);

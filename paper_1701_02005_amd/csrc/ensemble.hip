@@ -180,7 +180,7 @@ int tune_handle(nspnp_state *c, const char *cache_path, int trial) {
         const int cand_expl[] = {64, 128, 256};
         const int cand_cn[] = {64, 128, 256, 512};
         const int cand_fft[] = {512, 1024, 2048};
-        const int cand_th[] = {4, 8, 16, 32};
+        const int cand_th[] = {0, 4, 8, 16, 32};  // 0: z transforms and mode solves fused along y
         const int cand_corr[] = {128, 256};
         const int cand_slab[] = {4, 8, 16, 32};
         const int cand_cnslab[] = {0, 16, 32};
@@ -209,7 +209,7 @@ int tune_handle(nspnp_state *c, const char *cache_path, int trial) {
         if ((rc = sweep(&c->tiles.cn, cand_cn, 4))) return rc;
         if ((rc = sweep(&c->tiles.fftx, cand_fft, 3))) return rc;
         if ((rc = sweep(&c->tiles.fftz, cand_fft, 3))) return rc;
-        if ((rc = sweep(&c->tiles.thomas, cand_th, 4))) return rc;
+        if ((rc = sweep(&c->tiles.thomas, cand_th, 5))) return rc;
         if ((rc = sweep(&c->tiles.corr, cand_corr, 2))) return rc;
         if ((rc = sweep(&c->tiles.slab, cand_slab, 4))) return rc;
         if ((rc = sweep(&c->tiles.cnslab, cand_cnslab, 3))) return rc;
@@ -429,7 +429,7 @@ int nspnp_set_tiles(nspnp_state *s, const int32_t *t) {
         return false;
     };
     if (!one_of(t[0], {64, 128, 256}) || !one_of(t[1], {64, 128, 256, 512}) || t[2] < 64 || t[2] > 8192 ||
-        t[3] < 64 || t[3] > 8192 || t[4] < 1 || t[4] > 64 || !one_of(t[5], {64, 128, 256}) ||
+        t[3] < 64 || t[3] > 8192 || t[4] < 0 || t[4] > 64 || !one_of(t[5], {64, 128, 256}) ||
         t[6] < 1 || t[6] > kMaxRows || !one_of(t[7], {0, 16, 32}))
         return fail_code(NSPNP_ERR_INVALID, "launch shapes out of range");
     E_TRY(hipStreamSynchronize(s->stream));

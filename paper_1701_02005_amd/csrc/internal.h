@@ -280,7 +280,8 @@ struct Tiles {
     int cn;       // threads per block (columns) of the Crank-Nicolson solve
     int fftx;     // complex points per block of the x transforms
     int fftz;     // complex points per block of the z transforms
-    int thomas;   // modes per tile of the y solve of the elliptic problems (capped by LDS)
+    int thomas;   // modes per tile of the y solve of the elliptic problems (capped by LDS); 0: the z
+                  // transforms and the y solve fused into two row marches
     int corr;     // threads per block of the projection correction
     int slab;     // rows marched by one block of the explicit kernel
     int cnslab;   // Crank-Nicolson: 0 lane-scan method, 16 or 32 row-slab method with that many rows
@@ -357,6 +358,8 @@ struct nspnp_state {
     double *psi;         // pressure increment (n, FP64)
     double2 *spec;       // two half spectra, 2 * nxh * nz * M
     double2 *fac;        // Thomas pivots (1/den, c') of both elliptic operators, [kind][mode][row]
+    double *cpv;         // c' alone, [kind][row][mode], for the fused y-march (NULL: not kept)
+    double2 *mu;         // volume mean of the pinned pressure mode, per problem (fused y-march)
     double *cn_coef;     // Crank-Nicolson recurrence coefficients, 9 M per stage
     bool cn_fresh = false;  // cn_coef matches the device dt of the current step
     int cn_coef_slab = -1;  // slab rows the slab products in cn_coef were made for

@@ -114,6 +114,8 @@ extern "C" int nspnp_poisson_solve_noalloc(const nspnp_config *cfg, int32_t kind
     s.fac = (double2 *)(D.ptr + L.fac);
     s.spec = (double2 *)(D.ptr + L.spec);
     s.clock = nullptr;  // read only by divergence sources
+    s.cpv = nullptr;    // (the default mode-solve method keeps no row-order c' table)
+    s.mu = nullptr;
     s.host_tables.swap(D.host_tab);
     fill_tables(&s, (double *)(D.ptr + L.tab));  // also sets the device table pointers
     if (!D.have_grid || !same_grid(D.grid, *cfg)) {

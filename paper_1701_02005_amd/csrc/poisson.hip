@@ -536,13 +536,17 @@ __global__ void __launch_bounds__(256) k_fft_z(Dims d, FftPlan pl, const double2
 
 // One thread per (kind, mode): the forward pass of Thomas' algorithm on the
 // matrix only.
-__global__ void __launch_bounds__(256) k_thomas_factors(Dims d, Tables tb, double2 *fac_all, size_t ms) {
+// Also c' alone in row order, cpv[kind][row][mode], for the fused y-march
+// (cpv_all may be NULL).
+__global__ void __launch_bounds__(256) k_thomas_factors(Dims d, Tables tb, double2 *fac_all, double *cpv_all,
+                                                        size_t ms) {
     const int kind = blockIdx.y;
     const int64_t nmodes = (int64_t)d.nxh * d.nz;
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= nmodes) return;
     const int M = d.M;
     double2 *fac = member_ptr(fac_all, ms) + ((int64_t)kind * nmodes + m) * M;
+    double *cpv = cpv_all ? member_ptr(cpv_all, ms) + (int64_t)kind * M * nmodes + m : nullptr;
     const int kx = (int)(m / d.nz), kz = (int)(m % d.nz);  // spectrum layout [j][kx][kz]
     const double k2 = tb.kx2[kx] + tb.kz2[kz];
     const bool pin = (kind == 0 && m == 0);
@@ -564,6 +568,7 @@ __global__ void __launch_bounds__(256) k_thomas_factors(Dims d, Tables tb, doubl
         const double den = B - lo * cprev;
         const double cj = up / den;
         fac[j] = make_double2(1.0 / den, cj);
+        if (cpv) cpv[(int64_t)j * nmodes] = cj;
         cprev = cj;
     }
 }
@@ -760,6 +765,190 @@ __global__ void __launch_bounds__(256) k_thomas_tile(Dims d, Tables tb, PoissonB
     }
 }
 
+// ---- the elliptic chain fused along y (mode-solve method 0) ----
+// One block per tile of tk x-modes (every kz) and problem.  The forward
+// kernel marches the rows upward: the row's z transform in LDS, then one
+// forward-elimination step of every (kx, kz) mode's tridiagonal system with
+// the pivot formed on the way, den_j = B_j - lo_j c'_{j-1}, c'_j = up_j / den_j
+// (the arithmetic of k_thomas_factors), and d'_j = (r_j - lo_j d'_{j-1}) /
+// den_j stored in place.  The backward kernel marches down: x_j = d'_j -
+// c'_j x_{j+1} with c' from the precomputed row-order table, then the row's
+// inverse z transform.  Each solve thus reads and writes the spectrum twice
+// (plus c'), against three times for separate z transforms and mode solves.
+// The pressure problem's (0, 0) mode is pinned at row 0; its volume mean
+// sum_j w_j x_j / sum_j w_j (w = cell height) is known after the forward
+// march as sum_k a_k d'_k with a_k = w_k - c'_{k-1} a_{k-1} (a_0 = w_0),
+// and the backward march removes it.
+constexpr int kZtQ = 4;  // modes per thread (tk nz <= 1024)
+
+// one row's (j) wall-normal operator terms of mode kind, as k_thomas_factors
+__device__ __forceinline__ void ythomas_row(const Tables &tb, int kind, int M, int j, double &lo, double &up,
+                                            double &di) {
+    const double aa = uniform_load(tb.lyc_lo, j), cc = uniform_load(tb.lyc_up, j);
+    lo = (j > 0) ? aa : 0.0;
+    up = (j < M - 1) ? cc : 0.0;
+    di = -(lo + up);
+    if (kind == 1) {
+        if (j == 0) di -= aa;
+        if (j == M - 1) di -= cc;
+    }
+}
+
+template <bool kR8>
+__global__ void __launch_bounds__(256) k_zthomas_fwd(Dims d, Tables tb, FftPlan pl, PoissonBatch b,
+                                                     double2 *spec_all, double2 *mu_all, int64_t nspec, int tk) {
+    extern __shared__ double2 sm[];
+    const int prob = blockIdx.y, kind = b.kind[prob];
+    const int nz = d.nz, nxh = d.nxh, M = d.M;
+    double2 *spec = member_ptr(spec_all, b.ms) + prob * nspec;
+    const int kx0 = (int)blockIdx.x * tk;
+    const int nt = (nxh - kx0 < tk) ? nxh - kx0 : tk;
+    const int pts = nt * nz;
+    const int bs = tk * nz;
+    double2 *s_tw = sm + 2 * bs;
+    stage_twiddles(s_tw, tb.twz, nz);
+    const double scale = 1.0 / ((double)d.nx * (double)d.nz);
+    double k2[kZtQ], cprev[kZtQ];
+    double2 dprev[kZtQ];
+    double nre[kZtQ], nim[kZtQ];  // the next row (two arrays of doubles stay in registers)
+#pragma unroll
+    for (int q = 0; q < kZtQ; ++q) {
+        const int e = (int)threadIdx.x + q * (int)blockDim.x;
+        const int ee = e < pts ? e : 0;
+        k2[q] = tb.kx2[kx0 + ee / nz] + tb.kz2[ee % nz];
+        cprev[q] = 0.0;
+        dprev[q] = make_double2(0.0, 0.0);
+    }
+    const bool pin = (kind == 0 && kx0 == 0 && threadIdx.x == 0);  // mode (0, 0) of the pressure problem
+    double a = 0.0, vol = 0.0, sx = 0.0, sy = 0.0;
+    auto row_ptr = [&](int j) { return spec + ((int64_t)j * nxh + kx0) * nz; };
+    {
+        const double2 *r0 = row_ptr(0);
+#pragma unroll
+        for (int q = 0; q < kZtQ; ++q) {
+            const int e = (int)threadIdx.x + q * (int)blockDim.x;
+            const double2 v = r0[e < pts ? e : 0];
+            nre[q] = v.x;
+            nim[q] = v.y;
+        }
+    }
+    for (int j = 0; j < M; ++j) {
+#pragma unroll
+        for (int q = 0; q < kZtQ; ++q) {
+            const int e = (int)threadIdx.x + q * (int)blockDim.x;
+            if (e < pts) sm[e] = make_double2(nre[q], nim[q]);
+        }
+        __syncthreads();
+        if (j + 1 < M) {  // the next row's loads land during this row's passes
+            const double2 *rn = row_ptr(j + 1);
+#pragma unroll
+            for (int q = 0; q < kZtQ; ++q) {
+                const int e = (int)threadIdx.x + q * (int)blockDim.x;
+                const double2 v = rn[e < pts ? e : 0];
+                nre[q] = v.x;
+                nim[q] = v.y;
+            }
+        }
+        const int w = lds_fft<kR8>(sm, sm + bs, nz, nt, pl, s_tw, false);
+        const double2 *z = sm + w * bs;  // (offset from the LDS base: no flat access)
+        double lo, up0, di;
+        ythomas_row(tb, kind, M, j, lo, up0, di);
+        const double wj = tb.dn[j];
+        double2 *out = row_ptr(j);
+#pragma unroll
+        for (int q = 0; q < kZtQ; ++q) {
+            const int e = (int)threadIdx.x + q * (int)blockDim.x;
+            if (e < pts) {
+                double2 r = z[e];
+                r.x *= scale;
+                r.y *= scale;
+                double B = di - k2[q], up = up0;
+                if (pin && q == 0 && j == 0) {
+                    B = 1.0;
+                    up = 0.0;
+                    r = make_double2(0.0, 0.0);
+                }
+                const double den = B - lo * cprev[q];
+                const double g = 1.0 / den, mm = -lo * g;
+                const double2 dn_ = make_double2(g * r.x + mm * dprev[q].x, g * r.y + mm * dprev[q].y);
+                if (pin && q == 0) {  // volume-mean weights of the pinned mode
+                    a = (j == 0) ? wj : wj - cprev[q] * a;
+                    sx += a * dn_.x;
+                    sy += a * dn_.y;
+                    vol += wj;
+                }
+                cprev[q] = up / den;
+                dprev[q] = dn_;
+                out[e] = dn_;
+            }
+        }
+        __syncthreads();  // the staging buffer is refilled next row
+    }
+    if (pin) member_ptr(mu_all, b.ms)[prob] = make_double2(sx / vol, sy / vol);
+}
+
+template <bool kR8>
+__global__ void __launch_bounds__(256) k_zthomas_bwd(Dims d, Tables tb, FftPlan pl, PoissonBatch b,
+                                                     double2 *spec_all, const double *cpv_all, const double2 *mu_all,
+                                                     int64_t nspec, int tk) {
+    extern __shared__ double2 sm[];
+    const int prob = blockIdx.y, kind = b.kind[prob];
+    const int nz = d.nz, nxh = d.nxh, M = d.M;
+    const int64_t nmodes = (int64_t)nxh * nz;
+    double2 *spec = member_ptr(spec_all, b.ms) + prob * nspec;
+    const double *cpv = member_ptr(cpv_all, b.ms) + (int64_t)kind * M * nmodes;
+    const int kx0 = (int)blockIdx.x * tk;
+    const int nt = (nxh - kx0 < tk) ? nxh - kx0 : tk;
+    const int pts = nt * nz;
+    const int bs = tk * nz;
+    double2 *s_tw = sm + 2 * bs;
+    stage_twiddles(s_tw, tb.twz, nz);
+    const bool pin = (kind == 0 && kx0 == 0 && threadIdx.x == 0);
+    const double2 mu = pin ? member_ptr(mu_all, b.ms)[prob] : make_double2(0.0, 0.0);
+    double2 xprev[kZtQ], nd[kZtQ];
+    double nc[kZtQ];
+    auto row_ptr = [&](int j) { return spec + ((int64_t)j * nxh + kx0) * nz; };
+    auto cp_ptr = [&](int j) { return cpv + (int64_t)j * nmodes + (int64_t)kx0 * nz; };
+    {
+        const double2 *r0 = row_ptr(M - 1);
+        const double *c0 = cp_ptr(M - 1);
+#pragma unroll
+        for (int q = 0; q < kZtQ; ++q) {
+            const int e = (int)threadIdx.x + q * (int)blockDim.x;
+            nd[q] = r0[e < pts ? e : 0];
+            nc[q] = c0[e < pts ? e : 0];
+            xprev[q] = make_double2(0.0, 0.0);
+        }
+    }
+    for (int j = M - 1; j >= 0; --j) {
+#pragma unroll
+        for (int q = 0; q < kZtQ; ++q) {
+            const int e = (int)threadIdx.x + q * (int)blockDim.x;
+            if (e < pts) {
+                const double2 x = make_double2(nd[q].x - nc[q] * xprev[q].x, nd[q].y - nc[q] * xprev[q].y);
+                xprev[q] = x;
+                sm[e] = (pin && q == 0) ? make_double2(x.x - mu.x, x.y - mu.y) : x;
+            }
+        }
+        __syncthreads();
+        if (j > 0) {  // the next row's d' and c' land during this row's passes
+            const double2 *rn = row_ptr(j - 1);
+            const double *cn = cp_ptr(j - 1);
+#pragma unroll
+            for (int q = 0; q < kZtQ; ++q) {
+                const int e = (int)threadIdx.x + q * (int)blockDim.x;
+                nd[q] = rn[e < pts ? e : 0];
+                nc[q] = cn[e < pts ? e : 0];
+            }
+        }
+        const int w = lds_fft<kR8>(sm, sm + bs, nz, nt, pl, s_tw, true);
+        const double2 *z = sm + w * bs;
+        double2 *out = row_ptr(j);
+        for (int e = threadIdx.x; e < pts; e += blockDim.x) out[e] = z[e];
+        __syncthreads();
+    }
+}
+
 // modes per tile of the y solve: at most `want`, within 64 KB of LDS
 inline int thomas_tile_modes(int M, int want) {
     int tm = 65536 / (M * (int)sizeof(double2)) - 1;
@@ -839,47 +1028,70 @@ hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b) {
         }
 #undef NSPNP_R2C
     }
-    int tk = modes_per_tile(d.nz, d.nxh, s->tiles.fftz);
-    if (tk * d.nz > kZPer * 256) tk = std::max(1, kZPer * 256 / d.nz);
-    const int ztiles = d.M * ((d.nxh + tk - 1) / tk);
-    // persistent blocks: about 8 per CU over all problems and members
-    const int zblocks = std::max(1, std::min(ztiles, 2048 / std::max(1, b.nprob * nmem)));
-    const dim3 gz((unsigned)zblocks, (unsigned)b.nprob, (unsigned)nmem);
-    const size_t ldsz = (2 * (size_t)tk * d.nz + d.nz) * sizeof(double2);
-    {
-        ProfScope prof_(s, K_FFTZ_FWD);
-        if (r8z) k_fft_z<true><<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 0, b.ms);
-        else k_fft_z<false><<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 0, b.ms);
-    }
-    const int64_t nmodes = (int64_t)d.nxh * d.nz;
-    {
-        ProfScope prof_(s, K_THOMAS);
-        const int tm = thomas_tile_modes(d.M, s->tiles.thomas);
-        const dim3 gt((unsigned)((nmodes + tm - 1) / tm), (unsigned)b.nprob, (unsigned)nmem);
-        const size_t ldst = (size_t)d.M * (tm + 1) * sizeof(double2);
-        const int rpl = (d.M + 63) / 64;  // rows per lane (M <= 512: at most 8)
-#define NSPNP_TH_CASE(RR)                                                                                \
-    case RR:                                                                                             \
-        k_thomas_tile<RR><<<gt, 256, ldst, s->stream>>>(d, s->tb, b, s->spec, s->fac, nspec, tm);        \
-        break;
-        switch (rpl) {
-            NSPNP_TH_CASE(1)
-            NSPNP_TH_CASE(2)
-            NSPNP_TH_CASE(3)
-            NSPNP_TH_CASE(4)
-            NSPNP_TH_CASE(5)
-            NSPNP_TH_CASE(6)
-            NSPNP_TH_CASE(7)
-            NSPNP_TH_CASE(8)
-            default:
-                return hipErrorInvalidValue;
+    if (s->tiles.thomas == 0 && s->cpv && s->mu) {
+        // z transforms and mode solves fused into two row marches: tiles of
+        // tk x-modes, about one mode of a row per thread (the marches are
+        // serial in y, so the most tiles give the most parallelism)
+        const int tk = std::max(1, std::min(d.nxh, 256 / d.nz));
+        if (tk * d.nz > kZtQ * 256) return hipErrorInvalidValue;
+        const dim3 gy((unsigned)((d.nxh + tk - 1) / tk), (unsigned)b.nprob, (unsigned)nmem);
+        const size_t lds = (2 * (size_t)tk * d.nz + d.nz) * sizeof(double2);
+        {
+            ProfScope prof_(s, K_FFTZ_FWD);
+            if (r8z) k_zthomas_fwd<true><<<gy, 256, lds, s->stream>>>(d, s->tb, s->planz, b, s->spec, s->mu, nspec, tk);
+            else k_zthomas_fwd<false><<<gy, 256, lds, s->stream>>>(d, s->tb, s->planz, b, s->spec, s->mu, nspec, tk);
         }
+        {
+            ProfScope prof_(s, K_FFTZ_INV);
+            if (r8z)
+                k_zthomas_bwd<true><<<gy, 256, lds, s->stream>>>(d, s->tb, s->planz, b, s->spec, s->cpv, s->mu, nspec, tk);
+            else
+                k_zthomas_bwd<false><<<gy, 256, lds, s->stream>>>(d, s->tb, s->planz, b, s->spec, s->cpv, s->mu, nspec,
+                                                                 tk);
+        }
+    } else {
+        int tk = modes_per_tile(d.nz, d.nxh, s->tiles.fftz);
+        if (tk * d.nz > kZPer * 256) tk = std::max(1, kZPer * 256 / d.nz);
+        const int ztiles = d.M * ((d.nxh + tk - 1) / tk);
+        // persistent blocks: about 8 per CU over all problems and members
+        const int zblocks = std::max(1, std::min(ztiles, 2048 / std::max(1, b.nprob * nmem)));
+        const dim3 gz((unsigned)zblocks, (unsigned)b.nprob, (unsigned)nmem);
+        const size_t ldsz = (2 * (size_t)tk * d.nz + d.nz) * sizeof(double2);
+        {
+            ProfScope prof_(s, K_FFTZ_FWD);
+            if (r8z) k_fft_z<true><<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 0, b.ms);
+            else k_fft_z<false><<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 0, b.ms);
+        }
+        const int64_t nmodes = (int64_t)d.nxh * d.nz;
+        {
+            ProfScope prof_(s, K_THOMAS);
+            const int tm = thomas_tile_modes(d.M, s->tiles.thomas);
+            const dim3 gt((unsigned)((nmodes + tm - 1) / tm), (unsigned)b.nprob, (unsigned)nmem);
+            const size_t ldst = (size_t)d.M * (tm + 1) * sizeof(double2);
+            const int rpl = (d.M + 63) / 64;  // rows per lane (M <= 512: at most 8)
+#define NSPNP_TH_CASE(RR)                                                                                \
+        case RR:                                                                                             \
+            k_thomas_tile<RR><<<gt, 256, ldst, s->stream>>>(d, s->tb, b, s->spec, s->fac, nspec, tm);        \
+            break;
+            switch (rpl) {
+                NSPNP_TH_CASE(1)
+                NSPNP_TH_CASE(2)
+                NSPNP_TH_CASE(3)
+                NSPNP_TH_CASE(4)
+                NSPNP_TH_CASE(5)
+                NSPNP_TH_CASE(6)
+                NSPNP_TH_CASE(7)
+                NSPNP_TH_CASE(8)
+                default:
+                    return hipErrorInvalidValue;
+            }
 #undef NSPNP_TH_CASE
-    }
-    {
-        ProfScope prof_(s, K_FFTZ_INV);
-        if (r8z) k_fft_z<true><<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 1, b.ms);
-        else k_fft_z<false><<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 1, b.ms);
+        }
+        {
+            ProfScope prof_(s, K_FFTZ_INV);
+            if (r8z) k_fft_z<true><<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 1, b.ms);
+            else k_fft_z<false><<<gz, 256, ldsz, s->stream>>>(d, s->planz, s->tb.twz, s->spec, nspec, tk, 1, b.ms);
+        }
     }
     {
         ProfScope prof_(s, K_FFTX_INV);
@@ -926,7 +1138,7 @@ hipError_t prime_x_transform_lds(int lds_max) {
 hipError_t launch_thomas_factors(nspnp_state *s) {
     const int64_t nmodes = (int64_t)s->d.nxh * s->d.nz;
     const dim3 g((unsigned)((nmodes + 255) / 256), 2, (unsigned)s->nmem);
-    k_thomas_factors<<<g, 256, 0, s->stream>>>(s->d, s->tb, s->fac, s->mstride);
+    k_thomas_factors<<<g, 256, 0, s->stream>>>(s->d, s->tb, s->fac, s->cpv, s->mstride);
     return hipGetLastError();
 }
 

@@ -46,10 +46,18 @@ CLASSES = {
 CN_SLAB_KERNELS = ("k_cn_coef", "k_cn_slab_scan", "k_cn_slab_apply")
 
 
-def class_kernels(cls: str, cn_slab: bool = False):
+# the z transforms under the fused y-march method (mode-solve tile 0): the
+# forward march (z transform + forward elimination) and the backward march
+# (back-substitution + inverse z transform); no separate mode-solve kernel
+Z_FUSED_KERNELS = {"fft_z_fwd": ("k_zthomas_fwd",), "fft_z_inv": ("k_zthomas_bwd",)}
+
+
+def class_kernels(cls: str, cn_slab: bool = False, z_fused: bool = False):
     """HIP kernels that one launch of a profiler class runs."""
     if cls == "cn_tridiag" and cn_slab:
         return CN_SLAB_KERNELS
+    if z_fused and cls in Z_FUSED_KERNELS:
+        return Z_FUSED_KERNELS[cls]
     return CLASSES[cls][0]
 
 
@@ -103,6 +111,8 @@ def main(argv=None):
     for cls, (kernels, src) in CLASSES.items():
         if cls == "cn_tridiag" and all(k in per_kernel for k in CN_SLAB_KERNELS):
             kernels = CN_SLAB_KERNELS
+        if cls in Z_FUSED_KERNELS and all(k in per_kernel for k in Z_FUSED_KERNELS[cls]):
+            kernels = Z_FUSED_KERNELS[cls]
         if not all(k in per_kernel for k in kernels):
             continue
         fb = sum(per_kernel[k][0] for k in kernels)

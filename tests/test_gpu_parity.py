@@ -86,9 +86,14 @@ LONG_Z = dict(nx=512, ny=9, nz=768)
 
 @pytest.mark.parametrize("dims", [SMALL, RAGGED, TINY, LONG_X, LONG_Z], ids=["small", "ragged", "tiny", "long-x", "long-z"])
 @pytest.mark.parametrize("kind", [0, 1])
-def test_poisson_solve_matches_oracle(P, O, dims, kind):
+@pytest.mark.parametrize("thomas", [16, 0], ids=["mode-tiles", "fused-march"])
+def test_poisson_solve_matches_oracle(P, O, dims, kind, thomas):
+    """Both methods of the y solve: tiles of modes after separate z
+    transforms, and the z transforms fused with the y solve into two row
+    marches (launch shape thomas = 0)."""
     import torch
     g, o = make_pair(P, O, cfg_of(P, **dims))
+    g.set_tiles(thomas=thomas)
     rhs = random_field(o.shape, 10 + kind)
     if kind == 0:
         vol = o.dn[:, None, None] * np.ones(o.shape)
@@ -134,6 +139,18 @@ def test_small_case_200_substeps_match_oracle(P, O, cnslab, seed):
     d = g.diagnostics()
     assert d["max_div"] < 1e-12
     assert abs(d["ke"] - o.kinetic_energy()) < 1e-12 * o.kinetic_energy()
+
+
+def test_small_case_fused_elliptic_march_matches_oracle(P, O):
+    """The 200-substep small case with the z transforms and y solves fused
+    into row marches (thomas = 0), both operators every substep."""
+    g, o = make_pair(P, O, P.configs.couette_small(seed=1))
+    g.set_tiles(thomas=0)
+    g.step(200)
+    o.run(200)
+    err = worst(g, o)
+    note(f"fused elliptic march, 200 substeps: {max(err.values()):.3e}")
+    assert max(err.values()) < 1e-10, err
 
 
 def test_ragged_adaptive_case_matches_oracle(P, O):
@@ -206,17 +223,17 @@ def turbulent_oracle(P, O):
     return dict(init=init, final=o.state(), dt=o.dt, t=o.t, tau=o.wall_shear())
 
 
-@pytest.mark.parametrize("cnslab,cn", [(0, 256), (0, 512), (16, 256), (32, 256)])
-def test_full_size_turbulent_case_matches_oracle(P, turbulent_oracle, cnslab, cn):
+@pytest.mark.parametrize("cnslab,cn,thomas", [(0, 256, 16), (0, 512, 16), (16, 256, 16), (32, 256, 16), (32, 256, 0)])
+def test_full_size_turbulent_case_matches_oracle(P, turbulent_oracle, cnslab, cn, thomas):
     """256x193x256, Re 3000, lam 0.05, vhat 10, adaptive dt: initial state
     and 30 substeps (ten RK steps), with each Crank-Nicolson method the
     autotuner can pick (the other launch shapes do not change the arithmetic
     done per cell, line or mode)."""
     ref = turbulent_oracle
     cfg = P.configs.couette_turbulent(seed=0)
-    note(f"case: 256x193x256 fp64 cnslab={cnslab} cn={cn}, 30 substeps")
+    note(f"case: 256x193x256 fp64 cnslab={cnslab} cn={cn} thomas={thomas}, 30 substeps")
     g = P.Solver(cfg)
-    g.set_tiles(cnslab=cnslab, cn=cn)
+    g.set_tiles(cnslab=cnslab, cn=cn, thomas=thomas)
     gf = gpu_fields(g)
     err0 = {k: parity(gf[k], ref["init"][k]) for k in FIELDS}
     note(f"full size, initial state: {max(err0.values()):.3e}")

@@ -75,7 +75,9 @@ typedef struct {
                                0 the unweighted mean of the two cells,
                                1 hybrid: the upwind cell of the species'
                                drift on faces whose potential difference
-                               is at least 2, the mean elsewhere          */
+                               is at least 2, the mean elsewhere;
+                               2 as 1, and the advective face value of c
+                               limited (or_adv_face)                      */
 } or_config;
 
 enum { F_U = 0, F_V, F_W, F_CP, F_CM, F_PHI, F_P, F_NFIELD };
@@ -497,8 +499,28 @@ void or_coulomb(const or_solver *s, const double *cp, const double *cm, const do
  * when zs dphi > 0 and L otherwise; its equilibrium ratio 1 / (1 + zs dphi)
  * or 1 + |dphi| stays positive. */
 static double or_mig_face(const or_solver *s, double cL, double cR, double dphi, double zs) {
-    if (s->cfg.migration_face == 1 && fabs(dphi) >= 2.0) return (zs * dphi > 0.0) ? cR : cL;
+    if (s->cfg.migration_face >= 1 && fabs(dphi) >= 2.0) return (zs * dphi > 0.0) ? cR : cL;
     return 0.5 * (cL + cR);
+}
+
+/* Advective face value of c.  Sec. II's central differences take the mean of
+ * the two cells; at the ions' cell Peclet numbers of a turbulent run
+ * (Re Sc |u| dx ~ 10^2) that value lets a transported profile overshoot, and
+ * steep near-wall layers go negative.  The limited value (migration_face 2)
+ * starts from the upwind cell U of the face velocity and adds the van Leer
+ * slope: with a = c_U - c_UU and b = c_D - c_U (D the downwind cell, UU the
+ * cell beyond U), c_face = c_U + a b / (a + b) when a b > 0, else c_U.  On a
+ * linear profile of equal spacings a = b and this is the mean; at an extremum
+ * it is the upwind value, so no new extrema form.  vel_up: the face velocity
+ * is >= 0 (U on the low-index side).  have_uu = 0 (U is a wall row): the
+ * cell beyond the wall is taken as an image of U (zero gradient, as the
+ * wall's zero normal flux has it), so a = 0 and the face value is c_U. */
+static double or_adv_face(const or_solver *s, double cL, double cR, double cUU, int vel_up, int have_uu) {
+    if (s->cfg.migration_face != 2) return 0.5 * (cL + cR);
+    double cU = vel_up ? cL : cR, cD = vel_up ? cR : cL;
+    if (!have_uu) return cU;
+    double a = cU - cUU, b = cD - cU;
+    return (a * b > 0.0) ? cU + a * b / (a + b) : cU;
 }
 
 /* Ion transport terms for one species of valence zs = +1 / -1 except the
@@ -521,9 +543,16 @@ void or_ion_explicit(const or_solver *s, const double *u, const double *v, const
                 double cc = c[c0];
                 double cxp = c[IDX(s, ip, j, k)], cxm = c[IDX(s, im, j, k)];
                 double czp = c[IDX(s, i, j, kp)], czm = c[IDX(s, i, j, km)];
-                /* advection: face velocity times unweighted face value */
-                double ax = (u[IDX(s, ip, j, k)] * 0.5 * (cxp + cc) - u[c0] * 0.5 * (cc + cxm)) / dx;
-                double az = (w[IDX(s, i, j, kp)] * 0.5 * (czp + cc) - w[c0] * 0.5 * (cc + czm)) / dz;
+                double cxp2 = c[IDX(s, PX(ip), j, k)], cxm2 = c[IDX(s, MX(im), j, k)];
+                double czp2 = c[IDX(s, i, j, PZ(kp))], czm2 = c[IDX(s, i, j, MZ(km))];
+                /* advection: face velocity times face value (the mean, or the
+                 * limited upwind value; periodic in x and z) */
+                double uR = u[IDX(s, ip, j, k)], uL = u[c0];
+                double wF = w[IDX(s, i, j, kp)], wB = w[c0];
+                double ax = (uR * or_adv_face(s, cc, cxp, uR >= 0.0 ? cxm : cxp2, uR >= 0.0, 1) -
+                             uL * or_adv_face(s, cxm, cc, uL >= 0.0 ? cxm2 : cxp, uL >= 0.0, 1)) / dx;
+                double az = (wF * or_adv_face(s, cc, czp, wF >= 0.0 ? czm : czp2, wF >= 0.0, 1) -
+                             wB * or_adv_face(s, czm, cc, wB >= 0.0 ? czm2 : czp, wB >= 0.0, 1)) / dz;
                 double vt = 0.0, vb = 0.0, ft = 0.0, fb = 0.0;
                 /* potential differences across the faces (y: applied field
                  * e0 over the centre distance plus the perturbation) */
@@ -531,14 +560,20 @@ void or_ion_explicit(const or_solver *s, const double *u, const double *v, const
                     size_t cu = IDX(s, i, j + 1, k);
                     double cup = c[cu];
                     double dpy = e0 * s->dc[j + 1] + (phi[cu] - phi[c0]);
-                    vt = v[cu] * 0.5 * (cup + cc);
+                    int up = v[cu] >= 0.0;  /* U = row j (UU = j - 1), else U = j + 1 (UU = j + 2) */
+                    int have = up ? (j > 0) : (j + 2 < M);
+                    double cuu = have ? c[IDX(s, i, up ? j - 1 : j + 2, k)] : 0.0;
+                    vt = v[cu] * or_adv_face(s, cc, cup, cuu, up, have);
                     ft = or_mig_face(s, cc, cup, dpy, zs) * (e0 + (phi[cu] - phi[c0]) / s->dc[j + 1]);
                 }
                 if (j > 0) {
                     size_t cd = IDX(s, i, j - 1, k);
                     double cdn = c[cd];
                     double dpy = e0 * s->dc[j] + (phi[c0] - phi[cd]);
-                    vb = v[c0] * 0.5 * (cc + cdn);
+                    int up = v[c0] >= 0.0;  /* U = row j - 1 (UU = j - 2), else U = j (UU = j + 1) */
+                    int have = up ? (j > 1) : (j + 1 < M);
+                    double cuu = have ? c[IDX(s, i, up ? j - 2 : j + 1, k)] : 0.0;
+                    vb = v[c0] * or_adv_face(s, cdn, cc, cuu, up, have);
                     fb = or_mig_face(s, cdn, cc, dpy, zs) * (e0 + (phi[c0] - phi[cd]) / s->dc[j]);
                 }
                 double ay = (vt - vb) / s->dn[j];
@@ -1063,7 +1098,9 @@ void or_ion_flux(const or_solver *s, double *jp, double *jm, double *mp, double 
             for (int k = 0; k < s->nz; k++)
                 for (int i = 0; i < s->nx; i++) {
                     size_t c0 = IDX(s, i, j, k), cd = IDX(s, i, j - 1, k);
-                    double cf = 0.5 * (c[c0] + c[cd]);
+                    int up = v[c0] >= 0.0, have = up ? (j > 1) : (j + 1 < M);
+                    double cuu = have ? c[IDX(s, i, up ? j - 2 : j + 1, k)] : 0.0;
+                    double cf = or_adv_face(s, c[cd], c[c0], cuu, up, have);
                     double ey = e0 + (phi[c0] - phi[cd]) / s->dc[j];
                     double cmig = or_mig_face(s, c[cd], c[c0], e0 * s->dc[j] + (phi[c0] - phi[cd]), zs);
                     sum += v[c0] * cf - kd * ((c[c0] - c[cd]) / s->dc[j] + zs * cmig * ey);

@@ -114,7 +114,16 @@ typedef struct nspnp_config {
      * difference dPhi across a face exceeds 2 thermal volts.  1: hybrid, the
      * cell the species' drift comes from (upwind) on faces with |dPhi| >= 2,
      * the mean elsewhere; its stationary ratios 1/(1 + z dPhi) and 1 + |dPhi|
-     * stay positive (first order on those faces only). */
+     * stay positive (first order on those faces only).  2: as 1, and the
+     * face value of c in the advective flux limited as well: the upwind cell
+     * of the face velocity plus the van Leer slope a b / (a + b) (a, b the
+     * differences across the upwind cell and across the face; c_U alone when
+     * a b <= 0 or when the upwind cell is a wall row), so that a profile advected
+     * at cell Peclet numbers Re Sc |u| h >> 2 forms no new extrema; equal to
+     * the mean on a linear profile of equal spacings.  Applies to the update
+     * and to the flux diagnostics alike; the row-slab Crank-Nicolson method
+     * (whose first pass runs inside the explicit kernel) is replaced by the
+     * lane-scan method under this setting.  Other values: NSPNP_ERR_INVALID. */
     int32_t migration_face;
 } nspnp_config;
 

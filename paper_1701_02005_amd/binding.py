@@ -68,7 +68,8 @@ class Config:
     u_noise: float = 0.01
     c_noise: float = 1e-3
     implicit_xz: int = 0  # 1: x/z diffusion implicit too (three-direction factorisation)
-    migration_face: int = 0  # 1: hybrid (upwind where the potential jump across a face is >= 2)
+    migration_face: int = 0  # 1: hybrid (upwind where the potential jump across a face is >= 2);
+    # 2: hybrid, and limited (van Leer) advective face values of the ions
 
     def to_c(self) -> _CConfig:
         c = _CConfig()

@@ -86,7 +86,7 @@ def equilibrium_ions(cfg: Config):
     ion flux, so with the central face value of the migration flux each
     species' neighbour ratio is c_{j+1}/c_j = (1 -+ dPhi/2) / (1 +- dPhi/2)
     (dPhi = Phi_{j+1} - Phi_j, Phi = (vhat/2) y + phi); with the hybrid face
-    value (migration_face = 1) faces with |dPhi| >= 2 take the upwind ratio
+    value (migration_face = 1 or 2) faces with |dPhi| >= 2 take the upwind ratio
     1/(1 + z dPhi) (z dPhi > 0) or 1 - z dPhi instead.  Each species' content
     equals the gap volume (mean 1); phi solves the discrete potential equation
     with zero wall values.  Returns (c+, c-, phi) per cell row.  With the
@@ -98,7 +98,7 @@ def equilibrium_ions(cfg: Config):
     dc = np.concatenate([[yc[0] - yn[0]], np.diff(yc), [yn[M] - yc[M - 1]]])
     e0, lam = 0.5 * cfg.vhat, cfg.debye
 
-    hybrid = getattr(cfg, "migration_face", 0) == 1
+    hybrid = getattr(cfg, "migration_face", 0) >= 1  # (advective face values play no part at zero velocity)
 
     def conc(phi, zs):
         dphi = e0 * dc[1:M] + np.diff(phi)
@@ -232,6 +232,7 @@ def run_campaign(cfg: Config, t_spin: float, t_avg: float, every: int = 10, moni
     cf_se = 2.0 * tau_se
     re_tau_se = cfg.re * 0.5 * tau_se / math.sqrt(abs(st["tau"])) if st["tau"] > 0 else float("nan")
     return {
+        "rms_peaks": rms_peaks(st, cfg),
         "config": dataclasses.asdict(cfg), "ion_start": ion_start, "t_charge": t_charge, "wall_vhat": wall_v,
         "t_spin": t_spin, "t_avg": t_avg, "sample_every": every, "samples": st["samples"],
         "averaged_time": st["time"], "substeps": int(state["ns"]), "wall_s": wall, "stopped": stopped,
@@ -243,6 +244,26 @@ def run_campaign(cfg: Config, t_spin: float, t_avg: float, every: int = 10, moni
         "mean": st["mean"], "rms": st["rms"],
         "tau_history": h.tolist(),
     }
+
+
+def rms_peaks(st: dict, cfg) -> dict:
+    """Position of the largest RMS fluctuation of c+ and c- in each half of
+    the gap, in wall units of its own wall (y+ = distance from the wall times
+    Re u_tau, u_tau from the mean wall shear of both walls), with the peak
+    value; NaN before the first sample."""
+    yc = np.asarray(st["yc"], dtype=np.float64)
+    out = {}
+    u_tau = st["u_tau"]
+    for f in ("cp", "cm"):
+        r = np.asarray(st["rms"][f], dtype=np.float64)
+        for half, sel, dist in (("lower", yc < 0.0, yc + 1.0), ("upper", yc > 0.0, 1.0 - yc)):
+            idx = np.flatnonzero(sel)
+            if not len(idx) or not np.all(np.isfinite(r[idx])) or not (u_tau > 0):
+                out[f"{f}_{half}"] = {"y_plus": float("nan"), "rms": float("nan")}
+                continue
+            m = idx[np.argmax(r[idx])]
+            out[f"{f}_{half}"] = {"y_plus": float(dist[m] * cfg.re * u_tau), "rms": float(r[m])}
+    return out
 
 
 def main():
@@ -257,8 +278,9 @@ def main():
     ap.add_argument("--re", type=float, default=None)
     ap.add_argument("--ny", type=int, default=None, help="wall-normal node count (resolution of the double layer)")
     ap.add_argument("--beta", type=float, default=None, help="electrokinetic coupling beta")
-    ap.add_argument("--migration-face", type=int, default=0, choices=[0, 1],
-                    help="1: hybrid face value of the migration flux (upwind where |dPhi| >= 2)")
+    ap.add_argument("--migration-face", type=int, default=0, choices=[0, 1, 2],
+                    help="1: hybrid face value of the migration flux (upwind where |dPhi| >= 2); "
+                         "2: also limited advective face values of the ions")
     ap.add_argument("--t-spin", type=float, default=150.0)
     ap.add_argument("--t-avg", type=float, default=200.0)
     ap.add_argument("--every", type=int, default=10)
@@ -289,6 +311,9 @@ def main():
     print(f"[campaign] c_f = {rep['cf']:.4e} +- {rep['cf_stderr']:.1e}  Re_tau = {rep['re_tau']:.1f} "
           f"+- {rep['re_tau_stderr']:.1f}  (paper: c_f {PAPER_CF:.3e}, Re_tau {PAPER_RE_TAU:.0f}); "
           f"{rep['substeps']} substeps in {rep['wall_s']:.1f} s", flush=True)
+    pk = rep["rms_peaks"]
+    print("[campaign] RMS peaks (y+, rms): " + "  ".join(
+        f"{k} ({v['y_plus']:.1f}, {v['rms']:.3e})" for k, v in pk.items()), flush=True)
 
 
 if __name__ == "__main__":

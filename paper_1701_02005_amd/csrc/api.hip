@@ -72,8 +72,9 @@ int check_config(const nspnp_config *c) {
         return fail(NSPNP_ERR_INVALID, "non-finite configuration value");
     if (c->dt <= 0.0 && !(c->cfl > 0.0)) return fail(NSPNP_ERR_INVALID, "adaptive dt needs cfl > 0");
     if (c->implicit_xz != 0 && c->implicit_xz != 1) return fail(NSPNP_ERR_INVALID, "implicit_xz must be 0 or 1");
-    if (c->migration_face != 0 && c->migration_face != 1)
-        return fail(NSPNP_ERR_INVALID, "migration_face must be 0 (mean) or 1 (hybrid)");
+    if (c->migration_face < 0 || c->migration_face > 2)
+        return fail(NSPNP_ERR_INVALID,
+                    "migration_face must be 0 (mean), 1 (hybrid) or 2 (hybrid + limited advective face values)");
     return NSPNP_OK;
 }
 
@@ -265,6 +266,7 @@ Phys make_phys(const nspnp_config *cfg) {
     ph.adaptive = cfg->dt > 0.0 ? 0.0 : 1.0;
     ph.implicit_xz = cfg->implicit_xz ? 1.0 : 0.0;
     ph.hybrid = cfg->migration_face ? 1.0 : 0.0;
+    ph.limited = cfg->migration_face == 2 ? 1.0 : 0.0;
     return ph;
 }
 

@@ -65,6 +65,7 @@ struct Phys {
     double adaptive;    // 1: dt from the CFL rule at stage 1; 0: fixed dt
     double implicit_xz; // 1: x/z diffusion implicit (no explicit diffusion limit on dt)
     double hybrid;      // 1: hybrid face value of c in the migration flux (mig_face)
+    double limited;     // 1: limited face value of c in the advective flux (adv_face)
 };
 
 // Face value of c in the migration flux of a species of valence zs across a
@@ -78,6 +79,22 @@ template <typename T>
 __device__ __forceinline__ T mig_face(bool hyb, T mean, T cl, T cr, T dphi, T zs) {
     if (hyb && fabs(dphi) >= T(2)) return (zs * dphi > T(0)) ? cr : cl;
     return mean;
+}
+// Face value of c in the advective flux, limited form (migration_face 2):
+// the upwind cell U of the face velocity plus the van Leer slope a b/(a + b),
+// a = c_U - c_UU, b = c_D - c_U (D the downwind cell, UU the cell beyond U),
+// when a b > 0, else c_U alone; equal to the mean of the two cells on a linear
+// profile of equal spacings, and no new extrema where it is not.  up: the face
+// velocity is >= 0 (U = cl); have: UU exists.  U a wall row (no UU): the cell
+// beyond the wall is an image of U (zero gradient, as the zero normal flux
+// has it), so the face value is c_U.
+template <typename T>
+__device__ __forceinline__ T adv_face(T cl, T cr, T cuu, bool up, bool have) {
+    const T cu = up ? cl : cr, cd = up ? cr : cl;
+    if (!have) return cu;
+    const T a = cu - cuu, b = cd - cu;
+    const T ab = a * b;
+    return (ab > T(0)) ? cu + ab / (a + b) : cu;
 }
 // Potential difference across a wall-normal face: the applied field e0 over
 // the centre distance dc plus the perturbation difference, each operation
@@ -412,6 +429,7 @@ class ProfScope {
 // launchers (one translation unit each; all queue on s->stream)
 hipError_t launch_explicit(nspnp_state *s, const Stage &st, bool write_r);
 hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]);
+hipError_t launch_adv_limit(nspnp_state *s, const Stage &st, double *const out[5]);
 hipError_t launch_cn_solve(nspnp_state *s, const Stage &st);
 hipError_t launch_correct(nspnp_state *s, const Stage &st, bool update_p, double fixed_scale, bool advance_clock);
 hipError_t launch_poisson_batch(nspnp_state *s, const PoissonBatch &b);

@@ -241,13 +241,21 @@ __global__ void __launch_bounds__(kRedThreads) k_plane(Dims d, const Phys *phys,
         if (j > 0) {
             const int64_t qd = q - pl;
             const double e_y = ph.e0 + ((double)phi[q] - (double)phi[qd]) / dcj;
-            const double f1 = 0.5 * (c1 + (double)cp[qd]);
-            const double f2 = 0.5 * (c2 + (double)cm[qd]);
+            const double m1 = 0.5 * (c1 + (double)cp[qd]);
+            const double m2 = 0.5 * (c2 + (double)cm[qd]);
+            // advective face values: the mean, or the limited upwind value
+            double f1 = m1, f2 = m2;
+            if (ph.limited != 0.0) {
+                const bool up = vv >= 0.0, have = up ? (j > 1) : (j + 1 < d.M);
+                const int64_t quu = up ? q - 2 * pl : q + pl;
+                f1 = adv_face((double)cp[qd], c1, have ? (double)cp[quu] : 0.0, up, have);
+                f2 = adv_face((double)cm[qd], c2, have ? (double)cm[quu] : 0.0, up, have);
+            }
             // migration face values (hybrid rule: upwind where |dPhi| >= 2)
             const bool hyb = ph.hybrid != 0.0;
             const double dpy = hyb ? y_dphi(ph.e0, dcj, (double)phi[q] - (double)phi[qd]) : 0.0;
-            const double g1 = mig_face(hyb, f1, (double)cp[qd], c1, dpy, 1.0);
-            const double g2 = mig_face(hyb, f2, (double)cm[qd], c2, dpy, -1.0);
+            const double g1 = mig_face(hyb, m1, (double)cp[qd], c1, dpy, 1.0);
+            const double g2 = mig_face(hyb, m2, (double)cm[qd], c2, dpy, -1.0);
             acc[3] += vv * f1 - ph.kd * ((c1 - (double)cp[qd]) / dcj + g1 * e_y);
             acc[4] += vv * f2 - ph.kd * ((c2 - (double)cm[qd]) / dcj - g2 * e_y);
             acc[5] += 0.5 * vv * vv * d.dx * dcj * d.dz;

@@ -1269,7 +1269,9 @@ static hipError_t explicit_launch(nspnp_state *s, const ExplicitArgs &a, int thr
 // elliptic solves.
 int cn_slab_rows(const nspnp_state *s) {
     const int L = s->tiles.cnslab;
-    if (L != 16 && L != 32 || s->cfg.implicit_xz) return 0;  // the factorisation uses the lane-scan method
+    // the factorisation uses the lane-scan method; so do limited advective
+    // face values (they change r after the explicit kernel has run)
+    if (L != 16 && L != 32 || s->cfg.implicit_xz || s->cfg.migration_face == 2) return 0;
     const int S = (s->d.M + L - 1) / L;
     const int64_t need = 2 * 5 * (int64_t)S * s->d.plane;             // doubles
     const int64_t have = 4 * (int64_t)s->d.nxh * s->d.nz * s->d.M;      // two half spectra
@@ -1298,6 +1300,104 @@ static hipError_t launch_cn_coef(nspnp_state *s, const Stage &st) {
     return hipGetLastError();
 }
 
+namespace {
+
+// Limited advective face values of the ions (migration_face 2).  The explicit
+// kernel forms the central advective flux; this kernel adds, cell by cell,
+// the difference between the limited flux's divergence and the central one to
+// the ions' H (when the stage keeps it) and to their Crank-Nicolson
+// right-hand side (dt gam times the difference), or, in mode 1, to the
+// exported H.  One thread per cell; the face values reach two cells upwind
+// (periodic in x and z; the upwind cell alone where it is a wall row).
+struct AdvArgs {
+    Dims d;
+    size_t ms;
+    Tables tb;
+    Stage st;
+    const void *u, *v, *w, *c[2];
+    void *h[2], *r[2];
+    double *dbg[2];
+    const double *clock;
+    int mode;  // 0: substep (H, r of this stage); 1: dbg only
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adv_limit(AdvArgs a) {
+    const int64_t pl = a.d.plane;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= pl) return;
+    const int j = (int)blockIdx.y, M = a.d.M, nx = a.d.nx, nz = a.d.nz;
+    const size_t ms = a.ms;
+    const T *u = member_ptr((const T *)a.u, ms), *v = member_ptr((const T *)a.v, ms);
+    const T *w = member_ptr((const T *)a.w, ms);
+    const int i = (int)(e % nx), k = (int)(e / nx);
+    auto wrap = [](int q, int n) { return q < 0 ? q + n : (q >= n ? q - n : q); };  // n >= 4
+    const int64_t row = (int64_t)j * pl, q0 = row + e;
+    const int64_t xp = row + (int64_t)k * nx + wrap(i + 1, nx), xm = row + (int64_t)k * nx + wrap(i - 1, nx);
+    const int64_t xp2 = row + (int64_t)k * nx + wrap(i + 2, nx), xm2 = row + (int64_t)k * nx + wrap(i - 2, nx);
+    const int64_t zp = row + (int64_t)wrap(k + 1, nz) * nx + i, zm = row + (int64_t)wrap(k - 1, nz) * nx + i;
+    const int64_t zp2 = row + (int64_t)wrap(k + 2, nz) * nx + i, zm2 = row + (int64_t)wrap(k - 2, nz) * nx + i;
+    const T half = T(0.5);
+    const T uL = u[q0], uR = u[xp], wB = w[q0], wF = w[zp];
+    const T vb = (j > 0) ? v[q0] : T(0), vt = (j + 1 < M) ? v[q0 + pl] : T(0);
+    const T idx_ = T(1.0 / a.d.dx), idz_ = T(1.0 / a.d.dz), idn = T(a.tb.idn[j]);
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+        const T *c = member_ptr((const T *)a.c[sp], ms);
+        const T cc = c[q0], cxp = c[xp], cxm = c[xm], czp = c[zp], czm = c[zm];
+        const bool ur = uR >= T(0), ul = uL >= T(0), wf = wF >= T(0), wb = wB >= T(0);
+        const T dR = adv_face(cc, cxp, ur ? cxm : c[xp2], ur, true) - half * (cxp + cc);
+        const T dL = adv_face(cxm, cc, ul ? c[xm2] : cxp, ul, true) - half * (cc + cxm);
+        const T dF = adv_face(cc, czp, wf ? czm : c[zp2], wf, true) - half * (czp + cc);
+        const T dB = adv_face(czm, cc, wb ? c[zm2] : czp, wb, true) - half * (cc + czm);
+        T dT = T(0), dD = T(0);
+        if (j + 1 < M) {  // top face: between rows j and j + 1
+            const T cu = c[q0 + pl];
+            const bool up = vt >= T(0), have = up ? (j > 0) : (j + 2 < M);
+            const T cuu = have ? c[up ? q0 - pl : q0 + 2 * pl] : T(0);
+            dT = adv_face(cc, cu, cuu, up, have) - half * (cu + cc);
+        }
+        if (j > 0) {  // bottom face: between rows j - 1 and j
+            const T cd = c[q0 - pl];
+            const bool up = vb >= T(0), have = up ? (j > 1) : (j + 1 < M);
+            const T cuu = have ? c[up ? q0 - 2 * pl : q0 + pl] : T(0);
+            dD = adv_face(cd, cc, cuu, up, have) - half * (cc + cd);
+        }
+        const T delta = -((uR * dR - uL * dL) * idx_ + (wF * dF - wB * dB) * idz_ + (vt * dT - vb * dD) * idn);
+        if (a.mode == 1) {
+            a.dbg[sp][q0] += (double)delta;
+            continue;
+        }
+        const T dt = T(member_ptr(a.clock, ms)[1]);
+        T *h = member_ptr((T *)a.h[sp], ms), *r = member_ptr((T *)a.r[sp], ms);
+        if (a.st.k < 2) h[q0] += delta;
+        r[q0] += dt * T(a.st.gam) * delta;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_adv_limit(nspnp_state *s, const Stage &st, double *const out[5]) {
+    AdvArgs a{};
+    a.d = s->d;
+    a.ms = out ? 0 : s->mstride;
+    a.tb = s->tb;
+    a.st = st;
+    a.u = s->f[0]; a.v = s->f[1]; a.w = s->f[2];
+    for (int q = 0; q < 2; ++q) {
+        a.c[q] = s->f[3 + q];
+        a.h[q] = s->h[3 + q];
+        a.r[q] = s->r[3 + q];
+        a.dbg[q] = out ? out[3 + q] : nullptr;
+    }
+    a.clock = s->clock;
+    a.mode = out ? 1 : 0;
+    const dim3 g((unsigned)((s->d.plane + 255) / 256), (unsigned)s->d.M, out ? 1u : (unsigned)s->nmem);
+    if (s->fp64) k_adv_limit<double><<<g, 256, 0, s->stream>>>(a);
+    else k_adv_limit<float><<<g, 256, 0, s->stream>>>(a);
+    return hipGetLastError();
+}
+
 hipError_t launch_explicit(nspnp_state *s, const Stage &st, bool /*write_r*/) {
     ExplicitArgs a{};
     a.d = s->d;
@@ -1322,7 +1422,9 @@ hipError_t launch_explicit(nspnp_state *s, const Stage &st, bool /*write_r*/) {
     }
     const int tb = s->tiles.expl;
     explicit_tiling(s->d, s->fp64, tb, L ? L : s->tiles.slab, a);
-    return explicit_launch(s, a, tb, (unsigned)((int64_t)a.chunks * a.slabs * s->nmem));
+    const hipError_t e2 = explicit_launch(s, a, tb, (unsigned)((int64_t)a.chunks * a.slabs * s->nmem));
+    if (e2 != hipSuccess || s->cfg.migration_face != 2) return e2;
+    return launch_adv_limit(s, st, nullptr);
 }
 
 hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]) {
@@ -1338,7 +1440,9 @@ hipError_t launch_explicit_debug(nspnp_state *s, double *const out[5]) {
     a.mode = 1;
     a.implicit_xz = s->cfg.implicit_xz;
     explicit_tiling(s->d, s->fp64, 256, s->tiles.slab, a);
-    return explicit_launch(s, a, 256, (unsigned)((int64_t)a.chunks * a.slabs));
+    const hipError_t e = explicit_launch(s, a, 256, (unsigned)((int64_t)a.chunks * a.slabs));
+    if (e != hipSuccess || s->cfg.migration_face != 2) return e;
+    return launch_adv_limit(s, a.st, out);
 }
 
 static hipError_t launch_cn_lane(nspnp_state *s, const CnArgs &a);

@@ -63,3 +63,23 @@ def test_equilibrium_double_layer_is_stationary_in_the_oracle(oracle_mod):
     oracle_mod.set_threads(8)
     cp0, cm0, phi0 = equilibrium_ions(dataclasses.replace(cfg, vhat=0.0))
     assert np.max(np.abs(cp0 - 1.0)) < 1e-14 and np.max(np.abs(phi0)) < 1e-14
+
+
+def test_rms_peaks_in_wall_units():
+    """Peak of a synthetic RMS profile, one per half: y+ is the distance of
+    the peak row from its own wall times Re u_tau."""
+    from types import SimpleNamespace
+    from paper_1701_02005_amd.campaign import rms_peaks
+    yc = np.linspace(-0.95, 0.95, 20)
+    r_cp = np.exp(-((yc + 0.85) / 0.05) ** 2) + 0.5 * np.exp(-((yc - 0.75) / 0.05) ** 2)
+    r_cm = np.exp(-((yc + 0.65) / 0.05) ** 2) + 2.0 * np.exp(-((yc - 0.95) / 0.05) ** 2)
+    st = {"yc": yc, "rms": {"cp": r_cp, "cm": r_cm}, "u_tau": 0.05}
+    pk = rms_peaks(st, SimpleNamespace(re=3000.0))
+    scale = 3000.0 * 0.05
+    assert abs(pk["cp_lower"]["y_plus"] - (yc[1] + 1) * scale) < 1e-9
+    assert abs(pk["cp_upper"]["y_plus"] - (1 - yc[17]) * scale) < 1e-9
+    assert abs(pk["cm_lower"]["y_plus"] - (yc[3] + 1) * scale) < 1e-9
+    assert abs(pk["cm_upper"]["y_plus"] - (1 - yc[19]) * scale) < 1e-9
+    assert pk["cm_upper"]["rms"] == r_cm[19]
+    st["u_tau"] = float("nan")
+    assert np.isnan(rms_peaks(st, SimpleNamespace(re=3000.0))["cp_lower"]["y_plus"])

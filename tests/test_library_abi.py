@@ -39,6 +39,6 @@ def test_config_validation_without_gpu():
     assert P.workspace_bytes(ok) > 0
     assert P.workspace_bytes(dataclasses.replace(ok, ny=513)) > 0
     for bad in (dict(nx=30), dict(nz=7), dict(ny=4), dict(ny=514), dict(re=0.0), dict(precision="fp64", debye=-1.0),
-                dict(migration_face=2), dict(implicit_xz=3)):
+                dict(migration_face=3), dict(migration_face=-1), dict(implicit_xz=3)):
         assert P.workspace_bytes(dataclasses.replace(ok, **bad)) == 0
         assert P.load_library().nspnp_last_error()

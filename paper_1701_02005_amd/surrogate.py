@@ -3,11 +3,14 @@
 Pipeline (all GPU work through the HIP library):
 
 1. an ensemble of independent runs over (Re, vhat, Debye length) is advanced
-   together and its time-mean plane profiles of u, rho = c+ - c- and Phi are
-   recorded over the second half of every run;
-2. the profiles are sampled at each run's wall-normal nodes (wall values from
-   the boundary conditions: u = u_bot / u_top, Phi = -+vhat/2, rho linearly
-   extrapolated) and interpolated onto the nodes of the target grid;
+   together, long enough for the double layer of every run to become
+   stationary; each run's lower-half charge is recorded chunk by chunk and
+   the stationarity rule below decides which runs are stationary over the
+   averaging window (only those are training data);
+2. the time-mean plane profiles of u, rho = c+ - c- and Phi over the
+   averaging window are sampled at each run's wall-normal nodes (wall values
+   from the boundary conditions: u = u_bot / u_top, Phi = -+vhat/2, rho
+   linearly extrapolated) and interpolated onto the nodes of the target grid;
 3. a GELU network (BF16 matrix-core kernels, Adam) learns the map from the
    scaled control parameters to the encoded profiles (u as is, asinh(rho),
    Phi / (vhat/2 + 1e-6), each standardised);
@@ -15,9 +18,9 @@ Pipeline (all GPU work through the HIP library):
    plus the same seeded noise as the plain start, c+- rebuilt from rho with
    c+ c- = A^2 and both ion contents fixed, phi re-solved;
 5. warm and plain starts are advanced side by side and the times after which
-   the mean wall shear stress (and the charge of the lower half gap, the
-   quantity the double layer sets) stay within 1 % of their stationary values
-   are compared.
+   the mean wall shear stress and the charge of the lower half gap (the
+   quantity the double layer sets) stay within 1 % of their stationary
+   values are compared.
 
 The stationarity rule: the reference is the mean over the second half of
 the plain run; t* is the first time after which the average over a window
@@ -43,14 +46,27 @@ RANGES = {"re": (500.0, 3000.0), "vhat": (0.0, 20.0), "lnlam": (math.log(0.02), 
 
 
 # ---------------------------------------------------------------- features
-def scale_inputs(re, vhat, lam) -> np.ndarray:
-    """(Re, vhat, ln lam) mapped linearly onto [-1, 1] over the ensemble ranges."""
+def scale_inputs(re, vhat, lam, ranges=RANGES) -> np.ndarray:
+    """(Re, vhat, ln lam) mapped linearly onto [-1, 1] over the sampling ranges."""
     cols = []
     for val, key in ((np.asarray(re, float), "re"), (np.asarray(vhat, float), "vhat"),
                      (np.log(np.asarray(lam, float)), "lnlam")):
-        lo, hi = RANGES[key]
+        lo, hi = ranges[key]
         cols.append(2.0 * (val - lo) / (hi - lo) - 1.0)
     return np.stack(cols, axis=-1)
+
+
+def sample_points(seed: int, n: int, ranges=RANGES):
+    """Point i: (Re, vhat, lam) from a generator seeded with (seed, i): Re and
+    vhat uniform, lam log-uniform over the ranges (the ensemble sampler)."""
+    pts = []
+    for i in range(n):
+        rng = np.random.default_rng([seed, i])
+        re = float(rng.uniform(*ranges["re"]))
+        vhat = float(rng.uniform(*ranges["vhat"]))
+        lam = float(math.exp(rng.uniform(*ranges["lnlam"])))
+        pts.append((re, vhat, lam))
+    return pts
 
 
 def node_profiles(cfg: Config, u_c, rho_c, phi_c):
@@ -137,42 +153,73 @@ def stationary_time(t, series, ref, window, tol):
     return float(t[last_bad + 1]), False
 
 
+def lower_half_charge(cfg: Config, rho):
+    """Charge of the lower half gap per unit wall area, sum over the rows
+    below the mid-plane of rho dy."""
+    yn, yc = (np.asarray(a) for a in grid(cfg))
+    low = yc < 0
+    return float(np.sum(np.asarray(rho)[low] * np.diff(yn)[low]))
+
+
 # ---------------------------------------------------------------- stages
-def ensemble_data(seed: int, substeps: int, stats_from: int, target_ny: int, log=print, tune_cache=None):
-    members = configs.ensemble_members(seed)
+def ensemble_data(members, substeps: int, window_substeps: int, target: Config, chunk: int = 3000,
+                  tol: float = 0.01, log=print, tune_cache=None):
+    """Advance the training ensemble substeps substeps in graph replays of
+    chunk substeps; per chunk, every run's chunk-mean profiles.  A run is
+    training data when its lower-half charge, chunk by chunk, stays within
+    tol of its mean over the last window_substeps throughout that window.
+    Returns inputs X, encoded targets Y (runs kept), target nodes, report."""
     t0 = time.perf_counter()
     ens = Ensemble(members)
     tiles = ens.autotune(tune_cache, 6)
     done = ens.clock(0)[2]
-    first = (max(stats_from, done) - done) // 30 * 30
-    ens.capture(30)
-    ens.step(first)
-    ens.stats(True)          # statistics over the rest of the run
-    ens.capture(30)          # the replayed graph now includes the statistics kernel
-    ens.step(substeps - done - first)
+    ens.stats(True)      # on before the capture: the replayed graph then includes the statistics kernel
+    ens.capture(chunk)
+    nchunk = max(1, (substeps - done) // chunk)
+    series = [[] for _ in members]  # (t, q, wt, u, rho, phi) per chunk
+    for it in range(nchunk):
+        ens.stats(True)
+        ens.step(chunk)
+        for m, c in enumerate(members):
+            u, rho, phi, wt = ens.profiles(m)
+            series[m].append((ens.clock(m)[0], lower_half_charge(c, rho), wt, u, rho, phi))
+        if (it + 1) % 10 == 0 or it == nchunk - 1:
+            log(f"ensemble: {done + chunk * (it + 1)} substeps, {time.perf_counter() - t0:.1f} s")
     ens.sync()
     wall = time.perf_counter() - t0
-    tgt = dataclasses.replace(configs.couette_turbulent(), ny=target_ny)
-    y_t, _ = grid(tgt)
+    y_t, _ = grid(target)
+    nwin = max(1, window_substeps // chunk)
     X, Y, meta = [], [], []
     for m, c in enumerate(members):
-        u_c, rho_c, phi_c, wt = ens.profiles(m)
-        yn, u, rho, Phi = node_profiles(c, u_c, rho_c, phi_c)
-        ui, ri, Pi = (np.interp(y_t, yn, f) for f in (u, rho, Phi))
-        X.append((c.re, c.vhat, c.debye))
-        Y.append(encode(ui, ri, Pi, c.vhat))
-        t_m, dt_m, _ = ens.clock(m)
+        ser = series[m][-nwin:]
+        wts = np.array([s[2] for s in ser])
+        qs = np.array([s[1] for s in ser])
+        qref = float(np.sum(wts * qs) / wts.sum())
+        drift = float(np.max(np.abs(qs - qref)) / max(abs(qref), 1e-12))
+        stationary = drift <= tol
+        prof = [np.sum([w * np.asarray(s[k]) for w, s in zip(wts, ser)], axis=0) / wts.sum() for k in (3, 4, 5)]
         try:
             dg = ens.diagnostics(m)
         except Exception as exc:  # non-finite member
             dg = {"error": str(exc)}
+            stationary = False
         meta.append({"re": c.re, "vhat": c.vhat, "debye": c.debye, "grid": f"{c.nx}x{c.ny}x{c.nz}",
-                     "time_averaged": wt, "t_end": t_m, "dt_end": dt_m, "diagnostics": dg})
+                     "t_end": series[m][-1][0], "window_start_t": ser[0][0] - 0.0, "charge": qref,
+                     "charge_drift": drift, "stationary": stationary, "diagnostics": dg})
+        if stationary:
+            yn, u, rho, Phi = node_profiles(c, *prof)
+            ui, ri, Pi = (np.interp(y_t, yn, f) for f in (u, rho, Phi))
+            X.append((c.re, c.vhat, c.debye))
+            Y.append(encode(ui, ri, Pi, c.vhat))
     points = sum(c.points for c in members) * substeps
+    kept = len(X)
     log(f"ensemble: {len(members)} runs, {substeps} substeps in {wall:.1f} s "
-        f"({points / wall / 1e6:.0f} Mpoint-substeps/s incl. autotune and capture)")
-    info = {"members": len(members), "substeps": substeps, "stats_from": stats_from, "wall_s": wall,
-            "mpoint_substeps_per_s": points / wall / 1e6, "tiles": tiles, "runs": meta}
+        f"({points / wall / 1e6:.0f} Mpoint-substeps/s incl. autotune and capture); "
+        f"{kept} stationary in charge over the last {nwin} chunks; member times "
+        f"{min(r['t_end'] for r in meta):.1f} .. {max(r['t_end'] for r in meta):.1f}")
+    info = {"members": len(members), "substeps": substeps, "window_substeps": nwin * chunk, "chunk": chunk,
+            "tol": tol, "wall_s": wall, "mpoint_substeps_per_s": points / wall / 1e6, "tiles": tiles,
+            "stationary": kept, "runs": meta}
     return np.array(X), np.array(Y), np.asarray(y_t), info
 
 
@@ -187,12 +234,12 @@ def init_params(sizes, seed):
     return np.concatenate(out).astype(np.float32)
 
 
-def train_network(X, Y, steps: int, lr: float, seed: int, log=print):
+def train_network(X, Y, steps: int, lr: float, seed: int, sizes=SIZES, ranges=RANGES, log=print):
     import torch
-    xs = scale_inputs(X[:, 0], X[:, 1], X[:, 2]).astype(np.float32)
+    xs = scale_inputs(X[:, 0], X[:, 1], X[:, 2], ranges).astype(np.float32)
     std = Standardizer.fit(Y)
     ys = std.fwd(Y).astype(np.float32)
-    net = Mlp(SIZES, max(64, len(xs)), init_params(SIZES, seed))
+    net = Mlp(sizes, max(64, len(xs)), init_params(sizes, seed))
     xt = torch.tensor(xs, device=net.device)
     yt = torch.tensor(ys, device=net.device)
     losses = []
@@ -205,22 +252,21 @@ def train_network(X, Y, steps: int, lr: float, seed: int, log=print):
     wall = time.perf_counter() - t0
     final = net.gradients(xt, yt)
     log(f"training: {steps} Adam steps in {wall:.2f} s, loss {losses[0][1]:.3e} -> {final:.3e}")
-    return net, std, {"steps": steps, "lr": lr, "wall_s": wall, "loss_curve": losses, "final_loss": final}
+    return net, std, {"steps": steps, "lr": lr, "wall_s": wall, "loss_curve": losses, "final_loss": final,
+                      "samples": int(len(xs))}
 
 
-def predict(net, std, X):
+def predict(net, std, X, ranges=RANGES):
     import torch
-    xs = torch.tensor(scale_inputs(X[:, 0], X[:, 1], X[:, 2]).astype(np.float32), device=net.device)
+    xs = torch.tensor(scale_inputs(X[:, 0], X[:, 1], X[:, 2], ranges).astype(np.float32), device=net.device)
     out = net.forward(xs).cpu().numpy().astype(np.float64)
     return std.inv(out)
 
 
-def test_members(seed: int, n: int, precision: str):
-    """Unseen parameter points (same sampler, another seed) on the 256x193x256 grid."""
-    base = configs.couette_turbulent(precision=precision)
-    pts = configs.ensemble_members(seed, n_large=n, n_small=0)
-    return [dataclasses.replace(base, re=p.re, vhat=p.vhat, debye=p.debye, seed=base.seed + 7 * q)
-            for q, p in enumerate(pts)]
+def test_members(seed: int, n: int, base: Config, ranges=RANGES):
+    """Unseen parameter points (the sampler with another seed) on the grid of base."""
+    return [dataclasses.replace(base, re=re, vhat=vhat, debye=lam, seed=base.seed + 7 * q)
+            for q, (re, vhat, lam) in enumerate(sample_points(seed, n, ranges))]
 
 
 def warm_start(ens: Ensemble, members, preds, y_t, log=print):
@@ -242,15 +288,15 @@ def warm_start(ens: Ensemble, members, preds, y_t, log=print):
     ens.sync()
 
 
-def monitor(ens: Ensemble, members, chunk: int, t_end: float, log=print):
-    """Advance until every member reaches t_end; per chunk record the
-    chunk-mean wall shear stress and lower-half charge of every member."""
+def monitor(ens: Ensemble, members, chunk: int, t_end: float, log=print, max_substeps: int | None = None,
+            label: str = ""):
+    """Advance until every member reaches t_end (or max_substeps per member
+    have run); per chunk record the chunk-mean wall shear stress and
+    lower-half charge of every member.  Logs progress every 30 s."""
     out = [{"t": [], "tau": [], "q": []} for _ in members]
-    geo = []
-    for c in members:
-        yn, yc = (np.asarray(a) for a in grid(c))
-        geo.append((yn, yc, np.diff(yn)))
+    geo = [tuple(np.asarray(a) for a in grid(c)) for c in members]
     t0 = time.perf_counter()
+    t_log = t0
     nsub = 0
     while True:
         ens.stats(True)
@@ -259,54 +305,55 @@ def monitor(ens: Ensemble, members, chunk: int, t_end: float, log=print):
         tmin = math.inf
         for m, c in enumerate(members):
             u, rho, phi, wt = ens.profiles(m)
-            yn, yc, dn = geo[m]
+            yn, yc = geo[m]
             t = ens.clock(m)[0]
             tb = (u[0] - c.u_bot) / (c.re * (yc[0] - yn[0]))
             tt = (c.u_top - u[-1]) / (c.re * (yn[-1] - yc[-1]))
-            lower = yc < 0
             out[m]["t"].append(t)
             out[m]["tau"].append(0.5 * (tb + tt))
-            out[m]["q"].append(float(np.sum(np.asarray(rho)[lower] * dn[lower])))
+            out[m]["q"].append(lower_half_charge(c, rho))
             out[m].setdefault("prof", []).append((wt, u, rho, phi))
             tmin = min(tmin, t)
-        if tmin >= t_end:
+        now = time.perf_counter()
+        if now - t_log >= 30.0:
+            t_log = now
+            log(f"{label}: {nsub} substeps, slowest member at t = {tmin:.1f}, {now - t0:.0f} s")
+        if tmin >= t_end or (max_substeps is not None and nsub >= max_substeps):
             break
     ens.sync()
     wall = time.perf_counter() - t0
     return out, nsub, wall
 
 
-def run(out_path: str, seed: int = 0, ens_substeps: int = 5000, stats_from: int = 2500, train_steps: int = 3000,
-        lr: float = 1e-3, n_test: int = 8, t_end: float = 30.0, chunk: int = 60, window: float = 5.0,
-        tol: float = 0.01, precision: str = "mixed", log=print):
-    report = {"seed": seed}
-    X, Y, y_t, report["ensemble"] = ensemble_data(seed, ens_substeps, stats_from, 193, log)
-    net, std, report["training"] = train_network(X, Y, train_steps, lr, seed, log)
-    members = test_members(seed + 1, n_test, precision)
-    Xt = np.array([(c.re, c.vhat, c.debye) for c in members])
-    preds = predict(net, std, Xt)
-    log(f"test points: {[(round(c.re), round(c.vhat, 2), round(c.debye, 4)) for c in members]}")
+def compare_starts(members, preds, y_t, t_end: float, chunk: int, window: float, tol: float, log=print,
+                   max_substeps: int | None = None):
+    """Plain and warm starts of the test runs advanced side by side; t* of
+    the drag and of the lower-half charge for both, against the plain run's
+    second-half mean.  max_substeps caps each start (the runs then end
+    before t_end, which the report states per member)."""
     results = {}
     for label in ("plain", "warm"):
         ens = Ensemble(members)
+        init_s = 0.0
         if label == "warm":
             t0 = time.perf_counter()
             warm_start(ens, members, preds, y_t, log)
-            results["warm_init_s"] = time.perf_counter() - t0
-        ens.stats(True)
+            init_s = time.perf_counter() - t0
+        ens.stats(True)  # on before the capture (the graph then includes the statistics kernel)
         ens.capture(chunk)
-        series, nsub, wall = monitor(ens, members, chunk, t_end, log)
-        results[label] = (series, nsub, wall)
+        series, nsub, wall = monitor(ens, members, chunk, t_end, log, max_substeps, label)
+        results[label] = (series, nsub, wall, init_s)
         log(f"{label}: {nsub} substeps per run to t >= {t_end} in {wall:.1f} s")
         del ens
-    plain, _, wall_p = results["plain"]
-    warm, _, wall_w = results["warm"]
+    plain, _, wall_p, _ = results["plain"]
+    warm, _, wall_w, init_w = results["warm"]
     per = []
     for m, c in enumerate(members):
         ps, ws = plain[m], warm[m]
         tp = np.array(ps["t"])
         half = tp >= 0.5 * tp[-1]
-        rec = {"re": c.re, "vhat": c.vhat, "debye": c.debye}
+        rec = {"re": c.re, "vhat": c.vhat, "debye": c.debye, "t_reached_plain": float(tp[-1]),
+               "t_reached_warm": float(ws["t"][-1]), "capped": bool(tp[-1] < t_end or ws["t"][-1] < t_end)}
         for key in ("tau", "q"):
             ref = float(np.mean(np.array(ps[key])[half]))
             t_p, cen_p = stationary_time(ps["t"], ps[key], ref, window, tol)
@@ -316,7 +363,7 @@ def run(out_path: str, seed: int = 0, ens_substeps: int = 5000, stats_from: int 
             rec[key] = {"ref": ref, "t_plain": t_p, "t_warm": t_w, "censored_plain": cen_p, "censored_warm": cen_w,
                         "substeps_plain": n_p, "substeps_warm": n_w,
                         "wall_plain_s": wall_p * n_p / max(1, len(tp) * chunk),
-                        "wall_warm_s": wall_w * n_w / max(1, len(ws["t"]) * chunk)}
+                        "wall_warm_s": wall_w * n_w / max(1, len(ws["t"]) * chunk) + init_w}
         # profile error of the prediction against the plain run's late-time mean
         late = [p for p, h in zip(ps["prof"], half) if h]
         wts = np.array([p[0] for p in late])
@@ -333,8 +380,33 @@ def run(out_path: str, seed: int = 0, ens_substeps: int = 5000, stats_from: int 
             f"warm {rec['q']['t_warm']:.2f}{'(c)' if rec['q']['censored_warm'] else ''} | "
             f"L2 u {rec['profile_rel_l2']['u']:.2e} rho {rec['profile_rel_l2']['rho']:.2e} "
             f"Phi {rec['profile_rel_l2']['Phi']:.2e}")
-    report["test"] = {"points": per, "t_end": t_end, "window": window, "tol": tol, "chunk": chunk,
-                      "wall_plain_s": wall_p, "wall_warm_s": wall_w, "warm_init_s": results.get("warm_init_s")}
+    return per, {"wall_plain_s": wall_p, "wall_warm_s": wall_w, "warm_init_s": init_w}
+
+
+def run(out_path: str, seed: int = 0, ens_substeps: int = 240000, window_substeps: int = 30000,
+        train_steps: int = 3000, lr: float = 1e-3, n_test: int = 8, test_plane: int = 32, t_end: float = 4000.0,
+        chunk: int = 300, window: float = 5.0, tol: float = 0.01, precision: str = "mixed", log=print,
+        max_substeps: int | None = None):
+    """The experiment at the production sizes: the 64-run ensemble (hybrid
+    migration face value, so that every voltage of the sampler stays
+    positive) as training data, the 3 -> 4 x 256 -> 3 x 193 network, and
+    n_test unseen points on the 193-node wall-normal grid of the turbulent
+    workload with test_plane x test_plane horizontal points."""
+    report = {"seed": seed}
+    members = [dataclasses.replace(c, migration_face=1) for c in configs.ensemble_members(seed, precision=precision)]
+    target = configs.couette_turbulent(precision=precision)
+    X, Y, y_t, report["ensemble"] = ensemble_data(members, ens_substeps, window_substeps, target, log=log)
+    net, std, report["training"] = train_network(X, Y, train_steps, lr, seed, log=log)
+    base = dataclasses.replace(target, nx=test_plane, nz=test_plane, migration_face=1)
+    tests = test_members(seed + 1, n_test, base)
+    Xt = np.array([(c.re, c.vhat, c.debye) for c in tests])
+    t0 = time.perf_counter()
+    preds = predict(net, std, Xt)
+    report["inference_s"] = time.perf_counter() - t0
+    log(f"test points: {[(round(c.re), round(c.vhat, 2), round(c.debye, 4)) for c in tests]}")
+    per, walls = compare_starts(tests, preds, y_t, t_end, chunk, window, tol, log, max_substeps)
+    report["test"] = {"points": per, "grid": f"{base.nx}x{base.ny}x{base.nz}", "t_end": t_end, "window": window,
+                      "tol": tol, "chunk": chunk, **walls}
     Path(out_path).parent.mkdir(parents=True, exist_ok=True)
     Path(out_path).write_text(json.dumps(report, indent=1, default=float))
     return report
@@ -344,14 +416,17 @@ def main():
     ap = argparse.ArgumentParser(description="ensemble -> surrogate network -> warm-started runs")
     ap.add_argument("--out", default="surrogate_report.json")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--ens-substeps", type=int, default=5000)
-    ap.add_argument("--stats-from", type=int, default=2500)
+    ap.add_argument("--ens-substeps", type=int, default=240000)
+    ap.add_argument("--window-substeps", type=int, default=30000)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--n-test", type=int, default=8)
-    ap.add_argument("--t-end", type=float, default=30.0)
+    ap.add_argument("--test-plane", type=int, default=32)
+    ap.add_argument("--t-end", type=float, default=4000.0)
+    ap.add_argument("--max-substeps", type=int, default=None, help="cap per start of the test runs")
     args = ap.parse_args()
-    run(args.out, seed=args.seed, ens_substeps=args.ens_substeps, stats_from=args.stats_from,
-        train_steps=args.train_steps, n_test=args.n_test, t_end=args.t_end,
+    run(args.out, seed=args.seed, ens_substeps=args.ens_substeps, window_substeps=args.window_substeps,
+        train_steps=args.train_steps, n_test=args.n_test, test_plane=args.test_plane, t_end=args.t_end,
+        max_substeps=args.max_substeps,
         log=lambda s: print(s, flush=True))
 
 

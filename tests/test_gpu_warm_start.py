@@ -48,6 +48,7 @@ def test_warm_start_reaches_stationary_charge_sooner():
     preds = S.predict(net, std, np.array([(c.re, c.vhat, c.debye) for c in tests]), ranges=RANGES)
     per, walls = S.compare_starts(tests, preds, y_t, t_end=1500.0, chunk=30, window=5.0, tol=0.01, log=note)
     for rec in per:
+        assert "q" in rec, rec  # no start stopped by the health check
         q = rec["q"]
         assert not q["censored_plain"], rec
         assert not q["censored_warm"], rec

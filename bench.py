@@ -53,8 +53,12 @@ def kernel_bytes(cfg, name: str, launches: int, substeps: int) -> float:
     w = 8 if cfg.precision == "fp64" else 4
     n = cfg.nx * cfg.nz * (cfg.ny - 1)
     sp = 16.0 * (cfg.nx // 2 + 1) / cfg.nx
+    # limited advective face values of the ions (migration_face 2): the
+    # correction pass reads u, v, w and c+-, updates the ions' r and (two
+    # stages of three) their H
+    lim = (3 * w + 2 * w + 2 * 2 * w + 2 * 2 * w * (2.0 / 3.0)) if getattr(cfg, "migration_face", 0) == 2 else 0.0
     per = {
-        "explicit_rhs": 7 * w + 5 * w + 5 * w * (2.0 / 3.0) + 5 * w * (2.0 / 3.0),
+        "explicit_rhs": 7 * w + 5 * w + 5 * w * (2.0 / 3.0) + 5 * w * (2.0 / 3.0) + lim,
         # implicit wall-normal diffusion: r and the field read, the field written; with the
         # three-direction factorisation x-lines (r in place), y (r in place), z-lines (q += x)
         "cn_tridiag": 5 * (7 if getattr(cfg, "implicit_xz", 0) else 3) * w,
@@ -167,7 +171,8 @@ def measure(cfg, args, P, torch, tiles_trial: int) -> dict:
     # source they were taken from is unchanged
     traffic = None
     tr_file = ROOT / "profiles" / "traffic.json"
-    if tr_file.exists() and not args.implicit_xz:  # (counters were taken without the x/z solves)
+    # (counters were taken with the default face rules and without the x/z solves)
+    if tr_file.exists() and not args.implicit_xz and not args.migration_face:
         try:
             from paper_1701_02005_amd import pmc_traffic
             ent = json.loads(tr_file.read_text()).get(f"{args.workload}/{cfg.precision}/{dom}")
@@ -220,6 +225,9 @@ def main():
                          "(a separate measurement; the default line has no sampling)")
     ap.add_argument("--implicit-xz", action="store_true",
                     help="diffusion implicit in x and z too (three-direction approximate factorisation)")
+    ap.add_argument("--migration-face", type=int, default=0, choices=[0, 1, 2],
+                    help="face rules of the ion fluxes: 1 hybrid migration, 2 also limited advection "
+                         "(a separate measurement of the positivity options)")
     ap.add_argument("--wall-amplitude", type=float, default=0.0,
                     help="time with a wall-potential pattern A cos(x) cos(2z) on both walls "
                          "(a separate measurement of the inhomogeneous potential solve)")
@@ -250,6 +258,8 @@ def main():
     cfg = P.configs.WORKLOADS[args.workload](precision=args.precision)
     if args.implicit_xz:
         cfg = dataclasses.replace(cfg, implicit_xz=1)
+    if args.migration_face:
+        cfg = dataclasses.replace(cfg, migration_face=args.migration_face)
     print(f"[bench] workload {args.workload} {cfg.nx}x{cfg.ny}x{cfg.nz} {args.precision}", file=sys.stderr,
           flush=True)
     if args.copy_calibration_mb > 0:
@@ -283,7 +293,8 @@ def main():
                    "points": cfg.points, "cells": cfg.cells, "precision": args.precision,
                    "parallelism": "single GPU", **({"stats_every": args.stats_every} if args.stats_every else {}),
                    **({"wall_amplitude": args.wall_amplitude} if args.wall_amplitude else {}),
-                   **({"implicit_xz": 1} if args.implicit_xz else {})},
+                   **({"implicit_xz": 1} if args.implicit_xz else {}),
+                   **({"migration_face": args.migration_face} if args.migration_face else {})},
         **{k: res[k] for k in ("roofline", "substep_roofline", "kernels", "launch_shapes", "profiled_region_ms",
                                "state_check")},
     }

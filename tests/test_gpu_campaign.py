@@ -41,3 +41,24 @@ def test_laminar_campaign_and_resume(P, tmp_path):
     rest = C.run_campaign(cfg, t_spin=0.5, t_avg=2.0, every=1, monitor=0.1, resume=str(ck), log=lambda m: None)
     assert rest["samples"] > part["samples"]
     assert abs(rest["cf"] - 2.0 / cfg.re) < 1e-11
+
+
+def test_charged_laminar_campaign_with_limited_advection(P):
+    """The sweep's path (migration_face 2, equilibrium double layer, charged
+    walls) on laminar flow: the Coulomb force is wall-normal and balanced by
+    the pressure, so c_f = 2/Re; the layer stays at the discrete equilibrium
+    the host solved, and the ion RMS is zero."""
+    from paper_1701_02005_amd import campaign as C
+    cfg = dataclasses.replace(P.configs.couette_small(), nx=16, ny=33, nz=16, vhat=10.0, debye=0.1, sc=1.0,
+                              migration_face=2, u_noise=0.0, c_noise=0.0, dt=0.0, cfl=0.5)
+    print("case: charged laminar campaign 16x33x16, vhat 10, migration_face 2", flush=True)
+    sys.stdout.flush()
+    cp_eq, cm_eq, _ = C.equilibrium_ions(cfg)
+    rep = C.run_campaign(cfg, t_spin=0.5, t_avg=1.0, every=1, monitor=0.1, amp=0.0, log=lambda m: None)
+    assert rep["stopped"] is None
+    assert abs(rep["cf"] - 2.0 / cfg.re) < 1e-9
+    np.testing.assert_allclose(rep["mean"]["cp"], cp_eq, rtol=1e-7)
+    np.testing.assert_allclose(rep["mean"]["cm"], cm_eq, rtol=1e-7)
+    # (the RMS is sqrt(<q^2> - <q>^2): rounding of q^2 ~ 10^3 leaves ~1e-5 absolute)
+    assert max(rep["rms"]["cp"]) < 1e-4 * max(cp_eq) and max(rep["rms"]["cm"]) < 1e-4 * max(cp_eq)
+    assert set(rep["rms_peaks"]) == {"cp_lower", "cp_upper", "cm_lower", "cm_upper"}

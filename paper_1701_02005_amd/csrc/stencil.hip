@@ -1323,55 +1323,77 @@ struct AdvArgs {
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_adv_limit(AdvArgs a) {
-    const int64_t pl = a.d.plane;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int pl = (int)a.d.plane;
+    const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (e >= pl) return;
     const int j = (int)blockIdx.y, M = a.d.M, nx = a.d.nx, nz = a.d.nz;
     const size_t ms = a.ms;
+    const int i = e % nx, k = e / nx;
+    auto wrap = [](int q, int n) { return q < 0 ? q + n : (q >= n ? q - n : q); };  // n >= 4
+    // every access is a field's base plus a 32-bit byte offset (a field of
+    // every supported grid is below 2^32 bytes); rows outside the grid are
+    // clamped to an existing row and their values not used, so that all
+    // loads are unconditional and issued before any arithmetic
+    const unsigned W = (unsigned)sizeof(T), P = (unsigned)pl * W;
+    const unsigned row = (unsigned)j * P, kx = (unsigned)(k * nx) * W;
+    const unsigned o0 = row + (unsigned)e * W;
+    const unsigned oxp = row + kx + (unsigned)wrap(i + 1, nx) * W, oxm = row + kx + (unsigned)wrap(i - 1, nx) * W;
+    const unsigned oxp2 = row + kx + (unsigned)wrap(i + 2, nx) * W, oxm2 = row + kx + (unsigned)wrap(i - 2, nx) * W;
+    const unsigned ozp = row + (unsigned)(wrap(k + 1, nz) * nx + i) * W;
+    const unsigned ozm = row + (unsigned)(wrap(k - 1, nz) * nx + i) * W;
+    const unsigned ozp2 = row + (unsigned)(wrap(k + 2, nz) * nx + i) * W;
+    const unsigned ozm2 = row + (unsigned)(wrap(k - 2, nz) * nx + i) * W;
+    auto rowoff = [&](int jj) { return (unsigned)(jj < 0 ? 0 : (jj >= M ? M - 1 : jj)) * P + (unsigned)e * W; };
+    const unsigned oyp = rowoff(j + 1), oym = rowoff(j - 1), oyp2 = rowoff(j + 2), oym2 = rowoff(j - 2);
     const T *u = member_ptr((const T *)a.u, ms), *v = member_ptr((const T *)a.v, ms);
     const T *w = member_ptr((const T *)a.w, ms);
-    const int i = (int)(e % nx), k = (int)(e / nx);
-    auto wrap = [](int q, int n) { return q < 0 ? q + n : (q >= n ? q - n : q); };  // n >= 4
-    const int64_t row = (int64_t)j * pl, q0 = row + e;
-    const int64_t xp = row + (int64_t)k * nx + wrap(i + 1, nx), xm = row + (int64_t)k * nx + wrap(i - 1, nx);
-    const int64_t xp2 = row + (int64_t)k * nx + wrap(i + 2, nx), xm2 = row + (int64_t)k * nx + wrap(i - 2, nx);
-    const int64_t zp = row + (int64_t)wrap(k + 1, nz) * nx + i, zm = row + (int64_t)wrap(k - 1, nz) * nx + i;
-    const int64_t zp2 = row + (int64_t)wrap(k + 2, nz) * nx + i, zm2 = row + (int64_t)wrap(k - 2, nz) * nx + i;
-    const T half = T(0.5);
-    const T uL = u[q0], uR = u[xp], wB = w[q0], wF = w[zp];
-    const T vb = (j > 0) ? v[q0] : T(0), vt = (j + 1 < M) ? v[q0 + pl] : T(0);
-    const T idx_ = T(1.0 / a.d.dx), idz_ = T(1.0 / a.d.dz), idn = T(a.tb.idn[j]);
+    const T uL = *byte_at(u, o0), uR = *byte_at(u, oxp), wB = *byte_at(w, o0), wF = *byte_at(w, ozp);
+    const T vb0 = *byte_at(v, o0), vt0 = *byte_at(v, oyp);
+    T c[2][13];  // own; x +1 -1 +2 -2; z +1 -1 +2 -2; y +1 -1 +2 -2
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp) {
-        const T *c = member_ptr((const T *)a.c[sp], ms);
-        const T cc = c[q0], cxp = c[xp], cxm = c[xm], czp = c[zp], czm = c[zm];
-        const bool ur = uR >= T(0), ul = uL >= T(0), wf = wF >= T(0), wb = wB >= T(0);
-        const T dR = adv_face(cc, cxp, ur ? cxm : c[xp2], ur, true) - half * (cxp + cc);
-        const T dL = adv_face(cxm, cc, ul ? c[xm2] : cxp, ul, true) - half * (cc + cxm);
-        const T dF = adv_face(cc, czp, wf ? czm : c[zp2], wf, true) - half * (czp + cc);
-        const T dB = adv_face(czm, cc, wb ? c[zm2] : czp, wb, true) - half * (cc + czm);
-        T dT = T(0), dD = T(0);
-        if (j + 1 < M) {  // top face: between rows j and j + 1
-            const T cu = c[q0 + pl];
-            const bool up = vt >= T(0), have = up ? (j > 0) : (j + 2 < M);
-            const T cuu = have ? c[up ? q0 - pl : q0 + 2 * pl] : T(0);
-            dT = adv_face(cc, cu, cuu, up, have) - half * (cu + cc);
-        }
-        if (j > 0) {  // bottom face: between rows j - 1 and j
-            const T cd = c[q0 - pl];
-            const bool up = vb >= T(0), have = up ? (j > 1) : (j + 1 < M);
-            const T cuu = have ? c[up ? q0 - 2 * pl : q0 + pl] : T(0);
-            dD = adv_face(cd, cc, cuu, up, have) - half * (cc + cd);
-        }
-        const T delta = -((uR * dR - uL * dL) * idx_ + (wF * dF - wB * dB) * idz_ + (vt * dT - vb * dD) * idn);
-        if (a.mode == 1) {
-            a.dbg[sp][q0] += (double)delta;
-            continue;
-        }
-        const T dt = T(member_ptr(a.clock, ms)[1]);
+        const T *cf = member_ptr((const T *)a.c[sp], ms);
+        const unsigned off[13] = {o0, oxp, oxm, oxp2, oxm2, ozp, ozm, ozp2, ozm2, oyp, oym, oyp2, oym2};
+#pragma unroll
+        for (int q = 0; q < 13; ++q) c[sp][q] = *byte_at(cf, off[q]);
+    }
+    const T half = T(0.5);
+    const T vb = (j > 0) ? vb0 : T(0), vt = (j + 1 < M) ? vt0 : T(0);
+    const T idx_ = T(1.0 / a.d.dx), idz_ = T(1.0 / a.d.dz), idn = T(uniform_load(a.tb.idn, j));
+    const bool ur = uR >= T(0), ul = uL >= T(0), wf = wF >= T(0), wb = wB >= T(0);
+    const bool upt = vt >= T(0), upb = vb >= T(0);
+    const bool have_t = upt ? (j > 0) : (j + 2 < M), have_b = upb ? (j > 1) : (j + 1 < M);
+    T delta[2];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+        const T *q = c[sp];
+        const T cc = q[0], cxp = q[1], cxm = q[2], czp = q[5], czm = q[6], cyp = q[9], cym = q[10];
+        const T dR = adv_face(cc, cxp, ur ? cxm : q[3], ur, true) - half * (cxp + cc);
+        const T dL = adv_face(cxm, cc, ul ? q[4] : cxp, ul, true) - half * (cc + cxm);
+        const T dF = adv_face(cc, czp, wf ? czm : q[7], wf, true) - half * (czp + cc);
+        const T dB = adv_face(czm, cc, wb ? q[8] : czp, wb, true) - half * (cc + czm);
+        // top face (rows j, j + 1) and bottom face (rows j - 1, j)
+        const T dT = (j + 1 < M) ? adv_face(cc, cyp, upt ? cym : q[11], upt, have_t) - half * (cyp + cc) : T(0);
+        const T dD = (j > 0) ? adv_face(cym, cc, upb ? q[12] : cyp, upb, have_b) - half * (cc + cym) : T(0);
+        delta[sp] = -((uR * dR - uL * dL) * idx_ + (wF * dF - wB * dB) * idz_ + (vt * dT - vb * dD) * idn);
+    }
+    if (a.mode == 1) {
+        const size_t q0 = (size_t)j * (size_t)pl + (size_t)e;
+        a.dbg[0][q0] += (double)delta[0];
+        a.dbg[1][q0] += (double)delta[1];
+        return;
+    }
+    const T dtg = T(member_ptr(a.clock, ms)[1]) * T(a.st.gam);
+    const bool keep = a.st.k < 2;
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
         T *h = member_ptr((T *)a.h[sp], ms), *r = member_ptr((T *)a.r[sp], ms);
-        if (a.st.k < 2) h[q0] += delta;
-        r[q0] += dt * T(a.st.gam) * delta;
+        T *rp = byte_at(r, o0);
+        if (keep) {
+            T *hp = byte_at(h, o0);
+            *hp += delta[sp];
+        }
+        *rp += dtg * delta[sp];
     }
 }
 

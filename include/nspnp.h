@@ -121,9 +121,7 @@ typedef struct nspnp_config {
      * a b <= 0 or when the upwind cell is a wall row), so that a profile advected
      * at cell Peclet numbers Re Sc |u| h >> 2 forms no new extrema; equal to
      * the mean on a linear profile of equal spacings.  Applies to the update
-     * and to the flux diagnostics alike; the row-slab Crank-Nicolson method
-     * (whose first pass runs inside the explicit kernel) is replaced by the
-     * lane-scan method under this setting.  Other values: NSPNP_ERR_INVALID. */
+     * and to the flux diagnostics alike.  Other values: NSPNP_ERR_INVALID. */
     int32_t migration_face;
 } nspnp_config;
 

@@ -1269,9 +1269,7 @@ static hipError_t explicit_launch(nspnp_state *s, const ExplicitArgs &a, int thr
 // elliptic solves.
 int cn_slab_rows(const nspnp_state *s) {
     const int L = s->tiles.cnslab;
-    // the factorisation uses the lane-scan method; so do limited advective
-    // face values (they change r after the explicit kernel has run)
-    if (L != 16 && L != 32 || s->cfg.implicit_xz || s->cfg.migration_face == 2) return 0;
+    if (L != 16 && L != 32 || s->cfg.implicit_xz) return 0;  // the factorisation uses the lane-scan method
     const int S = (s->d.M + L - 1) / L;
     const int64_t need = 2 * 5 * (int64_t)S * s->d.plane;             // doubles
     const int64_t have = 4 * (int64_t)s->d.nxh * s->d.nz * s->d.M;      // two half spectra
@@ -1303,12 +1301,20 @@ static hipError_t launch_cn_coef(nspnp_state *s, const Stage &st) {
 namespace {
 
 // Limited advective face values of the ions (migration_face 2).  The explicit
-// kernel forms the central advective flux; this kernel adds, cell by cell,
-// the difference between the limited flux's divergence and the central one to
+// kernel forms the central advective flux; this pass adds, cell by cell, the
+// difference between the limited flux's divergence and the central one to
 // the ions' H (when the stage keeps it) and to their Crank-Nicolson
 // right-hand side (dt gam times the difference), or, in mode 1, to the
-// exported H.  One thread per cell; the face values reach two cells upwind
-// (periodic in x and z; the upwind cell alone where it is a wall row).
+// exported H.  The face values reach two cells upwind (periodic in x and z;
+// the upwind cell alone where it is a wall row).
+//
+// One thread per (x, z) column marches a slab of rows with rows j-2 .. j+2
+// of c+- of its own column in registers (the next row loaded one step
+// ahead); x and z neighbours come from the same row, which the neighbouring
+// columns' threads read at the same time.  With the row-slab Crank-Nicolson
+// method, whose first pass ran inside the explicit kernel on the r before
+// this correction, the pass adds the slab exits of its own change of r to
+// the method's scratch (the exits are linear in r), on the same slabs.
 struct AdvArgs {
     Dims d;
     size_t ms;
@@ -1318,82 +1324,132 @@ struct AdvArgs {
     void *h[2], *r[2];
     double *dbg[2];
     const double *clock;
-    int mode;  // 0: substep (H, r of this stage); 1: dbg only
+    int mode;            // 0: substep (H, r of this stage); 1: dbg only
+    int ntiles;          // 256-column tiles per plane
+    int slabs, slab_rows;
+    const double *cn_coef;  // this stage's row-slab CN coefficients (NULL: no exits to update)
+    double *cn_scr;
 };
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_adv_limit(AdvArgs a) {
+    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);  // column tiles fastest: z-neighbours share an L2
+    const unsigned ct = tile % (unsigned)a.ntiles;
+    const unsigned slab = (tile / (unsigned)a.ntiles) % (unsigned)a.slabs;
+    const unsigned mem = tile / ((unsigned)a.ntiles * (unsigned)a.slabs);
     const int pl = (int)a.d.plane;
-    const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int e = (int)(ct * blockDim.x + threadIdx.x);
     if (e >= pl) return;
-    const int j = (int)blockIdx.y, M = a.d.M, nx = a.d.nx, nz = a.d.nz;
+    const int M = a.d.M, nx = a.d.nx, nz = a.d.nz;
     const size_t ms = a.ms;
     const int i = e % nx, k = e / nx;
     auto wrap = [](int q, int n) { return q < 0 ? q + n : (q >= n ? q - n : q); };  // n >= 4
-    // every access is a field's base plus a 32-bit byte offset (a field of
-    // every supported grid is below 2^32 bytes); rows outside the grid are
-    // clamped to an existing row and their values not used, so that all
-    // loads are unconditional and issued before any arithmetic
+    // a field's base plus a 32-bit byte offset (a field of every supported
+    // grid is below 2^32 bytes); rows outside the grid are clamped to an
+    // existing row and their values not used
     const unsigned W = (unsigned)sizeof(T), P = (unsigned)pl * W;
-    const unsigned row = (unsigned)j * P, kx = (unsigned)(k * nx) * W;
-    const unsigned o0 = row + (unsigned)e * W;
-    const unsigned oxp = row + kx + (unsigned)wrap(i + 1, nx) * W, oxm = row + kx + (unsigned)wrap(i - 1, nx) * W;
-    const unsigned oxp2 = row + kx + (unsigned)wrap(i + 2, nx) * W, oxm2 = row + kx + (unsigned)wrap(i - 2, nx) * W;
-    const unsigned ozp = row + (unsigned)(wrap(k + 1, nz) * nx + i) * W;
-    const unsigned ozm = row + (unsigned)(wrap(k - 1, nz) * nx + i) * W;
-    const unsigned ozp2 = row + (unsigned)(wrap(k + 2, nz) * nx + i) * W;
-    const unsigned ozm2 = row + (unsigned)(wrap(k - 2, nz) * nx + i) * W;
-    auto rowoff = [&](int jj) { return (unsigned)(jj < 0 ? 0 : (jj >= M ? M - 1 : jj)) * P + (unsigned)e * W; };
-    const unsigned oyp = rowoff(j + 1), oym = rowoff(j - 1), oyp2 = rowoff(j + 2), oym2 = rowoff(j - 2);
-    const T *u = member_ptr((const T *)a.u, ms), *v = member_ptr((const T *)a.v, ms);
-    const T *w = member_ptr((const T *)a.w, ms);
-    const T uL = *byte_at(u, o0), uR = *byte_at(u, oxp), wB = *byte_at(w, o0), wF = *byte_at(w, ozp);
-    const T vb0 = *byte_at(v, o0), vt0 = *byte_at(v, oyp);
-    T c[2][13];  // own; x +1 -1 +2 -2; z +1 -1 +2 -2; y +1 -1 +2 -2
-#pragma unroll
-    for (int sp = 0; sp < 2; ++sp) {
-        const T *cf = member_ptr((const T *)a.c[sp], ms);
-        const unsigned off[13] = {o0, oxp, oxm, oxp2, oxm2, ozp, ozm, ozp2, ozm2, oyp, oym, oyp2, oym2};
-#pragma unroll
-        for (int q = 0; q < 13; ++q) c[sp][q] = *byte_at(cf, off[q]);
-    }
+    const unsigned kx = (unsigned)(k * nx) * W;
+    const unsigned ex = (unsigned)e * W;
+    const unsigned dxp = kx + (unsigned)wrap(i + 1, nx) * W, dxm = kx + (unsigned)wrap(i - 1, nx) * W;
+    const unsigned dxp2 = kx + (unsigned)wrap(i + 2, nx) * W, dxm2 = kx + (unsigned)wrap(i - 2, nx) * W;
+    const unsigned dzp = (unsigned)(wrap(k + 1, nz) * nx + i) * W, dzm = (unsigned)(wrap(k - 1, nz) * nx + i) * W;
+    const unsigned dzp2 = (unsigned)(wrap(k + 2, nz) * nx + i) * W, dzm2 = (unsigned)(wrap(k - 2, nz) * nx + i) * W;
+    auto rowb = [&](int jj) { return (unsigned)(jj < 0 ? 0 : (jj >= M ? M - 1 : jj)) * P; };
+    const T *u = member_ptr_at((const T *)a.u, ms, mem), *v = member_ptr_at((const T *)a.v, ms, mem);
+    const T *w = member_ptr_at((const T *)a.w, ms, mem);
+    const T *cf[2] = {member_ptr_at((const T *)a.c[0], ms, mem), member_ptr_at((const T *)a.c[1], ms, mem)};
+    T *hf[2] = {member_ptr_at((T *)a.h[0], ms, mem), member_ptr_at((T *)a.h[1], ms, mem)};
+    T *rf[2] = {member_ptr_at((T *)a.r[0], ms, mem), member_ptr_at((T *)a.r[1], ms, mem)};
     const T half = T(0.5);
-    const T vb = (j > 0) ? vb0 : T(0), vt = (j + 1 < M) ? vt0 : T(0);
-    const T idx_ = T(1.0 / a.d.dx), idz_ = T(1.0 / a.d.dz), idn = T(uniform_load(a.tb.idn, j));
-    const bool ur = uR >= T(0), ul = uL >= T(0), wf = wF >= T(0), wb = wB >= T(0);
-    const bool upt = vt >= T(0), upb = vb >= T(0);
-    const bool have_t = upt ? (j > 0) : (j + 2 < M), have_b = upb ? (j > 1) : (j + 1 < M);
-    T delta[2];
-#pragma unroll
-    for (int sp = 0; sp < 2; ++sp) {
-        const T *q = c[sp];
-        const T cc = q[0], cxp = q[1], cxm = q[2], czp = q[5], czm = q[6], cyp = q[9], cym = q[10];
-        const T dR = adv_face(cc, cxp, ur ? cxm : q[3], ur, true) - half * (cxp + cc);
-        const T dL = adv_face(cxm, cc, ul ? q[4] : cxp, ul, true) - half * (cc + cxm);
-        const T dF = adv_face(cc, czp, wf ? czm : q[7], wf, true) - half * (czp + cc);
-        const T dB = adv_face(czm, cc, wb ? q[8] : czp, wb, true) - half * (cc + czm);
-        // top face (rows j, j + 1) and bottom face (rows j - 1, j)
-        const T dT = (j + 1 < M) ? adv_face(cc, cyp, upt ? cym : q[11], upt, have_t) - half * (cyp + cc) : T(0);
-        const T dD = (j > 0) ? adv_face(cym, cc, upb ? q[12] : cyp, upb, have_b) - half * (cc + cym) : T(0);
-        delta[sp] = -((uR * dR - uL * dL) * idx_ + (wF * dF - wB * dB) * idz_ + (vt * dT - vb * dD) * idn);
-    }
-    if (a.mode == 1) {
-        const size_t q0 = (size_t)j * (size_t)pl + (size_t)e;
-        a.dbg[0][q0] += (double)delta[0];
-        a.dbg[1][q0] += (double)delta[1];
-        return;
-    }
-    const T dtg = T(member_ptr(a.clock, ms)[1]) * T(a.st.gam);
+    const T idx_ = T(1.0 / a.d.dx), idz_ = T(1.0 / a.d.dz);
+    const T dtg = T(member_ptr_at(a.clock, ms, mem)[1]) * T(a.st.gam);
     const bool keep = a.st.k < 2;
+    const bool fuse = a.mode == 0 && a.cn_coef != nullptr;
+    const double *cnc = fuse ? member_ptr_at(a.cn_coef, ms, mem) : nullptr;
+    double cl[2] = {0.0, 0.0}, ck[2] = {0.0, 0.0};
+    const int j0 = (int)slab * a.slab_rows;
+    const int j1 = (j0 + a.slab_rows < M) ? j0 + a.slab_rows : M;
+    // own-column window rows j-2 .. j+2 of both species, and v at row j
+    T win[2][5];
 #pragma unroll
-    for (int sp = 0; sp < 2; ++sp) {
-        T *h = member_ptr((T *)a.h[sp], ms), *r = member_ptr((T *)a.r[sp], ms);
-        T *rp = byte_at(r, o0);
-        if (keep) {
-            T *hp = byte_at(h, o0);
-            *hp += delta[sp];
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) win[sp][q] = *byte_at(cf[sp], rowb(j0 - 2 + q) + ex);
+    T vj = *byte_at(v, rowb(j0) + ex);
+    for (int j = j0; j < j1; ++j) {
+        const unsigned rb = rowb(j);
+        // this row's loads, then the next row's window entry (one step ahead)
+        const T uL = *byte_at(u, rb + ex), uR = *byte_at(u, rb + dxp);
+        const T wB = *byte_at(w, rb + ex), wF = *byte_at(w, rb + dzp);
+        const T vn = *byte_at(v, rowb(j + 1) + ex);
+        T nb[2][8];  // x +1 -1 +2 -2, z +1 -1 +2 -2
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) {
+            const unsigned off[8] = {dxp, dxm, dxp2, dxm2, dzp, dzm, dzp2, dzm2};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) nb[sp][q] = *byte_at(cf[sp], rb + off[q]);
         }
-        *rp += dtg * delta[sp];
+        T hv[2], rv[2];
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) {
+            hv[sp] = *byte_at((const T *)hf[sp], rb + ex);  // (read in every mode and stage: unconditional)
+            rv[sp] = *byte_at((const T *)rf[sp], rb + ex);
+        }
+        T nxt[2];
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) nxt[sp] = *byte_at(cf[sp], rowb(j + 3) + ex);
+        const T vb = (j > 0) ? vj : T(0), vt = (j + 1 < M) ? vn : T(0);
+        const T idn = T(uniform_load(a.tb.idn, j));
+        const bool ur = uR >= T(0), ul = uL >= T(0), wf = wF >= T(0), wb = wB >= T(0);
+        const bool upt = vt >= T(0), upb = vb >= T(0);
+        const bool have_t = upt ? (j > 0) : (j + 2 < M), have_b = upb ? (j > 1) : (j + 1 < M);
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) {
+            const T *q = nb[sp];
+            const T cc = win[sp][2], cyp = win[sp][3], cym = win[sp][1];
+            const T cxp = q[0], cxm = q[1], czp = q[4], czm = q[5];
+            const T dR = adv_face(cc, cxp, ur ? cxm : q[2], ur, true) - half * (cxp + cc);
+            const T dL = adv_face(cxm, cc, ul ? q[3] : cxp, ul, true) - half * (cc + cxm);
+            const T dF = adv_face(cc, czp, wf ? czm : q[6], wf, true) - half * (czp + cc);
+            const T dB = adv_face(czm, cc, wb ? q[7] : czp, wb, true) - half * (cc + czm);
+            // top face (rows j, j + 1) and bottom face (rows j - 1, j)
+            const T dT = (j + 1 < M) ? adv_face(cc, cyp, upt ? cym : win[sp][4], upt, have_t) - half * (cyp + cc)
+                                     : T(0);
+            const T dD = (j > 0) ? adv_face(cym, cc, upb ? win[sp][0] : cyp, upb, have_b) - half * (cc + cym) : T(0);
+            const T delta = -((uR * dR - uL * dL) * idx_ + (wF * dF - wB * dB) * idz_ + (vt * dT - vb * dD) * idn);
+            if (a.mode == 1) {
+                a.dbg[sp][(size_t)j * (size_t)pl + (size_t)e] += (double)delta;
+            } else {
+                if (keep) *byte_at(hf[sp], rb + ex) = hv[sp] + delta;
+                const T rn = rv[sp] + dtg * delta;
+                *byte_at(rf[sp], rb + ex) = rn;
+                if (fuse) {  // the ions' system (2): g, m at 2 * 3M; its n-products after the slab products
+                    const double *cfc = cnc + 2 * 3 * (size_t)M;
+                    const double *np = cnc + 9 * (size_t)M + 9 * kCnMaxSlabs + 2 * (size_t)M;
+                    const double dr = (double)rn - (double)rv[sp];  // the change the CN solve will see
+                    cl[sp] = uniform_load(cfc, j) * dr + uniform_load(cfc + M, j) * cl[sp];
+                    ck[sp] += uniform_load(np, j) * cl[sp];
+                }
+            }
+        }
+        // advance the window
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) win[sp][q] = win[sp][q + 1];
+            win[sp][4] = nxt[sp];
+        }
+        vj = vn;
+    }
+    if (fuse) {  // add this pass's slab exits to the explicit kernel's
+        const unsigned S = (unsigned)a.slabs;
+        double *scr = member_ptr_at(a.cn_scr, ms, mem);
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp) {
+            const int f = 3 + sp;
+            scr[((size_t)f * S + slab) * (size_t)pl + (size_t)e] += cl[sp];
+            scr[((size_t)(5 + f) * S + slab) * (size_t)pl + (size_t)e] += ck[sp];
+        }
     }
 }
 
@@ -1414,9 +1470,20 @@ hipError_t launch_adv_limit(nspnp_state *s, const Stage &st, double *const out[5
     }
     a.clock = s->clock;
     a.mode = out ? 1 : 0;
-    const dim3 g((unsigned)((s->d.plane + 255) / 256), (unsigned)s->d.M, out ? 1u : (unsigned)s->nmem);
-    if (s->fp64) k_adv_limit<double><<<g, 256, 0, s->stream>>>(a);
-    else k_adv_limit<float><<<g, 256, 0, s->stream>>>(a);
+    a.ntiles = (int)((s->d.plane + 255) / 256);
+    // the row-slab CN method's slabs (its exits get this pass's share), else
+    // 32-row slabs
+    const int L = out ? 0 : cn_slab_rows(s);
+    a.slab_rows = L ? L : 32;
+    a.slabs = (s->d.M + a.slab_rows - 1) / a.slab_rows;
+    if (L) {
+        a.cn_coef = s->cn_coef + (size_t)st.k * cn_stage_stride(s->d.M);
+        a.cn_scr = (double *)s->spec;
+    }
+    const int nm = out ? 1 : s->nmem;
+    const unsigned blocks = (unsigned)((int64_t)a.ntiles * a.slabs * nm);
+    if (s->fp64) k_adv_limit<double><<<blocks, 256, 0, s->stream>>>(a);
+    else k_adv_limit<float><<<blocks, 256, 0, s->stream>>>(a);
     return hipGetLastError();
 }
 

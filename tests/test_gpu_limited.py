@@ -102,6 +102,24 @@ def test_limited_run_matches_oracle(P, O, dims):
     assert abs(mp - omp) < 1e-12 * omp and abs(mm - omm) < 1e-12 * omm
 
 
+@pytest.mark.parametrize("cnslab", [0, 16, 32])
+def test_limited_run_with_each_cn_method(P, O, cnslab):
+    """The limited correction after the explicit kernel under the lane-scan
+    (0) and the row-slab (16, 32 rows) Crank-Nicolson methods: the row-slab
+    method's first pass ran inside the explicit kernel on the uncorrected r,
+    and the correction pass adds the slab exits of its own change of r."""
+    cfg, g, o = pair(P, O, nx=32, ny=65, nz=24, re=1500.0, debye=0.06, vhat=12.0, dt=0.0, cfl=0.5, seed=9,
+                     u_noise=0.3)
+    g.set_tiles(cnslab=cnslab)
+    assert g.tiles()["cnslab"] == cnslab
+    for chunk in range(3):
+        g.step(20)
+        o.run(20)
+        err = errors(g, o)
+        note(f"  cnslab {cnslab}, after {20 * (chunk + 1)} substeps: {max(err.values()):.3e}")
+        assert max(err.values()) < 1e-10, err
+
+
 def test_stirred_blob_keeps_bounds_on_the_gpu(P, O):
     """Uncharged ions (vhat 0, c+ = c-) in a discretely divergence-free
     cellular flow between the walls: the limited update keeps the blob

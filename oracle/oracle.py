@@ -19,6 +19,11 @@ import numpy as np
 _HERE = Path(__file__).resolve().parent
 _SRC = _HERE / "nspnp_oracle.c"
 _LIB = _HERE / "libnspnp_oracle.so"
+# An instrumented (address and undefined-behaviour checking) build of the same
+# source, made by the CPU sanitizer test, is loaded instead of the plain one
+# when NSPNP_ORACLE_SANITIZE=1 (the process then has the checker's runtime
+# preloaded)
+_LIB_SAN = _HERE / "libnspnp_oracle_san.so"
 
 FIELDS = {"u": 0, "v": 1, "w": 2, "cp": 3, "cm": 4, "phi": 5, "p": 6}
 
@@ -55,9 +60,15 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not _LIB.exists():
-        build(force=False)
-    lib = ctypes.CDLL(str(_LIB))
+    if os.environ.get("NSPNP_ORACLE_SANITIZE") == "1":
+        if not _LIB_SAN.exists():
+            raise RuntimeError(f"{_LIB_SAN} is not built (the CPU sanitizer test builds it)")
+        path = _LIB_SAN
+    else:
+        if not _LIB.exists():
+            build(force=False)
+        path = _LIB
+    lib = ctypes.CDLL(str(path))
     sig = {
         "or_create": (_P, [ctypes.POINTER(_Config)]),
         "or_destroy": (None, [_P]),

@@ -144,10 +144,44 @@ def batch_means(x: np.ndarray, nbatch: int = 10):
     return float(b.mean()), float(b.std(ddof=1) / math.sqrt(nbatch))
 
 
+def metrics_record(s, prev: dict | None = None, kernels: bool = False) -> dict:
+    """One line of run metrics from the library's reductions: clock, wall
+    stresses with the instantaneous c_f = 2 tau and Re_tau = Re sqrt(tau)
+    (tau the mean of both walls), ion contents, KE, max |div u|, the
+    concentration minima, max |dPhi| and the KE-budget terms.  With the
+    previous record, the budget residual dKE/dt - (wall work - dissipation +
+    force work), the rate from the two records' KE and the mean of their
+    terms (first order in the interval).  kernels: per-class ms per launch of
+    the event profiler since the previous record (the profiler is on)."""
+    t, dt, _, ns = s.clock()
+    tb, tt = s.wall_shear_stress()
+    _, _, mp, mm = s.ion_flux()
+    d = s.diagnostics()
+    eb = s.energy_budget()
+    tau = 0.5 * (tb + tt)
+    rec = {"t": t, "dt": dt, "substeps": int(ns), "tau_bottom": tb, "tau_top": tt, "cf": 2.0 * tau,
+           "re_tau": s.cfg.re * math.sqrt(tau) if tau > 0 else float("nan"), "ion_content": [mp, mm],
+           "ke": d["ke"], "max_div": d["max_div"], "min_c": [d["min_cp"], d["min_cm"]], "max_dphi": d["max_dphi"],
+           "energy": eb}
+
+    def net(e):
+        return e["wall_work"] - e["dissipation"] + e["force_work"]
+
+    if prev is not None and t > prev["t"]:
+        rec["budget_residual"] = (d["ke"] - prev["ke"]) / (t - prev["t"]) - 0.5 * (net(eb) + net(prev["energy"]))
+    if kernels:
+        tot = s.profile_read()
+        last = (prev or {}).get("_kernel_totals", {})
+        rec["kernel_ms"] = {k: (ms - last.get(k, (0.0, 0))[0]) / max(1, n - last.get(k, (0.0, 0))[1])
+                            for k, (ms, n) in tot.items() if n > last.get(k, (0.0, 0))[1]}
+        rec["_kernel_totals"] = tot
+    return rec
+
+
 def run_campaign(cfg: Config, t_spin: float, t_avg: float, every: int = 10, monitor: float = 0.5,
                  amp: float = 0.3, seed: int = 7, ckpt: str | None = None, ckpt_every: float = 50.0,
                  resume: str | None = None, ion_start: str = "equilibrium", t_charge: float | None = None,
-                 log=print) -> dict:
+                 log=print, metrics: str | None = None, metrics_kernels: bool = False) -> dict:
     """t_charge (optional): the run starts uncharged (the configuration's
     vhat is applied as wall values -+vhat/2 of phi, a discretely identical
     form of the same walls, only from t_charge on, together with the
@@ -165,6 +199,10 @@ def run_campaign(cfg: Config, t_spin: float, t_avg: float, every: int = 10, moni
         perturbed_start(s, amp, seed)
     t0 = time.time()
     hist = []  # (t, tau_bottom, tau_top)
+    mfile = open(metrics, "a") if metrics else None  # JSON lines, one per monitor interval
+    if mfile and metrics_kernels:
+        s.profile_enable(True)
+    mprev = {"rec": None}
     st0 = s.clock()
     state = {"t": st0[0], "dt": st0[1], "ns": st0[3], "averaging": st0[0] >= t_spin, "next_ckpt": st0[0] + ckpt_every}
     if state["averaging"] and not resume:
@@ -201,6 +239,11 @@ def run_campaign(cfg: Config, t_spin: float, t_avg: float, every: int = 10, moni
             state.update(t=t, dt=dt, ns=ns)
             tb, tt = s.wall_shear_stress()
             hist.append((t, tb, tt))
+            if mfile:
+                rec = metrics_record(s, mprev["rec"], metrics_kernels)
+                mprev["rec"] = rec
+                mfile.write(json.dumps({k: v for k, v in rec.items() if not k.startswith("_")}) + "\n")
+                mfile.flush()
             if ckpt and t >= state["next_ckpt"]:
                 s.save(ckpt)
                 state["next_ckpt"] = t + ckpt_every
@@ -221,6 +264,8 @@ def run_campaign(cfg: Config, t_spin: float, t_avg: float, every: int = 10, moni
         stopped = {"t": state["t"], "reason": str(e)}
         log(f"[campaign] stopped at t = {state['t']:.2f}: {e}")
     wall = time.time() - t0
+    if mfile:
+        mfile.close()
     st = s.statistics()
     if st["samples"] == 0:  # nothing averaged: no statistics to report
         for k in ("cf", "re_tau", "tau", "tau_bottom", "tau_top"):
@@ -293,6 +338,9 @@ def main():
                     help="start uncharged and apply the wall voltage (with the equilibrium double layer) "
                          "at this time")
     ap.add_argument("--out", default="campaign_report.json")
+    ap.add_argument("--metrics", default=None, help="append one JSON line of run metrics per monitor interval")
+    ap.add_argument("--metrics-kernels", action="store_true",
+                    help="include per-class kernel ms from the event profiler in the metrics lines")
     a = ap.parse_args()
     cfg = configs.WORKLOADS[a.workload](precision=a.precision)
     over = {"vhat": a.vhat, "u_noise": 0.0, "c_noise": 0.0, "migration_face": a.migration_face}
@@ -304,7 +352,7 @@ def main():
     cfg = dataclasses.replace(cfg, **over)
     rep = run_campaign(cfg, a.t_spin, a.t_avg, every=a.every, amp=a.amp, ckpt=a.ckpt, resume=a.resume,
                        ion_start=a.ion_start, t_charge=a.t_charge,
-                       log=lambda m: print(m, flush=True))
+                       log=lambda m: print(m, flush=True), metrics=a.metrics, metrics_kernels=a.metrics_kernels)
     Path(a.out).write_text(json.dumps(rep, indent=1) + "\n")
     if rep["stopped"]:
         print(f"[campaign] stopped early at t = {rep['stopped']['t']:.2f}: {rep['stopped']['reason']}", flush=True)

@@ -83,3 +83,43 @@ def test_rms_peaks_in_wall_units():
     assert pk["cm_upper"]["rms"] == r_cm[19]
     st["u_tau"] = float("nan")
     assert np.isnan(rms_peaks(st, SimpleNamespace(re=3000.0))["cp_lower"]["y_plus"])
+
+
+def test_metrics_record_from_a_stub_solver():
+    """The metrics line's derived values: c_f = 2 tau and Re_tau = Re
+    sqrt(tau) from the mean wall stress, the KE-budget residual between two
+    records, and per-launch kernel times from the profiler's running totals."""
+    from types import SimpleNamespace
+    from paper_1701_02005_amd.campaign import metrics_record
+
+    class Stub:
+        def __init__(self, t, ke, ww, dis, fw, prof):
+            self.cfg = SimpleNamespace(re=400.0)
+            self._t, self._ke, self._e, self._prof = t, ke, (ww, dis, fw), prof
+
+        def clock(self):
+            return self._t, 1e-3, 0, int(self._t * 1000)
+
+        def wall_shear_stress(self):
+            return 2.4e-3, 2.6e-3
+
+        def ion_flux(self):
+            return [0.0], [0.0], 4.0, 4.0
+
+        def diagnostics(self):
+            return {"ke": self._ke, "max_div": 1e-14, "min_cp": 0.9, "min_cm": 0.8, "max_dphi": 0.5}
+
+        def energy_budget(self):
+            return dict(zip(("wall_work", "dissipation", "force_work"), self._e))
+
+        def profile_read(self):
+            return self._prof
+
+    a = metrics_record(Stub(1.0, 1.0, 0.30, 0.10, 0.0, {"explicit_rhs": (4.0, 2)}), None, kernels=True)
+    assert abs(a["cf"] - 5.0e-3) < 1e-15 and abs(a["re_tau"] - 400.0 * math.sqrt(2.5e-3)) < 1e-12
+    assert "budget_residual" not in a and a["kernel_ms"] == {"explicit_rhs": 2.0}
+    b = metrics_record(Stub(1.5, 1.1, 0.30, 0.10, 0.0, {"explicit_rhs": (10.0, 5)}), a, kernels=True)
+    assert abs(b["budget_residual"] - (0.2 - 0.2)) < 1e-12  # dKE/dt = 0.2 = wall work - dissipation
+    assert abs(b["kernel_ms"]["explicit_rhs"] - 2.0) < 1e-12  # (10 - 4) ms over 3 launches
+    c = metrics_record(Stub(2.0, 1.1, 0.30, 0.10, -0.05, {}), b)
+    assert abs(c["budget_residual"] - (0.0 - 0.175)) < 1e-12

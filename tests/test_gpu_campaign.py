@@ -62,3 +62,29 @@ def test_charged_laminar_campaign_with_limited_advection(P):
     # (the RMS is sqrt(<q^2> - <q>^2): rounding of q^2 ~ 10^3 leaves ~1e-5 absolute)
     assert max(rep["rms"]["cp"]) < 1e-4 * max(cp_eq) and max(rep["rms"]["cm"]) < 1e-4 * max(cp_eq)
     assert set(rep["rms_peaks"]) == {"cp_lower", "cp_upper", "cm_lower", "cm_upper"}
+
+
+def test_metrics_lines_on_laminar_flow(P, tmp_path):
+    """The JSON-lines metrics of a laminar campaign: c_f = 2/Re, Re_tau =
+    sqrt(Re), constant ion contents, a divergence-free field, a KE budget that
+    closes (steady flow: wall work = dissipation, no Coulomb work) and the
+    event profiler's per-class times."""
+    import json
+    from paper_1701_02005_amd import campaign as C
+    cfg = dataclasses.replace(P.configs.couette_small(), vhat=0.0, u_noise=0.0, c_noise=0.0, dt=0.0, cfl=0.5)
+    print("case: laminar campaign metrics 32x33x32", flush=True)
+    sys.stdout.flush()
+    path = tmp_path / "metrics.jsonl"
+    C.run_campaign(cfg, t_spin=0.3, t_avg=0.6, every=1, monitor=0.1, amp=0.0, log=lambda m: None,
+                   metrics=str(path), metrics_kernels=True)
+    recs = [json.loads(line) for line in path.read_text().splitlines()]
+    assert len(recs) >= 8
+    m0 = recs[0]["ion_content"]
+    for r in recs:
+        assert abs(r["cf"] - 2.0 / cfg.re) < 1e-11
+        assert abs(r["re_tau"] - math.sqrt(cfg.re)) < 1e-8
+        assert abs(r["ion_content"][0] - m0[0]) < 1e-12 * m0[0] and abs(r["ion_content"][1] - m0[1]) < 1e-12 * m0[1]
+        assert r["max_div"] < 1e-12
+        assert "explicit_rhs" in r["kernel_ms"] and r["kernel_ms"]["explicit_rhs"] > 0
+    for r in recs[1:]:
+        assert abs(r["budget_residual"]) < 1e-9 * r["energy"]["dissipation"]

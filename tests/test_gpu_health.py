@@ -207,3 +207,32 @@ def test_launch_order_shapes_are_bitwise_neutral(P, precision, dims):
         ref = a.get_field(k).cpu()
         assert torch.equal(ref, b.get_field(k).cpu()), k
         assert torch.equal(ref, c.get_field(k).cpu()), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_identical_runs_are_bitwise_reproducible(P, precision):
+    """Every reduction (the adaptive dt, run statistics, diagnostics, ion flux,
+    KE budget) combines partial sums in a fixed order, without atomics: two
+    runs of one configuration agree bit for bit, fields and reductions alike."""
+    import torch
+    cfg = small(P, nx=48, ny=33, nz=36, dt=0.0, cfl=0.5, re=1500.0, vhat=12.0, debye=0.08, seed=21,
+                u_noise=0.2, migration_face=2, precision=precision)
+    note(f"case: two identical runs 48x33x36 {precision}, migration face 2")
+    out = []
+    for _ in range(2):
+        g = P.Solver(cfg)
+        g.stats_begin(1)
+        g.step(60)
+        g.sync()
+        st = g.stats_read()
+        out.append({"fields": {k: g.get_field(k).cpu() for k in FIELDS}, "clock": g.clock(), "stats": st,
+                    "diag": g.diagnostics(), "flux": g.ion_flux(), "energy": g.energy_budget(),
+                    "tau": g.wall_shear_stress()})
+    a, b = out
+    for k in FIELDS:
+        assert torch.equal(a["fields"][k], b["fields"][k]), k
+    assert a["clock"] == b["clock"] and a["diag"] == b["diag"] and a["energy"] == b["energy"]
+    assert a["tau"] == b["tau"]
+    assert a["stats"][0] == b["stats"][0] and a["stats"][1] == b["stats"][1] and a["stats"][2] == b["stats"][2]
+    assert list(a["flux"][0]) == list(b["flux"][0]) and list(a["flux"][1]) == list(b["flux"][1])
+    assert a["flux"][2:] == b["flux"][2:]
